@@ -1,0 +1,218 @@
+"""Pins of the oracle's SGSPM / GSPM step and energies against the paper and mathematics."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import demag, manufactured as mf, operators, scheme
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_accuracy.json")
+
+
+def _manufactured_error(dim, n, dt, method):
+    shape = {1: (1, 1, n), 2: (1, n, n), 3: (n, n, n)}[dim]
+    nxyz = shape[::-1]
+    h = tuple(1.0 / k if k > 1 else 1.0 for k in nxyz)
+    P = scheme.Problem(n=nxyz, h=h, eps=1.0, dt=dt)
+    alpha = 1e-3
+    step = scheme.sgspm_step if method == "sgspm" else scheme.gspm_step
+    m = mf.exact(shape, 0.0, dim)
+    steps = int(round(1.0 / dt))
+    for k in range(steps):
+        m = step(P, m, alpha, (0.0, 0.0, 0.0), src=mf.forcing(shape, k * dt, dim, 1.0, alpha))
+    return float(np.abs(m - mf.exact(shape, 1.0, dim)).max())
+
+
+def _golden_rows():
+    with open(GOLDEN) as f:
+        rows = json.load(f)["rows"]
+    out = []
+    for r in rows:
+        for method in ("sgspm", "gspm"):
+            if r["n"] == 2 and method == "gspm":
+                continue  # identical to SGSPM on a 2x2x2 grid (uniform exact solution)
+            out.append(pytest.param(r, method, id=f"{r['table']}-n{r['n']}-dt{r['dt']}-{method}"))
+    return out
+
+
+@pytest.mark.parametrize("row,method", _golden_rows())
+def test_paper_printed_errors(row, method):
+    """Paper §5.1 tables: the printed max-norm errors, reproduced by the oracle's readings.
+
+    3-D rows agree to better than 2e-8 relative (observed 1e-12 ... 1e-8); the 1-D rows
+    agree to ~1e-5 relative only (the paper's 1-D set-up differs in some unstated detail).
+    """
+    err = _manufactured_error(row["dim"], row["n"], row["dt"], method)
+    rtol = 2e-8 if row["dim"] == 3 else 3e-5
+    assert err == pytest.approx(row[method], rel=rtol)
+
+
+def test_first_order_in_time_2d():
+    errs = [_manufactured_error(2, 32, dt, "sgspm") for dt in (0.05, 0.025, 0.0125)]
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all((orders > 0.85) & (orders < 1.2)), orders
+
+
+def _random_unit(shape, seed):
+    rng = np.random.default_rng(seed)
+    m = rng.normal(size=(3,) + shape)
+    return m / np.linalg.norm(m, axis=0)
+
+
+def test_sweeps_equal_theory_form():
+    """§4: the g-form updates equal (m^s - m^n)/dt = -m_j Lap_h g_k + m_k Lap_h g_j (eps = 1, f = 0)."""
+    shape = (3, 4, 5)
+    P = scheme.Problem(n=shape[::-1], h=(0.2, 0.25, 0.3), eps=1.0, dt=0.01)
+    m = _random_unit(shape, 7)
+    t = {}
+    scheme.sgspm_step(P, m, 0.0, (0.0, 0.0, 0.0), tape=t)
+    L = lambda g: operators.laplacian(g, P.h)  # noqa: E731
+    dt = P.dt
+    m1, m2, m3 = m
+    chk = [
+        ((t["m1s"] - m1) / dt, -m2 * L(t["g3n"]) + m3 * L(t["g2n"])),
+        ((t["m2s"] - m2) / dt, -m3 * L(t["g1s"]) + t["m1s"] * L(t["g3n"])),
+        ((t["m3s"] - m3) / dt, -t["m1s"] * L(t["g2s"]) + t["m2s"] * L(t["g1s"])),
+        ((t["m2ss"] - m2) / dt, -t["m3s"] * L(t["g1s"]) + t["m1s"] * L(t["g3ss"])),
+        ((t["m1ss"] - m1) / dt, -t["m2ss"] * L(t["g3ss"]) + t["m3s"] * L(t["g2ss"])),
+    ]
+    for lhs, rhs in chk:
+        assert np.allclose(lhs, rhs, atol=1e-9)
+
+
+def test_unit_length_after_projection():
+    shape = (2, 5, 6)
+    P = scheme.Problem(n=shape[::-1], h=(1.0, 1.0, 1.0), eps=0.8, dt=0.1, Q=0.2, stray=True)
+    m = _random_unit(shape, 8)
+    for _ in range(3):
+        m = scheme.sgspm_step(P, m, 0.05, (0.01, 0.0, 0.02))
+        assert np.abs(np.linalg.norm(m, axis=0) - 1.0).max() <= 4 * np.finfo(float).eps
+
+
+def test_macrospin_closed_form_first_order():
+    """Single cell, h_e = h0 e3: phi = phi0 + h0 t, tan(theta/2) = tan(theta0/2) exp(-alpha h0 t)."""
+    h0, alpha, T = 1.0, 0.2, 2.0
+    th0, ph0 = 1.0, 0.3
+    exact_th = 2 * np.arctan(np.tan(th0 / 2) * np.exp(-alpha * h0 * T))
+    exact = np.array([np.sin(exact_th) * np.cos(ph0 + h0 * T),
+                      np.sin(exact_th) * np.sin(ph0 + h0 * T), np.cos(exact_th)])
+    errs = []
+    for dt in (0.02, 0.01, 0.005):
+        P = scheme.Problem(n=(1, 1, 1), h=(1.0, 1.0, 1.0), eps=1.0, dt=dt)
+        m = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)]).reshape(3, 1, 1, 1)
+        for _ in range(int(round(T / dt))):
+            m = scheme.sgspm_step(P, m, alpha, (0.0, 0.0, h0))
+        errs.append(np.abs(m.ravel() - exact).max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all((orders > 0.9) & (orders < 1.1)), (errs, orders)
+
+
+def test_fixed_points():
+    shape = (2, 3, 4)
+    P = scheme.Problem(n=shape[::-1], h=(1.0, 1.0, 1.0), eps=1.0, dt=0.1)
+    u = np.ones(shape)
+    m = np.stack([0.6 * u, 0.0 * u, 0.8 * u])
+    assert np.allclose(scheme.sgspm_step(P, m, 0.1, (0, 0, 0)), m, atol=1e-15)
+    Pa = scheme.Problem(n=shape[::-1], h=(1.0, 1.0, 1.0), eps=1.0, dt=0.1, Q=0.5)
+    for s in (1.0, -1.0):
+        e1 = np.stack([s * u, 0 * u, 0 * u])
+        assert np.allclose(scheme.sgspm_step(Pa, e1, 0.1, (0, 0, 0)), e1, atol=1e-15)
+
+
+def test_cubic_cell_self_field():
+    """One cubic cell with stray field: -m/3 cancels in Step 1 and rescales Step 2 only."""
+    m = np.array([0.48, -0.6, 0.64]).reshape(3, 1, 1, 1)
+    he = (0.05, -0.1, 0.2)
+    dt, alpha = 0.1, 0.3
+    Ps = scheme.Problem(n=(1, 1, 1), h=(1.0, 1.0, 1.0), eps=1.0, dt=dt, stray=True)
+    P0 = scheme.Problem(n=(1, 1, 1), h=(1.0, 1.0, 1.0), eps=1.0, dt=dt)
+    ts, t0 = {}, {}
+    ms = scheme.sgspm_step(Ps, m, alpha, he, tape=ts)
+    scheme.sgspm_step(P0, m, alpha, he, tape=t0)
+    for k in ("m1s", "m2s", "m3s", "m2ss", "m1ss"):
+        assert np.allclose(ts[k], t0[k], atol=1e-15)
+    b = np.stack([t0["m1ss"], t0["m2ss"], t0["m3s"]]).reshape(3)
+    c = (1 - alpha * dt / 3) * b + alpha * dt * np.array(he)
+    assert np.allclose(ms.reshape(3), c / np.linalg.norm(c), atol=1e-15)
+
+
+def _paper_ic(shape):
+    """Paper eq. (m0-1): (cos(cos(pi x)) sin 0.01, sin(cos(pi x)) sin 0.01, cos 0.01)."""
+    nz, ny, nx = shape
+    x = (np.arange(nx) + 0.5) / nx
+    c = np.broadcast_to(np.cos(np.pi * x), shape)
+    return np.stack([np.cos(c) * np.sin(0.01), np.sin(c) * np.sin(0.01), np.full(shape, np.cos(0.01))])
+
+
+@pytest.mark.parametrize("dim", [1, 3])
+def test_energy_decay_sgspm_vs_gspm(dim):
+    """§3.2 / §5.2: SGSPM exchange-only energy decays every step for alpha = 0 and alpha > 0;
+    GSPM with alpha = 0 does not (its energy rises)."""
+    shape = (1, 1, 64) if dim == 1 else (8, 8, 8)
+    nxyz = shape[::-1]
+    h = tuple(1.0 / k if k > 1 else 1.0 for k in nxyz)
+    P = scheme.Problem(n=nxyz, h=h, eps=1.0, dt=0.01)
+    for alpha in (0.0, 0.01, 0.1):
+        m = _paper_ic(shape)
+        E = [scheme.energies(P, m, (0, 0, 0))["total"]]
+        for _ in range(60):
+            m = scheme.sgspm_step(P, m, alpha, (0, 0, 0))
+            E.append(scheme.energies(P, m, (0, 0, 0))["total"])
+        assert np.all(np.diff(E) < 0), alpha
+    m = _paper_ic(shape)
+    E = [scheme.energies(P, m, (0, 0, 0))["total"]]
+    for _ in range(60):
+        m = scheme.gspm_step(P, m, 0.0, (0, 0, 0))
+        E.append(scheme.energies(P, m, (0, 0, 0))["total"])
+    assert np.max(np.diff(E)) > 0
+
+
+def test_energy_gradient_is_minus_effective_field():
+    """h_eff = -(1/V) dE/dm (§2), checked by central differences on a small film."""
+    shape = (2, 3, 4)
+    P = scheme.Problem(n=shape[::-1], h=(1.0, 0.8, 0.6), eps=0.7, dt=0.1, Q=0.3, stray=True)
+    rng = np.random.default_rng(9)
+    m = rng.normal(size=(3,) + shape)
+    he = (0.1, -0.05, 0.2)
+    heff = scheme.effective_field(P, m, he)
+    for _ in range(5):
+        idx = (rng.integers(3),) + tuple(rng.integers(s) for s in shape)
+        e = 1e-6
+        mp, mm = m.copy(), m.copy()
+        mp[idx] += e
+        mm[idx] -= e
+        dE = (scheme.energies(P, mp, he)["total"] - scheme.energies(P, mm, he)["total"]) / (2 * e)
+        assert -dE / P.volume == pytest.approx(heff[idx], rel=1e-6, abs=1e-8)
+
+
+def test_exchange_energy_summation_by_parts():
+    shape = (3, 4, 5)
+    h = (0.5, 0.6, 0.7)
+    P = scheme.Problem(n=shape[::-1], h=h, eps=0.9, dt=0.1)
+    m = _random_unit(shape, 10)
+    ref = -0.5 * P.eps * P.volume * float(np.sum(m * operators.laplacian_vec(m, h)))
+    assert scheme.energies(P, m, (0, 0, 0))["exchange"] == pytest.approx(ref, rel=1e-12)
+
+
+def test_stray_energy_matches_direct_sum():
+    shape = (1, 2, 3)
+    h = (1.0, 1.0, 0.5)
+    P = scheme.Problem(n=shape[::-1], h=h, eps=1.0, dt=0.1, stray=True)
+    m = _random_unit(shape, 11)
+    cells = [(i, j, k) for k in range(shape[0]) for j in range(shape[1]) for i in range(shape[2])]
+    pair = {(0, 0): "xx", (1, 1): "yy", (2, 2): "zz", (0, 1): "xy", (1, 0): "xy",
+            (0, 2): "xz", (2, 0): "xz", (1, 2): "yz", (2, 1): "yz"}
+    E = 0.0
+    for (i, j, k) in cells:
+        for (ii, jj, kk) in cells:
+            t = demag.tensor_at(i - ii, j - jj, k - kk, h)
+            for a in range(3):
+                for b in range(3):
+                    E += 0.5 * P.volume * m[a, k, j, i] * float(t[pair[(a, b)]]) * m[b, kk, jj, ii]
+    assert scheme.energies(P, m, (0, 0, 0))["stray"] == pytest.approx(E, rel=1e-12)
+
+
+def test_projection_rejects_zero_norm():
+    with pytest.raises(FloatingPointError):
+        scheme.project(np.zeros((3, 1, 1, 2)))
