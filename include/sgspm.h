@@ -1,0 +1,165 @@
+/*
+ * sgspm.h - C ABI of the MI355X (gfx950) library for one time step of the
+ * symmetric Gauss-Seidel projection method (SGSPM) for the Landau-Lifshitz
+ * equation, and of its adjoint.
+ *
+ * Method (Miao & Xie, "Improved Energy Stable Symmetric Gauss-Seidel Projection
+ * Method for Micromagnetics Simulations"):
+ *   model      §2, eq. (c1-large): m_t = -m x h - alpha m x (m x h), |m| = 1,
+ *              h = eps Lap m - Q (m2 e2 + m3 e3) + h_s + h_e, Neumann BC
+ *              (eq. boundary-large);
+ *   SGSPM      §3.2: Step 1 forward then backward Gauss-Seidel sweep with
+ *              g_i = (I - eps dt Lap_h)^{-1}(m_i + dt f_i); Step 2 heat flow
+ *              (I - alpha eps dt Lap_h) m*** = m** + alpha dt f**; Step 3
+ *              projection m^{n+1} = m*** / |m***|;
+ *   GSPM       §3.1: forward sweep only, then Steps 2 and 3.
+ *
+ * Discretisation (the paper states none; these readings are shared with the
+ * CPU oracle as a specification): cell-centred cells, 7-point Lap_h with
+ * mirror ghosts (exactly diagonalised by DCT-II/III), stray field
+ * h_s = -N (*) m with the Newell cell-averaged tensor (point-dipole form for
+ * offsets beyond 20 cells in max norm) by 2x zero-padded FFT.  The "f" of
+ * every Gauss-Seidel stage is evaluated at the latest component values.
+ *
+ * Layout of every field argument: device memory, contiguous [3][nz][ny][nx],
+ * x fastest, of the plan's precision (float for SGSPM_FP32, double for
+ * SGSPM_FP64).  The caller owns every pointer it passes; the library never
+ * frees caller memory.  All calls are asynchronous on the plan's HIP stream
+ * except sgspm_energy and sgspm_check, which synchronise it.
+ *
+ * Errors: every function returns 0 (SGSPM_OK) or a negative code;
+ * sgspm_last_error() returns a thread-local message for the last failure.
+ * Parameters are validated on the host before any HIP call.
+ */
+#ifndef SGSPM_H
+#define SGSPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SGSPM_OK = 0,
+  SGSPM_EINVAL = -1,       /* bad argument (null pointer, non-positive size, ...) */
+  SGSPM_EUNSUPPORTED = -2, /* valid but not implemented (e.g. non power-of-two axis) */
+  SGSPM_ENOMEM = -3,       /* device allocation failed */
+  SGSPM_EHIP = -4,         /* a HIP runtime call failed */
+  SGSPM_ENUMERIC = -5      /* a projection met |m***| = 0 or a non-finite value */
+};
+
+enum { SGSPM_TERM_EXCHANGE = 1, SGSPM_TERM_ANISO = 2, SGSPM_TERM_STRAY = 4, SGSPM_TERM_ZEEMAN = 8 };
+enum { SGSPM_UNITS_SI = 0, SGSPM_UNITS_REDUCED = 1 };
+enum { SGSPM_FP32 = 0, SGSPM_FP64 = 1 };
+enum { SGSPM_SCHEME_SGS = 0, SGSPM_SCHEME_GS = 1 };
+
+/* Problem statement (paper §2 and §3): grid, cell size, constants, time step. */
+typedef struct {
+  int32_t nx, ny, nz;   /* cells; each a power of two in [1, 1024]; with the stray field the
+                           last axis of extent > 1 among (ny, nz) is at most 512 (FP32) / 256 (FP64) */
+  double dx, dy, dz;    /* cell edges: metres (SI) or reduced lengths */
+  int32_t units;        /* SGSPM_UNITS_SI or SGSPM_UNITS_REDUCED */
+  double A, Ms, Ku;     /* SI only: exchange J/m, saturation A/m, uniaxial J/m^3 (easy axis x) */
+  double eps, Q;        /* REDUCED only: the paper's epsilon and Q */
+  double dt;            /* seconds (SI) or reduced time */
+  uint32_t terms;       /* bitmask of SGSPM_TERM_* */
+  int32_t precision;    /* SGSPM_FP32 or SGSPM_FP64 */
+  int32_t scheme;       /* SGSPM_SCHEME_SGS (default) or SGSPM_SCHEME_GS */
+} sgspm_params;
+
+typedef struct sgspm_plan_s* sgspm_plan_t;
+
+/* Host-only checks of a parameter set (no HIP call).  Returns 0 or
+ * SGSPM_EINVAL / SGSPM_EUNSUPPORTED with a message. */
+int sgspm_validate(const sgspm_params* p);
+
+/* The non-dimensional constants the plan will use: out[0] = eps (m^2 in SI,
+ * reduced otherwise), out[1] = Q, out[2] = dt (reduced time), out[3] = field
+ * scale (h_e = B * out[3] for B in tesla; 1 in reduced units), out[4] =
+ * energy scale (multiplies reduced energy x volume: mu0 Ms^2 in SI, else 1).
+ * Host only. */
+int sgspm_reduced_constants(const sgspm_params* p, double out[5]);
+
+/* Build a plan: validates, allocates the workspace (device), builds the
+ * FP64 twiddle / eigenvalue tables and, if SGSPM_TERM_STRAY, computes the
+ * Newell tensor and its spectrum on the GPU in FP64.  hip_stream is a
+ * hipStream_t (0 = default stream).  The plan owns its workspace. */
+int sgspm_plan(const sgspm_params* p, void* hip_stream, sgspm_plan_t* out);
+
+/* One SGSPM (or GSPM) step, in place: m^n -> m^{n+1} (paper §3.2 / §3.1).
+ *   m      device [3][nz][ny][nx], in/out
+ *   alpha  damping (>= 0), per call
+ *   h_e    applied field, host double[3]: tesla (SI, B = mu0 H) or reduced
+ *   src    optional device [3][nz][ny][nx] source s (reduced units, rate per
+ *          reduced time) added as dt * s_i to every Gauss-Seidel component
+ *          update of Step 1 (forcing of a manufactured solution, §5.1); or NULL.
+ * A zero or non-finite |m***| sets a device flag reported by sgspm_check. */
+int sgspm_step(sgspm_plan_t plan, void* m, double alpha, const double h_e[3], const void* src);
+
+/* Energies of m (paper §2, with the 1/2 factors that make h = -dE/dm):
+ * e_out = {total, exchange, anisotropy, stray, zeeman}, host double[5], in
+ * joules (SI) or reduced energy x volume.  FP64 accumulation with a fixed
+ * reduction tree (deterministic).  Synchronises the stream. */
+int sgspm_energy(sgspm_plan_t plan, const void* m, const double h_e[3], double e_out[5]);
+
+/* Effective field h_eff = eps Lap_h m - Q(m2 e2 + m3 e3) + h_s + h_e (paper §2)
+ * of m into h_out (device [3][nz][ny][nx], reduced units). */
+int sgspm_field(sgspm_plan_t plan, const void* m, const double h_e[3], void* h_out);
+
+/* Stray field h_s = -N (*) m alone into hs_out (device [3][nz][ny][nx]). */
+int sgspm_stray(sgspm_plan_t plan, const void* m, void* hs_out);
+
+/* Heat-type solve of §3 (Step 1 with s = 1, Step 2 with s = alpha):
+ * g = (I - s eps dt Lap_h)^{-1} r for one scalar field r (device [nz][ny][nx]);
+ * r and g may alias. */
+int sgspm_heat_solve(sgspm_plan_t plan, const void* r, double s, void* g);
+
+/* Adjoint of one step (the chain rule of the step above; the paper has none):
+ * given m_n (the state the step starts from) and lam = dL/dm^{n+1}, overwrite
+ * lam with dL/dm^n and ADD dL/dh_e^n (3 values, per unit of the h_e argument:
+ * per tesla in SI) and dL/dalpha into grad_dev, a DEVICE double[4] =
+ * {dh_e[0], dh_e[1], dh_e[2], dalpha}.  The step is recomputed internally from
+ * m_n.  Asynchronous.  Source terms carry no gradient and are not accepted. */
+int sgspm_adjoint_step(sgspm_plan_t plan, const void* m_n, double alpha, const double h_e[3],
+                       void* lam, double* grad_dev);
+
+/* Measurement support.  Kernel classes of the step's launches: */
+enum {
+  SGSPM_KC_ROW_FWD = 0, /* x rows: [c2r] -> right-hand side -> [DCT-II] / [r2c] */
+  SGSPM_KC_ROW_INV = 1, /* x rows: inverse DCT -> Gauss-Seidel update or projection -> [r2c] */
+  SGSPM_KC_COL_DCT = 2, /* y / z pencils: DCT passes and the fused diagonal solve */
+  SGSPM_KC_COL_FFT = 3, /* y pencils: padded FFT / cropped inverse FFT of spectra */
+  SGSPM_KC_CONV = 4,    /* last-axis FFT, demagnetising-tensor multiply, inverse FFT */
+  SGSPM_KC_OTHER = 5,
+  SGSPM_KC_COUNT = 6
+};
+
+/* Enable (1) or disable (0) timing of every later launch with HIP events on
+ * the plan's stream; clears what was recorded.  Timing adds two event records
+ * per launch. */
+int sgspm_timing(sgspm_plan_t plan, int enable);
+
+/* Synchronise and return, per kernel class since the last enable/read: total
+ * kernel milliseconds, total algorithmic bytes (each input array read once and
+ * each output written once per launch) and the number of launches (host
+ * arrays of SGSPM_KC_COUNT entries).  Clears the records. */
+int sgspm_timing_read(sgspm_plan_t plan, double ms[SGSPM_KC_COUNT], double bytes[SGSPM_KC_COUNT],
+                      int64_t launches[SGSPM_KC_COUNT]);
+
+/* Synchronise the stream and report (then clear) the projection flag:
+ * SGSPM_ENUMERIC if any projection since the last check met a zero or
+ * non-finite |m***|. */
+int sgspm_check(sgspm_plan_t plan);
+
+/* Free the plan's device memory (synchronises its stream first). */
+int sgspm_destroy(sgspm_plan_t plan);
+
+/* Thread-local message for the last failure on this thread ("" if none). */
+const char* sgspm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGSPM_H */

@@ -1,0 +1,183 @@
+"""ctypes binding of libsgspm.so: the C ABI of include/sgspm.h, same names, no logic."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(HERE, "libsgspm.so")
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ENUMERIC = 0, -1, -2, -3, -4, -5
+TERM_EXCHANGE, TERM_ANISO, TERM_STRAY, TERM_ZEEMAN = 1, 2, 4, 8
+TERM_ALL = 15
+UNITS_SI, UNITS_REDUCED = 0, 1
+FP32, FP64 = 0, 1
+SCHEME_SGS, SCHEME_GS = 0, 1
+
+EXPORTS = ("sgspm_validate", "sgspm_reduced_constants", "sgspm_plan", "sgspm_step", "sgspm_energy",
+           "sgspm_field", "sgspm_stray", "sgspm_heat_solve", "sgspm_adjoint_step", "sgspm_timing",
+           "sgspm_timing_read", "sgspm_check", "sgspm_destroy", "sgspm_last_error")
+KERNEL_CLASSES = ("row_fwd", "row_inv", "col_dct", "col_fft", "conv", "other")
+
+
+class SGSPMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sgspm error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("units", ctypes.c_int32),
+                ("A", ctypes.c_double), ("Ms", ctypes.c_double), ("Ku", ctypes.c_double),
+                ("eps", ctypes.c_double), ("Q", ctypes.c_double),
+                ("dt", ctypes.c_double),
+                ("terms", ctypes.c_uint32),
+                ("precision", ctypes.c_int32),
+                ("scheme", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(lib_path):
+        raise ImportError(f"{lib_path} is missing: build it with __graft_entry__.build() "
+                          "or python paper_2606_28113_amd/build.py (no CPU fallback exists)")
+    L = ctypes.CDLL(lib_path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    L.sgspm_validate.argtypes = [ctypes.POINTER(Params)]
+    L.sgspm_reduced_constants.argtypes = [ctypes.POINTER(Params), dp]
+    L.sgspm_plan.argtypes = [ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
+    L.sgspm_step.argtypes = [vp, vp, ctypes.c_double, dp, vp]
+    L.sgspm_energy.argtypes = [vp, vp, dp, dp]
+    L.sgspm_field.argtypes = [vp, vp, dp, vp]
+    L.sgspm_stray.argtypes = [vp, vp, vp]
+    L.sgspm_heat_solve.argtypes = [vp, vp, ctypes.c_double, vp]
+    L.sgspm_adjoint_step.argtypes = [vp, vp, ctypes.c_double, dp, vp, vp]
+    L.sgspm_timing.argtypes = [vp, ctypes.c_int]
+    L.sgspm_timing_read.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_int64)]
+    L.sgspm_check.argtypes = [vp]
+    L.sgspm_destroy.argtypes = [vp]
+    L.sgspm_last_error.argtypes = []
+    L.sgspm_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS[:-1]:
+        getattr(L, name).restype = ip
+    return L
+
+
+lib = _load()
+
+
+def _check(rc):
+    if rc != OK:
+        raise SGSPMError(rc, lib.sgspm_last_error().decode())
+
+
+def make_params(nx, ny, nz, dx, dy, dz, dt, units=UNITS_SI, A=0.0, Ms=1.0, Ku=0.0, eps=0.0, Q=0.0,
+                terms=TERM_ALL, precision=FP32, scheme=SCHEME_SGS):
+    return Params(nx, ny, nz, dx, dy, dz, units, A, Ms, Ku, eps, Q, dt, terms, precision, scheme)
+
+
+def validate(**kw):
+    p = make_params(**kw)
+    _check(lib.sgspm_validate(ctypes.byref(p)))
+
+
+def reduced_constants(**kw):
+    """(eps, Q, dt_reduced, field scale per tesla, energy scale) of a parameter set."""
+    p = make_params(**kw)
+    out = (ctypes.c_double * 5)()
+    _check(lib.sgspm_reduced_constants(ctypes.byref(p), out))
+    return tuple(out)
+
+
+def _d3(v):
+    return (ctypes.c_double * 3)(*[float(x) for x in v])
+
+
+class Plan:
+    """A plan on the current torch CUDA stream (fixed at creation).
+
+    Keyword arguments are the fields of sgspm_params (see make_params).
+    Field tensors: CUDA, contiguous, shape (3, nz, ny, nx), dtype float32 for
+    FP32 plans and float64 for FP64 plans.
+    """
+
+    def __init__(self, **kw):
+        import torch
+        self.kw = dict(kw)
+        self.params = make_params(**kw)
+        self.n = (self.params.nx, self.params.ny, self.params.nz)
+        self.dtype = torch.float64 if self.params.precision == FP64 else torch.float32
+        self.stream = torch.cuda.current_stream()
+        self._h = ctypes.c_void_p()
+        _check(lib.sgspm_plan(ctypes.byref(self.params), ctypes.c_void_p(self.stream.cuda_stream),
+                              ctypes.byref(self._h)))
+
+    @property
+    def shape(self):
+        nx, ny, nz = self.n
+        return (3, nz, ny, nx)
+
+    def _ptr(self, t, shape=None, name="tensor"):
+        if not t.is_cuda or not t.is_contiguous() or t.dtype != self.dtype:
+            raise ValueError(f"{name} must be a contiguous CUDA {self.dtype} tensor")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def step(self, m, alpha, h_e, src=None):
+        s = None if src is None else self._ptr(src, self.shape, "src")
+        _check(lib.sgspm_step(self._h, self._ptr(m, self.shape, "m"), float(alpha), _d3(h_e), s))
+
+    def energy(self, m, h_e):
+        out = (ctypes.c_double * 5)()
+        _check(lib.sgspm_energy(self._h, self._ptr(m, self.shape, "m"), _d3(h_e), out))
+        return dict(zip(("total", "exchange", "anisotropy", "stray", "zeeman"), list(out)))
+
+    def field(self, m, h_e, out=None):
+        import torch
+        out = torch.empty_like(m) if out is None else out
+        _check(lib.sgspm_field(self._h, self._ptr(m, self.shape, "m"), _d3(h_e), self._ptr(out, self.shape, "out")))
+        return out
+
+    def stray(self, m, out=None):
+        import torch
+        out = torch.empty_like(m) if out is None else out
+        _check(lib.sgspm_stray(self._h, self._ptr(m, self.shape, "m"), self._ptr(out, self.shape, "out")))
+        return out
+
+    def heat_solve(self, r, s, out=None):
+        import torch
+        out = torch.empty_like(r) if out is None else out
+        shp = self.shape[1:]
+        _check(lib.sgspm_heat_solve(self._h, self._ptr(r, shp, "r"), float(s), self._ptr(out, shp, "out")))
+        return out
+
+    def adjoint_step(self, m_n, alpha, h_e, lam, grad):
+        import torch
+        if not grad.is_cuda or grad.dtype != torch.float64 or grad.numel() != 4 or not grad.is_contiguous():
+            raise ValueError("grad must be a contiguous CUDA float64 tensor of 4 values")
+        _check(lib.sgspm_adjoint_step(self._h, self._ptr(m_n, self.shape, "m_n"), float(alpha), _d3(h_e),
+                                      self._ptr(lam, self.shape, "lam"), ctypes.c_void_p(grad.data_ptr())))
+
+    def timing(self, enable=True):
+        _check(lib.sgspm_timing(self._h, 1 if enable else 0))
+
+    def timing_read(self):
+        """{class: (ms, algorithmic bytes, launches)} since the last enable / read."""
+        n = len(KERNEL_CLASSES)
+        ms, by, cnt = (ctypes.c_double * n)(), (ctypes.c_double * n)(), (ctypes.c_int64 * n)()
+        _check(lib.sgspm_timing_read(self._h, ms, by, cnt))
+        return {k: (ms[i], by[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def check(self):
+        _check(lib.sgspm_check(self._h))
+
+    def close(self):
+        if self._h:
+            lib.sgspm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

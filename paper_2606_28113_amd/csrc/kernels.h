@@ -1,0 +1,143 @@
+// Argument blocks of the gfx950 kernels of the SGSPM step and their launchers.
+//
+// Array conventions (all device memory):
+//   real field       [nz][ny][nx], x fastest (row pitch nx)
+//   x-level spectrum [nz][ny][Kxp] complex: the zero-padded real-to-complex
+//                    transform along x of a field (Kx = Px/2 + 1 bins, pitch Kxp)
+//   y-level spectrum [nz][Py][Kxp] complex: the above, also transformed (padded)
+//                    along y
+//   heat array       [nz][ny][nx] real: a field after type-II cosine transforms
+//                    along some of its axes
+// A "channel" is one of up to three independent arrays handled by one launch
+// (grid.z); each argument block carries one pointer per channel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.h"
+
+namespace sgspm {
+
+// Row kernels (pencils along x; two real rows share one complex FFT).
+template <typename T> struct RowFwd {
+  int nrows;       // real rows per channel
+  int lgN;         // log2 of values per real row
+  int lgLmax;      // log2 of the longest FFT in the launch (sets the tile)
+  int lgP;         // log2 of complex pencils per tile (2P rows)
+  int lgTw;        // log2 length of the global twiddle table
+  const cx<T>* tw;
+  // row value v = a[ch] * u + b * (hs + he[ch]); u may be null (0)
+  const T* u[3];
+  T a[3];
+  T b;
+  T he[3];
+  // optional hs by complex-to-real transform (crop) of an x-level spectrum
+  const cx<T>* xin[3];
+  int lgLc;
+  int xin_pitch;
+  T* hs_out[3];     // optional store of hs
+  T* dct_out[3];    // optional type-II DCT of v along x
+  const cx<T>* dtw; // exp(-i pi k / (2n)), k < n
+  cx<T>* xout[3];   // optional zero-padded real-to-complex transform of v
+  int lgLr;
+  int xout_pitch;
+};
+
+enum { ROW_OP_NONE = 0, ROW_OP_GS = 1, ROW_OP_PROJECT = 2 };
+
+template <typename T> struct RowInv {
+  int nrows, lgN, lgLmax, lgP, lgTw;
+  const cx<T>* tw;
+  const cx<T>* dtw;
+  int nch;             // heat arrays to invert along x (1..3)
+  const T* heat[3];
+  T* gout[3];          // optional stores of the inverted arrays
+  int op;
+  // ROW_OP_GS: out = base + Pf * Qf - Rf * Sf + ds * src; Pch/Rch >= 0 select an
+  // inverted channel in place of Pf / Rf
+  const T* base;
+  const T* Pf;
+  const T* Qf;
+  const T* Rf;
+  const T* Sf;
+  int Pch, Rch;
+  const T* src;
+  T ds;
+  T* out;
+  // ROW_OP_PROJECT: mout = c / |c| over the three channels, nrm = |c|
+  T* mout[3];
+  T* nrm;
+  int* flag;
+  // optional zero-padded real-to-complex transform of `out`
+  cx<T>* xout;
+  int lgLr;
+  int xout_pitch;
+};
+
+// Column kernels (pencils along a strided axis; tiles of consecutive inner indices).
+enum { COL_DCT_FWD = 0, COL_DCT_INV = 1, COL_DCT_SOLVE = 2 };
+
+template <typename T> struct ColDct {
+  int mode;
+  int lgN;           // pencil length
+  int lgP;           // complex pencils per tile (2P real pencils)
+  int ni;            // inner extent
+  long sa, sb;       // element strides along the axis and along the batch (grid.y)
+  T* data[3];        // in place
+  const cx<T>* dtw;
+  const cx<T>* tw;
+  int lgTw;
+  // COL_DCT_SOLVE diagonal 1 / (1 + s (lamX[i] + lamB[batch] + lamA[k]))
+  const T* lamX;
+  const T* lamB;
+  const T* lamA;
+  T s;
+};
+
+template <typename T> struct ColFft {
+  int lgL, n_in, n_out, lgP, ni;
+  long sa_in, sb_in, sa_out, sb_out;
+  const cx<T>* in[3];
+  cx<T>* out[3];
+  int inv;
+  const cx<T>* tw;
+  int lgTw;
+};
+
+// Last-axis convolution: FFT of the three component spectra, multiply by the
+// six-component symmetric tensor spectrum, inverse FFT of the requested outputs.
+template <typename T> struct Conv {
+  int lgL, n, lgP, ni;
+  long sa, sb;
+  const cx<T>* S[3];
+  cx<T>* O[3];       // null = output not requested
+  const T* tens;     // [6][Hc][Hb][ni]
+  long tcs;
+  int Hb, Pb;        // folded / full length of the batch axis
+  int oddc, oddb;    // bitmask of components odd along the pencil / batch axis
+  const cx<T>* tw;
+  int lgTw;
+};
+
+template <typename T> void launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_t s);
+template <typename T> void launch_row_inv(const RowInv<T>& a, hipStream_t s);
+template <typename T> void launch_col_dct(const ColDct<T>& a, int nbatch, int nch, hipStream_t s);
+template <typename T> void launch_col_fft(const ColFft<T>& a, int nbatch, int nch, hipStream_t s);
+template <typename T> void launch_conv(const Conv<T>& a, int nbatch, hipStream_t s);
+
+// Demagnetising tensor (FP64): fill the padded real array of one component.
+void launch_newell_fill(double* out, int comp, int nx, int ny, int nz, int Px, int Py, int Pz, double hx, double hy,
+                        double hz, int rfar, hipStream_t s);
+// Real part of the FP64 spectrum on the folded octant, times scale, as T.
+template <typename T>
+void launch_tensor_pack(const cx<double>* spec, T* out, int Hz, int Hy, int Kx, int Kxp, int Py, double scale,
+                        hipStream_t s);
+
+// Pointwise and reduction kernels.
+template <typename T>
+void launch_field_assemble(const T* m, const T* hs, T* out, int nx, int ny, int nz, double cxx, double cyy, double czz,
+                           double eps_on, double Q, const double he[3], hipStream_t s);
+template <typename T>
+void launch_energy(const T* m, const T* hs, int nx, int ny, int nz, double cxx, double cyy, double czz,
+                   const double he[3], double* partials, int nblocks, double* out, hipStream_t s);
+
+}  // namespace sgspm

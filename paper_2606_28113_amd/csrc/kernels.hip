@@ -1,0 +1,789 @@
+// gfx950 kernels of one SGSPM step: x-row transforms with fused pointwise
+// prologues/epilogues, strided column transforms, the last-axis fused
+// DCT-diagonal-IDCT heat solve, the last-axis fused FFT-tensor-IFFT stray-field
+// convolution, the FP64 Newell tensor, and FP64 reductions.
+//
+// Heat-type solve (paper §3, g = (I - c Lap_h)^{-1} r with Neumann BC): the
+// mirror-ghost Lap_h is diagonal in the type-II DCT basis; each 1-D DCT-II of
+// length n is computed by Makhoul's method, a length-n complex FFT of the
+// even/odd-reordered sequence followed by a twiddle, with two real pencils
+// packed into one complex FFT.  Stray field (h_s = -N (*) m): zero-padded
+// real-to-complex FFT along x, complex FFTs along y and z, multiplication by the
+// precomputed real tensor spectrum, inverse transforms cropped to the grid.
+#include <cmath>
+
+#include "kernels.h"
+
+namespace sgspm {
+
+template <typename T> __device__ __forceinline__ cx<T> zero() { return mk<T>((T)0, (T)0); }
+
+// ---------------------------------------------------------------------------
+// Shared row-kernel helpers (tile: P complex pencils = 2P real rows).
+
+// Zero-padded real-to-complex transform of the per-thread row values `val`
+// (element e = tid + i NT of the tile) and store of bins 0..Lr/2.
+template <typename T, int NV>
+__device__ __forceinline__ void row_r2c_store(cx<T>* buf, const cx<T>* tw, const T (&val)[NV], int tot, int lgN, int lgLr,
+                                              int lgLmax, int lgP, int row0, int nrows, cx<T>* xout, int pitch) {
+  const int n = 1 << lgN;
+  const int Lr = 1 << lgLr;
+  const int P = 1 << lgP;
+  T* bufr = reinterpret_cast<T*>(buf);
+  for (int t = threadIdx.x; t < (P << lgLr); t += NT) {
+    if ((t & (Lr - 1)) >= n) buf[t] = zero<T>();
+  }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < tot) {
+      const int row = e >> lgN, x = e & (n - 1);
+      bufr[2 * (((row >> 1) << lgLr) + x) + (row & 1)] = val[i];
+    }
+  }
+  __syncthreads();
+  FftGeom g{lgLr, lgP, 1, false, Lr, 1, lgLmax - lgLr};
+  fft_lds(buf, tw, g, false);
+  const int half = Lr >> 1;
+  for (int t = threadIdx.x; t < (P << lgLr); t += NT) {
+    const int k = t & (Lr - 1);
+    if (k > half) continue;
+    const int q = t >> lgLr;
+    const cx<T> Zk = buf[(q << lgLr) + k];
+    const cx<T> Zm = buf[(q << lgLr) + ((Lr - k) & (Lr - 1))];
+    // X_a = (Z_k + conj Z_{-k}) / 2 ; X_b = (Z_k - conj Z_{-k}) / (2i)
+    const cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+    const cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+    const int ra = row0 + 2 * q;
+    if (ra < nrows) xout[(long)ra * pitch + k] = Xa;
+    if (ra + 1 < nrows) xout[(long)(ra + 1) * pitch + k] = Xb;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Row forward kernel: [c2r of x-level hs] -> v = a u + b (hs + he) ->
+// [DCT-II along x] and/or [zero-padded r2c along x].
+template <typename T>
+__global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int NV = 2 * Tile<T>::VPT;
+  const int ch = blockIdx.z;
+  const int Lmax = 1 << A.lgLmax;
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + Lmax;
+  load_twiddles(tw, A.tw, A.lgLmax, A.lgTw);
+  const int P = 1 << A.lgP;
+  const int row0 = blockIdx.x * 2 * P;
+  const int n = 1 << A.lgN;
+  const int tot = (2 * P) << A.lgN;
+  T hs[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) hs[i] = (T)0;
+  __syncthreads();
+
+  const cx<T>* xin = A.xin[ch];
+  if (xin) {
+    const int Lc = 1 << A.lgLc;
+    const int half = Lc >> 1;
+    for (int t = threadIdx.x; t < (P << A.lgLc); t += NT) {
+      const int q = t >> A.lgLc, k = t & (Lc - 1);
+      const int ra = row0 + 2 * q;
+      const bool cj = k > half;
+      const int kk = cj ? Lc - k : k;
+      cx<T> Xa = zero<T>(), Xb = zero<T>();
+      if (ra < A.nrows) Xa = xin[(long)ra * A.xin_pitch + kk];
+      if (ra + 1 < A.nrows) Xb = xin[(long)(ra + 1) * A.xin_pitch + kk];
+      if (kk == 0 || kk == half) {
+        Xa.y = (T)0;
+        Xb.y = (T)0;
+      }
+      if (cj) {
+        Xa.y = -Xa.y;
+        Xb.y = -Xb.y;
+      }
+      buf[(q << A.lgLc) + k] = mk<T>(Xa.x - Xb.y, Xa.y + Xb.x);
+    }
+    __syncthreads();
+    FftGeom g{A.lgLc, A.lgP, 1, false, Lc, 1, A.lgLmax - A.lgLc};
+    fft_lds(buf, tw, g, true);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e = threadIdx.x + i * NT;
+      if (e < tot) {
+        const int row = e >> A.lgN, x = e & (n - 1);
+        const cx<T> z = buf[((row >> 1) << A.lgLc) + x];
+        hs[i] = (row & 1) ? z.y : z.x;
+      }
+    }
+    __syncthreads();
+  }
+
+  T val[NV];
+  const T* u = A.u[ch];
+  T* hso = A.hs_out[ch];
+  const T ac = A.a[ch], hec = A.he[ch], bc = A.b;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int e = threadIdx.x + i * NT;
+    val[i] = (T)0;
+    if (e < tot) {
+      const int row = e >> A.lgN, x = e & (n - 1);
+      const int grow = row0 + row;
+      if (grow < A.nrows) {
+        const long idx = ((long)grow << A.lgN) + x;
+        const T uu = u ? u[idx] : (T)0;
+        if (hso) hso[idx] = hs[i];
+        val[i] = ac * uu + bc * (hs[i] + hec);
+      }
+    }
+  }
+
+  T* dout = A.dct_out[ch];
+  if (dout) {
+    T* bufr = reinterpret_cast<T*>(buf);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e = threadIdx.x + i * NT;
+      if (e < tot) {
+        const int row = e >> A.lgN, x = e & (n - 1);
+        bufr[2 * (((row >> 1) << A.lgN) + makhoul_pos(x, n)) + (row & 1)] = val[i];
+      }
+    }
+    __syncthreads();
+    FftGeom g{A.lgN, A.lgP, 1, false, n, 1, A.lgLmax - A.lgN};
+    fft_lds(buf, tw, g, false);
+    for (int t = threadIdx.x; t < (P << A.lgN); t += NT) {
+      const int q = t >> A.lgN, k = t & (n - 1);
+      const cx<T> Zk = buf[(q << A.lgN) + k];
+      const cx<T> Zm = buf[(q << A.lgN) + ((n - k) & (n - 1))];
+      const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+      const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+      const cx<T> w = A.dtw[k];
+      const int ra = row0 + 2 * q;
+      if (ra < A.nrows) dout[((long)ra << A.lgN) + k] = w.x * Va.x - w.y * Va.y;
+      if (ra + 1 < A.nrows) dout[((long)(ra + 1) << A.lgN) + k] = w.x * Vb.x - w.y * Vb.y;
+    }
+    __syncthreads();
+  }
+
+  cx<T>* xo = A.xout[ch];
+  if (xo) row_r2c_store<T, NV>(buf, tw, val, tot, A.lgN, A.lgLr, A.lgLmax, A.lgP, row0, A.nrows, xo, A.xout_pitch);
+}
+
+// ---------------------------------------------------------------------------
+// Row inverse kernel: inverse DCT-II along x of 1..3 heat arrays, then a
+// Gauss-Seidel update or the projection, then optionally the zero-padded r2c
+// transform of the updated component.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int NV = 2 * Tile<T>::VPT;
+  const int Lmax = 1 << A.lgLmax;
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + Lmax;
+  load_twiddles(tw, A.tw, A.lgLmax, A.lgTw);
+  const int P = 1 << A.lgP;
+  const int row0 = blockIdx.x * 2 * P;
+  const int n = 1 << A.lgN;
+  const int tot = (2 * P) << A.lgN;
+  const T invn = (T)1 / (T)n;
+  T g[3][NV];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) g[c][i] = (T)0;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c < A.nch) {
+      __syncthreads();
+      const T* H = A.heat[c];
+      for (int t = threadIdx.x; t < (P << A.lgN); t += NT) {
+        const int q = t >> A.lgN, k = t & (n - 1);
+        const int ra = row0 + 2 * q;
+        T xak = 0, xam = 0, xbk = 0, xbm = 0;
+        if (ra < A.nrows) {
+          xak = H[((long)ra << A.lgN) + k];
+          if (k) xam = H[((long)ra << A.lgN) + n - k];
+        }
+        if (ra + 1 < A.nrows) {
+          xbk = H[((long)(ra + 1) << A.lgN) + k];
+          if (k) xbm = H[((long)(ra + 1) << A.lgN) + n - k];
+        }
+        const cx<T> w = conjg(A.dtw[k]);
+        const cx<T> Va = cmul(w, mk<T>(xak, -xam));
+        const cx<T> Vb = cmul(w, mk<T>(xbk, -xbm));
+        buf[t] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
+      }
+      __syncthreads();
+      FftGeom gm{A.lgN, A.lgP, 1, false, n, 1, A.lgLmax - A.lgN};
+      fft_lds(buf, tw, gm, true);
+      T* go = A.gout[c];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (e < tot) {
+          const int row = e >> A.lgN, x = e & (n - 1);
+          const cx<T> z = buf[((row >> 1) << A.lgN) + makhoul_pos(x, n)];
+          g[c][i] = ((row & 1) ? z.y : z.x) * invn;
+          if (go && row0 + row < A.nrows) go[((long)(row0 + row) << A.lgN) + x] = g[c][i];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  if (A.op == ROW_OP_GS) {
+    T val[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e = threadIdx.x + i * NT;
+      val[i] = (T)0;
+      if (e < tot) {
+        const int row = e >> A.lgN, x = e & (n - 1);
+        if (row0 + row < A.nrows) {
+          const long idx = ((long)(row0 + row) << A.lgN) + x;
+          const T pv = A.Pch == 0 ? g[0][i] : (A.Pch == 1 ? g[1][i] : A.Pf[idx]);
+          const T rv = A.Rch == 0 ? g[0][i] : (A.Rch == 1 ? g[1][i] : A.Rf[idx]);
+          T o = A.base[idx] + pv * A.Qf[idx] - rv * A.Sf[idx];
+          if (A.src) o += A.ds * A.src[idx];
+          A.out[idx] = o;
+          val[i] = o;
+        }
+      }
+    }
+    if (A.xout)
+      row_r2c_store<T, NV>(buf, tw, val, tot, A.lgN, A.lgLr, A.lgLmax, A.lgP, row0, A.nrows, A.xout, A.xout_pitch);
+  } else if (A.op == ROW_OP_PROJECT) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e = threadIdx.x + i * NT;
+      if (e < tot) {
+        const int row = e >> A.lgN, x = e & (n - 1);
+        if (row0 + row < A.nrows) {
+          const long idx = ((long)(row0 + row) << A.lgN) + x;
+          const T c0 = g[0][i], c1 = g[1][i], c2 = g[2][i];
+          const T nr = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+          if (!(nr > (T)0) || !isfinite(nr)) A.flag[0] = 1;
+          const T inr = (T)1 / nr;
+          A.mout[0][idx] = c0 * inr;
+          A.mout[1][idx] = c1 * inr;
+          A.mout[2][idx] = c2 * inr;
+          if (A.nrm) A.nrm[idx] = nr;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column DCT kernel (in place): forward DCT-II, inverse, or the full heat solve
+// along the pencil axis (forward, diagonal, inverse).  Real pencils
+// i0 + q and i0 + q + P share complex pencil q; LDS layout buf[j * P + q].
+template <typename T>
+__global__ __launch_bounds__(NT) void k_col_dct(const ColDct<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int VPT = Tile<T>::VPT;
+  const int n = 1 << A.lgN;
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + n;
+  load_twiddles(tw, A.tw, A.lgN, A.lgTw);
+  const int P = 1 << A.lgP;
+  const int i0 = blockIdx.x * 2 * P;
+  const int b = blockIdx.y;
+  T* D = A.data[blockIdx.z] + (long)b * A.sb;
+  T* bufr = reinterpret_cast<T*>(buf);
+  const T invn = (T)1 / (T)n;
+  __syncthreads();
+
+  if (A.mode == COL_DCT_FWD || A.mode == COL_DCT_SOLVE) {
+    for (int t = threadIdx.x; t < ((2 * P) << A.lgN); t += NT) {
+      const int j = t >> (A.lgP + 1), ii = t & (2 * P - 1);
+      const int i = i0 + ii;
+      const T v = (i < A.ni) ? D[(long)j * A.sa + i] : (T)0;
+      bufr[2 * (makhoul_pos(j, n) * P + (ii & (P - 1))) + (ii >> A.lgP)] = v;
+    }
+    __syncthreads();
+    FftGeom g{A.lgN, A.lgP, 1, true, 1, P, 0};
+    fft_lds(buf, tw, g, false);
+    T xa[VPT], xb[VPT];
+#pragma unroll
+    for (int s = 0; s < VPT; ++s) {
+      const int t = threadIdx.x + s * NT;
+      xa[s] = xb[s] = (T)0;
+      if (t < (P << A.lgN)) {
+        const int k = t >> A.lgP, q = t & (P - 1);
+        const cx<T> Zk = buf[k * P + q];
+        const cx<T> Zm = buf[((n - k) & (n - 1)) * P + q];
+        const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+        const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+        const cx<T> w = A.dtw[k];
+        xa[s] = w.x * Va.x - w.y * Va.y;
+        xb[s] = w.x * Vb.x - w.y * Vb.y;
+        const int ia = i0 + q, ib = i0 + q + P;
+        if (A.mode == COL_DCT_FWD) {
+          if (ia < A.ni) D[(long)k * A.sa + ia] = xa[s];
+          if (ib < A.ni) D[(long)k * A.sa + ib] = xb[s];
+        } else {
+          const T lb = (A.lamB ? A.lamB[b] : (T)0) + A.lamA[k];
+          if (ia < A.ni) xa[s] *= (T)1 / ((T)1 + A.s * (A.lamX[ia] + lb));
+          if (ib < A.ni) xb[s] *= (T)1 / ((T)1 + A.s * (A.lamX[ib] + lb));
+        }
+      }
+    }
+    if (A.mode == COL_DCT_FWD) return;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < VPT; ++s) {
+      const int t = threadIdx.x + s * NT;
+      if (t < (P << A.lgN)) buf[t] = mk<T>(xa[s], xb[s]);
+    }
+    __syncthreads();
+  }
+
+  // inverse: V_k = exp(+i pi k / 2n) (X_k - i X_{n-k}); x = IFFT(V) / n, un-reordered
+  {
+    cx<T> z[VPT];
+#pragma unroll
+    for (int s = 0; s < VPT; ++s) {
+      const int t = threadIdx.x + s * NT;
+      z[s] = zero<T>();
+      if (t < (P << A.lgN)) {
+        const int k = t >> A.lgP, q = t & (P - 1);
+        T xak, xam = 0, xbk, xbm = 0;
+        if (A.mode == COL_DCT_INV) {
+          const int ia = i0 + q, ib = i0 + q + P;
+          xak = (ia < A.ni) ? D[(long)k * A.sa + ia] : (T)0;
+          xbk = (ib < A.ni) ? D[(long)k * A.sa + ib] : (T)0;
+          if (k) {
+            xam = (ia < A.ni) ? D[(long)(n - k) * A.sa + ia] : (T)0;
+            xbm = (ib < A.ni) ? D[(long)(n - k) * A.sa + ib] : (T)0;
+          }
+        } else {
+          const cx<T> Xk = buf[k * P + q];
+          xak = Xk.x;
+          xbk = Xk.y;
+          if (k) {
+            const cx<T> Xm = buf[(n - k) * P + q];
+            xam = Xm.x;
+            xbm = Xm.y;
+          }
+        }
+        const cx<T> w = conjg(A.dtw[k]);
+        const cx<T> Va = cmul(w, mk<T>(xak, -xam));
+        const cx<T> Vb = cmul(w, mk<T>(xbk, -xbm));
+        z[s] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < VPT; ++s) {
+      const int t = threadIdx.x + s * NT;
+      if (t < (P << A.lgN)) buf[t] = z[s];
+    }
+    __syncthreads();
+    FftGeom g{A.lgN, A.lgP, 1, true, 1, P, 0};
+    fft_lds(buf, tw, g, true);
+    for (int t = threadIdx.x; t < ((2 * P) << A.lgN); t += NT) {
+      const int j = t >> (A.lgP + 1), ii = t & (2 * P - 1);
+      const int i = i0 + ii;
+      if (i < A.ni) D[(long)j * A.sa + i] = bufr[2 * (makhoul_pos(j, n) * P + (ii & (P - 1))) + (ii >> A.lgP)] * invn;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column complex FFT (forward with zero padding n_in -> L, or inverse with
+// crop L -> n_out).  In place allowed (in == out, same strides).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_col_fft(const ColFft<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = 1 << A.lgL;
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + L;
+  load_twiddles(tw, A.tw, A.lgL, A.lgTw);
+  const int P = 1 << A.lgP;
+  const int i0 = blockIdx.x * P;
+  const int b = blockIdx.y;
+  const cx<T>* in = A.in[blockIdx.z] + (long)b * A.sb_in;
+  cx<T>* out = A.out[blockIdx.z] + (long)b * A.sb_out;
+  for (int t = threadIdx.x; t < (P << A.lgL); t += NT) {
+    const int j = t >> A.lgP, q = t & (P - 1);
+    const int i = i0 + q;
+    buf[t] = (j < A.n_in && i < A.ni) ? in[(long)j * A.sa_in + i] : zero<T>();
+  }
+  __syncthreads();
+  FftGeom g{A.lgL, A.lgP, 1, true, 1, P, 0};
+  fft_lds(buf, tw, g, A.inv != 0);
+  for (int t = threadIdx.x; t < P * A.n_out; t += NT) {
+    const int j = t >> A.lgP, q = t & (P - 1);
+    const int i = i0 + q;
+    if (i < A.ni) out[(long)j * A.sa_out + i] = buf[t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Last-axis stray-field convolution.  LDS layout buf[j * 3P + c * P + q].
+__device__ __forceinline__ int comp_index(int a, int b) {
+  // xx yy zz xy xz yz
+  if (a == b) return a;
+  const int s = a + b;  // 1: xy, 2: xz, 3: yz
+  return 2 + s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_conv(const Conv<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int L = 1 << A.lgL;
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + L;
+  load_twiddles(tw, A.tw, A.lgL, A.lgTw);
+  const int P = 1 << A.lgP;
+  const int es = 3 * P;
+  const int i0 = blockIdx.x * P;
+  const int b = blockIdx.y;
+  const long boff = (long)b * A.sb;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<T>* S = A.S[c] + boff;
+    for (int t = threadIdx.x; t < (P << A.lgL); t += NT) {
+      const int j = t >> A.lgP, q = t & (P - 1);
+      const int i = i0 + q;
+      buf[j * es + c * P + q] = (j < A.n && i < A.ni) ? S[(long)j * A.sa + i] : zero<T>();
+    }
+  }
+  __syncthreads();
+  {
+    FftGeom g{A.lgL, A.lgP, 3, true, 1, es, 0};
+    fft_lds(buf, tw, g, false);
+  }
+  const int bh = A.Pb >> 1;
+  const bool bneg = b > bh;
+  const int bf = bneg ? A.Pb - b : b;
+  const int ch = L >> 1;
+  for (int t = threadIdx.x; t < (P << A.lgL); t += NT) {
+    const int j = t >> A.lgP, q = t & (P - 1);
+    const int kx = i0 + q;
+    if (kx >= A.ni) continue;
+    const bool cneg = j > ch;
+    const int kf = cneg ? L - j : j;
+    const long base = ((long)kf * A.Hb + bf) * A.ni + kx;
+    const cx<T> s0 = buf[j * es + q], s1 = buf[j * es + P + q], s2 = buf[j * es + 2 * P + q];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (!A.O[a]) continue;
+      T tv[3];
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb) {
+        const int c = comp_index(a, bb);
+        T v = A.tens[(long)c * A.tcs + base];
+        if (cneg && ((A.oddc >> c) & 1)) v = -v;
+        if (bneg && ((A.oddb >> c) & 1)) v = -v;
+        tv[bb] = v;
+      }
+      buf[j * es + a * P + q] =
+          mk<T>(tv[0] * s0.x + tv[1] * s1.x + tv[2] * s2.x, tv[0] * s0.y + tv[1] * s1.y + tv[2] * s2.y);
+    }
+  }
+  __syncthreads();
+  const bool all3 = A.O[0] && A.O[1] && A.O[2];
+  if (all3) {
+    FftGeom g{A.lgL, A.lgP, 3, true, 1, es, 0};
+    fft_lds(buf, tw, g, true);
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (A.O[a]) {
+        FftGeom g{A.lgL, A.lgP, 1, true, 1, es, 0};
+        fft_lds(buf + a * P, tw, g, true);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cx<T>* O = A.O[a];
+    if (!O) continue;
+    O += boff;
+    for (int t = threadIdx.x; t < P * A.n; t += NT) {
+      const int j = t >> A.lgP, q = t & (P - 1);
+      const int i = i0 + q;
+      if (i < A.ni) O[(long)j * A.sa + i] = buf[j * es + a * P + q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Newell cell-averaged demagnetising tensor (FP64), point-dipole beyond rfar.
+__device__ __forceinline__ double asinh_ratio(double a, double b) { return b != 0.0 ? asinh(a / b) : 0.0; }
+__device__ __forceinline__ double atan_ratio(double a, double b) { return b != 0.0 ? atan(a / b) : 0.0; }
+
+__device__ double newell_f(double x, double y, double z) {
+  const double x2 = x * x, y2 = y * y, z2 = z * z;
+  const double R = sqrt(x2 + y2 + z2);
+  double t = (2.0 * x2 - y2 - z2) * R / 6.0;
+  t += 0.5 * y * (z2 - x2) * asinh_ratio(y, sqrt(x2 + z2));
+  t += 0.5 * z * (y2 - x2) * asinh_ratio(z, sqrt(x2 + y2));
+  t -= x * y * z * atan_ratio(y * z, x * R);
+  return t;
+}
+
+__device__ double newell_g(double x, double y, double z) {
+  const double x2 = x * x, y2 = y * y, z2 = z * z;
+  const double R = sqrt(x2 + y2 + z2);
+  double t = -x * y * R / 3.0;
+  t += x * y * z * asinh_ratio(z, sqrt(x2 + y2));
+  t += y / 6.0 * (3.0 * z2 - y2) * asinh_ratio(x, sqrt(y2 + z2));
+  t += x / 6.0 * (3.0 * z2 - x2) * asinh_ratio(y, sqrt(x2 + z2));
+  t -= z2 * z / 6.0 * atan_ratio(x * y, z * R);
+  t -= z * y2 / 2.0 * atan_ratio(x * z, y * R);
+  t -= z * x2 / 2.0 * atan_ratio(y * z, x * R);
+  return t;
+}
+
+template <int G>
+__device__ double newell_sum(double X, double Y, double Z, double a, double b, double c) {
+  const double w[3] = {-1.0, 2.0, -1.0};
+  double acc = 0.0;
+  for (int i = -1; i <= 1; ++i)
+    for (int j = -1; j <= 1; ++j)
+      for (int k = -1; k <= 1; ++k) {
+        const double f = G ? newell_g(X + i * a, Y + j * b, Z + k * c) : newell_f(X + i * a, Y + j * b, Z + k * c);
+        acc += w[i + 1] * w[j + 1] * w[k + 1] * f;
+      }
+  return acc / (4.0 * M_PI * a * b * c);
+}
+
+__global__ void k_newell_fill(double* out, int comp, int nx, int ny, int nz, int Px, int Py, int Pz, double hx,
+                              double hy, double hz, int rfar) {
+  const long total = (long)Px * Py * Pz;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const int kx = (int)(t % Px);
+    const int ky = (int)((t / Px) % Py);
+    const int kz = (int)(t / ((long)Px * Py));
+    const int ix = kx < nx ? kx : kx - Px;
+    const int iy = ky < ny ? ky : ky - Py;
+    const int iz = kz < nz ? kz : kz - Pz;
+    double v = 0.0;
+    if (abs(ix) <= nx - 1 && abs(iy) <= ny - 1 && abs(iz) <= nz - 1) {
+      const double X = ix * hx, Y = iy * hy, Z = iz * hz;
+      const int mx = max(abs(ix), max(abs(iy), abs(iz)));
+      if (mx > rfar) {
+        const double r2 = X * X + Y * Y + Z * Z;
+        const double s = hx * hy * hz / (4.0 * M_PI) / (r2 * r2 * sqrt(r2));
+        switch (comp) {
+          case 0: v = s * (r2 - 3.0 * X * X); break;
+          case 1: v = s * (r2 - 3.0 * Y * Y); break;
+          case 2: v = s * (r2 - 3.0 * Z * Z); break;
+          case 3: v = s * (-3.0 * X * Y); break;
+          case 4: v = s * (-3.0 * X * Z); break;
+          default: v = s * (-3.0 * Y * Z); break;
+        }
+      } else {
+        switch (comp) {
+          case 0: v = newell_sum<0>(X, Y, Z, hx, hy, hz); break;
+          case 1: v = newell_sum<0>(Y, X, Z, hy, hx, hz); break;
+          case 2: v = newell_sum<0>(Z, Y, X, hz, hy, hx); break;
+          case 3: v = newell_sum<1>(X, Y, Z, hx, hy, hz); break;
+          case 4: v = newell_sum<1>(X, Z, Y, hx, hz, hy); break;
+          default: v = newell_sum<1>(Y, Z, X, hy, hz, hx); break;
+        }
+      }
+    }
+    out[t] = v;
+  }
+}
+
+template <typename T>
+__global__ void k_tensor_pack(const cx<double>* spec, T* out, int Hz, int Hy, int Kx, int Kxp, int Py, double scale) {
+  const long total = (long)Hz * Hy * Kx;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const int kx = (int)(t % Kx);
+    const int ky = (int)((t / Kx) % Hy);
+    const int kz = (int)(t / ((long)Kx * Hy));
+    out[t] = (T)(spec[((long)kz * Py + ky) * Kxp + kx].x * scale);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise: effective field h = eps Lap_h m - Q (m2 e2 + m3 e3) + hs + he.
+template <typename T>
+__global__ void k_field_assemble(const T* m, const T* hs, T* out, int nx, int ny, int nz, double cxx, double cyy,
+                                 double czz, double eps_on, double Q, double he0, double he1, double he2) {
+  const long N = (long)nx * ny * nz;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < N; idx += (long)gridDim.x * blockDim.x) {
+    const int x = (int)(idx % nx);
+    const int y = (int)((idx / nx) % ny);
+    const int z = (int)(idx / ((long)nx * ny));
+    const double he[3] = {he0, he1, he2};
+    for (int c = 0; c < 3; ++c) {
+      const T* mc = m + c * N;
+      const double v = mc[idx];
+      double lap = 0.0;
+      if (nx > 1) lap += cxx * ((double)mc[x > 0 ? idx - 1 : idx] + (double)mc[x < nx - 1 ? idx + 1 : idx] - 2.0 * v);
+      if (ny > 1) lap += cyy * ((double)mc[y > 0 ? idx - nx : idx] + (double)mc[y < ny - 1 ? idx + nx : idx] - 2.0 * v);
+      if (nz > 1)
+        lap += czz * ((double)mc[z > 0 ? idx - (long)nx * ny : idx] + (double)mc[z < nz - 1 ? idx + (long)nx * ny : idx] -
+                      2.0 * v);
+      double h = eps_on * lap + he[c];
+      if (c > 0) h -= Q * v;
+      if (hs) h += (double)hs[c * N + idx];
+      out[c * N + idx] = (T)h;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Energies: per-cell FP64 densities, fixed-order block partials, fixed final sum.
+// acc[0] = sum over faces |dm|^2 / h^2 (times per-axis weights cxx, cyy, czz)
+// acc[1] = sum m2^2 + m3^2, acc[2] = sum m . hs, acc[3] = sum m . he
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_energy(const T* m, const T* hs, int nx, int ny, int nz, double cxx, double cyy,
+                                               double czz, double he0, double he1, double he2, double* partials) {
+  const long N = (long)nx * ny * nz;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long idx = blockIdx.x * (long)NT + threadIdx.x; idx < N; idx += (long)gridDim.x * NT) {
+    const int x = (int)(idx % nx);
+    const int y = (int)((idx / nx) % ny);
+    const int z = (int)(idx / ((long)nx * ny));
+    const double m0 = m[idx], m1 = m[N + idx], m2 = m[2 * N + idx];
+    double ex = 0.0;
+    if (x < nx - 1) {
+      const double d0 = m[idx + 1] - m0, d1 = m[N + idx + 1] - m1, d2 = m[2 * N + idx + 1] - m2;
+      ex += cxx * (d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    if (y < ny - 1) {
+      const long o = idx + nx;
+      const double d0 = m[o] - m0, d1 = m[N + o] - m1, d2 = m[2 * N + o] - m2;
+      ex += cyy * (d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    if (z < nz - 1) {
+      const long o = idx + (long)nx * ny;
+      const double d0 = m[o] - m0, d1 = m[N + o] - m1, d2 = m[2 * N + o] - m2;
+      ex += czz * (d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    acc[0] += ex;
+    acc[1] += m1 * m1 + m2 * m2;
+    if (hs) acc[2] += m0 * (double)hs[idx] + m1 * (double)hs[N + idx] + m2 * (double)hs[2 * N + idx];
+    acc[3] += m0 * he0 + m1 * he1 + m2 * he2;
+  }
+  __shared__ double red[4][NT / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) red[k][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+    for (int w = 0; w < NT / 64; ++w) s += red[threadIdx.x][w];
+    partials[(long)blockIdx.x * 4 + threadIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_energy_final(const double* partials, int nblocks, double* out) {
+  __shared__ double red[4][NT];
+  for (int k = 0; k < 4; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += NT) s += partials[(long)b * 4 + k];
+    red[k][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+template <typename T> void launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_t s) {
+  const int rows = 2 << a.lgP;
+  dim3 grid(ceil_div(a.nrows, rows), 1, nch);
+  const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << (a.lgP + a.lgLmax))) * sizeof(cx<T>);
+  hipLaunchKernelGGL(k_row_fwd<T>, grid, dim3(NT), lds, s, a);
+}
+
+template <typename T> void launch_row_inv(const RowInv<T>& a, hipStream_t s) {
+  const int rows = 2 << a.lgP;
+  dim3 grid(ceil_div(a.nrows, rows), 1, 1);
+  const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << (a.lgP + a.lgLmax))) * sizeof(cx<T>);
+  hipLaunchKernelGGL(k_row_inv<T>, grid, dim3(NT), lds, s, a);
+}
+
+template <typename T> void launch_col_dct(const ColDct<T>& a, int nbatch, int nch, hipStream_t s) {
+  dim3 grid(ceil_div(a.ni, 2 << a.lgP), nbatch, nch);
+  const size_t lds = ((size_t)(1 << a.lgN) + ((size_t)1 << (a.lgP + a.lgN))) * sizeof(cx<T>);
+  hipLaunchKernelGGL(k_col_dct<T>, grid, dim3(NT), lds, s, a);
+}
+
+template <typename T> void launch_col_fft(const ColFft<T>& a, int nbatch, int nch, hipStream_t s) {
+  dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, nch);
+  const size_t lds = ((size_t)(1 << a.lgL) + ((size_t)1 << (a.lgP + a.lgL))) * sizeof(cx<T>);
+  hipLaunchKernelGGL(k_col_fft<T>, grid, dim3(NT), lds, s, a);
+}
+
+template <typename T> void launch_conv(const Conv<T>& a, int nbatch, hipStream_t s) {
+  dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, 1);
+  const size_t lds = ((size_t)(1 << a.lgL) + 3 * ((size_t)1 << (a.lgP + a.lgL))) * sizeof(cx<T>);
+  hipLaunchKernelGGL(k_conv<T>, grid, dim3(NT), lds, s, a);
+}
+
+void launch_newell_fill(double* out, int comp, int nx, int ny, int nz, int Px, int Py, int Pz, double hx, double hy,
+                        double hz, int rfar, hipStream_t s) {
+  const long total = (long)Px * Py * Pz;
+  const int blocks = (int)std::min<long>((total + NT - 1) / NT, 65536);
+  hipLaunchKernelGGL(k_newell_fill, dim3(blocks), dim3(NT), 0, s, out, comp, nx, ny, nz, Px, Py, Pz, hx, hy, hz, rfar);
+}
+
+template <typename T>
+void launch_tensor_pack(const cx<double>* spec, T* out, int Hz, int Hy, int Kx, int Kxp, int Py, double scale,
+                        hipStream_t s) {
+  const long total = (long)Hz * Hy * Kx;
+  const int blocks = (int)std::min<long>((total + NT - 1) / NT, 65536);
+  hipLaunchKernelGGL(k_tensor_pack<T>, dim3(blocks), dim3(NT), 0, s, spec, out, Hz, Hy, Kx, Kxp, Py, scale);
+}
+
+template <typename T>
+void launch_field_assemble(const T* m, const T* hs, T* out, int nx, int ny, int nz, double cxx, double cyy, double czz,
+                           double eps_on, double Q, const double he[3], hipStream_t s) {
+  const long N = (long)nx * ny * nz;
+  const int blocks = (int)std::min<long>((N + NT - 1) / NT, 65536);
+  hipLaunchKernelGGL(k_field_assemble<T>, dim3(blocks), dim3(NT), 0, s, m, hs, out, nx, ny, nz, cxx, cyy, czz, eps_on, Q,
+                     he[0], he[1], he[2]);
+}
+
+template <typename T>
+void launch_energy(const T* m, const T* hs, int nx, int ny, int nz, double cxx, double cyy, double czz,
+                   const double he[3], double* partials, int nblocks, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy<T>, dim3(nblocks), dim3(NT), 0, s, m, hs, nx, ny, nz, cxx, cyy, czz, he[0], he[1], he[2],
+                     partials);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(NT), 0, s, partials, nblocks, out);
+}
+
+#define SGSPM_INSTANTIATE(T)                                                                                          \
+  template void launch_row_fwd<T>(const RowFwd<T>&, int, hipStream_t);                                              \
+  template void launch_row_inv<T>(const RowInv<T>&, hipStream_t);                                                   \
+  template void launch_col_dct<T>(const ColDct<T>&, int, int, hipStream_t);                                         \
+  template void launch_col_fft<T>(const ColFft<T>&, int, int, hipStream_t);                                         \
+  template void launch_conv<T>(const Conv<T>&, int, hipStream_t);                                                   \
+  template void launch_tensor_pack<T>(const cx<double>*, T*, int, int, int, int, int, double, hipStream_t);         \
+  template void launch_field_assemble<T>(const T*, const T*, T*, int, int, int, double, double, double, double,    \
+                                         double, const double*, hipStream_t);                                       \
+  template void launch_energy<T>(const T*, const T*, int, int, int, double, double, double, const double*, double*, \
+                                 int, double*, hipStream_t);
+
+SGSPM_INSTANTIATE(float)
+SGSPM_INSTANTIATE(double)
+
+}  // namespace sgspm

@@ -1,0 +1,1013 @@
+// Host side of the SGSPM library: validation, unit reduction, plan
+// construction (tables, workspace, FP64 demagnetising-tensor spectrum) and the
+// stage-by-stage schedule of one SGSPM / GSPM step on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sgspm.h"
+#include "kernels.h"
+
+using namespace sgspm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+const double MU0 = 4.0e-7 * M_PI;
+const double GAMMA = 1.7609e11;  // rad / (s T)
+const int R_FAR = 20;            // cells: Newell sum within, point dipole beyond
+
+bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+int ilog2(long n) {
+  int l = 0;
+  while ((1L << l) < n) ++l;
+  return l;
+}
+
+int validate(const sgspm_params* p) {
+  if (!p) return fail(SGSPM_EINVAL, "params is NULL");
+  const int n[3] = {p->nx, p->ny, p->nz};
+  const char* nm[3] = {"nx", "ny", "nz"};
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] <= 0) return fail(SGSPM_EINVAL, std::string(nm[a]) + " must be positive");
+    if (n[a] > 1024) return fail(SGSPM_EUNSUPPORTED, std::string(nm[a]) + " above 1024 is not supported");
+    if (!pow2(n[a])) return fail(SGSPM_EUNSUPPORTED, std::string(nm[a]) + " must be a power of two");
+  }
+  const double h[3] = {p->dx, p->dy, p->dz};
+  for (int a = 0; a < 3; ++a)
+    if (!(h[a] > 0.0) || !std::isfinite(h[a])) return fail(SGSPM_EINVAL, "cell sizes must be positive and finite");
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(SGSPM_EINVAL, "dt must be positive and finite");
+  if (p->units != SGSPM_UNITS_SI && p->units != SGSPM_UNITS_REDUCED) return fail(SGSPM_EINVAL, "unknown units");
+  if (p->units == SGSPM_UNITS_SI) {
+    if (!(p->Ms > 0.0) || !std::isfinite(p->Ms)) return fail(SGSPM_EINVAL, "Ms must be positive");
+    if (!(p->A >= 0.0) || !std::isfinite(p->A)) return fail(SGSPM_EINVAL, "A must be non-negative");
+    if (!std::isfinite(p->Ku)) return fail(SGSPM_EINVAL, "Ku must be finite");
+  } else {
+    if (!(p->eps >= 0.0) || !std::isfinite(p->eps)) return fail(SGSPM_EINVAL, "eps must be non-negative");
+    if (!std::isfinite(p->Q)) return fail(SGSPM_EINVAL, "Q must be finite");
+  }
+  if (p->terms & ~15u) return fail(SGSPM_EINVAL, "unknown term bits");
+  if (p->precision != SGSPM_FP32 && p->precision != SGSPM_FP64) return fail(SGSPM_EINVAL, "unknown precision");
+  if (p->scheme != SGSPM_SCHEME_SGS && p->scheme != SGSPM_SCHEME_GS) return fail(SGSPM_EINVAL, "unknown scheme");
+  const long N = (long)p->nx * p->ny * p->nz;
+  if (N > (1L << 28)) return fail(SGSPM_EUNSUPPORTED, "grid too large");
+  if (p->terms & SGSPM_TERM_STRAY) {
+    // the last-axis convolution holds three padded pencils of its axis in one tile
+    const int nc = p->nz > 1 ? p->nz : p->ny;
+    const int lim = p->precision == SGSPM_FP64 ? 256 : 512;
+    if (nc > lim)
+      return fail(SGSPM_EUNSUPPORTED, std::string(p->nz > 1 ? "nz" : "ny") + " above " + std::to_string(lim) +
+                                          " is not supported with the stray field at this precision");
+  }
+  return SGSPM_OK;
+}
+
+// eps, Q, dt (reduced), field scale (per tesla), energy scale
+void reduce(const sgspm_params* p, double out[5]) {
+  const bool ex = p->terms & SGSPM_TERM_EXCHANGE, an = p->terms & SGSPM_TERM_ANISO;
+  if (p->units == SGSPM_UNITS_SI) {
+    const double sc = MU0 * p->Ms * p->Ms;
+    out[0] = ex ? 2.0 * p->A / sc : 0.0;
+    out[1] = an ? 2.0 * p->Ku / sc : 0.0;
+    out[2] = p->dt * GAMMA * MU0 * p->Ms;
+    out[3] = 1.0 / (MU0 * p->Ms);
+    out[4] = sc;
+  } else {
+    out[0] = ex ? p->eps : 0.0;
+    out[1] = an ? p->Q : 0.0;
+    out[2] = p->dt;
+    out[3] = 1.0;
+    out[4] = 1.0;
+  }
+}
+
+}  // namespace
+
+struct sgspm_plan_s {
+  sgspm_params prm;
+  hipStream_t s = nullptr;
+  bool fp64 = false;
+  int nx = 1, ny = 1, nz = 1;
+  long N = 0;
+  int Px = 1, Py = 1, Pz = 1, Kx = 1, Kxp = 1, Hy = 1, Hz = 1;
+  bool stray = false, zeeman = false, has_mid = false;
+  double eps = 0, Q = 0, dt = 0, fscale = 1, escale = 1;
+  double cxx = 0, cyy = 0, czz = 0;  // eps / h^2 per axis (reduced)
+  int lgTw = 0;
+  // typed (T) device tables
+  void* tw = nullptr;
+  void* dtw[3] = {nullptr, nullptr, nullptr};
+  void* lam[3] = {nullptr, nullptr, nullptr};
+  // FP64 twiddles for the tensor precompute
+  void* tw64 = nullptr;
+  // workspace
+  void* fld = nullptr;     // NF fields of N values
+  void* heat = nullptr;    // 3 x N
+  void* xlev = nullptr;    // 3 x nz*ny*Kxp complex
+  void* ylev = nullptr;    // 3 x nz*Py*Kxp complex (3-D) or null
+  void* yout = nullptr;    // 3 x conv outputs
+  void* tens = nullptr;    // 6 x Hz*Hy*Kx
+  double* partials = nullptr;
+  double* eout = nullptr;
+  int* flag = nullptr;
+  int nred = 0;
+  std::vector<void*> allocs;
+  // optional per-kernel-class timing (HIP events around every launch)
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool timing = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evnext = 0;
+  std::vector<Rec> recs;
+};
+
+namespace {
+
+enum { F_G2N, F_G3N, F_A1, F_G1S, F_A2, F_G2S, F_A3, F_G3SS, F_B2, F_G2SS, F_B1, F_NRM, F_HS0, F_HS1, F_HS2, NF };
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SGSPM_OK;
+  return fail(SGSPM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int dalloc(sgspm_plan_s* P, void** out, size_t bytes) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 256));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SGSPM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  P->allocs.push_back(p);
+  *out = p;
+  return SGSPM_OK;
+}
+
+template <typename T> int upload(sgspm_plan_s* P, void** out, const std::vector<T>& h) {
+  int rc = dalloc(P, out, h.size() * sizeof(T));
+  if (rc) return rc;
+  return hip_check(hipMemcpyAsync(*out, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, P->s), "upload");
+}
+
+// Tiles: complex elements per tile for each precision.
+template <typename T> int lg_tile() { return ilog2(tile_elems<T>()); }
+
+// largest lgP with (2 << lgP) rows not beyond what the rows need
+int cap_lgP(int lgP, long count_pencils) {
+  int need = ilog2(std::max<long>(1, count_pencils));
+  return std::max(0, std::min(lgP, need));
+}
+
+// ---------------------------------------------------------------------------
+template <typename T> struct Eng {
+  sgspm_plan_s& P;
+  hipStream_t s;
+  const cx<T>* tw;
+  const cx<T>* dtw[3];
+  const T* lam[3];
+  T* f[NF];
+  T* heat[3];
+  cx<T>* xlev[3];
+  cx<T>* ylev[3];
+  cx<T>* yout[3];
+  const T* tens;
+
+  explicit Eng(sgspm_plan_s& p) : P(p), s(p.s) {
+    tw = (const cx<T>*)P.tw;
+    for (int a = 0; a < 3; ++a) {
+      dtw[a] = (const cx<T>*)P.dtw[a];
+      lam[a] = (const T*)P.lam[a];
+    }
+    for (int i = 0; i < NF; ++i) f[i] = (T*)P.fld + (long)i * P.N;
+    for (int c = 0; c < 3; ++c) heat[c] = (T*)P.heat + (long)c * P.N;
+    const long xl = (long)P.nz * P.ny * P.Kxp;
+    const long yl = (long)P.nz * P.Py * P.Kxp;
+    for (int c = 0; c < 3; ++c) {
+      xlev[c] = P.xlev ? (cx<T>*)P.xlev + c * xl : nullptr;
+      ylev[c] = P.ylev ? (cx<T>*)P.ylev + c * yl : nullptr;
+      yout[c] = P.yout ? (cx<T>*)P.yout + c * (P.has_mid ? yl : xl) : nullptr;
+    }
+    tens = (const T*)P.tens;
+  }
+
+  // ---- timing: events around a launch, with the launch's algorithmic bytes
+  hipEvent_t ev() {
+    if (P.evnext == P.evpool.size()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      P.evpool.push_back(e);
+    }
+    return P.evpool[P.evnext++];
+  }
+  template <class F> void timed(int cls, double bytes, F&& fn) {
+    if (!P.timing) {
+      fn();
+      return;
+    }
+    hipEvent_t a = ev(), b = ev();
+    (void)hipEventRecord(a, s);
+    fn();
+    (void)hipEventRecord(b, s);
+    P.recs.push_back({cls, a, b, bytes});
+  }
+  static constexpr double TS = sizeof(T);
+
+  // component spectra at the level the last-axis convolution reads
+  cx<T>* comp_spec(int c) { return P.has_mid ? ylev[c] : xlev[c]; }
+  // real-to-complex output slot of component c (x level)
+  cx<T>* r2c_slot(int c) { return xlev[c]; }
+  // complex-to-real source of stray-field component a (x level)
+  const cx<T>* c2r_src(int a) { return P.has_mid ? xlev[a] : yout[a]; }
+
+  // ---- row kernels
+  void row_fwd(int nch, const T* const u[3], const T a[3], T b, const T he[3], bool with_hs, T* const hs_out[3],
+               T* const dct_out[3], cx<T>* const xout[3]) {
+    RowFwd<T> A{};
+    A.nrows = P.ny * P.nz;
+    A.lgN = ilog2(P.nx);
+    A.lgLc = ilog2(P.Px);
+    A.lgLr = ilog2(P.Px);
+    int lgL = 0;
+    bool any_x = with_hs;
+    for (int c = 0; c < nch; ++c) {
+      if (xout && xout[c]) any_x = true;
+      if (dct_out && dct_out[c]) lgL = std::max(lgL, A.lgN);
+    }
+    if (any_x) lgL = std::max(lgL, A.lgLr);
+    A.lgLmax = lgL;
+    A.lgP = cap_lgP(lg_tile<T>() - lgL, (A.nrows + 1) / 2);
+    A.lgTw = P.lgTw;
+    A.tw = tw;
+    A.dtw = dtw[0];
+    A.b = b;
+    A.xin_pitch = P.Kxp;
+    A.xout_pitch = P.Kxp;
+    for (int c = 0; c < nch; ++c) {
+      A.u[c] = u ? u[c] : nullptr;
+      A.a[c] = a ? a[c] : (T)1;
+      A.he[c] = he ? he[c] : (T)0;
+      A.xin[c] = with_hs ? c2r_src_for_[c] : nullptr;
+      A.hs_out[c] = hs_out ? hs_out[c] : nullptr;
+      A.dct_out[c] = dct_out ? dct_out[c] : nullptr;
+      A.xout[c] = xout ? xout[c] : nullptr;
+    }
+    double by = 0;
+    const double rows = A.nrows, cpx = (double)A.nrows * P.Kx * 2 * TS;
+    for (int c = 0; c < nch; ++c)
+      by += (A.u[c] ? P.N * TS : 0) + (A.xin[c] ? cpx : 0) + (A.hs_out[c] ? P.N * TS : 0) +
+            (A.dct_out[c] ? P.N * TS : 0) + (A.xout[c] ? cpx : 0);
+    (void)rows;
+    timed(SGSPM_KC_ROW_FWD, by, [&] { launch_row_fwd<T>(A, nch, s); });
+  }
+  const cx<T>* c2r_src_for_[3] = {nullptr, nullptr, nullptr};
+
+  void row_inv(RowInv<T>& A, bool r2c) {
+    A.nrows = P.ny * P.nz;
+    A.lgN = ilog2(P.nx);
+    A.lgLr = ilog2(P.Px);
+    A.lgLmax = r2c ? std::max(A.lgN, A.lgLr) : A.lgN;
+    A.lgP = cap_lgP(lg_tile<T>() - A.lgLmax, (A.nrows + 1) / 2);
+    A.lgTw = P.lgTw;
+    A.tw = tw;
+    A.dtw = dtw[0];
+    A.xout_pitch = P.Kxp;
+    if (!r2c) A.xout = nullptr;
+    double by = A.nch * P.N * TS;
+    for (int c = 0; c < A.nch; ++c) by += A.gout[c] ? P.N * TS : 0;
+    if (A.op == ROW_OP_GS) by += (4 + (A.src ? 1 : 0) + 1) * P.N * TS;
+    if (A.op == ROW_OP_PROJECT) by += (3 + (A.nrm ? 1 : 0)) * P.N * TS;
+    if (A.xout) by += (double)A.nrows * P.Kx * 2 * TS;
+    timed(SGSPM_KC_ROW_INV, by, [&] { launch_row_inv<T>(A, s); });
+  }
+
+  // ---- heat solves: after row_fwd wrote DCT_x(rhs) into heat[0..nch)
+  void heat_rest(int nch, T scale) {
+    T* d[3] = {heat[0], heat[1], heat[2]};
+    const T sdt = (T)(scale * P.dt);
+    if (P.has_mid) {
+      ColDct<T> A{};
+      A.mode = COL_DCT_FWD;
+      A.lgN = ilog2(P.ny);
+      A.lgP = cap_lgP(lg_tile<T>() - A.lgN, (P.nx + 1) / 2);
+      A.ni = P.nx;
+      A.sa = P.nx;
+      A.sb = (long)P.ny * P.nx;
+      for (int c = 0; c < 3; ++c) A.data[c] = d[c];
+      A.dtw = dtw[1];
+      A.tw = tw;
+      A.lgTw = P.lgTw;
+      timed(SGSPM_KC_COL_DCT, 2.0 * nch * P.N * TS, [&] { launch_col_dct<T>(A, P.nz, nch, s); });
+    }
+    {
+      ColDct<T> A{};
+      A.mode = COL_DCT_SOLVE;
+      const bool z = P.nz > 1;
+      A.lgN = ilog2(z ? P.nz : P.ny);
+      A.lgP = cap_lgP(lg_tile<T>() - A.lgN, (P.nx + 1) / 2);
+      A.ni = P.nx;
+      A.sa = z ? (long)P.ny * P.nx : P.nx;
+      A.sb = z ? P.nx : 0;
+      for (int c = 0; c < 3; ++c) A.data[c] = d[c];
+      A.dtw = dtw[z ? 2 : 1];
+      A.tw = tw;
+      A.lgTw = P.lgTw;
+      A.lamX = lam[0];
+      A.lamB = z ? lam[1] : lam[2];
+      A.lamA = z ? lam[2] : lam[1];
+      A.s = sdt;
+      timed(SGSPM_KC_COL_DCT, 2.0 * nch * P.N * TS, [&] { launch_col_dct<T>(A, z ? P.ny : 1, nch, s); });
+    }
+    if (P.has_mid) {
+      ColDct<T> A{};
+      A.mode = COL_DCT_INV;
+      A.lgN = ilog2(P.ny);
+      A.lgP = cap_lgP(lg_tile<T>() - A.lgN, (P.nx + 1) / 2);
+      A.ni = P.nx;
+      A.sa = P.nx;
+      A.sb = (long)P.ny * P.nx;
+      for (int c = 0; c < 3; ++c) A.data[c] = d[c];
+      A.dtw = dtw[1];
+      A.tw = tw;
+      A.lgTw = P.lgTw;
+      timed(SGSPM_KC_COL_DCT, 2.0 * nch * P.N * TS, [&] { launch_col_dct<T>(A, P.nz, nch, s); });
+    }
+  }
+
+  // ---- stray field
+  // y-pass forward of x-level spectra of the listed components (3-D only)
+  void mid_fwd(int mask) {
+    if (!P.has_mid) return;
+    ColFft<T> A{};
+    A.lgL = ilog2(P.Py);
+    A.n_in = P.ny;
+    A.n_out = P.Py;
+    A.lgP = cap_lgP(lg_tile<T>() - A.lgL, P.Kx);
+    A.ni = P.Kx;
+    A.sa_in = P.Kxp;
+    A.sb_in = (long)P.ny * P.Kxp;
+    A.sa_out = P.Kxp;
+    A.sb_out = (long)P.Py * P.Kxp;
+    int k = 0;
+    for (int c = 0; c < 3; ++c)
+      if (mask >> c & 1) {
+        A.in[k] = xlev[c];
+        A.out[k] = ylev[c];
+        ++k;
+      }
+    A.inv = 0;
+    A.tw = tw;
+    A.lgTw = P.lgTw;
+    const double cb = (double)P.Kx * P.nz * 2 * TS;
+    timed(SGSPM_KC_COL_FFT, k * cb * (P.ny + P.Py), [&] { launch_col_fft<T>(A, P.nz, k, s); });
+  }
+  void mid_inv(int mask) {
+    if (!P.has_mid) return;
+    ColFft<T> A{};
+    A.lgL = ilog2(P.Py);
+    A.n_in = P.Py;
+    A.n_out = P.ny;
+    A.lgP = cap_lgP(lg_tile<T>() - A.lgL, P.Kx);
+    A.ni = P.Kx;
+    A.sa_in = P.Kxp;
+    A.sb_in = (long)P.Py * P.Kxp;
+    A.sa_out = P.Kxp;
+    A.sb_out = (long)P.ny * P.Kxp;
+    int k = 0;
+    for (int c = 0; c < 3; ++c)
+      if (mask >> c & 1) {
+        A.in[k] = yout[c];
+        A.out[k] = xlev[c];
+        ++k;
+      }
+    A.inv = 1;
+    A.tw = tw;
+    A.lgTw = P.lgTw;
+    const double cb = (double)P.Kx * P.nz * 2 * TS;
+    timed(SGSPM_KC_COL_FFT, k * cb * (P.ny + P.Py), [&] { launch_col_fft<T>(A, P.nz, k, s); });
+  }
+  void conv(int mask) {
+    Conv<T> A{};
+    const bool z = P.nz > 1;
+    const int L = z ? P.Pz : P.Py;
+    A.lgL = ilog2(L);
+    A.n = z ? P.nz : P.ny;
+    int lgP = 0;
+    while (3L * (2L << lgP) * L <= tile_elems<T>()) ++lgP;
+    A.lgP = cap_lgP(lgP, P.Kx);
+    A.ni = P.Kx;
+    if (z) {
+      A.sa = (P.has_mid ? (long)P.Py : 1L) * P.Kxp;
+      A.sb = P.has_mid ? P.Kxp : 0;
+      A.Hb = P.has_mid ? P.Hy : 1;
+      A.Pb = P.has_mid ? P.Py : 1;
+      A.oddc = (1 << 4) | (1 << 5);  // xz, yz odd in z
+      A.oddb = (1 << 3) | (1 << 5);  // xy, yz odd in y
+    } else {
+      A.sa = P.Kxp;
+      A.sb = 0;
+      A.Hb = 1;
+      A.Pb = 1;
+      A.oddc = (1 << 3) | (1 << 5);
+      A.oddb = 0;
+    }
+    for (int c = 0; c < 3; ++c) {
+      A.S[c] = comp_spec(c);
+      A.O[c] = (mask >> c & 1) ? yout[c] : nullptr;
+    }
+    A.tens = tens;
+    A.tcs = (long)P.Hz * P.Hy * P.Kx;
+    A.tw = tw;
+    A.lgTw = P.lgTw;
+    const int nb = (z && P.has_mid) ? P.Py : 1;
+    const double slab = (double)A.n * A.ni * nb * 2 * TS;
+    int nout = 0;
+    unsigned used = 0;
+    for (int a = 0; a < 3; ++a)
+      if (mask >> a & 1) {
+        ++nout;
+        for (int b = 0; b < 3; ++b) used |= 1u << (a == b ? a : 2 + a + b);
+      }
+    const double tb = __builtin_popcount(used) * (double)(z ? P.Hz : P.Hy) * A.Hb * A.ni * TS;
+    timed(SGSPM_KC_CONV, 3 * slab + nout * slab + tb, [&] { launch_conv<T>(A, nb, s); });
+  }
+
+  // forward transforms of real fields into the component spectra
+  void stray_from_fields(const T* const fields[3], int mask) {
+    const T* u[3] = {nullptr, nullptr, nullptr};
+    cx<T>* xo[3] = {nullptr, nullptr, nullptr};
+    T a[3] = {1, 1, 1};
+    int k = 0;
+    for (int c = 0; c < 3; ++c)
+      if (mask >> c & 1) {
+        u[k] = fields[c];
+        xo[k] = r2c_slot(c);
+        ++k;
+      }
+    row_fwd(k, u, a, (T)0, nullptr, false, nullptr, nullptr, xo);
+    mid_fwd(mask);
+  }
+
+  // the stray-field components of `mask` as x-level spectra ready for c2r
+  void stray_eval(int mask) {
+    conv(mask);
+    mid_inv(mask);
+  }
+
+  void set_c2r(const int comps[3], int nch) {
+    for (int c = 0; c < 3; ++c) c2r_src_for_[c] = nullptr;
+    for (int c = 0; c < nch; ++c) c2r_src_for_[c] = c2r_src(comps[c]);
+  }
+
+  // RHS + forward x DCT for heat solves of components comps[0..nch)
+  void heat_rhs(int nch, const int comps[3], const T* const u[3], T beta, const T he[3]) {
+    T a[3];
+    T hev[3];
+    for (int c = 0; c < nch; ++c) {
+      a[c] = (T)(1.0 - (double)beta * (comps[c] > 0 ? P.Q : 0.0));
+      hev[c] = he[comps[c]];
+    }
+    set_c2r(comps, nch);
+    T* outs[3] = {heat[0], heat[1], heat[2]};
+    row_fwd(nch, u, a, beta, hev, P.stray, nullptr, outs, nullptr);
+  }
+
+  // One SGSPM / GSPM step (paper §3.2 / §3.1), latest-state reading.
+  void step(T* m, double alpha, const double he_in[3], const T* src) {
+    const long N = P.N;
+    T* m1 = m;
+    T* m2 = m + N;
+    T* m3 = m + 2 * N;
+    const T dt = (T)P.dt;
+    T he[3];
+    for (int c = 0; c < 3; ++c) he[c] = P.zeeman ? (T)(he_in[c] * P.fscale) : (T)0;
+    const T* s1 = src ? src : nullptr;
+    const T* s2 = src ? src + N : nullptr;
+    const T* s3 = src ? src + 2 * N : nullptr;
+    const bool st = P.stray;
+    const bool sgs = P.prm.scheme == SGSPM_SCHEME_SGS;
+
+    // Stage A: g2^n, g3^n from m^n
+    if (st) {
+      const T* fl[3] = {m1, m2, m3};
+      stray_from_fields(fl, 7);
+      stray_eval(6);
+    }
+    {
+      const int comps[3] = {1, 2, 0};
+      const T* u[3] = {m2, m3, nullptr};
+      heat_rhs(2, comps, u, dt, he);
+      heat_rest(2, (T)1);
+    }
+    // Stage B: m1* = m1 + g2^n m3 - g3^n m2 (+ dt s1); g1* from (m1*, m2, m3)
+    {
+      RowInv<T> A{};
+      A.nch = 2;
+      A.heat[0] = heat[0];
+      A.heat[1] = heat[1];
+      A.gout[0] = f[F_G2N];
+      A.gout[1] = f[F_G3N];
+      A.op = ROW_OP_GS;
+      A.base = m1;
+      A.Pch = 0;
+      A.Qf = m3;
+      A.Rch = 1;
+      A.Sf = m2;
+      A.src = s1;
+      A.ds = dt;
+      A.out = f[F_A1];
+      A.xout = st ? r2c_slot(0) : nullptr;
+      row_inv(A, st);
+    }
+    single_stage(0, f[F_A1], dt, he, (T)1);
+    // Stage C: m2* = m2 + g3^n m1* - g1* m3 (+ dt s2); g2* from (m1*, m2*, m3)
+    gs_update(f[F_G1S], m2, f[F_G3N], -1, f[F_A1], 0, m3, s2, dt, f[F_A2], 1);
+    single_stage(1, f[F_A2], dt, he, (T)1);
+    // Stage D: m3* = m3 + g1* m2* - g2* m1* (+ dt s3)
+    gs_update(f[F_G2S], m3, f[F_G1S], -1, f[F_A2], 0, f[F_A1], s3, dt, f[F_A3], 2);
+    const T* uF[3];
+    if (sgs) {
+      // g3** from (m1*, m2*, m3** = m3*)
+      single_stage(2, f[F_A3], dt, he, (T)1);
+      // Stage E: m2** = m2 + g3** m1* - g1* m3** (+ dt s2); g2** from (m1*, m2**, m3**)
+      gs_update(f[F_G3SS], m2, nullptr, 0, f[F_A1], -1, f[F_A3], s2, dt, f[F_B2], 1, f[F_G1S]);
+      single_stage(1, f[F_B2], dt, he, (T)1);
+      // Stage F: m1** = m1 + g2** m3** - g3** m2** (+ dt s1)
+      gs_update(f[F_G2SS], m1, nullptr, 0, f[F_A3], -1, f[F_B2], s1, dt, f[F_B1], 0, f[F_G3SS]);
+      if (st) {
+        mid_fwd(1);
+        stray_eval(7);
+      }
+      uF[0] = f[F_B1];
+      uF[1] = f[F_B2];
+      uF[2] = f[F_A3];
+    } else {
+      if (st) {
+        mid_fwd(4);
+        stray_eval(7);
+      }
+      uF[0] = f[F_A1];
+      uF[1] = f[F_A2];
+      uF[2] = f[F_A3];
+    }
+    // Step 2: (I - alpha eps dt Lap_h) m*** = m** + alpha dt f**
+    {
+      const int comps[3] = {0, 1, 2};
+      heat_rhs(3, comps, uF, (T)(alpha * P.dt), he);
+      heat_rest(3, (T)alpha);
+    }
+    // Step 3: projection
+    {
+      RowInv<T> A{};
+      A.nch = 3;
+      for (int c = 0; c < 3; ++c) A.heat[c] = heat[c];
+      A.op = ROW_OP_PROJECT;
+      A.mout[0] = m1;
+      A.mout[1] = m2;
+      A.mout[2] = m3;
+      A.nrm = f[F_NRM];
+      A.flag = P.flag;
+      row_inv(A, false);
+    }
+  }
+
+  // stray evaluation for component c of the state (if on) followed by the RHS
+  // and the transforms of its precession solve (leaves DCT-level data in heat[0])
+  void single_stage(int c, const T* u_c, T beta, const T he[3], T scale) {
+    if (P.stray) {
+      mid_fwd(1 << c);
+      stray_eval(1 << c);
+    }
+    const int comps[3] = {c, 0, 0};
+    const T* u[3] = {u_c, nullptr, nullptr};
+    heat_rhs(1, comps, u, beta, he);
+    heat_rest(1, scale);
+  }
+
+  // Inverse x DCT of heat[0] into gstore, then out = base + Pv Q - Rv S (+ ds src)
+  // where a null Pv / Rv pointer (with Pch / Rch = 0) means the inverted array.
+  // If `other` is given it replaces the non-inverted operand among P/R.
+  void gs_update(T* gstore, const T* base, const T* Pv, int Pch_unused, const T* Q, int Rch_unused, const T* S,
+                 const T* src, T ds, T* out, int comp_out, const T* other = nullptr) {
+    (void)Pch_unused;
+    (void)Rch_unused;
+    RowInv<T> A{};
+    A.nch = 1;
+    A.heat[0] = heat[0];
+    A.gout[0] = gstore;
+    A.op = ROW_OP_GS;
+    A.base = base;
+    A.Qf = Q;
+    A.Sf = S;
+    if (Pv) {  // the inverted array is R
+      A.Pch = -1;
+      A.Pf = Pv;
+      A.Rch = 0;
+    } else {   // the inverted array is P, R is `other`
+      A.Pch = 0;
+      A.Rch = -1;
+      A.Rf = other;
+    }
+    A.src = src;
+    A.ds = ds;
+    A.out = out;
+    A.xout = P.stray ? r2c_slot(comp_out) : nullptr;
+    row_inv(A, P.stray);
+  }
+
+  // h_s of m into hs (3 fields)
+  void stray_to(const T* m, T* hs) {
+    const T* fl[3] = {m, m + P.N, m + 2 * P.N};
+    stray_from_fields(fl, 7);
+    stray_eval(7);
+    const int comps[3] = {0, 1, 2};
+    set_c2r(comps, 3);
+    T* ho[3] = {hs, hs + P.N, hs + 2 * P.N};
+    T a[3] = {0, 0, 0};
+    row_fwd(3, nullptr, a, (T)0, nullptr, true, ho, nullptr, nullptr);
+  }
+
+  void heat_solve(const T* r, T scale, T* g) {
+    const T* u[3] = {r, nullptr, nullptr};
+    T a[3] = {1, 1, 1};
+    T* outs[3] = {heat[0], nullptr, nullptr};
+    row_fwd(1, u, a, (T)0, nullptr, false, nullptr, outs, nullptr);
+    heat_rest(1, scale);
+    RowInv<T> A{};
+    A.nch = 1;
+    A.heat[0] = heat[0];
+    A.gout[0] = g;
+    A.op = ROW_OP_NONE;
+    row_inv(A, false);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Plan-time FP64 demagnetising tensor spectrum.
+int build_tensor(sgspm_plan_s* P) {
+  const long padded = (long)P->Px * P->Py * P->Pz;
+  const long speclen = (long)P->Pz * P->Py * P->Kxp;
+  void* real = nullptr;
+  void* spec = nullptr;
+  int rc;
+  if ((rc = dalloc(P, &real, padded * sizeof(double)))) return rc;
+  if ((rc = dalloc(P, &spec, speclen * sizeof(cx<double>)))) return rc;
+  const double hs = std::max(P->prm.dx, std::max(P->prm.dy, P->prm.dz));
+  const double hx = P->prm.dx / hs, hy = P->prm.dy / hs, hz = P->prm.dz / hs;
+  const long tcs = (long)P->Hz * P->Hy * P->Kx;
+  const double scale = -1.0 / (double)padded;
+  const cx<double>* tw64 = (const cx<double>*)P->tw64;
+  for (int comp = 0; comp < 6; ++comp) {
+    launch_newell_fill((double*)real, comp, P->nx, P->ny, P->nz, P->Px, P->Py, P->Pz, hx, hy, hz, R_FAR, P->s);
+    // x: real-to-complex, full length
+    {
+      RowFwd<double> A{};
+      A.nrows = P->Py * P->Pz;
+      A.lgN = ilog2(P->Px);
+      A.lgLr = A.lgN;
+      A.lgLc = A.lgN;
+      A.lgLmax = A.lgN;
+      A.lgP = cap_lgP(lg_tile<double>() - A.lgN, (A.nrows + 1) / 2);
+      A.lgTw = P->lgTw;
+      A.tw = tw64;
+      A.u[0] = (const double*)real;
+      A.a[0] = 1.0;
+      A.b = 0.0;
+      A.xout[0] = (cx<double>*)spec;
+      A.xout_pitch = P->Kxp;
+      launch_row_fwd<double>(A, 1, P->s);
+    }
+    // y and z: complex, full length, in place
+    for (int ax = 1; ax <= 2; ++ax) {
+      const int L = ax == 1 ? P->Py : P->Pz;
+      if (L == 1) continue;
+      ColFft<double> A{};
+      A.lgL = ilog2(L);
+      A.n_in = L;
+      A.n_out = L;
+      A.lgP = cap_lgP(lg_tile<double>() - A.lgL, P->Kx);
+      A.ni = P->Kx;
+      if (ax == 1) {
+        A.sa_in = A.sa_out = P->Kxp;
+        A.sb_in = A.sb_out = (long)P->Py * P->Kxp;
+      } else {
+        A.sa_in = A.sa_out = (long)P->Py * P->Kxp;
+        A.sb_in = A.sb_out = P->Kxp;
+      }
+      A.in[0] = (const cx<double>*)spec;
+      A.out[0] = (cx<double>*)spec;
+      A.inv = 0;
+      A.tw = tw64;
+      A.lgTw = P->lgTw;
+      launch_col_fft<double>(A, ax == 1 ? P->Pz : P->Py, 1, P->s);
+    }
+    if (P->fp64)
+      launch_tensor_pack<double>((const cx<double>*)spec, (double*)P->tens + comp * tcs, P->Hz, P->Hy, P->Kx, P->Kxp,
+                                 P->Py, scale, P->s);
+    else
+      launch_tensor_pack<float>((const cx<double>*)spec, (float*)P->tens + comp * tcs, P->Hz, P->Hy, P->Kx, P->Kxp,
+                                P->Py, scale, P->s);
+  }
+  rc = hip_check(hipGetLastError(), "tensor kernels");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(P->s), "tensor sync");
+  // release the FP64 scratch
+  for (void* p : {real, spec}) {
+    (void)hipFree(p);
+    P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), p));
+  }
+  return rc;
+}
+
+template <typename T> int make_tables(sgspm_plan_s* P) {
+  int rc;
+  const int Lmax = 1 << P->lgTw;
+  std::vector<cx<T>> tw(Lmax);
+  std::vector<cx<double>> tw64(Lmax);
+  for (int i = 0; i < Lmax; ++i) {
+    const double a = -2.0 * M_PI * (double)i / (double)Lmax;
+    tw64[i].x = std::cos(a);
+    tw64[i].y = std::sin(a);
+    tw[i].x = (T)tw64[i].x;
+    tw[i].y = (T)tw64[i].y;
+  }
+  if ((rc = upload(P, &P->tw, tw))) return rc;
+  if ((rc = upload(P, &P->tw64, tw64))) return rc;
+  const int n[3] = {P->nx, P->ny, P->nz};
+  const double c[3] = {P->cxx, P->cyy, P->czz};
+  for (int a = 0; a < 3; ++a) {
+    std::vector<cx<T>> d(n[a]);
+    std::vector<T> l(n[a]);
+    for (int k = 0; k < n[a]; ++k) {
+      const double ang = -M_PI * k / (2.0 * n[a]);
+      d[k].x = (T)std::cos(ang);
+      d[k].y = (T)std::sin(ang);
+      const double sn = std::sin(M_PI * k / (2.0 * n[a]));
+      l[k] = (T)(4.0 * c[a] * sn * sn);
+    }
+    if ((rc = upload(P, &P->dtw[a], d))) return rc;
+    if ((rc = upload(P, &P->lam[a], l))) return rc;
+  }
+  return SGSPM_OK;
+}
+
+template <typename T> int alloc_workspace(sgspm_plan_s* P) {
+  int rc;
+  if ((rc = dalloc(P, &P->fld, (size_t)NF * P->N * sizeof(T)))) return rc;
+  if ((rc = dalloc(P, &P->heat, (size_t)3 * P->N * sizeof(T)))) return rc;
+  if (P->stray) {
+    const long xl = (long)P->nz * P->ny * P->Kxp;
+    const long yl = (long)P->nz * P->Py * P->Kxp;
+    if ((rc = dalloc(P, &P->xlev, 3 * xl * sizeof(cx<T>)))) return rc;
+    if (P->has_mid) {
+      if ((rc = dalloc(P, &P->ylev, 3 * yl * sizeof(cx<T>)))) return rc;
+      if ((rc = dalloc(P, &P->yout, 3 * yl * sizeof(cx<T>)))) return rc;
+    } else {
+      if ((rc = dalloc(P, &P->yout, 3 * xl * sizeof(cx<T>)))) return rc;
+    }
+    if ((rc = dalloc(P, &P->tens, (size_t)6 * P->Hz * P->Hy * P->Kx * sizeof(T)))) return rc;
+  }
+  P->nred = (int)std::min<long>(1024, (P->N + NT - 1) / NT);
+  if ((rc = dalloc(P, (void**)&P->partials, (size_t)P->nred * 4 * sizeof(double)))) return rc;
+  if ((rc = dalloc(P, (void**)&P->eout, 8 * sizeof(double)))) return rc;
+  if ((rc = dalloc(P, (void**)&P->flag, sizeof(int)))) return rc;
+  rc = hip_check(hipMemsetAsync(P->flag, 0, sizeof(int), P->s), "flag clear");
+  if (rc) return rc;
+  return make_tables<T>(P);
+}
+
+template <typename T> int dispatch_step(sgspm_plan_s* P, void* m, double alpha, const double he[3], const void* src) {
+  Eng<T> e(*P);
+  e.step((T*)m, alpha, he, (const T*)src);
+  return hip_check(hipGetLastError(), "sgspm_step launch");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int sgspm_validate(const sgspm_params* p) { return validate(p); }
+
+int sgspm_reduced_constants(const sgspm_params* p, double out[5]) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!out) return fail(SGSPM_EINVAL, "out is NULL");
+  reduce(p, out);
+  return SGSPM_OK;
+}
+
+const char* sgspm_last_error(void) { return g_err.c_str(); }
+
+int sgspm_plan(const sgspm_params* p, void* hip_stream, sgspm_plan_t* out) {
+  if (!out) return fail(SGSPM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  sgspm_plan_s* P = new sgspm_plan_s();
+  P->prm = *p;
+  P->s = (hipStream_t)hip_stream;
+  P->fp64 = p->precision == SGSPM_FP64;
+  P->nx = p->nx;
+  P->ny = p->ny;
+  P->nz = p->nz;
+  P->N = (long)p->nx * p->ny * p->nz;
+  P->Px = p->nx > 1 ? 2 * p->nx : 1;
+  P->Py = p->ny > 1 ? 2 * p->ny : 1;
+  P->Pz = p->nz > 1 ? 2 * p->nz : 1;
+  P->Kx = P->Px / 2 + 1;
+  P->Kxp = (P->Kx + 15) / 16 * 16;
+  P->Hy = P->Py / 2 + 1;
+  P->Hz = P->Pz / 2 + 1;
+  P->stray = p->terms & SGSPM_TERM_STRAY;
+  P->zeeman = p->terms & SGSPM_TERM_ZEEMAN;
+  P->has_mid = p->nz > 1 && p->ny > 1;
+  double red[5];
+  reduce(p, red);
+  P->eps = red[0];
+  P->Q = red[1];
+  P->dt = red[2];
+  P->fscale = red[3];
+  P->escale = red[4];
+  P->cxx = p->nx > 1 ? P->eps / (p->dx * p->dx) : 0.0;
+  P->cyy = p->ny > 1 ? P->eps / (p->dy * p->dy) : 0.0;
+  P->czz = p->nz > 1 ? P->eps / (p->dz * p->dz) : 0.0;
+  P->lgTw = std::max(2, ilog2(std::max(std::max(P->Px, P->Py), P->Pz)));
+  rc = P->fp64 ? alloc_workspace<double>(P) : alloc_workspace<float>(P);
+  if (!rc && P->stray) rc = build_tensor(P);
+  if (!rc) rc = hip_check(hipStreamSynchronize(P->s), "plan sync");
+  if (rc) {
+    std::string keep = g_err;
+    sgspm_destroy(P);
+    g_err = keep;
+    return rc;
+  }
+  *out = P;
+  return SGSPM_OK;
+}
+
+int sgspm_step(sgspm_plan_t P, void* m, double alpha, const double h_e[3], const void* src) {
+  if (!P || !m || !h_e) return fail(SGSPM_EINVAL, "NULL argument");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SGSPM_EINVAL, "alpha must be >= 0 and finite");
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(h_e[c])) return fail(SGSPM_EINVAL, "h_e must be finite");
+  return P->fp64 ? dispatch_step<double>(P, m, alpha, h_e, src) : dispatch_step<float>(P, m, alpha, h_e, src);
+}
+
+int sgspm_stray(sgspm_plan_t P, const void* m, void* hs_out) {
+  if (!P || !m || !hs_out) return fail(SGSPM_EINVAL, "NULL argument");
+  if (!P->stray) {
+    const size_t bytes = 3 * P->N * (P->fp64 ? 8 : 4);
+    return hip_check(hipMemsetAsync(hs_out, 0, bytes, P->s), "stray zero");
+  }
+  if (P->fp64) Eng<double>(*P).stray_to((const double*)m, (double*)hs_out);
+  else Eng<float>(*P).stray_to((const float*)m, (float*)hs_out);
+  return hip_check(hipGetLastError(), "sgspm_stray launch");
+}
+
+int sgspm_field(sgspm_plan_t P, const void* m, const double h_e[3], void* h_out) {
+  if (!P || !m || !h_e || !h_out) return fail(SGSPM_EINVAL, "NULL argument");
+  double he[3];
+  for (int c = 0; c < 3; ++c) he[c] = P->zeeman ? h_e[c] * P->fscale : 0.0;
+  const bool ex = P->eps != 0.0;
+  if (P->fp64) {
+    Eng<double> e(*P);
+    double* hs = P->stray ? e.f[F_HS0] : nullptr;
+    if (hs) e.stray_to((const double*)m, hs);
+    launch_field_assemble<double>((const double*)m, hs, (double*)h_out, P->nx, P->ny, P->nz,
+                                  ex ? 1.0 / (P->prm.dx * P->prm.dx) : 0.0, ex ? 1.0 / (P->prm.dy * P->prm.dy) : 0.0,
+                                  ex ? 1.0 / (P->prm.dz * P->prm.dz) : 0.0, P->eps, P->Q, he, P->s);
+  } else {
+    Eng<float> e(*P);
+    float* hs = P->stray ? e.f[F_HS0] : nullptr;
+    if (hs) e.stray_to((const float*)m, hs);
+    launch_field_assemble<float>((const float*)m, hs, (float*)h_out, P->nx, P->ny, P->nz,
+                                 ex ? 1.0 / (P->prm.dx * P->prm.dx) : 0.0, ex ? 1.0 / (P->prm.dy * P->prm.dy) : 0.0,
+                                 ex ? 1.0 / (P->prm.dz * P->prm.dz) : 0.0, P->eps, P->Q, he, P->s);
+  }
+  return hip_check(hipGetLastError(), "sgspm_field launch");
+}
+
+int sgspm_heat_solve(sgspm_plan_t P, const void* r, double s, void* g) {
+  if (!P || !r || !g) return fail(SGSPM_EINVAL, "NULL argument");
+  if (!(s >= 0.0) || !std::isfinite(s)) return fail(SGSPM_EINVAL, "s must be >= 0 and finite");
+  if (P->fp64) Eng<double>(*P).heat_solve((const double*)r, s, (double*)g);
+  else Eng<float>(*P).heat_solve((const float*)r, (float)s, (float*)g);
+  return hip_check(hipGetLastError(), "sgspm_heat_solve launch");
+}
+
+int sgspm_energy(sgspm_plan_t P, const void* m, const double h_e[3], double e_out[5]) {
+  if (!P || !m || !h_e || !e_out) return fail(SGSPM_EINVAL, "NULL argument");
+  double he[3];
+  for (int c = 0; c < 3; ++c) he[c] = P->zeeman ? h_e[c] * P->fscale : 0.0;
+  const double cx_ = P->nx > 1 ? 1.0 / (P->prm.dx * P->prm.dx) : 0.0;
+  const double cy_ = P->ny > 1 ? 1.0 / (P->prm.dy * P->prm.dy) : 0.0;
+  const double cz_ = P->nz > 1 ? 1.0 / (P->prm.dz * P->prm.dz) : 0.0;
+  if (P->fp64) {
+    Eng<double> e(*P);
+    double* hs = P->stray ? e.f[F_HS0] : nullptr;
+    if (hs) e.stray_to((const double*)m, hs);
+    launch_energy<double>((const double*)m, hs, P->nx, P->ny, P->nz, cx_, cy_, cz_, he, P->partials, P->nred, P->eout,
+                          P->s);
+  } else {
+    Eng<float> e(*P);
+    float* hs = P->stray ? e.f[F_HS0] : nullptr;
+    if (hs) e.stray_to((const float*)m, hs);
+    launch_energy<float>((const float*)m, hs, P->nx, P->ny, P->nz, cx_, cy_, cz_, he, P->partials, P->nred, P->eout,
+                         P->s);
+  }
+  int rc = hip_check(hipGetLastError(), "sgspm_energy launch");
+  if (rc) return rc;
+  double acc[4];
+  rc = hip_check(hipMemcpyAsync(acc, P->eout, sizeof(acc), hipMemcpyDeviceToHost, P->s), "energy copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(P->s), "energy sync");
+  if (rc) return rc;
+  const double V = P->prm.dx * P->prm.dy * P->prm.dz;
+  const double es = P->escale;
+  const double ex = 0.5 * P->eps * V * acc[0];
+  const double an = 0.5 * P->Q * V * acc[1];
+  const double st = -0.5 * V * acc[2];
+  const double ze = -V * acc[3];
+  e_out[1] = ex * es;
+  e_out[2] = an * es;
+  e_out[3] = st * es;
+  e_out[4] = ze * es;
+  e_out[0] = (ex + an + st + ze) * es;
+  return SGSPM_OK;
+}
+
+int sgspm_adjoint_step(sgspm_plan_t P, const void* m_n, double alpha, const double h_e[3], void* lam,
+                       double* grad_dev) {
+  if (!P || !m_n || !h_e || !lam || !grad_dev) return fail(SGSPM_EINVAL, "NULL argument");
+  (void)alpha;
+  return fail(SGSPM_EUNSUPPORTED, "adjoint step not built yet");
+}
+
+int sgspm_timing(sgspm_plan_t P, int enable) {
+  if (!P) return fail(SGSPM_EINVAL, "NULL plan");
+  P->timing = enable != 0;
+  P->recs.clear();
+  P->evnext = 0;
+  return SGSPM_OK;
+}
+
+int sgspm_timing_read(sgspm_plan_t P, double ms[SGSPM_KC_COUNT], double bytes[SGSPM_KC_COUNT],
+                      int64_t launches[SGSPM_KC_COUNT]) {
+  if (!P || !ms || !bytes || !launches) return fail(SGSPM_EINVAL, "NULL argument");
+  int rc = hip_check(hipStreamSynchronize(P->s), "timing sync");
+  if (rc) return rc;
+  for (int k = 0; k < SGSPM_KC_COUNT; ++k) {
+    ms[k] = 0.0;
+    bytes[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (const auto& r : P->recs) {
+    float t = 0.f;
+    rc = hip_check(hipEventElapsedTime(&t, r.a, r.b), "event elapsed");
+    if (rc) return rc;
+    ms[r.cls] += t;
+    bytes[r.cls] += r.bytes;
+    launches[r.cls] += 1;
+  }
+  P->recs.clear();
+  P->evnext = 0;
+  return SGSPM_OK;
+}
+
+int sgspm_check(sgspm_plan_t P) {
+  if (!P) return fail(SGSPM_EINVAL, "NULL plan");
+  int h = 0;
+  int rc = hip_check(hipMemcpyAsync(&h, P->flag, sizeof(int), hipMemcpyDeviceToHost, P->s), "flag copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(P->s), "flag sync");
+  if (rc) return rc;
+  if (h) {
+    rc = hip_check(hipMemsetAsync(P->flag, 0, sizeof(int), P->s), "flag clear");
+    if (rc) return rc;
+    return fail(SGSPM_ENUMERIC, "a projection met |m***| = 0 or a non-finite value");
+  }
+  return SGSPM_OK;
+}
+
+int sgspm_destroy(sgspm_plan_t P) {
+  if (!P) return SGSPM_OK;
+  if (P->s || !P->allocs.empty()) (void)hipStreamSynchronize(P->s);
+  for (void* p : P->allocs) (void)hipFree(p);
+  for (hipEvent_t e : P->evpool) (void)hipEventDestroy(e);
+  delete P;
+  return SGSPM_OK;
+}
+
+}  // extern "C"

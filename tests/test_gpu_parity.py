@@ -1,0 +1,289 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle,
+element by element, on the same seeded inputs.
+
+Tolerances: FP64 plans agree with the oracle to rounding (1e-12 relative on
+the linear operators; the stray field to 1e-10, bounded by the FP64 Newell
+cancellation of ~1e-12 per tensor entry); FP32 plans to a few FP32 ulps scaled
+by the transform depth (5e-6 relative on linear operators), and to 1e-5 max-abs
+in m after 1000 steps of the 128x64 film (the stated target).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import demag, manufactured as mf, operators, scheme
+
+from helpers import (gpu_plan_reduced, gpu_plan_si, oracle_field_si, oracle_problem_si, rounded_like,
+                     to_dev)
+
+pytestmark = pytest.mark.gpu
+
+ALL = ("exchange", "aniso", "stray", "zeeman")
+CELL = (4e-9, 4e-9, 4e-9)
+DT = 0.1e-12
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_28113_amd as sg
+    return torch, sg
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    import sys
+    sys.stderr.write(f"\n[gpu-case] {request.node.nodeid}\n")
+    sys.stderr.flush()
+
+
+HEAT_SHAPES = [(32, 32, 1), (128, 64, 1), (16, 8, 4), (8, 1, 1), (1, 1, 1), (1, 16, 1), (4, 1, 8),
+               (64, 32, 8), (2, 2, 2), (512, 32, 4), (1024, 2, 1), (256, 256, 32)]
+
+
+@pytest.mark.parametrize("n", HEAT_SHAPES, ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_heat_solve(env, n, prec):
+    torch, sg = env
+    rng = np.random.default_rng(100)
+    shape = (n[2], n[1], n[0])
+    h = tuple(1.0 / k if k > 1 else 1.0 for k in n)
+    plan = gpu_plan_reduced(sg, n, h, 0.01, 1.0, 0.0, ("exchange",), prec)
+    r = rng.normal(size=shape)
+    for s in (1.0, 0.37, 0.0):
+        g = plan.heat_solve(to_dev(torch, r, prec), s).cpu().numpy()
+        ref = operators.heat_solve(rounded_like(r, prec), s * 1.0 * 0.01, h)
+        tol = 1e-12 if prec == 1 else 5e-6
+        assert np.abs(g - ref).max() <= tol * np.abs(r).max(), (n, s)
+
+
+STRAY_SHAPES = [(8, 4, 2), (16, 8, 1), (4, 4, 4), (32, 1, 1), (1, 1, 1), (2, 2, 2), (1, 8, 4), (4, 1, 4),
+                (128, 64, 1), (64, 32, 8), (512, 32, 4), (128, 128, 1)]
+
+
+@pytest.mark.parametrize("n", STRAY_SHAPES, ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_stray_field(env, n, prec):
+    torch, sg = env
+    shape = (n[2], n[1], n[0])
+    m = workloads.random_unit(shape, 101)
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, prec)
+    hs = plan.stray(to_dev(torch, m, prec)).cpu().numpy()
+    ref = demag.stray_field(rounded_like(m, prec), demag.kernel_spectra(shape, CELL))
+    tol = 1e-10 if prec == 1 else 2e-6
+    assert np.abs(hs - ref).max() <= tol
+
+
+@pytest.mark.parametrize("n", [(16, 8, 4), (32, 32, 1), (64, 1, 1), (8, 8, 8)], ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_effective_field_and_energy(env, n, prec):
+    torch, sg = env
+    shape = (n[2], n[1], n[0])
+    m = workloads.random_unit(shape, 102)
+    B = (3e-3, -1e-3, 2e-3)
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, prec)
+    P = oracle_problem_si(n, CELL, DT, ALL)
+    he = oracle_field_si(B, ALL)
+    md = to_dev(torch, m, prec)
+    h = plan.field(md, B).cpu().numpy()
+    m64 = rounded_like(m, prec)
+    ref = scheme.effective_field(P, m64, he)
+    scale = np.abs(ref).max()
+    assert np.abs(h - ref).max() <= (1e-11 if prec == 1 else 3e-6) * scale
+    e = plan.energy(md, B)
+    eref = scheme.energies(P, m64, he)
+    mu0ms2 = 4e-7 * np.pi * workloads.MS_PY ** 2
+    for k in eref:
+        tol = (1e-11 if prec == 1 else 1e-6) * (abs(eref["total"]) + abs(eref[k]) + 1e-30)
+        assert abs(e[k] / mu0ms2 - eref[k]) <= tol, k
+
+
+def _run_gpu(plan, torch, m0, alphas, fields, prec, src=None):
+    m = to_dev(torch, m0, prec)
+    for n in range(len(fields)):
+        plan.step(m, alphas[n] if np.ndim(alphas) else alphas, fields[n],
+                  None if src is None else to_dev(torch, src[n], prec))
+    torch.cuda.synchronize()
+    plan.check()
+    return m.cpu().numpy()
+
+
+def _run_oracle(P, m0, alpha, fields, method="sgspm", src=None):
+    step = scheme.sgspm_step if method == "sgspm" else scheme.gspm_step
+    m = np.asarray(m0, np.float64)
+    for n in range(len(fields)):
+        m = step(P, m, alpha, fields[n], src=None if src is None else src[n])
+    return m
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_c1_manufactured_film(env, prec):
+    """32x32 exchange-only film with the 2-D manufactured forcing, 200 steps."""
+    torch, sg = env
+    c = workloads.config("c1")
+    shape = c.shape
+    plan = gpu_plan_reduced(sg, c.n, c.h, c.dt, c.eps, 0.0, ("exchange",), prec)
+    m0 = workloads.initial_state(c)
+    src = [mf.forcing(shape, k * c.dt, 2, c.eps, c.alpha) for k in range(c.steps)]
+    fields = [(0.0, 0.0, 0.0)] * c.steps
+    got = _run_gpu(plan, torch, m0, c.alpha, fields, prec, src=src)
+    P = scheme.Problem(n=c.n, h=c.h, eps=c.eps, dt=c.dt)
+    src64 = [rounded_like(s, prec) for s in src]
+    ref = _run_oracle(P, rounded_like(m0, prec), c.alpha, fields, src=src64)
+    err = np.abs(got - ref).max()
+    print(f"c1 {'fp64' if prec else 'fp32'}: max|m - m_oracle| = {err:.3e}; "
+          f"max|m - m_exact| = {np.abs(got - mf.exact(shape, c.steps * c.dt, 2)).max():.3e}")
+    assert err <= (1e-11 if prec == 1 else 1e-5)
+
+
+@pytest.mark.parametrize("n", [(16, 8, 4), (32, 16, 1), (8, 1, 8), (16, 1, 1)], ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("method", ["sgspm", "gspm"])
+def test_full_step_fp64(env, n, method):
+    torch, sg = env
+    shape = (n[2], n[1], n[0])
+    m0 = workloads.random_unit(shape, 103)
+    B = [(5e-3, 1e-3, -2e-3)] * 10
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, 1, scheme_=0 if method == "sgspm" else 1)
+    got = _run_gpu(plan, torch, m0, 0.02, B, 1)
+    P = oracle_problem_si(n, CELL, DT, ALL)
+    ref = _run_oracle(P, m0, 0.02, [oracle_field_si(b, ALL) for b in B], method)
+    assert np.abs(got - ref).max() <= 1e-10
+
+
+@pytest.mark.parametrize("terms", [("exchange",), ("exchange", "aniso"), ("stray",), ("exchange", "zeeman"),
+                                   ("aniso", "stray", "zeeman")], ids=lambda t: "+".join(t))
+def test_term_subsets_fp64(env, terms):
+    torch, sg = env
+    n = (16, 8, 2)
+    shape = (n[2], n[1], n[0])
+    m0 = workloads.random_unit(shape, 104)
+    B = [(5e-3, 1e-3, -2e-3)] * 5
+    plan = gpu_plan_si(sg, n, CELL, DT, terms, 1)
+    got = _run_gpu(plan, torch, m0, 0.05, B, 1)
+    P = oracle_problem_si(n, CELL, DT, terms)
+    ref = _run_oracle(P, m0, 0.05, [oracle_field_si(b, terms) for b in B])
+    assert np.abs(got - ref).max() <= 1e-10
+
+
+def test_c2_film_fp64_random_start(env):
+    """128x64 permalloy-like film, all fields, 5 mT, alpha 0.01, from i.i.d. random unit vectors:
+    the FP64 library against the FP64 oracle.
+
+    This start is chaotic: two oracle runs whose m0 differ by 1e-7 drift apart to 5e-6 after
+    100 steps, 6e-5 after 200 and O(1) after 700.  The two FP64 implementations differ by
+    ~1e-12 per Newell-tensor entry (independent libm, cancellation), which that growth lifts to
+    ~1e-4 by step 1000; the test bounds the early steps and sanity-checks step 1000."""
+    torch, sg = env
+    c = workloads.config("c2")
+    m0 = workloads.initial_state(c)
+    B = workloads.field_schedule(c)
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 1)
+    P = oracle_problem_si(c.n, c.h, c.dt, ALL)
+    m = to_dev(torch, m0, 1)
+    ref = np.asarray(m0, np.float64)
+    done = 0
+    for k, tol in ((100, 2e-8), (200, 1e-7), (1000, 1e-2)):
+        for n in range(done, k):
+            plan.step(m, c.alpha, B[n])
+            ref = scheme.sgspm_step(P, ref, c.alpha, oracle_field_si(B[n], ALL))
+        done = k
+        err = np.abs(m.cpu().numpy() - ref).max()
+        print(f"c2 fp64 random start, step {k}: max|m - m_oracle| = {err:.3e}")
+        assert err <= tol, k
+
+
+def test_c2_film_fp32_random_start_early(env):
+    """FP32 on the chaotic c2 start: bounded while the trajectory sensitivity is moderate."""
+    torch, sg = env
+    c = workloads.config("c2")
+    m0 = workloads.initial_state(c)
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 0)
+    P = oracle_problem_si(c.n, c.h, c.dt, ALL)
+    he = oracle_field_si((5e-3, 0.0, 0.0), ALL)
+    m = to_dev(torch, m0, 0)
+    ref = rounded_like(m0, 0)
+    done = 0
+    for k, tol in ((1, 1e-6), (10, 1e-5), (100, 2e-4)):
+        for _ in range(k - done):
+            plan.step(m, c.alpha, (5e-3, 0.0, 0.0))
+            ref = scheme.sgspm_step(P, ref, c.alpha, he)
+        done = k
+        err = np.abs(m.cpu().numpy() - ref).max()
+        print(f"c2 fp32 random start, step {k}: max|m - m_oracle| = {err:.3e}")
+        assert err <= tol, k
+
+
+def test_c2_film_fp32_1000_steps_paper_start(env):
+    """128x64 film, all fields, 1000 steps from the paper's eq. (m0-1) state, a well-conditioned
+    trajectory (a 1e-7 perturbation stays below 4e-7): FP32 library within 1e-5 of the FP64 oracle."""
+    torch, sg = env
+    c = workloads.config("c2")
+    m0 = workloads.paper_ic(c.shape)
+    B = workloads.field_schedule(c)
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 0)
+    got = _run_gpu(plan, torch, m0, c.alpha, B, 0)
+    P = oracle_problem_si(c.n, c.h, c.dt, ALL)
+    ref = _run_oracle(P, rounded_like(m0, 0), c.alpha, [oracle_field_si(b, ALL) for b in B])
+    err = np.abs(got - ref).max()
+    e_gpu = plan.energy(to_dev(torch, got, 0), B[-1])["total"]
+    e_ref = scheme.energies(P, ref, oracle_field_si(B[-1], ALL))["total"] * 4e-7 * np.pi * workloads.MS_PY ** 2
+    print(f"c2 fp32 1000 steps (paper start): max|m - m_oracle| = {err:.3e}, "
+          f"relative energy error {abs(e_gpu - e_ref) / abs(e_ref):.3e}")
+    assert err <= 1e-5
+
+
+def test_c3_strip_fp64_20_steps(env):
+    torch, sg = env
+    c = workloads.config("c3")
+    m0 = workloads.initial_state(c)
+    B = [(10e-3, 0.0, 0.0)] * 20
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 1)
+    got = _run_gpu(plan, torch, m0, 1e-3, B, 1)
+    P = oracle_problem_si(c.n, c.h, c.dt, ALL)
+    ref = _run_oracle(P, m0, 1e-3, [oracle_field_si(b, ALL) for b in B])
+    assert np.abs(got - ref).max() <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_c5_block_one_step(env, prec):
+    """256x256x32 block, full fields, one step at full size (the benchmark launch shapes)."""
+    torch, sg = env
+    c = workloads.config("c5")
+    m0 = workloads.initial_state(c)
+    B = workloads.field_schedule(c, 1)
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, prec)
+    got = _run_gpu(plan, torch, m0, c.alpha, B, prec)
+    P = oracle_problem_si(c.n, c.h, c.dt, ALL)
+    ref = _run_oracle(P, rounded_like(m0, prec), c.alpha, [oracle_field_si(b, ALL) for b in B])
+    err = np.abs(got - ref).max()
+    print(f"c5 {'fp64' if prec else 'fp32'} one step: max|m - m_oracle| = {err:.3e}")
+    assert err <= (1e-10 if prec == 1 else 2e-6)
+
+
+def test_projection_flags_non_finite(env):
+    torch, sg = env
+    n = (8, 4, 1)
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, 0)
+    m = workloads.random_unit((1, 4, 8), 105)
+    m[:, 0, 2, 3] = np.nan
+    md = to_dev(torch, m, 0)
+    plan.step(md, 0.01, (0.0, 0.0, 0.0))
+    with pytest.raises(sg.SGSPMError) as e:
+        plan.check()
+    assert e.value.code == -5
+    plan.check()  # flag was cleared
+
+
+def test_bitwise_deterministic(env):
+    torch, sg = env
+    c = workloads.config("c3")
+    m0 = workloads.initial_state(c)
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 0)
+    a = _run_gpu(plan, torch, m0, 0.01, [(5e-3, 0, 0)] * 5, 0)
+    b = _run_gpu(plan, torch, m0, 0.01, [(5e-3, 0, 0)] * 5, 0)
+    assert np.array_equal(a, b)
+    e1 = plan.energy(to_dev(torch, a, 0), (5e-3, 0, 0))
+    e2 = plan.energy(to_dev(torch, a, 0), (5e-3, 0, 0))
+    assert e1 == e2

@@ -129,6 +129,15 @@ def neel_wall(shape, dx, width=20e-9, noise=1e-3, seed=3):
     return normalise(m)
 
 
+def paper_ic(shape):
+    """The paper's exchange-test state, eq. (m0-1): (cos(cos pi x) sin 0.01, sin(cos pi x) sin 0.01, cos 0.01),
+    x = (i + 1/2) / nx along the grid's x axis."""
+    nz, ny, nx = shape
+    x = (np.arange(nx) + 0.5) / nx
+    c = np.broadcast_to(np.cos(np.pi * x), tuple(shape))
+    return np.stack([np.cos(c) * np.sin(0.01), np.sin(c) * np.sin(0.01), np.full(tuple(shape), np.cos(0.01))])
+
+
 def c1_initial(shape, seed=1, noise=1e-3):
     """Exact manufactured solution at t = 0 (the constant e3) plus N(0, noise^2), renormalised."""
     rng = np.random.default_rng(seed)
