@@ -31,6 +31,8 @@ class SGSPMFunction(torch.autograd.Function):
         ctx.plan, ctx.he, ctx.alpha, ctx.K, ctx.ckpts = plan, he, a, K, ckpts
         ctx.h_e_dtype, ctx.h_e_device = h_e.dtype, h_e.device
         ctx.alpha_is_tensor = torch.is_tensor(alpha)
+        if ctx.alpha_is_tensor:
+            ctx.alpha_dtype, ctx.alpha_device = alpha.dtype, alpha.device
         return m
 
     @staticmethod
@@ -55,5 +57,5 @@ class SGSPMFunction(torch.autograd.Function):
                 dalpha += gstep[3]
         g_m0 = lam
         g_he = dhe.to(ctx.h_e_dtype).to(ctx.h_e_device)
-        g_alpha = dalpha.to(torch.float64) if ctx.alpha_is_tensor else None
+        g_alpha = dalpha.to(ctx.alpha_dtype).to(ctx.alpha_device) if ctx.alpha_is_tensor else None
         return g_m0, g_he, g_alpha, None, None

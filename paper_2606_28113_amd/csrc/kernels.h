@@ -25,11 +25,14 @@ template <typename T> struct RowFwd {
   int lgP;         // log2 of complex pencils per tile (2P rows)
   int lgTw;        // log2 length of the global twiddle table
   const cx<T>* tw;
-  // row value v = a[ch] * u + b * (hs + he[ch]); u may be null (0)
+  // row value v = a[ch] * u + b * (hs + he[ch]) + wc[ch] * w; u and w may be null (0)
   const T* u[3];
   T a[3];
   T b;
   T he[3];
+  const T* w[3];
+  T wc[3];
+  T* val_out[3];    // optional store of v (may alias u)
   // optional hs by complex-to-real transform (crop) of an x-level spectrum
   const cx<T>* xin[3];
   int lgLc;
@@ -108,7 +111,7 @@ template <typename T> struct ColFft {
 template <typename T> struct Conv {
   int lgL, n, lgP, ni;
   long sa, sb;
-  const cx<T>* S[3];
+  const cx<T>* S[3]; // null = component identically zero
   cx<T>* O[3];       // null = output not requested
   const T* tens;     // [6][Hc][Hb][ni]
   long tcs;
@@ -131,6 +134,33 @@ void launch_newell_fill(double* out, int comp, int nx, int ny, int nz, int Px, i
 template <typename T>
 void launch_tensor_pack(const cx<double>* spec, T* out, int Hz, int Hy, int Kx, int Kxp, int Py, double scale,
                         hipStream_t s);
+
+// Pointwise product terms: for each term t in order,
+//   out_t = (acc_t ? out_t : 0) + c0_t * x0_t * y0_t + c1_t * x1_t * y1_t
+// (a null y means 1, a null x drops the product).
+template <typename T> struct PwTerm {
+  T* out;
+  int acc;
+  double c0, c1;
+  const T *x0, *y0, *x1, *y1;
+};
+constexpr int PW_MAX = 6;
+template <typename T> void launch_pw(const PwTerm<T>* terms, int nterms, long N, hipStream_t s);
+
+// Adjoint of the projection: lc_i = (lam_i - (lam . u) u_i) / nrm.
+template <typename T> void launch_adj_project(const T* lam, const T* u, const T* nrm, T* lc, long N, hipStream_t s);
+
+// Deterministic weighted sums: grad[slot_k] += w_k * sum(x_k) (FP64 accumulation).
+template <typename T>
+void launch_wsum(const T* const x[4], const double w[4], const int slot[4], int nterms, long N, double* partials,
+                 int nblocks, double* grad, hipStream_t s);
+
+// Damping-stage sums of the adjoint: grad[3] += dt * sum lw . (eps Lap_h c + F),
+// grad[0..2] += wdh * sum lw_i, with c = nrm u, F_i = -Q_i uF_i + hsF_i + he_i.
+template <typename T>
+void launch_adj_damp(const T* lw, const T* u, const T* nrm, const T* const uF[3], const T* hsF, int nx, int ny,
+                     int nz, double ecx, double ecy, double ecz, double Q, const double he[3], double dt, double wdh,
+                     double* partials, int nblocks, double* grad, hipStream_t s);
 
 // Pointwise and reduction kernels.
 template <typename T>

@@ -121,8 +121,10 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
 
   T val[NV];
   const T* u = A.u[ch];
+  const T* w = A.w[ch];
   T* hso = A.hs_out[ch];
-  const T ac = A.a[ch], hec = A.he[ch], bc = A.b;
+  T* vo = A.val_out[ch];
+  const T ac = A.a[ch], hec = A.he[ch], bc = A.b, wcc = A.wc[ch];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const int e = threadIdx.x + i * NT;
@@ -135,6 +137,8 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
         const T uu = u ? u[idx] : (T)0;
         if (hso) hso[idx] = hs[i];
         val[i] = ac * uu + bc * (hs[i] + hec);
+        if (w) val[i] += wcc * w[idx];
+        if (vo) vo[idx] = val[i];
       }
     }
   }
@@ -446,11 +450,11 @@ __global__ __launch_bounds__(NT) void k_conv(const Conv<T> A) {
   const long boff = (long)b * A.sb;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const cx<T>* S = A.S[c] + boff;
+    const cx<T>* S = A.S[c];
     for (int t = threadIdx.x; t < (P << A.lgL); t += NT) {
       const int j = t >> A.lgP, q = t & (P - 1);
       const int i = i0 + q;
-      buf[j * es + c * P + q] = (j < A.n && i < A.ni) ? S[(long)j * A.sa + i] : zero<T>();
+      buf[j * es + c * P + q] = (S && j < A.n && i < A.ni) ? S[boff + (long)j * A.sa + i] : zero<T>();
     }
   }
   __syncthreads();
@@ -704,6 +708,124 @@ __global__ __launch_bounds__(NT) void k_energy_final(const double* partials, int
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint helpers
+template <typename T> struct PwPack {
+  PwTerm<T> t[PW_MAX];
+  int n;
+};
+
+template <typename T> __global__ void k_pw(const PwPack<T> A, long N) {
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < N; idx += (long)gridDim.x * blockDim.x) {
+    for (int k = 0; k < A.n; ++k) {
+      const PwTerm<T>& t = A.t[k];
+      double v = t.acc ? (double)t.out[idx] : 0.0;
+      if (t.x0) v += t.c0 * (double)t.x0[idx] * (t.y0 ? (double)t.y0[idx] : 1.0);
+      if (t.x1) v += t.c1 * (double)t.x1[idx] * (t.y1 ? (double)t.y1[idx] : 1.0);
+      t.out[idx] = (T)v;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_adj_project(const T* lam, const T* u, const T* nrm, T* lc, long N) {
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < N; idx += (long)gridDim.x * blockDim.x) {
+    const T l0 = lam[idx], l1 = lam[N + idx], l2 = lam[2 * N + idx];
+    const T u0 = u[idx], u1 = u[N + idx], u2 = u[2 * N + idx];
+    const T d = l0 * u0 + l1 * u1 + l2 * u2;
+    const T r = (T)1 / nrm[idx];
+    lc[idx] = (l0 - d * u0) * r;
+    lc[N + idx] = (l1 - d * u1) * r;
+    lc[2 * N + idx] = (l2 - d * u2) * r;
+  }
+}
+
+__device__ __forceinline__ void block_partials4(double acc[4], double* partials) {
+  __shared__ double red[4][NT / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double s = wave_sum(acc[k]);
+    if (lane == 0) red[k][wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+    for (int w = 0; w < NT / 64; ++w) s += red[threadIdx.x][w];
+    partials[(long)blockIdx.x * 4 + threadIdx.x] = s;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_wsum(const T* x0, const T* x1, const T* x2, const T* x3, int nterms, long N,
+                                              double* partials) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const T* xs[4] = {x0, x1, x2, x3};
+  for (long idx = blockIdx.x * (long)NT + threadIdx.x; idx < N; idx += (long)gridDim.x * NT) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k < nterms) acc[k] += (double)xs[k][idx];
+  }
+  block_partials4(acc, partials);
+}
+
+// Adds the weighted totals of the block partials into grad (one thread: fixed order).
+__global__ void k_partials_to_grad(const double* partials, int nblocks, int nterms, double w0, double w1, double w2,
+                                   double w3, int s0, int s1, int s2, int s3, double* grad) {
+  __shared__ double red[4][NT];
+  for (int k = 0; k < 4; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += NT) s += partials[(long)b * 4 + k];
+    red[k][threadIdx.x] = s;
+  }
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double ws[4] = {w0, w1, w2, w3};
+    const int ss[4] = {s0, s1, s2, s3};
+    for (int k = 0; k < nterms; ++k) grad[ss[k]] += ws[k] * red[k][0];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_adj_damp(const T* lw, const T* u, const T* nrm, const T* uF0, const T* uF1,
+                                                  const T* uF2, const T* hsF, int nx, int ny, int nz, double ecx,
+                                                  double ecy, double ecz, double Q, double he0, double he1, double he2,
+                                                  double* partials) {
+  const long N = (long)nx * ny * nz;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const T* uF[3] = {uF0, uF1, uF2};
+  const double he[3] = {he0, he1, he2};
+  for (long idx = blockIdx.x * (long)NT + threadIdx.x; idx < N; idx += (long)gridDim.x * NT) {
+    const int x = (int)(idx % nx);
+    const int y = (int)((idx / nx) % ny);
+    const int z = (int)(idx / ((long)nx * ny));
+    const long xm = x > 0 ? idx - 1 : idx, xp = x < nx - 1 ? idx + 1 : idx;
+    const long ym = y > 0 ? idx - nx : idx, yp = y < ny - 1 ? idx + nx : idx;
+    const long zm = z > 0 ? idx - (long)nx * ny : idx, zp = z < nz - 1 ? idx + (long)nx * ny : idx;
+    double t = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const T* uc = u + c * N;
+      const double cc = (double)nrm[idx] * uc[idx];
+      double lap = 0.0;
+      if (nx > 1) lap += ecx * ((double)nrm[xm] * uc[xm] + (double)nrm[xp] * uc[xp] - 2.0 * cc);
+      if (ny > 1) lap += ecy * ((double)nrm[ym] * uc[ym] + (double)nrm[yp] * uc[yp] - 2.0 * cc);
+      if (nz > 1) lap += ecz * ((double)nrm[zm] * uc[zm] + (double)nrm[zp] * uc[zp] - 2.0 * cc);
+      double F = he[c] + (hsF ? (double)hsF[c * N + idx] : 0.0);
+      if (c > 0) F -= Q * (double)uF[c][idx];
+      const double l = lw[c * N + idx];
+      t += l * (lap + F);
+      acc[c] += l;
+    }
+    acc[3] += t;
+  }
+  block_partials4(acc, partials);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
@@ -771,6 +893,38 @@ void launch_energy(const T* m, const T* hs, int nx, int ny, int nz, double cxx, 
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(NT), 0, s, partials, nblocks, out);
 }
 
+template <typename T> void launch_pw(const PwTerm<T>* terms, int nterms, long N, hipStream_t s) {
+  PwPack<T> A{};
+  for (int k = 0; k < nterms; ++k) A.t[k] = terms[k];
+  A.n = nterms;
+  const int blocks = (int)std::min<long>((N + NT - 1) / NT, 8192);
+  hipLaunchKernelGGL(k_pw<T>, dim3(blocks), dim3(NT), 0, s, A, N);
+}
+
+template <typename T> void launch_adj_project(const T* lam, const T* u, const T* nrm, T* lc, long N, hipStream_t s) {
+  const int blocks = (int)std::min<long>((N + NT - 1) / NT, 8192);
+  hipLaunchKernelGGL(k_adj_project<T>, dim3(blocks), dim3(NT), 0, s, lam, u, nrm, lc, N);
+}
+
+template <typename T>
+void launch_wsum(const T* const x[4], const double w[4], const int slot[4], int nterms, long N, double* partials,
+                 int nblocks, double* grad, hipStream_t s) {
+  hipLaunchKernelGGL(k_wsum<T>, dim3(nblocks), dim3(NT), 0, s, x[0], nterms > 1 ? x[1] : nullptr,
+                     nterms > 2 ? x[2] : nullptr, nterms > 3 ? x[3] : nullptr, nterms, N, partials);
+  hipLaunchKernelGGL(k_partials_to_grad, dim3(1), dim3(NT), 0, s, partials, nblocks, nterms, w[0], w[1], w[2], w[3],
+                     slot[0], slot[1], slot[2], slot[3], grad);
+}
+
+template <typename T>
+void launch_adj_damp(const T* lw, const T* u, const T* nrm, const T* const uF[3], const T* hsF, int nx, int ny,
+                     int nz, double ecx, double ecy, double ecz, double Q, const double he[3], double dt, double wdh,
+                     double* partials, int nblocks, double* grad, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_damp<T>, dim3(nblocks), dim3(NT), 0, s, lw, u, nrm, uF[0], uF[1], uF[2], hsF, nx, ny, nz,
+                     ecx, ecy, ecz, Q, he[0], he[1], he[2], partials);
+  hipLaunchKernelGGL(k_partials_to_grad, dim3(1), dim3(NT), 0, s, partials, nblocks, 4, wdh, wdh, wdh, dt, 0, 1, 2, 3,
+                     grad);
+}
+
 #define SGSPM_INSTANTIATE(T)                                                                                          \
   template void launch_row_fwd<T>(const RowFwd<T>&, int, hipStream_t);                                              \
   template void launch_row_inv<T>(const RowInv<T>&, hipStream_t);                                                   \
@@ -781,7 +935,14 @@ void launch_energy(const T* m, const T* hs, int nx, int ny, int nz, double cxx, 
   template void launch_field_assemble<T>(const T*, const T*, T*, int, int, int, double, double, double, double,    \
                                          double, const double*, hipStream_t);                                       \
   template void launch_energy<T>(const T*, const T*, int, int, int, double, double, double, const double*, double*, \
-                                 int, double*, hipStream_t);
+                                 int, double*, hipStream_t);                                                       \
+  template void launch_pw<T>(const PwTerm<T>*, int, long, hipStream_t);                                             \
+  template void launch_adj_project<T>(const T*, const T*, const T*, T*, long, hipStream_t);                         \
+  template void launch_wsum<T>(const T* const*, const double*, const int*, int, long, double*, int, double*,        \
+                               hipStream_t);                                                                        \
+  template void launch_adj_damp<T>(const T*, const T*, const T*, const T* const*, const T*, int, int, int, double,  \
+                                   double, double, double, const double*, double, double, double*, int, double*,   \
+                                   hipStream_t);
 
 SGSPM_INSTANTIATE(float)
 SGSPM_INSTANTIATE(double)

@@ -120,6 +120,7 @@ struct sgspm_plan_s {
   double* partials = nullptr;
   double* eout = nullptr;
   int* flag = nullptr;
+  void* adj = nullptr;     // adjoint workspace (16 fields), allocated on first use
   int nred = 0;
   std::vector<void*> allocs;
   // optional per-kernel-class timing (HIP events around every launch)
@@ -232,18 +233,30 @@ template <typename T> struct Eng {
   const cx<T>* c2r_src(int a) { return P.has_mid ? xlev[a] : yout[a]; }
 
   // ---- row kernels
-  void row_fwd(int nch, const T* const u[3], const T a[3], T b, const T he[3], bool with_hs, T* const hs_out[3],
-               T* const dct_out[3], cx<T>* const xout[3]) {
+  struct RowIO {
+    const T* u[3] = {nullptr, nullptr, nullptr};
+    T a[3] = {1, 1, 1};
+    T b = 0;
+    T he[3] = {0, 0, 0};
+    bool with_hs = false;
+    const T* w[3] = {nullptr, nullptr, nullptr};
+    T wc[3] = {0, 0, 0};
+    T* val_out[3] = {nullptr, nullptr, nullptr};
+    T* hs_out[3] = {nullptr, nullptr, nullptr};
+    T* dct_out[3] = {nullptr, nullptr, nullptr};
+    cx<T>* xout[3] = {nullptr, nullptr, nullptr};
+  };
+  void row_fwd(int nch, const RowIO& io) {
     RowFwd<T> A{};
     A.nrows = P.ny * P.nz;
     A.lgN = ilog2(P.nx);
     A.lgLc = ilog2(P.Px);
     A.lgLr = ilog2(P.Px);
     int lgL = 0;
-    bool any_x = with_hs;
+    bool any_x = io.with_hs;
     for (int c = 0; c < nch; ++c) {
-      if (xout && xout[c]) any_x = true;
-      if (dct_out && dct_out[c]) lgL = std::max(lgL, A.lgN);
+      if (io.xout[c]) any_x = true;
+      if (io.dct_out[c]) lgL = std::max(lgL, A.lgN);
     }
     if (any_x) lgL = std::max(lgL, A.lgLr);
     A.lgLmax = lgL;
@@ -251,27 +264,31 @@ template <typename T> struct Eng {
     A.lgTw = P.lgTw;
     A.tw = tw;
     A.dtw = dtw[0];
-    A.b = b;
+    A.b = io.b;
     A.xin_pitch = P.Kxp;
     A.xout_pitch = P.Kxp;
     for (int c = 0; c < nch; ++c) {
-      A.u[c] = u ? u[c] : nullptr;
-      A.a[c] = a ? a[c] : (T)1;
-      A.he[c] = he ? he[c] : (T)0;
-      A.xin[c] = with_hs ? c2r_src_for_[c] : nullptr;
-      A.hs_out[c] = hs_out ? hs_out[c] : nullptr;
-      A.dct_out[c] = dct_out ? dct_out[c] : nullptr;
-      A.xout[c] = xout ? xout[c] : nullptr;
+      A.u[c] = io.u[c];
+      A.a[c] = io.a[c];
+      A.he[c] = io.he[c];
+      A.w[c] = io.w[c];
+      A.wc[c] = io.wc[c];
+      A.val_out[c] = io.val_out[c];
+      A.xin[c] = io.with_hs ? c2r_src_for_[c] : nullptr;
+      A.hs_out[c] = io.hs_out[c];
+      A.dct_out[c] = io.dct_out[c];
+      A.xout[c] = io.xout[c];
     }
     double by = 0;
-    const double rows = A.nrows, cpx = (double)A.nrows * P.Kx * 2 * TS;
+    const double cpx = (double)A.nrows * P.Kx * 2 * TS;
     for (int c = 0; c < nch; ++c)
-      by += (A.u[c] ? P.N * TS : 0) + (A.xin[c] ? cpx : 0) + (A.hs_out[c] ? P.N * TS : 0) +
-            (A.dct_out[c] ? P.N * TS : 0) + (A.xout[c] ? cpx : 0);
-    (void)rows;
+      by += (A.u[c] ? P.N * TS : 0) + (A.w[c] ? P.N * TS : 0) + (A.xin[c] ? cpx : 0) +
+            (A.hs_out[c] ? P.N * TS : 0) + (A.val_out[c] ? P.N * TS : 0) + (A.dct_out[c] ? P.N * TS : 0) +
+            (A.xout[c] ? cpx : 0);
     timed(SGSPM_KC_ROW_FWD, by, [&] { launch_row_fwd<T>(A, nch, s); });
   }
   const cx<T>* c2r_src_for_[3] = {nullptr, nullptr, nullptr};
+  bool tape = false;
 
   void row_inv(RowInv<T>& A, bool r2c) {
     A.nrows = P.ny * P.nz;
@@ -397,7 +414,7 @@ template <typename T> struct Eng {
     const double cb = (double)P.Kx * P.nz * 2 * TS;
     timed(SGSPM_KC_COL_FFT, k * cb * (P.ny + P.Py), [&] { launch_col_fft<T>(A, P.nz, k, s); });
   }
-  void conv(int mask) {
+  void conv(int mask, int smask = 7) {
     Conv<T> A{};
     const bool z = P.nz > 1;
     const int L = z ? P.Pz : P.Py;
@@ -423,7 +440,7 @@ template <typename T> struct Eng {
       A.oddb = 0;
     }
     for (int c = 0; c < 3; ++c) {
-      A.S[c] = comp_spec(c);
+      A.S[c] = (smask >> c & 1) ? comp_spec(c) : nullptr;
       A.O[c] = (mask >> c & 1) ? yout[c] : nullptr;
     }
     A.tens = tens;
@@ -445,17 +462,15 @@ template <typename T> struct Eng {
 
   // forward transforms of real fields into the component spectra
   void stray_from_fields(const T* const fields[3], int mask) {
-    const T* u[3] = {nullptr, nullptr, nullptr};
-    cx<T>* xo[3] = {nullptr, nullptr, nullptr};
-    T a[3] = {1, 1, 1};
+    RowIO io;
     int k = 0;
     for (int c = 0; c < 3; ++c)
       if (mask >> c & 1) {
-        u[k] = fields[c];
-        xo[k] = r2c_slot(c);
+        io.u[k] = fields[c];
+        io.xout[k] = r2c_slot(c);
         ++k;
       }
-    row_fwd(k, u, a, (T)0, nullptr, false, nullptr, nullptr, xo);
+    row_fwd(k, io);
     mid_fwd(mask);
   }
 
@@ -471,16 +486,19 @@ template <typename T> struct Eng {
   }
 
   // RHS + forward x DCT for heat solves of components comps[0..nch)
-  void heat_rhs(int nch, const int comps[3], const T* const u[3], T beta, const T he[3]) {
-    T a[3];
-    T hev[3];
+  void heat_rhs(int nch, const int comps[3], const T* const u[3], T beta, const T he[3], T* const hs_store[3] = nullptr) {
+    RowIO io;
     for (int c = 0; c < nch; ++c) {
-      a[c] = (T)(1.0 - (double)beta * (comps[c] > 0 ? P.Q : 0.0));
-      hev[c] = he[comps[c]];
+      io.u[c] = u[c];
+      io.a[c] = (T)(1.0 - (double)beta * (comps[c] > 0 ? P.Q : 0.0));
+      io.he[c] = he[comps[c]];
+      io.dct_out[c] = heat[c];
+      if (hs_store) io.hs_out[c] = hs_store[c];
     }
+    io.b = beta;
+    io.with_hs = P.stray;
     set_c2r(comps, nch);
-    T* outs[3] = {heat[0], heat[1], heat[2]};
-    row_fwd(nch, u, a, beta, hev, P.stray, nullptr, outs, nullptr);
+    row_fwd(nch, io);
   }
 
   // One SGSPM / GSPM step (paper §3.2 / §3.1), latest-state reading.
@@ -564,7 +582,8 @@ template <typename T> struct Eng {
     // Step 2: (I - alpha eps dt Lap_h) m*** = m** + alpha dt f**
     {
       const int comps[3] = {0, 1, 2};
-      heat_rhs(3, comps, uF, (T)(alpha * P.dt), he);
+      T* hsF[3] = {f[F_HS0], f[F_HS1], f[F_HS2]};
+      heat_rhs(3, comps, uF, (T)(alpha * P.dt), he, (tape && P.stray) ? hsF : nullptr);
       heat_rest(3, (T)alpha);
     }
     // Step 3: projection
@@ -633,23 +652,217 @@ template <typename T> struct Eng {
     stray_eval(7);
     const int comps[3] = {0, 1, 2};
     set_c2r(comps, 3);
-    T* ho[3] = {hs, hs + P.N, hs + 2 * P.N};
-    T a[3] = {0, 0, 0};
-    row_fwd(3, nullptr, a, (T)0, nullptr, true, ho, nullptr, nullptr);
+    RowIO io;
+    io.with_hs = true;
+    for (int c = 0; c < 3; ++c) io.hs_out[c] = hs + c * P.N;
+    row_fwd(3, io);
   }
 
   void heat_solve(const T* r, T scale, T* g) {
-    const T* u[3] = {r, nullptr, nullptr};
-    T a[3] = {1, 1, 1};
-    T* outs[3] = {heat[0], nullptr, nullptr};
-    row_fwd(1, u, a, (T)0, nullptr, false, nullptr, outs, nullptr);
-    heat_rest(1, scale);
+    const T* in[3] = {r, nullptr, nullptr};
+    T* out[3] = {g, nullptr, nullptr};
+    heat_solve_n(1, in, scale, out);
+  }
+
+  // g_c = (I - scale eps dt Lap_h)^{-1} r_c for nch channels (in place allowed)
+  void heat_solve_n(int nch, const T* const r[3], T scale, T* const g[3]) {
+    RowIO io;
+    for (int c = 0; c < nch; ++c) {
+      io.u[c] = r[c];
+      io.dct_out[c] = heat[c];
+    }
+    row_fwd(nch, io);
+    heat_rest(nch, scale);
     RowInv<T> A{};
-    A.nch = 1;
-    A.heat[0] = heat[0];
-    A.gout[0] = g;
+    A.nch = nch;
+    for (int c = 0; c < nch; ++c) {
+      A.heat[c] = heat[c];
+      A.gout[c] = g[c];
+    }
     A.op = ROW_OP_NONE;
     row_inv(A, false);
+  }
+
+  // acc_a = acc_in_a + kscale K(v)_a + wc_a w_a for a = 0, 1, 2 (null v_c: zero component,
+  // null acc_in / w: zero); the stray operator is skipped when the plan has no stray field
+  void stray_accumulate(const T* const v[3], T kscale, T* const acc[3], const T* const acc_in[3],
+                        const T* const w[3], const T wc[3]) {
+    int mask = 0;
+    for (int c = 0; c < 3; ++c)
+      if (v[c]) mask |= 1 << c;
+    if (P.stray && mask) {
+      stray_from_fields(v, mask);
+      conv(7, mask);
+      mid_inv(7);
+      const int comps[3] = {0, 1, 2};
+      set_c2r(comps, 3);
+    }
+    RowIO io;
+    for (int c = 0; c < 3; ++c) {
+      io.u[c] = acc_in[c];
+      io.a[c] = 1;
+      io.w[c] = w[c];
+      io.wc[c] = wc[c];
+      io.val_out[c] = acc[c];
+    }
+    io.b = kscale;
+    io.with_hs = P.stray && mask;
+    row_fwd(3, io);
+  }
+
+  void pw(std::initializer_list<PwTerm<T>> terms) {
+    std::vector<PwTerm<T>> t(terms);
+    double by = 0;
+    for (auto& x : t) by += TS * P.N * (1 + x.acc + (x.x0 ? 1 : 0) + (x.y0 ? 1 : 0) + (x.x1 ? 1 : 0) + (x.y1 ? 1 : 0));
+    timed(SGSPM_KC_OTHER, by, [&] { launch_pw<T>(t.data(), (int)t.size(), P.N, s); });
+  }
+  static PwTerm<T> set1(T* out, double c0, const T* x0, const T* y0 = nullptr) {
+    return PwTerm<T>{out, 0, c0, 0.0, x0, y0, nullptr, nullptr};
+  }
+  static PwTerm<T> add1(T* out, double c0, const T* x0, const T* y0 = nullptr) {
+    return PwTerm<T>{out, 1, c0, 0.0, x0, y0, nullptr, nullptr};
+  }
+  void sums(std::initializer_list<const T*> xs, std::initializer_list<double> ws, std::initializer_list<int> slots,
+            double* grad) {
+    const T* x[4] = {nullptr, nullptr, nullptr, nullptr};
+    double w[4] = {0, 0, 0, 0};
+    int sl[4] = {0, 0, 0, 0};
+    int k = 0;
+    for (auto v : xs) x[k++] = v;
+    k = 0;
+    for (auto v : ws) w[k++] = v;
+    int n = 0;
+    for (auto v : slots) sl[n++] = v;
+    timed(SGSPM_KC_OTHER, n * P.N * TS, [&] { launch_wsum<T>(x, w, sl, n, P.N, P.partials, P.nred, grad, s); });
+  }
+
+  // Adjoint of one SGSPM step (reverse of step(), latest-state reading).
+  void adjoint(const T* m_n, double alpha, const double he_in[3], T* lam, double* grad) {
+    const long N = P.N;
+    T* J = (T*)P.adj;
+    enum { LA1, LA2, LA3, LB1, LB2, LG1, LG3, LG3N, TMP, MU, LW, MT = LW + 3, NJ = MT + 3 };
+    T* LW_[3] = {J + (long)LW * N, J + (long)(LW + 1) * N, J + (long)(LW + 2) * N};
+    T* mt = J + (long)MT * N;
+    auto Jf = [&](int k) { return J + (long)k * N; };
+    const T* m2 = m_n + N;
+    const T* m3 = m_n + 2 * N;
+    T* lam0 = lam;
+    T* lam1 = lam + N;
+    T* lam2 = lam + 2 * N;
+    const double dt = P.dt;
+    const double Q = P.Q;
+    const double dh = P.zeeman ? dt * P.fscale : 0.0;  // d(reduced h_e)/d(argument) * dt
+    double he[3];
+    for (int c = 0; c < 3; ++c) he[c] = P.zeeman ? he_in[c] * P.fscale : 0.0;
+    (void)hipMemcpyAsync(mt, m_n, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, s);
+    tape = true;
+    step(mt, alpha, he_in, nullptr);
+    tape = false;
+    const T* u = mt;
+    const T* nrm = f[F_NRM];
+    // projection and heat flow
+    launch_adj_project<T>(lam, u, nrm, LW_[0], N, s);
+    {
+      const T* in[3] = {LW_[0], LW_[1], LW_[2]};
+      heat_solve_n(3, in, (T)alpha, LW_);
+    }
+    {
+      const T* uF[3] = {f[F_B1], f[F_B2], f[F_A3]};
+      const double ex = P.eps;
+      launch_adj_damp<T>(LW_[0], u, nrm, uF, P.stray ? f[F_HS0] : nullptr, P.nx, P.ny, P.nz,
+                         P.nx > 1 ? ex / (P.prm.dx * P.prm.dx) : 0.0, P.ny > 1 ? ex / (P.prm.dy * P.prm.dy) : 0.0,
+                         P.nz > 1 ? ex / (P.prm.dz * P.prm.dz) : 0.0, Q, he, dt, alpha * dh, P.partials, P.nred, grad,
+                         s);
+    }
+    {
+      const T* v[3] = {LW_[0], LW_[1], LW_[2]};
+      T* acc[3] = {Jf(LB1), Jf(LB2), Jf(LA3)};
+      const T wc[3] = {0, (T)(-alpha * dt * Q), (T)(-alpha * dt * Q)};
+      stray_accumulate(v, (T)(alpha * dt), acc, v, v, wc);
+    }
+    const T cq = (T)(1.0 - dt * Q);
+    const T dtt = (T)dt;
+    // m1** = m1 + g2** m3** - g3** m2**
+    pw({set1(lam0, 1, Jf(LB1)), set1(Jf(TMP), 1, Jf(LB1), f[F_A3]), add1(Jf(LA3), 1, Jf(LB1), f[F_G2SS]),
+        set1(Jf(LG3), -1, Jf(LB1), f[F_B2]), add1(Jf(LB2), -1, Jf(LB1), f[F_G3SS])});
+    // g2** = H(m2** + dt f2(m1*, m2**, m3**))
+    {
+      const T* in[3] = {Jf(TMP)};
+      T* out[3] = {Jf(MU)};
+      heat_solve_n(1, in, (T)1, out);
+      sums({Jf(MU)}, {dh}, {1}, grad);
+      const T* v[3] = {nullptr, Jf(MU), nullptr};
+      T* acc[3] = {Jf(LA1), Jf(LB2), Jf(LA3)};
+      const T* ai[3] = {nullptr, Jf(LB2), Jf(LA3)};
+      const T* w[3] = {nullptr, Jf(MU), nullptr};
+      const T wc[3] = {0, cq, 0};
+      stray_accumulate(v, dtt, acc, ai, w, wc);
+    }
+    // m2** = m2 + g3** m1* - g1* m3**
+    pw({set1(lam1, 1, Jf(LB2)), add1(Jf(LG3), 1, Jf(LB2), f[F_A1]), add1(Jf(LA1), 1, Jf(LB2), f[F_G3SS]),
+        set1(Jf(LG1), -1, Jf(LB2), f[F_A3]), add1(Jf(LA3), -1, Jf(LB2), f[F_G1S])});
+    // g3** = H(m3** + dt f3(m1*, m2*, m3**))
+    {
+      const T* in[3] = {Jf(LG3)};
+      T* out[3] = {Jf(MU)};
+      heat_solve_n(1, in, (T)1, out);
+      sums({Jf(MU)}, {dh}, {2}, grad);
+      const T* v[3] = {nullptr, nullptr, Jf(MU)};
+      T* acc[3] = {Jf(LA1), Jf(LA2), Jf(LA3)};
+      const T* ai[3] = {Jf(LA1), nullptr, Jf(LA3)};
+      const T* w[3] = {nullptr, nullptr, Jf(MU)};
+      const T wc[3] = {0, 0, cq};
+      stray_accumulate(v, dtt, acc, ai, w, wc);
+    }
+    // m3* = m3 + g1* m2* - g2* m1*
+    pw({set1(lam2, 1, Jf(LA3)), add1(Jf(LG1), 1, Jf(LA3), f[F_A2]), add1(Jf(LA2), 1, Jf(LA3), f[F_G1S]),
+        set1(Jf(TMP), -1, Jf(LA3), f[F_A1]), add1(Jf(LA1), -1, Jf(LA3), f[F_G2S])});
+    // g2* = H(m2* + dt f2(m1*, m2*, m3))
+    {
+      const T* in[3] = {Jf(TMP)};
+      T* out[3] = {Jf(MU)};
+      heat_solve_n(1, in, (T)1, out);
+      sums({Jf(MU)}, {dh}, {1}, grad);
+      const T* v[3] = {nullptr, Jf(MU), nullptr};
+      T* acc[3] = {Jf(LA1), Jf(LA2), lam2};
+      const T* ai[3] = {Jf(LA1), Jf(LA2), lam2};
+      const T* w[3] = {nullptr, Jf(MU), nullptr};
+      const T wc[3] = {0, cq, 0};
+      stray_accumulate(v, dtt, acc, ai, w, wc);
+    }
+    // m2* = m2 + g3^n m1* - g1* m3
+    pw({add1(lam1, 1, Jf(LA2)), set1(Jf(LG3N), 1, Jf(LA2), f[F_A1]), add1(Jf(LA1), 1, Jf(LA2), f[F_G3N]),
+        add1(Jf(LG1), -1, Jf(LA2), m3), add1(lam2, -1, Jf(LA2), f[F_G1S])});
+    // g1* = H(m1* + dt f1(m1*, m2, m3))
+    {
+      const T* in[3] = {Jf(LG1)};
+      T* out[3] = {Jf(MU)};
+      heat_solve_n(1, in, (T)1, out);
+      sums({Jf(MU)}, {dh}, {0}, grad);
+      const T* v[3] = {Jf(MU), nullptr, nullptr};
+      T* acc[3] = {Jf(LA1), lam1, lam2};
+      const T* ai[3] = {Jf(LA1), lam1, lam2};
+      const T* w[3] = {Jf(MU), nullptr, nullptr};
+      const T wc[3] = {1, 0, 0};
+      stray_accumulate(v, dtt, acc, ai, w, wc);
+    }
+    // m1* = m1 + g2^n m3 - g3^n m2
+    pw({add1(lam0, 1, Jf(LA1)), set1(Jf(TMP), 1, Jf(LA1), m3), add1(lam2, 1, Jf(LA1), f[F_G2N]),
+        add1(Jf(LG3N), -1, Jf(LA1), m2), add1(lam1, -1, Jf(LA1), f[F_G3N])});
+    // g2^n = H(m2 + dt f2(m)), g3^n = H(m3 + dt f3(m))
+    {
+      const T* in[3] = {Jf(TMP), Jf(LG3N)};
+      T* out[3] = {Jf(MU), Jf(LG3)};
+      heat_solve_n(2, in, (T)1, out);
+      sums({Jf(MU), Jf(LG3)}, {dh, dh}, {1, 2}, grad);
+      const T* v[3] = {nullptr, Jf(MU), Jf(LG3)};
+      T* acc[3] = {lam0, lam1, lam2};
+      const T* ai[3] = {lam0, lam1, lam2};
+      const T* w[3] = {nullptr, Jf(MU), Jf(LG3)};
+      const T wc[3] = {0, cq, cq};
+      stray_accumulate(v, dtt, acc, ai, w, wc);
+    }
+    (void)NJ;
   }
 };
 
@@ -951,8 +1164,15 @@ int sgspm_energy(sgspm_plan_t P, const void* m, const double h_e[3], double e_ou
 int sgspm_adjoint_step(sgspm_plan_t P, const void* m_n, double alpha, const double h_e[3], void* lam,
                        double* grad_dev) {
   if (!P || !m_n || !h_e || !lam || !grad_dev) return fail(SGSPM_EINVAL, "NULL argument");
-  (void)alpha;
-  return fail(SGSPM_EUNSUPPORTED, "adjoint step not built yet");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SGSPM_EINVAL, "alpha must be >= 0 and finite");
+  if (P->prm.scheme != SGSPM_SCHEME_SGS) return fail(SGSPM_EUNSUPPORTED, "the adjoint covers the SGS scheme only");
+  if (!P->adj) {
+    int rc = dalloc(P, &P->adj, (size_t)16 * P->N * (P->fp64 ? 8 : 4));
+    if (rc) return rc;
+  }
+  if (P->fp64) Eng<double>(*P).adjoint((const double*)m_n, alpha, h_e, (double*)lam, grad_dev);
+  else Eng<float>(*P).adjoint((const float*)m_n, alpha, h_e, (float*)lam, grad_dev);
+  return hip_check(hipGetLastError(), "sgspm_adjoint_step launch");
 }
 
 int sgspm_timing(sgspm_plan_t P, int enable) {

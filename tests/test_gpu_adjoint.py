@@ -1,0 +1,151 @@
+"""GPU adjoint: the library's adjoint step and the checkpointed autograd function
+against the FP64 CPU oracle adjoint, and against central finite differences of
+the GPU FP64 forward (h = 1e-6)."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import adjoint as oadj, units
+
+from helpers import gpu_plan_si, oracle_field_si, oracle_problem_si, rounded_like, to_dev
+
+pytestmark = pytest.mark.gpu
+
+ALL = ("exchange", "aniso", "stray", "zeeman")
+CELL = (4e-9, 4e-9, 4e-9)
+DT = 0.1e-12
+FSCALE = 1.0 / (units.MU0 * workloads.MS_PY)   # reduced field per tesla
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_28113_amd as sg
+    return torch, sg
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    import sys
+    sys.stderr.write(f"\n[gpu-case] {request.node.nodeid}\n")
+    sys.stderr.flush()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+@pytest.mark.parametrize("n", [(16, 8, 4), (32, 16, 1), (8, 1, 8), (16, 1, 1), (4, 4, 4)],
+                         ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("terms", [ALL, ("exchange",), ("exchange", "aniso", "zeeman"), ("stray", "zeeman")],
+                         ids=lambda t: "+".join(t))
+def test_adjoint_step_fp64(env, n, terms):
+    torch, sg = env
+    shape = (n[2], n[1], n[0])
+    rng = np.random.default_rng(200)
+    m0 = workloads.random_unit(shape, 201)
+    lam = rng.normal(size=m0.shape)
+    B = (4e-3, -2e-3, 1e-3)
+    alpha = 0.05
+    plan = gpu_plan_si(sg, n, CELL, DT, terms, 1)
+    lam_d = to_dev(torch, lam, 1)
+    grad = torch.zeros(4, dtype=torch.float64, device="cuda")
+    plan.adjoint_step(to_dev(torch, m0, 1), alpha, B, lam_d, grad)
+    torch.cuda.synchronize()
+    P = oracle_problem_si(n, CELL, DT, terms)
+    lref, dh, da = oadj.adjoint_step(P, m0, alpha, oracle_field_si(B, terms), lam)
+    g = grad.cpu().numpy()
+    assert _rel(lam_d.cpu().numpy(), lref) <= 1e-11
+    if "zeeman" in terms:
+        assert np.allclose(g[:3], dh * FSCALE, rtol=1e-10, atol=1e-12 * np.abs(dh * FSCALE).max())
+    else:
+        assert np.all(g[:3] == 0)
+    assert g[3] == pytest.approx(da, rel=1e-10, abs=1e-14)
+
+
+def test_adjoint_step_fp32(env):
+    torch, sg = env
+    c = workloads.config("c4")
+    rng = np.random.default_rng(202)
+    m0 = workloads.initial_state(c)
+    lam = rng.normal(size=m0.shape)
+    B = (5e-3, 0.0, 0.0)
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 0)
+    lam_d = to_dev(torch, lam, 0)
+    grad = torch.zeros(4, dtype=torch.float64, device="cuda")
+    plan.adjoint_step(to_dev(torch, m0, 0), c.alpha, B, lam_d, grad)
+    torch.cuda.synchronize()
+    P = oracle_problem_si(c.n, c.h, c.dt, ALL)
+    lref, dh, da = oadj.adjoint_step(P, rounded_like(m0, 0), c.alpha, oracle_field_si(B, ALL),
+                                     rounded_like(lam, 0))
+    g = grad.cpu().numpy()
+    e_l, e_h, e_a = _rel(lam_d.cpu().numpy(), lref), _rel(g[:3], dh * FSCALE), abs(g[3] - da) / abs(da)
+    print(f"c4 fp32 adjoint step: rel err lam {e_l:.2e}, dh_e {e_h:.2e}, dalpha {e_a:.2e}")
+    assert e_l <= 1e-5 and e_h <= 1e-5 and e_a <= 1e-5
+
+
+def _loss_grads_gpu(torch, sg, plan, m0, B, alpha, target, ckpt, prec):
+    dt_ = torch.float64 if prec == 1 else torch.float32
+    m = torch.tensor(m0, dtype=dt_, device="cuda", requires_grad=True)
+    he = torch.tensor(B, dtype=torch.float64, requires_grad=True)
+    a = torch.tensor(alpha, dtype=torch.float64, requires_grad=True)
+    out = sg.SGSPMFunction.apply(m, he, a, plan, ckpt)
+    tgt = torch.tensor(target, dtype=dt_, device="cuda")
+    L = torch.mean((out - tgt) ** 2)
+    L.backward()
+    return float(L.detach()), m.grad.double().cpu().numpy(), he.grad.cpu().numpy(), float(a.grad)
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_checkpointed_gradients_vs_oracle(env, prec):
+    """128x128 film (the adjoint workload's grid), 20 steps, checkpoints every 5."""
+    torch, sg = env
+    c = workloads.config("c4")
+    S, K = 20, 5
+    m0 = workloads.initial_state(c)
+    B = workloads.field_schedule(c, S)
+    target = workloads.target_state(c)
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, prec)
+    L, gm, gh, ga = _loss_grads_gpu(torch, sg, plan, m0, B, c.alpha, target, K, prec)
+    P = oracle_problem_si(c.n, c.h, c.dt, ALL)
+    Lr, gmr, ghr, gar = oadj.run_with_grad(P, rounded_like(m0, prec), c.alpha,
+                                           [oracle_field_si(b, ALL) for b in B], rounded_like(target, prec))
+    errs = (_rel(gm, gmr), _rel(gh, ghr * FSCALE), abs(ga - gar) / abs(gar))
+    print(f"c4 {'fp64' if prec else 'fp32'} 20-step gradients: rel err m0 {errs[0]:.2e}, "
+          f"h_e {errs[1]:.2e}, alpha {errs[2]:.2e}; loss {L:.6e} vs {Lr:.6e}")
+    tol = 1e-10 if prec == 1 else 1e-4
+    assert max(errs) <= tol
+    assert L == pytest.approx(Lr, rel=1e-12 if prec == 1 else 1e-5)
+
+
+def test_gradients_vs_finite_differences_fp64(env):
+    torch, sg = env
+    n = (32, 16, 2)
+    shape = (n[2], n[1], n[0])
+    S, K = 6, 4
+    m0 = workloads.random_unit(shape, 203)
+    rng = np.random.default_rng(204)
+    B = 5e-3 * rng.normal(size=(S, 3))
+    target = workloads.random_unit(shape, 205)
+    alpha = 0.02
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, 1)
+    L, gm, gh, ga = _loss_grads_gpu(torch, sg, plan, m0, B, alpha, target, K, 1)
+
+    def loss(m, bb, a):
+        x = torch.tensor(m, dtype=torch.float64, device="cuda")
+        for k in range(S):
+            plan.step(x, a, bb[k])
+        return float(torch.mean((x - torch.tensor(target, dtype=torch.float64, device="cuda")) ** 2))
+
+    h = 1e-6
+    for _ in range(4):
+        v = rng.normal(size=m0.shape)
+        fd = (loss(m0 + h * v, B, alpha) - loss(m0 - h * v, B, alpha)) / (2 * h)
+        assert fd == pytest.approx(np.sum(gm * v), rel=1e-6)
+        w = rng.normal(size=B.shape)
+        fd = (loss(m0, B + h * w, alpha) - loss(m0, B - h * w, alpha)) / (2 * h)
+        assert fd == pytest.approx(np.sum(gh * w), rel=1e-6)
+    fd = (loss(m0, B, alpha + h) - loss(m0, B, alpha - h)) / (2 * h)
+    assert fd == pytest.approx(ga, rel=1e-6)
