@@ -13,7 +13,7 @@ around every launch, a second timed pass), the dominant kernel against the HBM
 roofline, the FP64 CPU oracle timed on the host, and the max |m - m_oracle| of
 the first step.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c5]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config block-256x256x32]
 """
 import argparse
 import json
@@ -29,12 +29,12 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {"row_fwd": "k_row_fwd", "row_inv": "k_row_inv", "col_dct": "k_col_dct",
                 "col_fft": "k_col_fft", "conv": "k_conv", "other": "other"}
 WORKLOAD_TEXT = {
-    "c5": "256x256x32 block, 4 nm cells, exchange+anisotropy+stray (padded 512x512x64 FFT)+rotating 10 mT, "
+    "block-256x256x32": "256x256x32 block, 4 nm cells, exchange+anisotropy+stray (padded 512x512x64 FFT)+rotating 10 mT, "
           "alpha 1e-3, dt 0.05 ps",
-    "c4": "128x128x1 film, 4 nm cells, all fields, alpha 0.01, dt 0.1 ps",
-    "c3": "512x32x4 Neel-wall strip, 4 nm cells, all fields, 10 mT, alpha 1e-3, dt 0.1 ps",
-    "c2": "128x64x1 film, 4 nm cells, all fields, 5 mT, alpha 0.01, dt 0.1 ps",
-    "c1": "32x32x1 exchange-only film, manufactured forcing off, alpha 0.01, dt 1e-3",
+    "adjoint-film-128x128": "128x128x1 film, 4 nm cells, all fields, alpha 0.01, dt 0.1 ps",
+    "wall-strip-512x32x4": "512x32x4 Neel-wall strip, 4 nm cells, all fields, 10 mT, alpha 1e-3, dt 0.1 ps",
+    "film-128x64": "128x64x1 film, 4 nm cells, all fields, 5 mT, alpha 0.01, dt 0.1 ps",
+    "mf-film-32x32": "32x32x1 exchange-only film, manufactured forcing off, alpha 0.01, dt 1e-3",
 }
 
 
@@ -61,10 +61,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c5")
+    ap.add_argument("--config", default="block-256x256x32")
     ap.add_argument("--fp64-steps", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (hardware-counter calibration)")
+    ap.add_argument("--skip-fp64", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures the single-GPU SGSPM step only; run it with --gpus 1 "
@@ -76,6 +79,14 @@ def main():
     import paper_2606_28113_amd as sg
     import workloads
 
+    if args.copy_calib_mb:
+        nb = args.copy_calib_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {nb} bytes read, {nb} bytes written", file=sys.stderr, flush=True)
+        del src, dst
     c = workloads.config(args.config)
     N = c.cells
     K, W = args.steps, args.warmup
@@ -120,6 +131,8 @@ def main():
     torch.cuda.empty_cache()
 
     # ---- FP64 forward (comparator on the same GPU)
+    if args.skip_fp64:
+        args.fp64_steps = 0
     p64 = make_plan(sg, c, sg.FP64)
     m = torch.tensor(m0, dtype=torch.float64, device="cuda")
     p64.step(m, alpha, B[0])
@@ -127,7 +140,7 @@ def main():
     m1_64 = m.detach().cpu().numpy()
     for n in range(1, 1 + min(W, 5)):
         p64.step(m, alpha, B[n])
-    K64 = min(args.fp64_steps, K)
+    K64 = max(1, min(args.fp64_steps, K))
     ms64 = time_steps(torch, p64, m, alpha, B, 1 + min(W, 5), K64)
     p64.check()
     print(f"[bench] fp64 forward {ms64:.4f} ms/step", file=sys.stderr, flush=True)
@@ -135,6 +148,8 @@ def main():
     # ---- adjoint step (FP32), if the library provides it
     adj = None
     try:
+        if args.adjoint_steps <= 0:
+            raise sg.SGSPMError(0, "adjoint timing skipped (--adjoint-steps 0)")
         pa = make_plan(sg, c, sg.FP32)
         ma = torch.tensor(m0, dtype=torch.float32, device="cuda")
         lam = torch.zeros_like(ma)

@@ -100,7 +100,7 @@ struct FftGeom {
   int twshift;
 };
 
-template <typename T, int R, int VPT>
+template <typename T, int R, int VPT, int NTH>
 __device__ __forceinline__ void fft_stage(cx<T>* __restrict__ buf, const cx<T>* __restrict__ tw, const FftGeom& g,
                                           int Ns, bool inv) {
   constexpr int NB = VPT / R;
@@ -112,7 +112,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* __restrict__ buf, const cx<T>* 
   int dst[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int b = threadIdx.x + i * NT;
+    const int b = threadIdx.x + i * NTH;
     dst[i] = -1;
     if (b < total) {
       int p, j;
@@ -154,35 +154,35 @@ __device__ __forceinline__ void fft_stage(cx<T>* __restrict__ buf, const cx<T>* 
   __syncthreads();
 }
 
-// Full transform; the caller has synchronised after filling buf.
-template <typename T>
+// Full transform; the caller has synchronised after filling buf.  A workgroup
+// of NTH threads holds at most VPT * NTH values per stage.
+template <typename T, int VPT = Tile<T>::VPT, int NTH = NT>
 __device__ __forceinline__ void fft_lds(cx<T>* __restrict__ buf, const cx<T>* __restrict__ tw, const FftGeom& g,
                                         bool inv) {
-  constexpr int VPT = Tile<T>::VPT;
   int Ns = 1;
   int rem = g.lgL;
   if (rem % 3 == 1) {
-    fft_stage<T, 2, VPT>(buf, tw, g, Ns, inv);
+    fft_stage<T, 2, VPT, NTH>(buf, tw, g, Ns, inv);
     Ns <<= 1;
     rem -= 1;
   } else if (rem % 3 == 2) {
-    fft_stage<T, 4, VPT>(buf, tw, g, Ns, inv);
+    fft_stage<T, 4, VPT, NTH>(buf, tw, g, Ns, inv);
     Ns <<= 2;
     rem -= 2;
   }
   while (rem > 0) {
-    fft_stage<T, 8, VPT>(buf, tw, g, Ns, inv);
+    fft_stage<T, 8, VPT, NTH>(buf, tw, g, Ns, inv);
     Ns <<= 3;
     rem -= 3;
   }
 }
 
 // Copy the length-2^lgL twiddle table (from a global table of length 2^lgTw) into LDS.
-template <typename T>
+template <typename T, int NTH = NT>
 __device__ __forceinline__ void load_twiddles(cx<T>* __restrict__ lds, const cx<T>* __restrict__ gtw, int lgL, int lgTw) {
   const int L = 1 << lgL;
   const int sh = lgTw - lgL;
-  for (int i = threadIdx.x; i < L; i += NT) lds[i] = gtw[i << sh];
+  for (int i = threadIdx.x; i < L; i += NTH) lds[i] = gtw[i << sh];
 }
 
 // Makhoul's reordering for the DCT-II through a length-n FFT:

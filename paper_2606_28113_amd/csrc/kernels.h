@@ -39,6 +39,7 @@ template <typename T> struct RowFwd {
   int xin_pitch;
   T* hs_out[3];     // optional store of hs
   T* dct_out[3];    // optional type-II DCT of v along x
+  int dct_xmajor;   // store it x-major: [nx][nrows] instead of [nrows][nx]
   const cx<T>* dtw; // exp(-i pi k / (2n)), k < n
   cx<T>* xout[3];   // optional zero-padded real-to-complex transform of v
   int lgLr;
@@ -53,6 +54,7 @@ template <typename T> struct RowInv {
   const cx<T>* dtw;
   int nch;             // heat arrays to invert along x (1..3)
   const T* heat[3];
+  int heat_xmajor;     // heat arrays are [nx][nrows]
   T* gout[3];          // optional stores of the inverted arrays
   int op;
   // ROW_OP_GS: out = base + Pf * Qf - Rf * Sf + ds * src; Pch/Rch >= 0 select an
@@ -106,6 +108,25 @@ template <typename T> struct ColFft {
   int lgTw;
 };
 
+// Heat solve across y and z of x-major planes [nx][nz][ny] (after the x DCT-II):
+// y DCT-II, z DCT-II, diagonal 1 / (1 + s (lamX + lamY + lamZ)), z and y
+// inverse, in place, 2^lgPP planes per workgroup.
+template <typename T> struct YZSolve {
+  T* data[3];
+  int nx, lgNy, lgNz, lgPP;
+  const cx<T>* dtwy;
+  const cx<T>* dtwz;
+  const cx<T>* tw;
+  int lgTw;
+  const T* lamX;
+  const T* lamY;
+  const T* lamZ;
+  T s;
+};
+template <typename T> void launch_yz_solve(const YZSolve<T>& a, int nch, hipStream_t s);
+// largest plane (ny * nz reals) the fused yz solve holds in one workgroup
+template <typename T> constexpr int yz_max_plane() { return sizeof(T) == 4 ? 8192 : 4096; }
+
 // Last-axis convolution: FFT of the three component spectra, multiply by the
 // six-component symmetric tensor spectrum, inverse FFT of the requested outputs.
 template <typename T> struct Conv {
@@ -115,6 +136,9 @@ template <typename T> struct Conv {
   cx<T>* O[3];       // null = output not requested
   const T* tens;     // [6][Hc][Hb][ni]
   long tcs;
+  int nt;            // tensor components used (listed in clist; cpos maps component -> slot)
+  int clist[6];
+  int cpos[6];
   int Hb, Pb;        // folded / full length of the batch axis
   int oddc, oddb;    // bitmask of components odd along the pencil / batch axis
   const cx<T>* tw;
@@ -126,6 +150,8 @@ template <typename T> void launch_row_inv(const RowInv<T>& a, hipStream_t s);
 template <typename T> void launch_col_dct(const ColDct<T>& a, int nbatch, int nch, hipStream_t s);
 template <typename T> void launch_col_fft(const ColFft<T>& a, int nbatch, int nch, hipStream_t s);
 template <typename T> void launch_conv(const Conv<T>& a, int nbatch, hipStream_t s);
+// kx tile (log2) of the convolution for a padded pencil of 2^lgL and nt tensor components
+template <typename T> int conv_lgP(int lgL, int ni, int nt);
 
 // Demagnetising tensor (FP64): fill the padded real array of one component.
 void launch_newell_fill(double* out, int comp, int nx, int ny, int nz, int Px, int Py, int Pz, double hx, double hy,

@@ -30,27 +30,29 @@ __device__ __forceinline__ void row_r2c_store(cx<T>* buf, const cx<T>* tw, const
   const int Lr = 1 << lgLr;
   const int P = 1 << lgP;
   T* bufr = reinterpret_cast<T*>(buf);
+  const int ps = Lr + 1;
   for (int t = threadIdx.x; t < (P << lgLr); t += NT) {
-    if ((t & (Lr - 1)) >= n) buf[t] = zero<T>();
+    const int x = t & (Lr - 1);
+    if (x >= n) buf[(t >> lgLr) * ps + x] = zero<T>();
   }
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const int e = threadIdx.x + i * NT;
     if (e < tot) {
       const int row = e >> lgN, x = e & (n - 1);
-      bufr[2 * (((row >> 1) << lgLr) + x) + (row & 1)] = val[i];
+      bufr[2 * ((row >> 1) * ps + x) + (row & 1)] = val[i];
     }
   }
   __syncthreads();
-  FftGeom g{lgLr, lgP, 1, false, Lr, 1, lgLmax - lgLr};
+  FftGeom g{lgLr, lgP, 1, false, ps, 1, lgLmax - lgLr};
   fft_lds(buf, tw, g, false);
   const int half = Lr >> 1;
   for (int t = threadIdx.x; t < (P << lgLr); t += NT) {
     const int k = t & (Lr - 1);
     if (k > half) continue;
     const int q = t >> lgLr;
-    const cx<T> Zk = buf[(q << lgLr) + k];
-    const cx<T> Zm = buf[(q << lgLr) + ((Lr - k) & (Lr - 1))];
+    const cx<T> Zk = buf[q * ps + k];
+    const cx<T> Zm = buf[q * ps + ((Lr - k) & (Lr - 1))];
     // X_a = (Z_k + conj Z_{-k}) / 2 ; X_b = (Z_k - conj Z_{-k}) / (2i)
     const cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
     const cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
@@ -102,17 +104,17 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
         Xa.y = -Xa.y;
         Xb.y = -Xb.y;
       }
-      buf[(q << A.lgLc) + k] = mk<T>(Xa.x - Xb.y, Xa.y + Xb.x);
+      buf[q * (Lc + 1) + k] = mk<T>(Xa.x - Xb.y, Xa.y + Xb.x);
     }
     __syncthreads();
-    FftGeom g{A.lgLc, A.lgP, 1, false, Lc, 1, A.lgLmax - A.lgLc};
+    FftGeom g{A.lgLc, A.lgP, 1, false, Lc + 1, 1, A.lgLmax - A.lgLc};
     fft_lds(buf, tw, g, true);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const int e = threadIdx.x + i * NT;
       if (e < tot) {
         const int row = e >> A.lgN, x = e & (n - 1);
-        const cx<T> z = buf[((row >> 1) << A.lgLc) + x];
+        const cx<T> z = buf[(row >> 1) * (Lc + 1) + x];
         hs[i] = (row & 1) ? z.y : z.x;
       }
     }
@@ -146,27 +148,36 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
   T* dout = A.dct_out[ch];
   if (dout) {
     T* bufr = reinterpret_cast<T*>(buf);
+    const int ps = n + 1;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const int e = threadIdx.x + i * NT;
       if (e < tot) {
         const int row = e >> A.lgN, x = e & (n - 1);
-        bufr[2 * (((row >> 1) << A.lgN) + makhoul_pos(x, n)) + (row & 1)] = val[i];
+        bufr[2 * ((row >> 1) * ps + makhoul_pos(x, n)) + (row & 1)] = val[i];
       }
     }
     __syncthreads();
-    FftGeom g{A.lgN, A.lgP, 1, false, n, 1, A.lgLmax - A.lgN};
+    FftGeom g{A.lgN, A.lgP, 1, false, ps, 1, A.lgLmax - A.lgN};
     fft_lds(buf, tw, g, false);
     for (int t = threadIdx.x; t < (P << A.lgN); t += NT) {
-      const int q = t >> A.lgN, k = t & (n - 1);
-      const cx<T> Zk = buf[(q << A.lgN) + k];
-      const cx<T> Zm = buf[(q << A.lgN) + ((n - k) & (n - 1))];
+      // x-major stores take consecutive rows per thread group, row-major consecutive k
+      const int q = A.dct_xmajor ? (t & (P - 1)) : (t >> A.lgN);
+      const int k = A.dct_xmajor ? (t >> A.lgP) : (t & (n - 1));
+      const cx<T> Zk = buf[q * ps + k];
+      const cx<T> Zm = buf[q * ps + ((n - k) & (n - 1))];
       const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
       const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
       const cx<T> w = A.dtw[k];
       const int ra = row0 + 2 * q;
-      if (ra < A.nrows) dout[((long)ra << A.lgN) + k] = w.x * Va.x - w.y * Va.y;
-      if (ra + 1 < A.nrows) dout[((long)(ra + 1) << A.lgN) + k] = w.x * Vb.x - w.y * Vb.y;
+      const T xa = w.x * Va.x - w.y * Va.y, xb = w.x * Vb.x - w.y * Vb.y;
+      if (A.dct_xmajor) {
+        if (ra < A.nrows) dout[(long)k * A.nrows + ra] = xa;
+        if (ra + 1 < A.nrows) dout[(long)k * A.nrows + ra + 1] = xb;
+      } else {
+        if (ra < A.nrows) dout[((long)ra << A.lgN) + k] = xa;
+        if (ra + 1 < A.nrows) dout[((long)(ra + 1) << A.lgN) + k] = xb;
+      }
     }
     __syncthreads();
   }
@@ -203,25 +214,39 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
     if (c < A.nch) {
       __syncthreads();
       const T* H = A.heat[c];
+      const int ps = n + 1;
       for (int t = threadIdx.x; t < (P << A.lgN); t += NT) {
-        const int q = t >> A.lgN, k = t & (n - 1);
+        const int q = A.heat_xmajor ? (t & (P - 1)) : (t >> A.lgN);
+        const int k = A.heat_xmajor ? (t >> A.lgP) : (t & (n - 1));
         const int ra = row0 + 2 * q;
         T xak = 0, xam = 0, xbk = 0, xbm = 0;
-        if (ra < A.nrows) {
-          xak = H[((long)ra << A.lgN) + k];
-          if (k) xam = H[((long)ra << A.lgN) + n - k];
-        }
-        if (ra + 1 < A.nrows) {
-          xbk = H[((long)(ra + 1) << A.lgN) + k];
-          if (k) xbm = H[((long)(ra + 1) << A.lgN) + n - k];
+        if (A.heat_xmajor) {
+          const long nr = A.nrows;
+          if (ra < A.nrows) {
+            xak = H[(long)k * nr + ra];
+            if (k) xam = H[(long)(n - k) * nr + ra];
+          }
+          if (ra + 1 < A.nrows) {
+            xbk = H[(long)k * nr + ra + 1];
+            if (k) xbm = H[(long)(n - k) * nr + ra + 1];
+          }
+        } else {
+          if (ra < A.nrows) {
+            xak = H[((long)ra << A.lgN) + k];
+            if (k) xam = H[((long)ra << A.lgN) + n - k];
+          }
+          if (ra + 1 < A.nrows) {
+            xbk = H[((long)(ra + 1) << A.lgN) + k];
+            if (k) xbm = H[((long)(ra + 1) << A.lgN) + n - k];
+          }
         }
         const cx<T> w = conjg(A.dtw[k]);
         const cx<T> Va = cmul(w, mk<T>(xak, -xam));
         const cx<T> Vb = cmul(w, mk<T>(xbk, -xbm));
-        buf[t] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
+        buf[q * ps + k] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
       }
       __syncthreads();
-      FftGeom gm{A.lgN, A.lgP, 1, false, n, 1, A.lgLmax - A.lgN};
+      FftGeom gm{A.lgN, A.lgP, 1, false, ps, 1, A.lgLmax - A.lgN};
       fft_lds(buf, tw, gm, true);
       T* go = A.gout[c];
 #pragma unroll
@@ -229,7 +254,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
         const int e = threadIdx.x + i * NT;
         if (e < tot) {
           const int row = e >> A.lgN, x = e & (n - 1);
-          const cx<T> z = buf[((row >> 1) << A.lgN) + makhoul_pos(x, n)];
+          const cx<T> z = buf[(row >> 1) * ps + makhoul_pos(x, n)];
           g[c][i] = ((row & 1) ? z.y : z.x) * invn;
           if (go && row0 + row < A.nrows) go[((long)(row0 + row) << A.lgN) + x] = g[c][i];
         }
@@ -397,6 +422,255 @@ __global__ __launch_bounds__(NT) void k_col_dct(const ColDct<T> A) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Fused yz heat solve on x-major planes.  Values travel between the passes in
+// registers; each pass scatters them into an element-major LDS layout with a
+// padded pencil stride (es = pencils + 1) and two real pencils per complex one.
+constexpr int YZ_NT = 512;
+constexpr int YZ_VPT = 8;
+
+template <typename T>
+__global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int NTH = YZ_NT;
+  constexpr int NV = 2 * YZ_VPT;  // reals per thread
+  const int ny = 1 << A.lgNy, nz = 1 << A.lgNz;
+  const int lgM = A.lgNy + A.lgNz;
+  const int lgR = lgM + A.lgPP;
+  const int R = 1 << lgR;
+  const int lgL = max(A.lgNy, A.lgNz);
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + (1 << lgL);
+  T* bufr = reinterpret_cast<T*>(buf);
+  load_twiddles<T, NTH>(tw, A.tw, lgL, A.lgTw);
+  const int p0 = blockIdx.x << A.lgPP;
+  const int nplanes = min(1 << A.lgPP, A.nx - p0);
+  T* D = A.data[blockIdx.z] + ((long)p0 << lgM);
+  T v[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int e = threadIdx.x + i * NTH;
+    v[i] = (e < R && (e >> lgM) < nplanes) ? D[e] : (T)0;
+  }
+  // y pass: real pencils rho = (p, z), 2^lgPy of them, paired rho <-> rho + Hy
+  const int lgPy = A.lgPP + A.lgNz;
+  const int lgHy = max(0, lgPy - 1), Hy = 1 << lgHy, esy = Hy + 1;
+  // z pass: real pencils rho' = (p, ky)
+  const int lgPz = A.lgPP + A.lgNy;
+  const int lgHz = max(0, lgPz - 1), Hz = 1 << lgHz, esz = Hz + 1;
+  // current order of v[]: 0 plane order (e = tid + i NTH), 1 after the y pass, 2 after the z pass
+  int order = 0;
+  auto decode = [&](int i, int& p, int& z, int& y) -> bool {
+    if (order == 1) {
+      const int t = threadIdx.x + (i >> 1) * NTH, part = i & 1;
+      if (t >= (Hy << A.lgNy) || (part && lgPy == 0)) return false;
+      const int rho = (t & (Hy - 1)) + part * Hy;
+      p = rho >> A.lgNz;
+      z = rho & (nz - 1);
+      y = t >> lgHy;
+      return true;
+    }
+    if (order == 2) {
+      const int t = threadIdx.x + i * NTH;
+      if (t >= R) return false;
+      const int rho = t >> A.lgNz;
+      p = rho >> A.lgNy;
+      y = rho & (ny - 1);
+      z = t & (nz - 1);
+      return true;
+    }
+    const int e = threadIdx.x + i * NTH;
+    if (e >= R) return false;
+    p = e >> lgM;
+    z = (e >> A.lgNy) & (nz - 1);
+    y = e & (ny - 1);
+    return true;
+  };
+  __syncthreads();
+
+  if (ny > 1) {
+    if (lgPy == 0)
+      for (int t = threadIdx.x; t < ny * esy; t += NTH) buf[t] = zero<T>();
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      int p, z, y;
+      if (decode(i, p, z, y)) {
+        const int rho = (p << A.lgNz) + z;
+        bufr[2 * (makhoul_pos(y, ny) * esy + (rho & (Hy - 1))) + (rho >> lgHy)] = v[i];
+      }
+    }
+    __syncthreads();
+    FftGeom g{A.lgNy, lgHy, 1, true, 1, esy, lgL - A.lgNy};
+    fft_lds<T, YZ_VPT, NTH>(buf, tw, g, false);
+#pragma unroll
+    for (int s2 = 0; s2 < YZ_VPT; ++s2) {
+      const int t = threadIdx.x + s2 * NTH;
+      v[2 * s2] = v[2 * s2 + 1] = (T)0;
+      if (t < (Hy << A.lgNy)) {
+        const int k = t >> lgHy, q = t & (Hy - 1);
+        const cx<T> Zk = buf[k * esy + q];
+        const cx<T> Zm = buf[((ny - k) & (ny - 1)) * esy + q];
+        const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+        const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+        const cx<T> w = A.dtwy[k];
+        v[2 * s2] = w.x * Va.x - w.y * Va.y;
+        v[2 * s2 + 1] = w.x * Vb.x - w.y * Vb.y;
+      }
+    }
+    order = 1;
+    __syncthreads();
+  }
+
+  if (nz > 1) {
+    if (lgPz == 0)
+      for (int t = threadIdx.x; t < nz * esz; t += NTH) buf[t] = zero<T>();
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      int p, z, y;
+      if (decode(i, p, z, y)) {
+        const int rho = (p << A.lgNy) + y;
+        bufr[2 * (makhoul_pos(z, nz) * esz + (rho & (Hz - 1))) + (rho >> lgHz)] = v[i];
+      }
+    }
+    __syncthreads();
+    FftGeom g{A.lgNz, lgHz, 1, true, 1, esz, lgL - A.lgNz};
+    fft_lds<T, YZ_VPT, NTH>(buf, tw, g, false);
+    T xa[YZ_VPT], xb[YZ_VPT];
+#pragma unroll
+    for (int s2 = 0; s2 < YZ_VPT; ++s2) {
+      const int t = threadIdx.x + s2 * NTH;
+      xa[s2] = xb[s2] = (T)0;
+      if (t < (Hz << A.lgNz)) {
+        const int k = t >> lgHz, q = t & (Hz - 1);
+        const cx<T> Zk = buf[k * esz + q];
+        const cx<T> Zm = buf[((nz - k) & (nz - 1)) * esz + q];
+        const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+        const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+        const cx<T> w = A.dtwz[k];
+        const int ra = q, rb = q + Hz;
+        const int pa = ra >> A.lgNy, pb = rb >> A.lgNy;
+        const T lx_a = (p0 + pa < A.nx) ? A.lamX[p0 + pa] : (T)0;
+        const T lx_b = (p0 + pb < A.nx) ? A.lamX[p0 + pb] : (T)0;
+        xa[s2] = (w.x * Va.x - w.y * Va.y) / ((T)1 + A.s * (lx_a + A.lamY[ra & (ny - 1)] + A.lamZ[k]));
+        xb[s2] = (w.x * Vb.x - w.y * Vb.y) / ((T)1 + A.s * (lx_b + A.lamY[rb & (ny - 1)] + A.lamZ[k]));
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < YZ_VPT; ++s2) {
+      const int t = threadIdx.x + s2 * NTH;
+      if (t < (Hz << A.lgNz)) buf[(t >> lgHz) * esz + (t & (Hz - 1))] = mk<T>(xa[s2], xb[s2]);
+    }
+    __syncthreads();
+    cx<T> zz[YZ_VPT];
+#pragma unroll
+    for (int s2 = 0; s2 < YZ_VPT; ++s2) {
+      const int t = threadIdx.x + s2 * NTH;
+      zz[s2] = zero<T>();
+      if (t < (Hz << A.lgNz)) {
+        const int k = t >> lgHz, q = t & (Hz - 1);
+        const cx<T> Xk = buf[k * esz + q];
+        const cx<T> Xm = k ? buf[(nz - k) * esz + q] : zero<T>();
+        const cx<T> w = conjg(A.dtwz[k]);
+        const cx<T> Va = cmul(w, mk<T>(Xk.x, -Xm.x));
+        const cx<T> Vb = cmul(w, mk<T>(Xk.y, -Xm.y));
+        zz[s2] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < YZ_VPT; ++s2) {
+      const int t = threadIdx.x + s2 * NTH;
+      if (t < (Hz << A.lgNz)) buf[(t >> lgHz) * esz + (t & (Hz - 1))] = zz[s2];
+    }
+    __syncthreads();
+    fft_lds<T, YZ_VPT, NTH>(buf, tw, g, true);
+    const T invn = (T)1 / (T)nz;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int t = threadIdx.x + i * NTH;
+      v[i] = (T)0;
+      if (t < R) {
+        const int rho = t >> A.lgNz, z = t & (nz - 1);
+        const cx<T> c = buf[makhoul_pos(z, nz) * esz + (rho & (Hz - 1))];
+        v[i] = ((rho >> lgHz) ? c.y : c.x) * invn;
+      }
+    }
+    order = 2;
+    __syncthreads();
+  } else {
+    // no z axis: the diagonal acts on the y (or plane) coefficients directly
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      int p, z, y;
+      if (decode(i, p, z, y)) {
+        const T lx = (p0 + p < A.nx) ? A.lamX[p0 + p] : (T)0;
+        v[i] /= (T)1 + A.s * (lx + A.lamY[y] + A.lamZ[0]);
+      }
+    }
+  }
+
+  if (ny > 1) {
+    if (lgPy == 0)
+      for (int t = threadIdx.x; t < ny * esy; t += NTH) buf[t] = zero<T>();
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      int p, z, y;
+      if (decode(i, p, z, y)) {
+        const int rho = (p << A.lgNz) + z;
+        bufr[2 * (y * esy + (rho & (Hy - 1))) + (rho >> lgHy)] = v[i];
+      }
+    }
+    __syncthreads();
+    cx<T> zz[YZ_VPT];
+#pragma unroll
+    for (int s2 = 0; s2 < YZ_VPT; ++s2) {
+      const int t = threadIdx.x + s2 * NTH;
+      zz[s2] = zero<T>();
+      if (t < (Hy << A.lgNy)) {
+        const int k = t >> lgHy, q = t & (Hy - 1);
+        const cx<T> Xk = buf[k * esy + q];
+        const cx<T> Xm = k ? buf[(ny - k) * esy + q] : zero<T>();
+        const cx<T> w = conjg(A.dtwy[k]);
+        const cx<T> Va = cmul(w, mk<T>(Xk.x, -Xm.x));
+        const cx<T> Vb = cmul(w, mk<T>(Xk.y, -Xm.y));
+        zz[s2] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < YZ_VPT; ++s2) {
+      const int t = threadIdx.x + s2 * NTH;
+      if (t < (Hy << A.lgNy)) buf[(t >> lgHy) * esy + (t & (Hy - 1))] = zz[s2];
+    }
+    __syncthreads();
+    FftGeom g{A.lgNy, lgHy, 1, true, 1, esy, lgL - A.lgNy};
+    fft_lds<T, YZ_VPT, NTH>(buf, tw, g, true);
+    const T invn = (T)1 / (T)ny;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e = threadIdx.x + i * NTH;
+      v[i] = (T)0;
+      if (e < R) {
+        const int rho = e >> A.lgNy, y = e & (ny - 1);
+        const cx<T> c = buf[makhoul_pos(y, ny) * esy + (rho & (Hy - 1))];
+        v[i] = ((rho >> lgHy) ? c.y : c.x) * invn;
+      }
+    }
+    order = 0;
+  }
+  // plane order here (with ny == 1 the z-pass order coincides with it)
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int e = threadIdx.x + i * NTH;
+    if (e < R && (e >> lgM) < nplanes) D[e] = v[i];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Column complex FFT (forward with zero padding n_in -> L, or inverse with
 // crop L -> n_out).  In place allowed (in == out, same strides).
@@ -436,83 +710,217 @@ __device__ __forceinline__ int comp_index(int a, int b) {
   return 2 + s;
 }
 
+// One workgroup: P consecutive kx, the full padded pencil along the last axis,
+// and the pair of batch rows b and Pb - b that share one folded tensor row (the
+// tensor tile is read once into LDS and used for both).  LDS layout of the
+// spectra: buf[j * 3P + c * P + q].
+constexpr int CONV_NT = 512;
+constexpr int CONV_VPT = 8;
+
 template <typename T>
-__global__ __launch_bounds__(NT) void k_conv(const Conv<T> A) {
+__global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int L = 1 << A.lgL;
-  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* buf = tw + L;
-  load_twiddles(tw, A.tw, A.lgL, A.lgTw);
+  const int LH = (L >> 1) + 1;
   const int P = 1 << A.lgP;
   const int es = 3 * P;
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + L;
+  T* tt = reinterpret_cast<T*>(buf + 3 * P * L);  // [ncomp][LH][P]
+  load_twiddles<T, CONV_NT>(tw, A.tw, A.lgL, A.lgTw);
   const int i0 = blockIdx.x * P;
-  const int b = blockIdx.y;
-  const long boff = (long)b * A.sb;
+  const int bf = blockIdx.y;
+  // folded tensor tile
+  for (int t = threadIdx.x; t < A.nt * LH * P; t += CONV_NT) {
+    const int q = t % P;
+    const int kf = (t / P) % LH;
+    const int ci = t / (P * LH);
+    const int kx = i0 + q;
+    tt[t] = (kx < A.ni) ? A.tens[(long)A.clist[ci] * A.tcs + ((long)kf * A.Hb + bf) * A.ni + kx] : (T)0;
+  }
+  const bool mirror = A.Pb > 1 && bf != 0 && 2 * bf != A.Pb;
+  const int ch = L >> 1;
+  for (int pass = 0; pass < (mirror ? 2 : 1); ++pass) {
+    const int b = pass ? A.Pb - bf : bf;
+    const bool bneg = pass == 1;
+    const long boff = (long)b * A.sb;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cx<T>* S = A.S[c];
+      for (int t = threadIdx.x; t < (P << A.lgL); t += CONV_NT) {
+        const int j = t >> A.lgP, q = t & (P - 1);
+        const int i = i0 + q;
+        buf[j * es + c * P + q] = (S && j < A.n && i < A.ni) ? S[boff + (long)j * A.sa + i] : zero<T>();
+      }
+    }
+    __syncthreads();
+    {
+      FftGeom g{A.lgL, A.lgP, 3, true, 1, es, 0};
+      fft_lds<T, CONV_VPT, CONV_NT>(buf, tw, g, false);
+    }
+    for (int t = threadIdx.x; t < (P << A.lgL); t += CONV_NT) {
+      const int j = t >> A.lgP, q = t & (P - 1);
+      if (i0 + q >= A.ni) continue;
+      const bool cneg = j > ch;
+      const int kf = cneg ? L - j : j;
+      const cx<T> s0 = buf[j * es + q], s1 = buf[j * es + P + q], s2 = buf[j * es + 2 * P + q];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (!A.O[a]) continue;
+        T tv[3];
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+          const int c = comp_index(a, bb);
+          T v = tt[(A.cpos[c] * LH + kf) * P + q];
+          if (cneg && ((A.oddc >> c) & 1)) v = -v;
+          if (bneg && ((A.oddb >> c) & 1)) v = -v;
+          tv[bb] = v;
+        }
+        buf[j * es + a * P + q] =
+            mk<T>(tv[0] * s0.x + tv[1] * s1.x + tv[2] * s2.x, tv[0] * s0.y + tv[1] * s1.y + tv[2] * s2.y);
+      }
+    }
+    __syncthreads();
+    if (A.O[0] && A.O[1] && A.O[2]) {
+      FftGeom g{A.lgL, A.lgP, 3, true, 1, es, 0};
+      fft_lds<T, CONV_VPT, CONV_NT>(buf, tw, g, true);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (A.O[a]) {
+          FftGeom g{A.lgL, A.lgP, 1, true, 1, es, 0};
+          fft_lds<T, CONV_VPT, CONV_NT>(buf + a * P, tw, g, true);
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cx<T>* O = A.O[a];
+      if (!O) continue;
+      O += boff;
+      for (int t = threadIdx.x; t < P * A.n; t += CONV_NT) {
+        const int j = t >> A.lgP, q = t & (P - 1);
+        const int i = i0 + q;
+        if (i < A.ni) O[(long)j * A.sa + i] = buf[j * es + a * P + q];
+      }
+    }
+  }
+}
+
+
+// Convolution for a 64-point padded pencil (last axis of extent 32): four-step
+// FFT 64 = 8 x 8 in registers.  Eight threads share a pencil, thread t holding
+// elements n = t + 8 m; after a register DFT-8 over m and the twiddles
+// W_64^{t k2} one LDS transpose lets thread k2 finish with a DFT-8 over t, so
+// thread k2 ends with the frequencies k2 + 8 k1.  The tensor multiply needs no
+// exchange (all three components of a frequency sit in one thread); the inverse
+// mirrors the forward and leaves thread b with z = 8 a + b.  A workgroup covers
+// P consecutive kx and the batch rows b and Pb - b that share a tensor row.
+constexpr int C64_NT = 256;
+
+template <typename T>
+__device__ __forceinline__ void tw64_apply(cx<T>* v, const cx<T>* w64, int t, bool inv) {
+#pragma unroll
+  for (int k = 1; k < 8; ++k) {
+    cx<T> w = w64[(t * k) & 63];
+    if (inv) w.y = -w.y;
+    v[k] = cmul(v[k], w);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(C64_NT) void k_conv64(const Conv<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int P = 1 << A.lgP;
+  const int NP = 2 * P;  // pencils per workgroup (two batch rows)
+  cx<T>* w64 = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* xb = w64 + 64;  // [3][8][8][NP]
+  const int tid = threadIdx.x;
+  const int q = tid & (P - 1);
+  const int t = (tid >> A.lgP) & 7;
+  const int r = tid >> (A.lgP + 3);
+  for (int i = tid; i < 64; i += C64_NT) w64[i] = A.tw[i << (A.lgTw - 6)];
+  const int bf = blockIdx.y;
+  const int kx0 = blockIdx.x * P;
+  const bool mirror = A.Pb > 1 && bf != 0 && 2 * bf != A.Pb;
+  const int kx = kx0 + q;
+  const bool act = kx < A.ni && (r == 0 || mirror);
+  const int b = r ? A.Pb - bf : bf;
+  const long boff = (long)b * A.sb + kx;
+  const int pen = r * P + q;
+
+  // forward: load, DFT-8 over m, twiddle, transpose, DFT-8 over t
+  cx<T> v[3][8];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const cx<T>* S = A.S[c];
-    for (int t = threadIdx.x; t < (P << A.lgL); t += NT) {
-      const int j = t >> A.lgP, q = t & (P - 1);
-      const int i = i0 + q;
-      buf[j * es + c * P + q] = (S && j < A.n && i < A.ni) ? S[boff + (long)j * A.sa + i] : zero<T>();
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int z = t + 8 * m;
+      v[c][m] = (act && S && m < 4 && z < A.n) ? S[boff + (long)z * A.sa] : zero<T>();
     }
   }
-  __syncthreads();
-  {
-    FftGeom g{A.lgL, A.lgP, 3, true, 1, es, 0};
-    fft_lds(buf, tw, g, false);
-  }
-  const int bh = A.Pb >> 1;
-  const bool bneg = b > bh;
-  const int bf = bneg ? A.Pb - b : b;
-  const int ch = L >> 1;
-  for (int t = threadIdx.x; t < (P << A.lgL); t += NT) {
-    const int j = t >> A.lgP, q = t & (P - 1);
-    const int kx = i0 + q;
-    if (kx >= A.ni) continue;
-    const bool cneg = j > ch;
-    const int kf = cneg ? L - j : j;
-    const long base = ((long)kf * A.Hb + bf) * A.ni + kx;
-    const cx<T> s0 = buf[j * es + q], s1 = buf[j * es + P + q], s2 = buf[j * es + 2 * P + q];
+  __syncthreads();  // w64 is in LDS
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (!A.O[a]) continue;
+  for (int c = 0; c < 3; ++c) {
+    dft8(v[c], false);
+    tw64_apply(v[c], w64, t, false);
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) xb[((c * 8 + k2) * 8 + t) * NP + pen] = v[c][k2];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int tt2 = 0; tt2 < 8; ++tt2) v[c][tt2] = xb[((c * 8 + t) * 8 + tt2) * NP + pen];
+    dft8(v[c], false);  // v[c][k1] = X[t + 8 k1]
+  }
+  __syncthreads();
+  // per output: multiply by the folded real tensor spectrum, IDFT-8 over k1,
+  // twiddle, then the transpose slot of that output
+  const bool bneg = r == 1;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (!A.O[a]) continue;
+    cx<T> o[8];
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) {
+      const int kz = t + 8 * k1;
+      const bool cneg = kz > 32;
+      const int kf = cneg ? 64 - kz : kz;
       T tv[3];
 #pragma unroll
       for (int bb = 0; bb < 3; ++bb) {
         const int c = comp_index(a, bb);
-        T v = A.tens[(long)c * A.tcs + base];
-        if (cneg && ((A.oddc >> c) & 1)) v = -v;
-        if (bneg && ((A.oddb >> c) & 1)) v = -v;
-        tv[bb] = v;
+        T w = act ? A.tens[(long)c * A.tcs + ((long)kf * A.Hb + bf) * A.ni + kx] : (T)0;
+        if (cneg && ((A.oddc >> c) & 1)) w = -w;
+        if (bneg && ((A.oddb >> c) & 1)) w = -w;
+        tv[bb] = w;
       }
-      buf[j * es + a * P + q] =
-          mk<T>(tv[0] * s0.x + tv[1] * s1.x + tv[2] * s2.x, tv[0] * s0.y + tv[1] * s1.y + tv[2] * s2.y);
+      o[k1] = mk<T>(tv[0] * v[0][k1].x + tv[1] * v[1][k1].x + tv[2] * v[2][k1].x,
+                    tv[0] * v[0][k1].y + tv[1] * v[1][k1].y + tv[2] * v[2][k1].y);
     }
+    dft8(o, true);
+    tw64_apply(o, w64, t, true);
+#pragma unroll
+    for (int bb = 0; bb < 8; ++bb) xb[((a * 8 + bb) * 8 + t) * NP + pen] = o[bb];
   }
   __syncthreads();
-  const bool all3 = A.O[0] && A.O[1] && A.O[2];
-  if (all3) {
-    FftGeom g{A.lgL, A.lgP, 3, true, 1, es, 0};
-    fft_lds(buf, tw, g, true);
-  } else {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (A.O[a]) {
-        FftGeom g{A.lgL, A.lgP, 1, true, 1, es, 0};
-        fft_lds(buf + a * P, tw, g, true);
-      }
-    }
-  }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     cx<T>* O = A.O[a];
     if (!O) continue;
-    O += boff;
-    for (int t = threadIdx.x; t < P * A.n; t += NT) {
-      const int j = t >> A.lgP, q = t & (P - 1);
-      const int i = i0 + q;
-      if (i < A.ni) O[(long)j * A.sa + i] = buf[j * es + a * P + q];
+    cx<T> u[8];
+#pragma unroll
+    for (int tt2 = 0; tt2 < 8; ++tt2) u[tt2] = xb[((a * 8 + t) * 8 + tt2) * NP + pen];
+    dft8(u, true);  // u[a'] = x[8 a' + t]
+    if (act) {
+#pragma unroll
+      for (int aa = 0; aa < 4; ++aa) {
+        const int z = 8 * aa + t;
+        if (z < A.n) O[boff + (long)z * A.sa] = u[aa];
+      }
     }
   }
 }
@@ -832,14 +1240,14 @@ static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 template <typename T> void launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_t s) {
   const int rows = 2 << a.lgP;
   dim3 grid(ceil_div(a.nrows, rows), 1, nch);
-  const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << (a.lgP + a.lgLmax))) * sizeof(cx<T>);
+  const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1)) * sizeof(cx<T>);
   hipLaunchKernelGGL(k_row_fwd<T>, grid, dim3(NT), lds, s, a);
 }
 
 template <typename T> void launch_row_inv(const RowInv<T>& a, hipStream_t s) {
   const int rows = 2 << a.lgP;
   dim3 grid(ceil_div(a.nrows, rows), 1, 1);
-  const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << (a.lgP + a.lgLmax))) * sizeof(cx<T>);
+  const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1)) * sizeof(cx<T>);
   hipLaunchKernelGGL(k_row_inv<T>, grid, dim3(NT), lds, s, a);
 }
 
@@ -855,10 +1263,48 @@ template <typename T> void launch_col_fft(const ColFft<T>& a, int nbatch, int nc
   hipLaunchKernelGGL(k_col_fft<T>, grid, dim3(NT), lds, s, a);
 }
 
+template <typename T> void launch_yz_solve(const YZSolve<T>& a, int nch, hipStream_t s) {
+  const int lgL = std::max(a.lgNy, a.lgNz);
+  const int lgR = a.lgNy + a.lgNz + a.lgPP;
+  const int Hy = 1 << std::max(0, a.lgPP + a.lgNz - 1), Hz = 1 << std::max(0, a.lgPP + a.lgNy - 1);
+  const size_t nbuf = std::max((size_t)(1 << a.lgNy) * (Hy + 1), (size_t)(1 << a.lgNz) * (Hz + 1));
+  const size_t lds = ((size_t)(1 << lgL) + nbuf) * sizeof(cx<T>);
+  (void)lgR;
+  dim3 grid(ceil_div(a.nx, 1 << a.lgPP), 1, nch);
+  hipLaunchKernelGGL(k_yz_solve<T>, grid, dim3(YZ_NT), lds, s, a);
+}
+
+template <typename T> size_t conv_lds(int lgL, int lgP, int nt) {
+  const size_t L = (size_t)1 << lgL, P = (size_t)1 << lgP;
+  return (L + 3 * P * L) * sizeof(cx<T>) + (size_t)nt * (L / 2 + 1) * P * sizeof(T);
+}
+
+template <typename T> int conv_lgP(int lgL, int ni, int nt) {
+  // widest power-of-two kx tile whose three padded pencils fit the FFT capacity
+  // and whose LDS (spectra + folded tensor tile) stays within 48 KiB
+  int lgP = 0;
+  while (true) {
+    const int nl = lgP + 1;
+    if ((3L << (nl + lgL)) > (long)CONV_VPT * CONV_NT) break;
+    if (conv_lds<T>(lgL, nl, nt) > 48 * 1024) break;
+    if ((1 << nl) > 2 * ni) break;
+    lgP = nl;
+  }
+  return lgP;
+}
+
 template <typename T> void launch_conv(const Conv<T>& a, int nbatch, hipStream_t s) {
+  if (a.lgL == 6 && a.n <= 32) {
+    // register four-step kernel: 16 kx x 2 batch rows x 8 threads per pencil
+    Conv<T> b = a;
+    b.lgP = 4;
+    dim3 grid(ceil_div(a.ni, 16), nbatch, 1);
+    const size_t lds = (64 + (size_t)3 * 64 * 32) * sizeof(cx<T>);
+    hipLaunchKernelGGL(k_conv64<T>, grid, dim3(C64_NT), lds, s, b);
+    return;
+  }
   dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, 1);
-  const size_t lds = ((size_t)(1 << a.lgL) + 3 * ((size_t)1 << (a.lgP + a.lgL))) * sizeof(cx<T>);
-  hipLaunchKernelGGL(k_conv<T>, grid, dim3(NT), lds, s, a);
+  hipLaunchKernelGGL(k_conv<T>, grid, dim3(CONV_NT), conv_lds<T>(a.lgL, a.lgP, a.nt), s, a);
 }
 
 void launch_newell_fill(double* out, int comp, int nx, int ny, int nz, int Px, int Py, int Pz, double hx, double hy,
@@ -931,6 +1377,8 @@ void launch_adj_damp(const T* lw, const T* u, const T* nrm, const T* const uF[3]
   template void launch_col_dct<T>(const ColDct<T>&, int, int, hipStream_t);                                         \
   template void launch_col_fft<T>(const ColFft<T>&, int, int, hipStream_t);                                         \
   template void launch_conv<T>(const Conv<T>&, int, hipStream_t);                                                   \
+  template int conv_lgP<T>(int, int, int);                                                                          \
+  template void launch_yz_solve<T>(const YZSolve<T>&, int, hipStream_t);                                            \
   template void launch_tensor_pack<T>(const cx<double>*, T*, int, int, int, int, int, double, hipStream_t);         \
   template void launch_field_assemble<T>(const T*, const T*, T*, int, int, int, double, double, double, double,    \
                                          double, const double*, hipStream_t);                                       \

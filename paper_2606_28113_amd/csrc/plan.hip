@@ -101,6 +101,7 @@ struct sgspm_plan_s {
   long N = 0;
   int Px = 1, Py = 1, Pz = 1, Kx = 1, Kxp = 1, Hy = 1, Hz = 1;
   bool stray = false, zeeman = false, has_mid = false;
+  bool yz = false;  // heat arrays x-major and solved across y, z by one fused kernel
   double eps = 0, Q = 0, dt = 0, fscale = 1, escale = 1;
   double cxx = 0, cyy = 0, czz = 0;  // eps / h^2 per axis (reduced)
   int lgTw = 0;
@@ -267,6 +268,7 @@ template <typename T> struct Eng {
     A.b = io.b;
     A.xin_pitch = P.Kxp;
     A.xout_pitch = P.Kxp;
+    A.dct_xmajor = P.yz ? 1 : 0;
     for (int c = 0; c < nch; ++c) {
       A.u[c] = io.u[c];
       A.a[c] = io.a[c];
@@ -300,6 +302,7 @@ template <typename T> struct Eng {
     A.tw = tw;
     A.dtw = dtw[0];
     A.xout_pitch = P.Kxp;
+    A.heat_xmajor = P.yz ? 1 : 0;
     if (!r2c) A.xout = nullptr;
     double by = A.nch * P.N * TS;
     for (int c = 0; c < A.nch; ++c) by += A.gout[c] ? P.N * TS : 0;
@@ -313,6 +316,28 @@ template <typename T> struct Eng {
   void heat_rest(int nch, T scale) {
     T* d[3] = {heat[0], heat[1], heat[2]};
     const T sdt = (T)(scale * P.dt);
+    if (P.yz) {
+      YZSolve<T> A{};
+      for (int c = 0; c < 3; ++c) A.data[c] = d[c];
+      A.nx = P.nx;
+      A.lgNy = ilog2(P.ny);
+      A.lgNz = ilog2(P.nz);
+      const int lgM = A.lgNy + A.lgNz;
+      // planes per workgroup: fill the tile, but keep at least ~256 workgroups
+      int lgPP = ilog2(yz_max_plane<T>()) - lgM;
+      while (lgPP > 0 && (P.nx >> lgPP) < 256) --lgPP;
+      A.lgPP = std::max(0, lgPP);
+      A.dtwy = dtw[1];
+      A.dtwz = dtw[2];
+      A.tw = tw;
+      A.lgTw = P.lgTw;
+      A.lamX = lam[0];
+      A.lamY = lam[1];
+      A.lamZ = lam[2];
+      A.s = sdt;
+      timed(SGSPM_KC_COL_DCT, 2.0 * nch * P.N * TS, [&] { launch_yz_solve<T>(A, nch, s); });
+      return;
+    }
     if (P.has_mid) {
       ColDct<T> A{};
       A.mode = COL_DCT_FWD;
@@ -420,9 +445,6 @@ template <typename T> struct Eng {
     const int L = z ? P.Pz : P.Py;
     A.lgL = ilog2(L);
     A.n = z ? P.nz : P.ny;
-    int lgP = 0;
-    while (3L * (2L << lgP) * L <= tile_elems<T>()) ++lgP;
-    A.lgP = cap_lgP(lgP, P.Kx);
     A.ni = P.Kx;
     if (z) {
       A.sa = (P.has_mid ? (long)P.Py : 1L) * P.Kxp;
@@ -439,24 +461,33 @@ template <typename T> struct Eng {
       A.oddc = (1 << 3) | (1 << 5);
       A.oddb = 0;
     }
+    unsigned used = 0;
+    int nout = 0;
     for (int c = 0; c < 3; ++c) {
       A.S[c] = (smask >> c & 1) ? comp_spec(c) : nullptr;
       A.O[c] = (mask >> c & 1) ? yout[c] : nullptr;
+      if (mask >> c & 1) {
+        ++nout;
+        for (int b = 0; b < 3; ++b) used |= 1u << (c == b ? c : 2 + c + b);
+      }
     }
+    A.nt = 0;
+    for (int c = 0; c < 6; ++c) {
+      A.cpos[c] = 0;
+      if (used >> c & 1) {
+        A.cpos[c] = A.nt;
+        A.clist[A.nt++] = c;
+      }
+    }
+    A.lgP = conv_lgP<T>(A.lgL, P.Kx, A.nt);
     A.tens = tens;
     A.tcs = (long)P.Hz * P.Hy * P.Kx;
     A.tw = tw;
     A.lgTw = P.lgTw;
-    const int nb = (z && P.has_mid) ? P.Py : 1;
-    const double slab = (double)A.n * A.ni * nb * 2 * TS;
-    int nout = 0;
-    unsigned used = 0;
-    for (int a = 0; a < 3; ++a)
-      if (mask >> a & 1) {
-        ++nout;
-        for (int b = 0; b < 3; ++b) used |= 1u << (a == b ? a : 2 + a + b);
-      }
-    const double tb = __builtin_popcount(used) * (double)(z ? P.Hz : P.Hy) * A.Hb * A.ni * TS;
+    const int nb = (z && P.has_mid) ? P.Hy : 1;
+    const int nrows = (z && P.has_mid) ? P.Py : 1;
+    const double slab = (double)A.n * A.ni * nrows * 2 * TS;
+    const double tb = A.nt * (double)(z ? P.Hz : P.Hy) * A.Hb * A.ni * TS;
     timed(SGSPM_KC_CONV, 3 * slab + nout * slab + tb, [&] { launch_conv<T>(A, nb, s); });
   }
 
@@ -1046,6 +1077,7 @@ int sgspm_plan(const sgspm_params* p, void* hip_stream, sgspm_plan_t* out) {
   P->stray = p->terms & SGSPM_TERM_STRAY;
   P->zeeman = p->terms & SGSPM_TERM_ZEEMAN;
   P->has_mid = p->nz > 1 && p->ny > 1;
+  P->yz = (long)p->ny * p->nz <= (P->fp64 ? yz_max_plane<double>() : yz_max_plane<float>());
   double red[5];
   reduce(p, red);
   P->eps = red[0];

@@ -67,7 +67,7 @@ def test_adjoint_step_fp64(env, n, terms):
 
 def test_adjoint_step_fp32(env):
     torch, sg = env
-    c = workloads.config("c4")
+    c = workloads.config("adjoint-film-128x128")
     rng = np.random.default_rng(202)
     m0 = workloads.initial_state(c)
     lam = rng.normal(size=m0.shape)
@@ -82,7 +82,7 @@ def test_adjoint_step_fp32(env):
                                      rounded_like(lam, 0))
     g = grad.cpu().numpy()
     e_l, e_h, e_a = _rel(lam_d.cpu().numpy(), lref), _rel(g[:3], dh * FSCALE), abs(g[3] - da) / abs(da)
-    print(f"c4 fp32 adjoint step: rel err lam {e_l:.2e}, dh_e {e_h:.2e}, dalpha {e_a:.2e}")
+    print(f"adjoint-film fp32 adjoint step: rel err lam {e_l:.2e}, dh_e {e_h:.2e}, dalpha {e_a:.2e}")
     assert e_l <= 1e-5 and e_h <= 1e-5 and e_a <= 1e-5
 
 
@@ -102,7 +102,7 @@ def _loss_grads_gpu(torch, sg, plan, m0, B, alpha, target, ckpt, prec):
 def test_checkpointed_gradients_vs_oracle(env, prec):
     """128x128 film (the adjoint workload's grid), 20 steps, checkpoints every 5."""
     torch, sg = env
-    c = workloads.config("c4")
+    c = workloads.config("adjoint-film-128x128")
     S, K = 20, 5
     m0 = workloads.initial_state(c)
     B = workloads.field_schedule(c, S)
@@ -113,7 +113,7 @@ def test_checkpointed_gradients_vs_oracle(env, prec):
     Lr, gmr, ghr, gar = oadj.run_with_grad(P, rounded_like(m0, prec), c.alpha,
                                            [oracle_field_si(b, ALL) for b in B], rounded_like(target, prec))
     errs = (_rel(gm, gmr), _rel(gh, ghr * FSCALE), abs(ga - gar) / abs(gar))
-    print(f"c4 {'fp64' if prec else 'fp32'} 20-step gradients: rel err m0 {errs[0]:.2e}, "
+    print(f"adjoint-film {'fp64' if prec else 'fp32'} 20-step gradients: rel err m0 {errs[0]:.2e}, "
           f"h_e {errs[1]:.2e}, alpha {errs[2]:.2e}; loss {L:.6e} vs {Lr:.6e}")
     tol = 1e-10 if prec == 1 else 1e-4
     assert max(errs) <= tol

@@ -119,10 +119,10 @@ def _run_oracle(P, m0, alpha, fields, method="sgspm", src=None):
 
 
 @pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
-def test_c1_manufactured_film(env, prec):
+def test_manufactured_film_32x32(env, prec):
     """32x32 exchange-only film with the 2-D manufactured forcing, 200 steps."""
     torch, sg = env
-    c = workloads.config("c1")
+    c = workloads.config("mf-film-32x32")
     shape = c.shape
     plan = gpu_plan_reduced(sg, c.n, c.h, c.dt, c.eps, 0.0, ("exchange",), prec)
     m0 = workloads.initial_state(c)
@@ -133,7 +133,7 @@ def test_c1_manufactured_film(env, prec):
     src64 = [rounded_like(s, prec) for s in src]
     ref = _run_oracle(P, rounded_like(m0, prec), c.alpha, fields, src=src64)
     err = np.abs(got - ref).max()
-    print(f"c1 {'fp64' if prec else 'fp32'}: max|m - m_oracle| = {err:.3e}; "
+    print(f"mf-film {'fp64' if prec else 'fp32'}: max|m - m_oracle| = {err:.3e}; "
           f"max|m - m_exact| = {np.abs(got - mf.exact(shape, c.steps * c.dt, 2)).max():.3e}")
     assert err <= (1e-11 if prec == 1 else 1e-5)
 
@@ -167,7 +167,7 @@ def test_term_subsets_fp64(env, terms):
     assert np.abs(got - ref).max() <= 1e-10
 
 
-def test_c2_film_fp64_random_start(env):
+def test_film_128x64_fp64_random_start(env):
     """128x64 permalloy-like film, all fields, 5 mT, alpha 0.01, from i.i.d. random unit vectors:
     the FP64 library against the FP64 oracle.
 
@@ -176,7 +176,7 @@ def test_c2_film_fp64_random_start(env):
     ~1e-12 per Newell-tensor entry (independent libm, cancellation), which that growth lifts to
     ~1e-4 by step 1000; the test bounds the early steps and sanity-checks step 1000."""
     torch, sg = env
-    c = workloads.config("c2")
+    c = workloads.config("film-128x64")
     m0 = workloads.initial_state(c)
     B = workloads.field_schedule(c)
     plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 1)
@@ -190,14 +190,14 @@ def test_c2_film_fp64_random_start(env):
             ref = scheme.sgspm_step(P, ref, c.alpha, oracle_field_si(B[n], ALL))
         done = k
         err = np.abs(m.cpu().numpy() - ref).max()
-        print(f"c2 fp64 random start, step {k}: max|m - m_oracle| = {err:.3e}")
+        print(f"film-128x64 fp64 random start, step {k}: max|m - m_oracle| = {err:.3e}")
         assert err <= tol, k
 
 
-def test_c2_film_fp32_random_start_early(env):
-    """FP32 on the chaotic c2 start: bounded while the trajectory sensitivity is moderate."""
+def test_film_128x64_fp32_random_start_early(env):
+    """FP32 on the chaotic random start of the 128x64 film: bounded while the trajectory sensitivity is moderate."""
     torch, sg = env
-    c = workloads.config("c2")
+    c = workloads.config("film-128x64")
     m0 = workloads.initial_state(c)
     plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 0)
     P = oracle_problem_si(c.n, c.h, c.dt, ALL)
@@ -211,15 +211,15 @@ def test_c2_film_fp32_random_start_early(env):
             ref = scheme.sgspm_step(P, ref, c.alpha, he)
         done = k
         err = np.abs(m.cpu().numpy() - ref).max()
-        print(f"c2 fp32 random start, step {k}: max|m - m_oracle| = {err:.3e}")
+        print(f"film-128x64 fp32 random start, step {k}: max|m - m_oracle| = {err:.3e}")
         assert err <= tol, k
 
 
-def test_c2_film_fp32_1000_steps_paper_start(env):
+def test_film_128x64_fp32_1000_steps_paper_start(env):
     """128x64 film, all fields, 1000 steps from the paper's eq. (m0-1) state, a well-conditioned
     trajectory (a 1e-7 perturbation stays below 4e-7): FP32 library within 1e-5 of the FP64 oracle."""
     torch, sg = env
-    c = workloads.config("c2")
+    c = workloads.config("film-128x64")
     m0 = workloads.paper_ic(c.shape)
     B = workloads.field_schedule(c)
     plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 0)
@@ -229,14 +229,14 @@ def test_c2_film_fp32_1000_steps_paper_start(env):
     err = np.abs(got - ref).max()
     e_gpu = plan.energy(to_dev(torch, got, 0), B[-1])["total"]
     e_ref = scheme.energies(P, ref, oracle_field_si(B[-1], ALL))["total"] * 4e-7 * np.pi * workloads.MS_PY ** 2
-    print(f"c2 fp32 1000 steps (paper start): max|m - m_oracle| = {err:.3e}, "
+    print(f"film-128x64 fp32 1000 steps (paper start): max|m - m_oracle| = {err:.3e}, "
           f"relative energy error {abs(e_gpu - e_ref) / abs(e_ref):.3e}")
     assert err <= 1e-5
 
 
-def test_c3_strip_fp64_20_steps(env):
+def test_wall_strip_512x32x4_fp64_20_steps(env):
     torch, sg = env
-    c = workloads.config("c3")
+    c = workloads.config("wall-strip-512x32x4")
     m0 = workloads.initial_state(c)
     B = [(10e-3, 0.0, 0.0)] * 20
     plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 1)
@@ -247,10 +247,10 @@ def test_c3_strip_fp64_20_steps(env):
 
 
 @pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
-def test_c5_block_one_step(env, prec):
+def test_block_256x256x32_one_step(env, prec):
     """256x256x32 block, full fields, one step at full size (the benchmark launch shapes)."""
     torch, sg = env
-    c = workloads.config("c5")
+    c = workloads.config("block-256x256x32")
     m0 = workloads.initial_state(c)
     B = workloads.field_schedule(c, 1)
     plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, prec)
@@ -258,7 +258,7 @@ def test_c5_block_one_step(env, prec):
     P = oracle_problem_si(c.n, c.h, c.dt, ALL)
     ref = _run_oracle(P, rounded_like(m0, prec), c.alpha, [oracle_field_si(b, ALL) for b in B])
     err = np.abs(got - ref).max()
-    print(f"c5 {'fp64' if prec else 'fp32'} one step: max|m - m_oracle| = {err:.3e}")
+    print(f"block {'fp64' if prec else 'fp32'} one step: max|m - m_oracle| = {err:.3e}")
     assert err <= (1e-10 if prec == 1 else 2e-6)
 
 
@@ -278,7 +278,7 @@ def test_projection_flags_non_finite(env):
 
 def test_bitwise_deterministic(env):
     torch, sg = env
-    c = workloads.config("c3")
+    c = workloads.config("wall-strip-512x32x4")
     m0 = workloads.initial_state(c)
     plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 0)
     a = _run_gpu(plan, torch, m0, 0.01, [(5e-3, 0, 0)] * 5, 0)

@@ -8,19 +8,19 @@ CPU oracle's tests draw their inputs from this module.
 Five configurations, shaped like the paper's runs (§5: manufactured solution,
 thin films, a Neel-wall strip) plus a large block for bandwidth measurements:
 
-  c1  32x32x1 on [0,1]^2, reduced units, exchange only (eps = 0.1), alpha = 0.01,
+  mf-film-32x32           32x32x1 on [0,1]^2, reduced units, exchange only (eps = 0.1), alpha = 0.01,
       dt = 1e-3, 200 steps, manufactured solution with forcing; m0 = exact(t=0)
       + N(0, 1e-3^2) noise, renormalised (seed 1).
-  c2  128x64x1 film, 4 nm cells, permalloy-like (A = 1.3e-11 J/m, Ms = 8e5 A/m,
+  film-128x64             128x64x1 film, 4 nm cells, permalloy-like (A = 1.3e-11 J/m, Ms = 8e5 A/m,
       K = 500 J/m^3 along x), all four fields, 5 mT along +x, alpha = 0.01,
       dt = 0.1 ps, 1000 steps, m0 i.i.d. uniform on the sphere (seed 2).
-  c3  512x32x4 strip, same material, tanh Neel wall along x of width 20 nm at
+  wall-strip-512x32x4     512x32x4 strip, same material, tanh Neel wall along x of width 20 nm at
       mid-strip plus 1e-3 transverse noise (seed 3); fields 1..20 mT (5 values)
       along +x, alpha in {1e-2, 1e-3, 1e-4}, dt = 0.1 ps, 5000 steps.
-  c4  128x128x1 film, all fields, alpha = 0.01, dt = 0.1 ps, 500 steps;
+  adjoint-film-128x128    128x128x1 film, all fields, alpha = 0.01, dt = 0.1 ps, 500 steps;
       h_e^n = 5 mT e1 + N(0, (0.5 mT)^2) per step and component (seed 4);
       m0 random unit (seed 40), target random unit (seed 41); checkpoints every 50.
-  c5  256x256x32 block, 4 nm cells, all fields, alpha = 1e-3, dt = 0.05 ps,
+  block-256x256x32        256x256x32 block, 4 nm cells, all fields, alpha = 1e-3, dt = 0.05 ps,
       2000 steps, rotating field 10 mT (cos 2 pi f t, sin 2 pi f t, 0), f = 1 GHz;
       m0 = random unit vectors (seed 5) smoothed by 3 passes of a 3-point box
       filter along each axis and renormalised; adjoint over 200 steps, target
@@ -68,25 +68,25 @@ class Config:
 
 
 def config(name):
-    if name == "c1":
-        return Config("c1", (32, 32, 1), (1 / 32, 1 / 32, 1.0), "reduced", 1e-3, 200, 0.01,
+    if name == "mf-film-32x32":
+        return Config("mf-film-32x32", (32, 32, 1), (1 / 32, 1 / 32, 1.0), "reduced", 1e-3, 200, 0.01,
                       terms=("exchange",), eps=0.1, Q=0.0)
-    if name == "c2":
-        return Config("c2", (128, 64, 1), (CELL,) * 3, "si", 0.1e-12, 1000, 0.01)
-    if name == "c3":
-        return Config("c3", (512, 32, 4), (CELL,) * 3, "si", 0.1e-12, 5000, 0.01,
+    if name == "film-128x64":
+        return Config("film-128x64", (128, 64, 1), (CELL,) * 3, "si", 0.1e-12, 1000, 0.01)
+    if name == "wall-strip-512x32x4":
+        return Config("wall-strip-512x32x4", (512, 32, 4), (CELL,) * 3, "si", 0.1e-12, 5000, 0.01,
                       extra={"fields_mT": list(np.linspace(1.0, 20.0, 5)),
                              "alphas": [1e-2, 1e-3, 1e-4]})
-    if name == "c4":
-        return Config("c4", (128, 128, 1), (CELL,) * 3, "si", 0.1e-12, 500, 0.01, ckpt_every=50,
+    if name == "adjoint-film-128x128":
+        return Config("adjoint-film-128x128", (128, 128, 1), (CELL,) * 3, "si", 0.1e-12, 500, 0.01, ckpt_every=50,
                       adjoint_steps=500)
-    if name == "c5":
-        return Config("c5", (256, 256, 32), (CELL,) * 3, "si", 0.05e-12, 2000, 1e-3, ckpt_every=20,
+    if name == "block-256x256x32":
+        return Config("block-256x256x32", (256, 256, 32), (CELL,) * 3, "si", 0.05e-12, 2000, 1e-3, ckpt_every=20,
                       adjoint_steps=200)
     raise KeyError(name)
 
 
-CONFIGS = ("c1", "c2", "c3", "c4", "c5")
+CONFIGS = ("mf-film-32x32", "film-128x64", "wall-strip-512x32x4", "adjoint-film-128x128", "block-256x256x32")
 
 
 def random_unit(shape, seed):
@@ -163,31 +163,31 @@ def c5_field_schedule(steps, dt, amp=10e-3, freq=1e9):
 
 def initial_state(cfg, seed=None):
     c = cfg.name
-    if c == "c1":
+    if c == "mf-film-32x32":
         return c1_initial(cfg.shape)
-    if c == "c2":
+    if c == "film-128x64":
         return random_unit(cfg.shape, 2 if seed is None else seed)
-    if c == "c3":
+    if c == "wall-strip-512x32x4":
         return neel_wall(cfg.shape, cfg.h[0])
-    if c == "c4":
+    if c == "adjoint-film-128x128":
         return random_unit(cfg.shape, 40 if seed is None else seed)
-    if c == "c5":
+    if c == "block-256x256x32":
         return box_smoothed_unit(cfg.shape, 5 if seed is None else seed)
     raise KeyError(c)
 
 
 def target_state(cfg):
-    return random_unit(cfg.shape, {"c4": 41, "c5": 51}[cfg.name])
+    return random_unit(cfg.shape, {"adjoint-film-128x128": 41, "block-256x256x32": 51}[cfg.name])
 
 
 def field_schedule(cfg, steps=None):
-    """Applied flux density per step in tesla (SI configs) or reduced h_e (c1)."""
+    """Applied flux density per step in tesla (SI configs) or reduced h_e (the manufactured film)."""
     steps = cfg.steps if steps is None else steps
-    if cfg.name == "c1":
+    if cfg.name == "mf-film-32x32":
         return np.zeros((steps, 3))
-    if cfg.name == "c4":
+    if cfg.name == "adjoint-film-128x128":
         return c4_field_schedule(steps)
-    if cfg.name == "c5":
+    if cfg.name == "block-256x256x32":
         return c5_field_schedule(steps, cfg.dt)
     B = np.zeros((steps, 3))
     B[:, 0] = 5e-3
