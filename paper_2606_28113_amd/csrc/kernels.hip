@@ -701,6 +701,114 @@ __global__ __launch_bounds__(NT) void k_col_fft(const ColFft<T> A) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// 512-point column FFT in registers: 512 = 8 x 8 x 8, 64 threads per pencil,
+// 8 values per thread.  Forward: thread t holds n = t + 64 m; DFT-8 over m and
+// W_512^{t k2}; transpose; thread (k2, t0) takes t = t0 + 8 t1, DFT-8 over t1
+// and W_64^{t0 ka}; transpose; thread (k2, ka) finishes with a DFT-8 over t0
+// and owns k = k2 + 8 ka + 64 kb.  The inverse runs the same digits backwards.
+// LDS rows are padded (S = 8P + 1) against bank conflicts.
+template <typename T, int P>
+__global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int S = 8 * P + 1;
+  cx<T>* w = reinterpret_cast<cx<T>*>(smem_raw);  // W_512^i
+  cx<T>* xb = w + 512;                             // [64][S]
+  const int tid = threadIdx.x;
+  const int q = tid % P;
+  const int t = tid / P;  // 0..63
+  for (int i = tid; i < 512; i += 64 * P) w[i] = A.tw[i << (A.lgTw - 9)];
+  const int kx = blockIdx.x * P + q;
+  const bool act = kx < A.ni;
+  const int b = blockIdx.y;
+  const cx<T>* in = A.in[blockIdx.z] + (long)b * A.sb_in + kx;
+  cx<T>* out = A.out[blockIdx.z] + (long)b * A.sb_out + kx;
+  const bool inv = A.inv != 0;
+  auto W = [&](int e) {  // W_512^{e} (conjugated for the inverse)
+    cx<T> v = w[e & 511];
+    if (inv) v.y = -v.y;
+    return v;
+  };
+  cx<T> v[8];
+  if (!inv) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int row = t + 64 * m;
+      v[m] = (act && row < A.n_in) ? in[(long)row * A.sa_in] : zero<T>();
+    }
+    __syncthreads();
+    dft8(v, false);
+    const int t0 = t & 7, t1 = t >> 3;
+#pragma unroll
+    for (int k2 = 1; k2 < 8; ++k2) v[k2] = cmul(v[k2], W(t * k2));
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) xb[(k2 * 8 + t0) * S + t1 * P + q] = v[k2];
+    __syncthreads();
+    {
+      const int k2 = t >> 3, u0 = t & 7;
+#pragma unroll
+      for (int u1 = 0; u1 < 8; ++u1) v[u1] = xb[(k2 * 8 + u0) * S + u1 * P + q];
+      dft8(v, false);
+#pragma unroll
+      for (int ka = 1; ka < 8; ++ka) v[ka] = cmul(v[ka], W(8 * u0 * ka));
+      __syncthreads();
+#pragma unroll
+      for (int ka = 0; ka < 8; ++ka) xb[(k2 * 8 + ka) * S + u0 * P + q] = v[ka];
+    }
+    __syncthreads();
+    {
+      const int k2 = t >> 3, ka = t & 7;
+#pragma unroll
+      for (int u0 = 0; u0 < 8; ++u0) v[u0] = xb[(k2 * 8 + ka) * S + u0 * P + q];
+      dft8(v, false);
+      if (act) {
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) {
+          const int k = k2 + 8 * ka + 64 * kb;
+          if (k < A.n_out) out[(long)k * A.sa_out] = v[kb];
+        }
+      }
+    }
+  } else {
+    const int k2 = t >> 3, ka = t & 7;
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      const int k = k2 + 8 * ka + 64 * kb;
+      v[kb] = (act && k < A.n_in) ? in[(long)k * A.sa_in] : zero<T>();
+    }
+    __syncthreads();
+    dft8(v, true);  // index t0
+#pragma unroll
+    for (int t0 = 1; t0 < 8; ++t0) v[t0] = cmul(v[t0], W(8 * t0 * ka));
+#pragma unroll
+    for (int t0 = 0; t0 < 8; ++t0) xb[(k2 * 8 + t0) * S + ka * P + q] = v[t0];
+    __syncthreads();
+    {
+      const int kk2 = t >> 3, t0 = t & 7;
+#pragma unroll
+      for (int a = 0; a < 8; ++a) v[a] = xb[(kk2 * 8 + t0) * S + a * P + q];
+      dft8(v, true);  // index t1
+#pragma unroll
+      for (int t1 = 0; t1 < 8; ++t1) v[t1] = cmul(v[t1], W((t0 + 8 * t1) * kk2));
+      __syncthreads();
+#pragma unroll
+      for (int t1 = 0; t1 < 8; ++t1) xb[(t0 + 8 * t1) * S + kk2 * P + q] = v[t1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk2 = 0; kk2 < 8; ++kk2) v[kk2] = xb[t * S + kk2 * P + q];
+    dft8(v, true);  // index m: x[t + 64 m]
+    if (act) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int row = t + 64 * m;
+        if (row < A.n_out) out[(long)row * A.sa_out] = v[m];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Last-axis stray-field convolution.  LDS layout buf[j * 3P + c * P + q].
 __device__ __forceinline__ int comp_index(int a, int b) {
@@ -1258,6 +1366,13 @@ template <typename T> void launch_col_dct(const ColDct<T>& a, int nbatch, int nc
 }
 
 template <typename T> void launch_col_fft(const ColFft<T>& a, int nbatch, int nch, hipStream_t s) {
+  if (a.lgL == 9) {
+    constexpr int P = sizeof(T) == 4 ? 8 : 4;
+    dim3 grid(ceil_div(a.ni, P), nbatch, nch);
+    const size_t lds = (512 + (size_t)64 * (8 * P + 1)) * sizeof(cx<T>);
+    hipLaunchKernelGGL((k_fft512<T, P>), grid, dim3(64 * P), lds, s, a);
+    return;
+  }
   dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, nch);
   const size_t lds = ((size_t)(1 << a.lgL) + ((size_t)1 << (a.lgP + a.lgL))) * sizeof(cx<T>);
   hipLaunchKernelGGL(k_col_fft<T>, grid, dim3(NT), lds, s, a);
