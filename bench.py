@@ -26,8 +26,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-updates/s per SGSPM step (fwd, adjoint) FP32 vs FP64 at stated error; %HBM"
 HBM_PEAK_GBS = 8000.0
+# timing class -> kernel (rocprofv3 shows the float instance as sgspm::k_...<float>)
 KERNEL_NAMES = {"row_fwd": "k_row_fwd", "row_inv": "k_row_inv", "col_dct": "k_col_dct",
-                "col_fft": "k_col_fft", "conv": "k_conv", "other": "other"}
+                "yz_solve": "k_yz_solve", "yz_reg": "k_yz_reg", "col_fft": "k_col_fft", "fft512": "k_fft512",
+                "conv": "k_conv", "conv64": "k_conv64", "other": "point-wise/reduction kernels"}
 WORKLOAD_TEXT = {
     "block-256x256x32": "256x256x32 block, 4 nm cells, exchange+anisotropy+stray (padded 512x512x64 FFT)+rotating 10 mT, "
           "alpha 1e-3, dt 0.05 ps",
@@ -181,7 +183,7 @@ def main():
             P = scheme.Problem(n=c.n, h=c.h, eps=c.eps, dt=c.dt)
             he = list(B[0])
         P.spectra()
-        S = 2 if N >= 1 << 20 else 20
+        S = 6 if N >= 1 << 20 else 20  # about 10-20 s of oracle work on 8 cores
         t0 = time.perf_counter()
         ref = np.asarray(m0, np.float64)
         first = None

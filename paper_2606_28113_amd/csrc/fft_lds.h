@@ -79,6 +79,95 @@ template <typename T> __device__ __forceinline__ void dft8(cx<T>* v, bool inv) {
   v[7] = e3 - w3;
 }
 
+// v * W_32^e (conjugated for the inverse) for a compile-time exponent e
+template <typename T, int E> __device__ __forceinline__ cx<T> tw32(cx<T> a, bool inv) {
+  constexpr int e = E & 31;
+  if constexpr (e == 0) return a;
+  else if constexpr (e == 8) return rot(a, inv);
+  else if constexpr (e == 16) return mk(-a.x, -a.y);
+  else if constexpr (e == 24) return rot(a, !inv);
+  else {
+    // cos and sin of pi e / 16, built from cos and sin of pi/16, 2 pi/16, 3 pi/16, 4 pi/16
+    constexpr double C1 = 0.98078528040323044912618223613424163, S1 = 0.19509032201612826784828486847702224;
+    constexpr double C2 = 0.92387953251128675612818318939678829, S2 = 0.38268343236508977172845998403039887;
+    constexpr double C3 = 0.83146961230254523707878837761790760, S3 = 0.55557023301960222474283081394853288;
+    constexpr double R2 = 0.70710678118654752440084436210484904;
+    constexpr double cq[9] = {1, C1, C2, C3, R2, S3, S2, S1, 0};  // cos(pi q / 16), q = 0..8
+    constexpr int q = e & 15;
+    constexpr double c0 = q <= 8 ? cq[q] : -cq[16 - q];
+    constexpr double s0 = q <= 8 ? cq[8 - q] : cq[q - 8];
+    constexpr double c = e < 16 ? c0 : -c0;
+    constexpr double sn = e < 16 ? s0 : -s0;
+    const T cr = (T)c;
+    const T sg = inv ? (T)sn : (T)-sn;
+    return mk(a.x * cr - a.y * sg, a.x * sg + a.y * cr);
+  }
+}
+template <typename T, int E> __device__ __forceinline__ cx<T> tw16(cx<T> a, bool inv) { return tw32<T, 2 * E>(a, inv); }
+
+// 16-point DFT in registers (4 x 4): natural order in and out
+template <typename T> __device__ __forceinline__ void dft16(cx<T>* v, bool inv) {
+  cx<T> u[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) {
+    cx<T> a0 = v[n1], a1 = v[n1 + 4], a2 = v[n1 + 8], a3 = v[n1 + 12];
+    dft4v(a0, a1, a2, a3, inv);
+    u[4 * n1] = a0;
+    u[4 * n1 + 1] = a1;
+    u[4 * n1 + 2] = a2;
+    u[4 * n1 + 3] = a3;
+  }
+  u[5] = tw16<T, 1>(u[5], inv);
+  u[6] = tw16<T, 2>(u[6], inv);
+  u[7] = tw16<T, 3>(u[7], inv);
+  u[9] = tw16<T, 2>(u[9], inv);
+  u[10] = tw16<T, 4>(u[10], inv);
+  u[11] = tw16<T, 6>(u[11], inv);
+  u[13] = tw16<T, 3>(u[13], inv);
+  u[14] = tw16<T, 6>(u[14], inv);
+  u[15] = tw16<T, 9>(u[15], inv);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<T> a0 = u[k1], a1 = u[4 + k1], a2 = u[8 + k1], a3 = u[12 + k1];
+    dft4v(a0, a1, a2, a3, inv);
+    v[k1] = a0;
+    v[k1 + 4] = a1;
+    v[k1 + 8] = a2;
+    v[k1 + 12] = a3;
+  }
+}
+
+// 32-point DFT in registers (even / odd halves), natural order
+template <typename T, int K = 0> __device__ __forceinline__ void dft32_merge(cx<T>* v, const cx<T>* e, const cx<T>* o,
+                                                                             bool inv) {
+  if constexpr (K < 16) {
+    const cx<T> t = tw32<T, K>(o[K], inv);
+    v[K] = e[K] + t;
+    v[K + 16] = e[K] - t;
+    dft32_merge<T, K + 1>(v, e, o, inv);
+  }
+}
+template <typename T> __device__ __forceinline__ void dft32(cx<T>* v, bool inv) {
+  cx<T> e[16], o[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    e[i] = v[2 * i];
+    o[i] = v[2 * i + 1];
+  }
+  dft16(e, inv);
+  dft16(o, inv);
+  dft32_merge<T>(v, e, o, inv);
+}
+
+// N-point DFT in registers, natural order, N <= 32 a power of two
+template <typename T, int N> __device__ __forceinline__ void dft_reg(cx<T>* v, bool inv) {
+  if constexpr (N == 2) dft2(v, inv);
+  else if constexpr (N == 4) dft4(v, inv);
+  else if constexpr (N == 8) dft8(v, inv);
+  else if constexpr (N == 16) dft16(v, inv);
+  else if constexpr (N == 32) dft32(v, inv);
+}
+
 template <typename T, int R> __device__ __forceinline__ void dftR(cx<T>* v, bool inv) {
   if constexpr (R == 2) dft2(v, inv);
   else if constexpr (R == 4) dft4(v, inv);

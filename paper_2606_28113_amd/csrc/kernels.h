@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_lds.h"
+#include "../../include/sgspm.h"
 
 namespace sgspm {
 
@@ -123,7 +124,7 @@ template <typename T> struct YZSolve {
   const T* lamZ;
   T s;
 };
-template <typename T> void launch_yz_solve(const YZSolve<T>& a, int nch, hipStream_t s);
+template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStream_t s);
 // largest plane (ny * nz reals) the fused yz solve holds in one workgroup
 template <typename T> constexpr int yz_max_plane() { return sizeof(T) == 4 ? 8192 : 4096; }
 
@@ -145,11 +146,11 @@ template <typename T> struct Conv {
   int lgTw;
 };
 
-template <typename T> void launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_t s);
-template <typename T> void launch_row_inv(const RowInv<T>& a, hipStream_t s);
-template <typename T> void launch_col_dct(const ColDct<T>& a, int nbatch, int nch, hipStream_t s);
-template <typename T> void launch_col_fft(const ColFft<T>& a, int nbatch, int nch, hipStream_t s);
-template <typename T> void launch_conv(const Conv<T>& a, int nbatch, hipStream_t s);
+template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_t s);
+template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s);
+template <typename T> int launch_col_dct(const ColDct<T>& a, int nbatch, int nch, hipStream_t s);
+template <typename T> int launch_col_fft(const ColFft<T>& a, int nbatch, int nch, hipStream_t s);
+template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t s);
 // kx tile (log2) of the convolution for a padded pencil of 2^lgL and nt tensor components
 template <typename T> int conv_lgP(int lgL, int ni, int nt);
 

@@ -1345,48 +1345,237 @@ __global__ __launch_bounds__(NT) void k_adj_damp(const T* lw, const T* u, const 
 // Launchers
 static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
-template <typename T> void launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_t s) {
+// 1 / x: the hardware reciprocal in single precision (within 1 ulp), a correctly
+// rounded division in double
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// ---------------------------------------------------------------------------
+// Register version of the y-z heat solve for one x-major plane [NZ][NY] per
+// workgroup (NY = 16 R2, NZ <= 32), one thread team of R2 threads per pair of
+// z rows (a = r, b = r + NZ/2) packed as one complex pencil.
+//  y forward: Makhoul reordering on the load, 16-point DFT in registers over
+//    the stride-R2 digit, twiddle, one padded LDS transpose, length-R2 DFTs:
+//    the pencil's spectrum lands in row r of the LDS array Zs.
+//  z: thread c owns the column pair (c, NY - c) (c = 0 owns 0 and NY/2); it
+//    separates the two rows of every pencil into y-DCT coefficients, packs its
+//    two columns into one complex z pencil and does the z DCT-II, the diagonal
+//    1 / (1 + s (lamX + lamY + lamZ)), and the z DCT-III entirely in registers,
+//    then writes the pre-twiddled y-inverse input of its columns back to Zs.
+//  y inverse: the forward steps mirrored; stores undo the reordering and scale
+//    by 1 / (NY NZ).
+template <typename T, int LGY, int LGZ>
+__global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(const YZSolve<T> A) {
+  constexpr int NY = 1 << LGY, NZ = 1 << LGZ, HZ = NZ / 2;
+  constexpr int R2 = NY / 16, G = 16 / R2, NTH = HZ * R2, RS = NY + 16;
+  static_assert(LGY >= 5 && LGY <= 8 && LGZ >= 1 && LGZ <= 5 && LGZ <= LGY, "unsupported plane");
+  static_assert(NY / 2 <= NTH, "one z thread per column pair");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* Wy = reinterpret_cast<cx<T>*>(smem_raw);  // W_NY^i
+  cx<T>* Zs = Wy + NY;                             // [HZ][RS]
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NY; i += NTH) Wy[i] = A.tw[i << (A.lgTw - LGY)];
+  const int r = tid / R2, t = tid % R2;
+  T* D = A.data[blockIdx.z] + (long)blockIdx.x * (NY * NZ);
+  cx<T>* zs = Zs + r * RS;
+  auto minv = [](int p) { return p < NY / 2 ? 2 * p : 2 * (NY - 1 - p) + 1; };
+
+  // ---- y forward
+  {
+    cx<T> v[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int y = minv(t + R2 * m);
+      v[m] = mk<T>(D[r * NY + y], D[(r + HZ) * NY + y]);
+    }
+    __syncthreads();
+    dft16(v, false);
+#pragma unroll
+    for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], Wy[(t * k1) & (NY - 1)]);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) zs[k1 * (R2 + 1) + t] = v[k1];
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int k1 = t * G + g;
+#pragma unroll
+      for (int q = 0; q < R2; ++q) v[g * R2 + q] = zs[k1 * (R2 + 1) + q];
+      dft_reg<T, R2>(v + g * R2, false);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int k1 = t * G + g;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) zs[k1 + 16 * k2] = v[g * R2 + k2];
+    }
+    __syncthreads();
+  }
+
+  // ---- z pass on column pairs
+  if (tid < NY / 2) {
+    const int c = tid;
+    const int ca = c, cb = c ? NY - c : NY / 2;
+    const cx<T> wa = A.dtwy[ca], wb = A.dtwy[cb];
+    cx<T> z[NZ];
+#pragma unroll
+    for (int q = 0; q < HZ; ++q) {
+      // the partner of column ca is cb, except for c = 0 where 0 and NY/2 pair with themselves
+      const cx<T> Za = Zs[q * RS + ca];
+      const cx<T> Zb = Zs[q * RS + cb];
+      const cx<T> Zam = c ? Zb : Za;
+      const cx<T> Zbm = c ? Za : Zb;
+      const cx<T> Va = mk<T>((Za.x + Zam.x) * (T)0.5, (Za.y - Zam.y) * (T)0.5);
+      const cx<T> Vb = mk<T>((Za.y + Zam.y) * (T)0.5, (Zam.x - Za.x) * (T)0.5);
+      const cx<T> Vc = mk<T>((Zb.x + Zbm.x) * (T)0.5, (Zb.y - Zbm.y) * (T)0.5);
+      const cx<T> Vd = mk<T>((Zb.y + Zbm.y) * (T)0.5, (Zbm.x - Zb.x) * (T)0.5);
+      // element z of the packed z pencil: column ca in .x, column cb in .y,
+      // stored at its Makhoul position
+      const int za = q, zb = q + HZ;
+      const int pa = (za & 1) ? NZ - 1 - (za >> 1) : (za >> 1);
+      const int pb = (zb & 1) ? NZ - 1 - (zb >> 1) : (zb >> 1);
+      z[pa] = mk<T>(wa.x * Va.x - wa.y * Va.y, wb.x * Vc.x - wb.y * Vc.y);
+      z[pb] = mk<T>(wa.x * Vb.x - wa.y * Vb.y, wb.x * Vd.x - wb.y * Vd.y);
+    }
+    dft_reg<T, NZ>(z, false);
+    const T lx = A.lamX[blockIdx.x];
+    const T da = (T)1 + A.s * (lx + A.lamY[ca]), db = (T)1 + A.s * (lx + A.lamY[cb]);
+    // z DCT-II coefficients at k and NZ - k come from the same two spectrum
+    // values, and so does the DCT-III input at both: process the pair in place
+#pragma unroll
+    for (int k = 0; k <= NZ / 2; ++k) {
+      const int m = (NZ - k) & (NZ - 1);
+      const cx<T> Zk = z[k], Zm = z[m];
+      const cx<T> VA = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+      const cx<T> VB = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+      const cx<T> wk = A.dtwz[k];
+      const T szk = A.s * A.lamZ[k];
+      const T xak = (wk.x * VA.x - wk.y * VA.y) * recip(da + szk);
+      const T xbk = (wk.x * VB.x - wk.y * VB.y) * recip(db + szk);
+      if (m == k) {
+        // k = 0 pairs with the absent coefficient NZ, k = NZ/2 with itself
+        const T pa = k ? xak : (T)0, pb = k ? xbk : (T)0;
+        const cx<T> ua = cmul(conjg(wk), mk<T>(xak, -pa));
+        const cx<T> ub = cmul(conjg(wk), mk<T>(xbk, -pb));
+        z[k] = mk<T>(ua.x - ub.y, ua.y + ub.x);
+      } else {
+        // the coefficients at m use conj(VA), conj(VB)
+        const cx<T> wm = A.dtwz[m];
+        const T szm = A.s * A.lamZ[m];
+        const T xam = (wm.x * VA.x + wm.y * VA.y) * recip(da + szm);
+        const T xbm = (wm.x * VB.x + wm.y * VB.y) * recip(db + szm);
+        const cx<T> uak = cmul(conjg(wk), mk<T>(xak, -xam));
+        const cx<T> ubk = cmul(conjg(wk), mk<T>(xbk, -xbm));
+        const cx<T> uam = cmul(conjg(wm), mk<T>(xam, -xak));
+        const cx<T> ubm = cmul(conjg(wm), mk<T>(xbm, -xbk));
+        z[k] = mk<T>(uak.x - ubk.y, uak.y + ubk.x);
+        z[m] = mk<T>(uam.x - ubm.y, uam.y + ubm.x);
+      }
+    }
+    dft_reg<T, NZ>(z, true);
+    const cx<T> ia = conjg(wa), ib = conjg(wb);
+#pragma unroll
+    for (int q = 0; q < HZ; ++q) {
+      const int za = q, zb = q + HZ;
+      const cx<T> A_ = z[(za & 1) ? NZ - 1 - (za >> 1) : (za >> 1)];  // row a: col ca (.x), col cb (.y)
+      const cx<T> B_ = z[(zb & 1) ? NZ - 1 - (zb >> 1) : (zb >> 1)];  // row b
+      // y-inverse input of each row at columns ca and cb
+      const cx<T> a_ca = cmul(ia, mk<T>(A_.x, c ? -A_.y : (T)0));
+      const cx<T> a_cb = cmul(ib, mk<T>(A_.y, c ? -A_.x : -A_.y));
+      const cx<T> b_ca = cmul(ia, mk<T>(B_.x, c ? -B_.y : (T)0));
+      const cx<T> b_cb = cmul(ib, mk<T>(B_.y, c ? -B_.x : -B_.y));
+      Zs[q * RS + ca] = mk<T>(a_ca.x - b_ca.y, a_ca.y + b_ca.x);
+      Zs[q * RS + cb] = mk<T>(a_cb.x - b_cb.y, a_cb.y + b_cb.x);
+    }
+  }
+  __syncthreads();
+
+  // ---- y inverse
+  {
+    cx<T> v[16];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int k1 = t * G + g;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) v[g * R2 + k2] = zs[k1 + 16 * k2];
+      dft_reg<T, R2>(v + g * R2, true);
+#pragma unroll
+      for (int q = 1; q < R2; ++q) v[g * R2 + q] = cmul(v[g * R2 + q], conjg(Wy[(q * k1) & (NY - 1)]));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int k1 = t * G + g;
+#pragma unroll
+      for (int q = 0; q < R2; ++q) zs[k1 * (R2 + 1) + q] = v[g * R2 + q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) v[k1] = zs[k1 * (R2 + 1) + t];
+    dft16(v, true);
+    const T sc = (T)1 / (T)(NY * NZ);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int y = minv(t + R2 * m);
+      D[r * NY + y] = v[m].x * sc;
+      D[(r + HZ) * NY + y] = v[m].y * sc;
+    }
+  }
+}
+
+template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_t s) {
   const int rows = 2 << a.lgP;
   dim3 grid(ceil_div(a.nrows, rows), 1, nch);
   const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1)) * sizeof(cx<T>);
   hipLaunchKernelGGL(k_row_fwd<T>, grid, dim3(NT), lds, s, a);
+  return SGSPM_KC_ROW_FWD;
 }
 
-template <typename T> void launch_row_inv(const RowInv<T>& a, hipStream_t s) {
+template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
   const int rows = 2 << a.lgP;
   dim3 grid(ceil_div(a.nrows, rows), 1, 1);
   const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1)) * sizeof(cx<T>);
   hipLaunchKernelGGL(k_row_inv<T>, grid, dim3(NT), lds, s, a);
+  return SGSPM_KC_ROW_INV;
 }
 
-template <typename T> void launch_col_dct(const ColDct<T>& a, int nbatch, int nch, hipStream_t s) {
+template <typename T> int launch_col_dct(const ColDct<T>& a, int nbatch, int nch, hipStream_t s) {
   dim3 grid(ceil_div(a.ni, 2 << a.lgP), nbatch, nch);
   const size_t lds = ((size_t)(1 << a.lgN) + ((size_t)1 << (a.lgP + a.lgN))) * sizeof(cx<T>);
   hipLaunchKernelGGL(k_col_dct<T>, grid, dim3(NT), lds, s, a);
+  return SGSPM_KC_COL_DCT;
 }
 
-template <typename T> void launch_col_fft(const ColFft<T>& a, int nbatch, int nch, hipStream_t s) {
+template <typename T> int launch_col_fft(const ColFft<T>& a, int nbatch, int nch, hipStream_t s) {
   if (a.lgL == 9) {
     constexpr int P = sizeof(T) == 4 ? 8 : 4;
     dim3 grid(ceil_div(a.ni, P), nbatch, nch);
     const size_t lds = (512 + (size_t)64 * (8 * P + 1)) * sizeof(cx<T>);
     hipLaunchKernelGGL((k_fft512<T, P>), grid, dim3(64 * P), lds, s, a);
-    return;
+    return SGSPM_KC_FFT512;
   }
   dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, nch);
   const size_t lds = ((size_t)(1 << a.lgL) + ((size_t)1 << (a.lgP + a.lgL))) * sizeof(cx<T>);
   hipLaunchKernelGGL(k_col_fft<T>, grid, dim3(NT), lds, s, a);
+  return SGSPM_KC_COL_FFT;
 }
 
-template <typename T> void launch_yz_solve(const YZSolve<T>& a, int nch, hipStream_t s) {
+template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStream_t s) {
   const int lgL = std::max(a.lgNy, a.lgNz);
   const int lgR = a.lgNy + a.lgNz + a.lgPP;
   const int Hy = 1 << std::max(0, a.lgPP + a.lgNz - 1), Hz = 1 << std::max(0, a.lgPP + a.lgNy - 1);
   const size_t nbuf = std::max((size_t)(1 << a.lgNy) * (Hy + 1), (size_t)(1 << a.lgNz) * (Hz + 1));
   const size_t lds = ((size_t)(1 << lgL) + nbuf) * sizeof(cx<T>);
   (void)lgR;
+  if (a.lgNy == 8 && a.lgNz == 5) {
+    constexpr int NY = 256, NZ = 32;
+    const size_t lr = (NY + (size_t)(NZ / 2) * (NY + 16)) * sizeof(cx<T>);
+    hipLaunchKernelGGL((k_yz_reg<T, 8, 5>), dim3(a.nx, 1, nch), dim3((NZ / 2) * (NY / 16)), lr, s, a);
+    return SGSPM_KC_YZ_REG;
+  }
   dim3 grid(ceil_div(a.nx, 1 << a.lgPP), 1, nch);
   hipLaunchKernelGGL(k_yz_solve<T>, grid, dim3(YZ_NT), lds, s, a);
+  return SGSPM_KC_YZ_SOLVE;
 }
 
 template <typename T> size_t conv_lds(int lgL, int lgP, int nt) {
@@ -1408,7 +1597,7 @@ template <typename T> int conv_lgP(int lgL, int ni, int nt) {
   return lgP;
 }
 
-template <typename T> void launch_conv(const Conv<T>& a, int nbatch, hipStream_t s) {
+template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t s) {
   if (a.lgL == 6 && a.n <= 32) {
     // register four-step kernel: 16 kx x 2 batch rows x 8 threads per pencil
     Conv<T> b = a;
@@ -1416,10 +1605,11 @@ template <typename T> void launch_conv(const Conv<T>& a, int nbatch, hipStream_t
     dim3 grid(ceil_div(a.ni, 16), nbatch, 1);
     const size_t lds = (64 + (size_t)3 * 64 * 32) * sizeof(cx<T>);
     hipLaunchKernelGGL(k_conv64<T>, grid, dim3(C64_NT), lds, s, b);
-    return;
+    return SGSPM_KC_CONV64;
   }
   dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, 1);
   hipLaunchKernelGGL(k_conv<T>, grid, dim3(CONV_NT), conv_lds<T>(a.lgL, a.lgP, a.nt), s, a);
+  return SGSPM_KC_CONV;
 }
 
 void launch_newell_fill(double* out, int comp, int nx, int ny, int nz, int Px, int Py, int Pz, double hx, double hy,
@@ -1487,13 +1677,13 @@ void launch_adj_damp(const T* lw, const T* u, const T* nrm, const T* const uF[3]
 }
 
 #define SGSPM_INSTANTIATE(T)                                                                                          \
-  template void launch_row_fwd<T>(const RowFwd<T>&, int, hipStream_t);                                              \
-  template void launch_row_inv<T>(const RowInv<T>&, hipStream_t);                                                   \
-  template void launch_col_dct<T>(const ColDct<T>&, int, int, hipStream_t);                                         \
-  template void launch_col_fft<T>(const ColFft<T>&, int, int, hipStream_t);                                         \
-  template void launch_conv<T>(const Conv<T>&, int, hipStream_t);                                                   \
+  template int launch_row_fwd<T>(const RowFwd<T>&, int, hipStream_t);                                              \
+  template int launch_row_inv<T>(const RowInv<T>&, hipStream_t);                                                   \
+  template int launch_col_dct<T>(const ColDct<T>&, int, int, hipStream_t);                                         \
+  template int launch_col_fft<T>(const ColFft<T>&, int, int, hipStream_t);                                         \
+  template int launch_conv<T>(const Conv<T>&, int, hipStream_t);                                                   \
   template int conv_lgP<T>(int, int, int);                                                                          \
-  template void launch_yz_solve<T>(const YZSolve<T>&, int, hipStream_t);                                            \
+  template int launch_yz_solve<T>(const YZSolve<T>&, int, hipStream_t);                                            \
   template void launch_tensor_pack<T>(const cx<double>*, T*, int, int, int, int, int, double, hipStream_t);         \
   template void launch_field_assemble<T>(const T*, const T*, T*, int, int, int, double, double, double, double,    \
                                          double, const double*, hipStream_t);                                       \

@@ -208,19 +208,20 @@ template <typename T> struct Eng {
   hipEvent_t ev() {
     if (P.evnext == P.evpool.size()) {
       hipEvent_t e;
-      (void)hipEventCreate(&e);
+      (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
       P.evpool.push_back(e);
     }
     return P.evpool[P.evnext++];
   }
-  template <class F> void timed(int cls, double bytes, F&& fn) {
+  // fn launches one kernel and returns its class (SGSPM_KC_*)
+  template <class F> void timed(double bytes, F&& fn) {
     if (!P.timing) {
-      fn();
+      (void)fn();
       return;
     }
     hipEvent_t a = ev(), b = ev();
     (void)hipEventRecord(a, s);
-    fn();
+    const int cls = fn();
     (void)hipEventRecord(b, s);
     P.recs.push_back({cls, a, b, bytes});
   }
@@ -287,7 +288,7 @@ template <typename T> struct Eng {
       by += (A.u[c] ? P.N * TS : 0) + (A.w[c] ? P.N * TS : 0) + (A.xin[c] ? cpx : 0) +
             (A.hs_out[c] ? P.N * TS : 0) + (A.val_out[c] ? P.N * TS : 0) + (A.dct_out[c] ? P.N * TS : 0) +
             (A.xout[c] ? cpx : 0);
-    timed(SGSPM_KC_ROW_FWD, by, [&] { launch_row_fwd<T>(A, nch, s); });
+    timed(by, [&] { return launch_row_fwd<T>(A, nch, s); });
   }
   const cx<T>* c2r_src_for_[3] = {nullptr, nullptr, nullptr};
   bool tape = false;
@@ -309,7 +310,7 @@ template <typename T> struct Eng {
     if (A.op == ROW_OP_GS) by += (4 + (A.src ? 1 : 0) + 1) * P.N * TS;
     if (A.op == ROW_OP_PROJECT) by += (3 + (A.nrm ? 1 : 0)) * P.N * TS;
     if (A.xout) by += (double)A.nrows * P.Kx * 2 * TS;
-    timed(SGSPM_KC_ROW_INV, by, [&] { launch_row_inv<T>(A, s); });
+    timed(by, [&] { return launch_row_inv<T>(A, s); });
   }
 
   // ---- heat solves: after row_fwd wrote DCT_x(rhs) into heat[0..nch)
@@ -335,7 +336,7 @@ template <typename T> struct Eng {
       A.lamY = lam[1];
       A.lamZ = lam[2];
       A.s = sdt;
-      timed(SGSPM_KC_COL_DCT, 2.0 * nch * P.N * TS, [&] { launch_yz_solve<T>(A, nch, s); });
+      timed(2.0 * nch * P.N * TS, [&] { return launch_yz_solve<T>(A, nch, s); });
       return;
     }
     if (P.has_mid) {
@@ -350,7 +351,7 @@ template <typename T> struct Eng {
       A.dtw = dtw[1];
       A.tw = tw;
       A.lgTw = P.lgTw;
-      timed(SGSPM_KC_COL_DCT, 2.0 * nch * P.N * TS, [&] { launch_col_dct<T>(A, P.nz, nch, s); });
+      timed(2.0 * nch * P.N * TS, [&] { return launch_col_dct<T>(A, P.nz, nch, s); });
     }
     {
       ColDct<T> A{};
@@ -369,7 +370,7 @@ template <typename T> struct Eng {
       A.lamB = z ? lam[1] : lam[2];
       A.lamA = z ? lam[2] : lam[1];
       A.s = sdt;
-      timed(SGSPM_KC_COL_DCT, 2.0 * nch * P.N * TS, [&] { launch_col_dct<T>(A, z ? P.ny : 1, nch, s); });
+      timed(2.0 * nch * P.N * TS, [&] { return launch_col_dct<T>(A, z ? P.ny : 1, nch, s); });
     }
     if (P.has_mid) {
       ColDct<T> A{};
@@ -383,7 +384,7 @@ template <typename T> struct Eng {
       A.dtw = dtw[1];
       A.tw = tw;
       A.lgTw = P.lgTw;
-      timed(SGSPM_KC_COL_DCT, 2.0 * nch * P.N * TS, [&] { launch_col_dct<T>(A, P.nz, nch, s); });
+      timed(2.0 * nch * P.N * TS, [&] { return launch_col_dct<T>(A, P.nz, nch, s); });
     }
   }
 
@@ -412,7 +413,7 @@ template <typename T> struct Eng {
     A.tw = tw;
     A.lgTw = P.lgTw;
     const double cb = (double)P.Kx * P.nz * 2 * TS;
-    timed(SGSPM_KC_COL_FFT, k * cb * (P.ny + P.Py), [&] { launch_col_fft<T>(A, P.nz, k, s); });
+    timed(k * cb * (P.ny + P.Py), [&] { return launch_col_fft<T>(A, P.nz, k, s); });
   }
   void mid_inv(int mask) {
     if (!P.has_mid) return;
@@ -437,7 +438,7 @@ template <typename T> struct Eng {
     A.tw = tw;
     A.lgTw = P.lgTw;
     const double cb = (double)P.Kx * P.nz * 2 * TS;
-    timed(SGSPM_KC_COL_FFT, k * cb * (P.ny + P.Py), [&] { launch_col_fft<T>(A, P.nz, k, s); });
+    timed(k * cb * (P.ny + P.Py), [&] { return launch_col_fft<T>(A, P.nz, k, s); });
   }
   void conv(int mask, int smask = 7) {
     Conv<T> A{};
@@ -488,7 +489,7 @@ template <typename T> struct Eng {
     const int nrows = (z && P.has_mid) ? P.Py : 1;
     const double slab = (double)A.n * A.ni * nrows * 2 * TS;
     const double tb = A.nt * (double)(z ? P.Hz : P.Hy) * A.Hb * A.ni * TS;
-    timed(SGSPM_KC_CONV, 3 * slab + nout * slab + tb, [&] { launch_conv<T>(A, nb, s); });
+    timed(3 * slab + nout * slab + tb, [&] { return launch_conv<T>(A, nb, s); });
   }
 
   // forward transforms of real fields into the component spectra
@@ -745,7 +746,7 @@ template <typename T> struct Eng {
     std::vector<PwTerm<T>> t(terms);
     double by = 0;
     for (auto& x : t) by += TS * P.N * (1 + x.acc + (x.x0 ? 1 : 0) + (x.y0 ? 1 : 0) + (x.x1 ? 1 : 0) + (x.y1 ? 1 : 0));
-    timed(SGSPM_KC_OTHER, by, [&] { launch_pw<T>(t.data(), (int)t.size(), P.N, s); });
+    timed(by, [&] { launch_pw<T>(t.data(), (int)t.size(), P.N, s); return (int)SGSPM_KC_OTHER; });
   }
   static PwTerm<T> set1(T* out, double c0, const T* x0, const T* y0 = nullptr) {
     return PwTerm<T>{out, 0, c0, 0.0, x0, y0, nullptr, nullptr};
@@ -764,7 +765,7 @@ template <typename T> struct Eng {
     for (auto v : ws) w[k++] = v;
     int n = 0;
     for (auto v : slots) sl[n++] = v;
-    timed(SGSPM_KC_OTHER, n * P.N * TS, [&] { launch_wsum<T>(x, w, sl, n, P.N, P.partials, P.nred, grad, s); });
+    timed(n * P.N * TS, [&] { launch_wsum<T>(x, w, sl, n, P.N, P.partials, P.nred, grad, s); return (int)SGSPM_KC_OTHER; });
   }
 
   // Adjoint of one SGSPM step (reverse of step(), latest-state reading).

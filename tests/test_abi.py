@@ -20,6 +20,16 @@ def test_header_and_binding_agree():
     assert _declared() == sorted(binding.EXPORTS)
 
 
+def test_kernel_classes_match_header():
+    """The binding's timing-class names follow the header's SGSPM_KC_* order."""
+    from paper_2606_28113_amd import binding
+    text = open(HEADER).read()
+    kc = dict((n, int(v)) for n, v in re.findall(r"SGSPM_KC_(\w+)\s*=\s*(\d+)", text))
+    count = kc.pop("COUNT")
+    assert count == len(binding.KERNEL_CLASSES)
+    assert [n.lower() for n, _ in sorted(kc.items(), key=lambda t: t[1])] == list(binding.KERNEL_CLASSES)
+
+
 def test_library_exports_every_declared_symbol():
     from paper_2606_28113_amd import binding
     lib = ctypes.CDLL(binding.lib_path)

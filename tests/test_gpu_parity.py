@@ -40,7 +40,7 @@ def _announce(request):
 
 
 HEAT_SHAPES = [(32, 32, 1), (128, 64, 1), (16, 8, 4), (8, 1, 1), (1, 1, 1), (1, 16, 1), (4, 1, 8),
-               (64, 32, 8), (2, 2, 2), (512, 32, 4), (1024, 2, 1), (256, 256, 32)]
+               (64, 32, 8), (2, 2, 2), (512, 32, 4), (1024, 2, 1), (256, 256, 32), (8, 256, 32)]
 
 
 @pytest.mark.parametrize("n", HEAT_SHAPES, ids=lambda n: "x".join(map(str, n)))
