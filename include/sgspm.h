@@ -127,17 +127,19 @@ int sgspm_adjoint_step(sgspm_plan_t plan, const void* m_n, double alpha, const d
 /* Measurement support.  Kernel classes of the step's launches; each class is
  * one kernel (its float or double instance): */
 enum {
-  SGSPM_KC_ROW_FWD = 0,  /* k_row_fwd: x rows: [c2r] -> right-hand side -> [DCT-II] / [r2c] */
-  SGSPM_KC_ROW_INV = 1,  /* k_row_inv: x rows: inverse DCT -> Gauss-Seidel update or projection -> [r2c] */
-  SGSPM_KC_COL_DCT = 2,  /* k_col_dct: y / z pencil DCT passes (grids without the fused solve) */
-  SGSPM_KC_YZ_SOLVE = 3, /* k_yz_solve: y and z DCTs and the diagonal solve of x-major planes */
-  SGSPM_KC_YZ_REG = 4,   /* k_yz_reg: the same for 256 x 32 planes, z pass in registers */
-  SGSPM_KC_COL_FFT = 5,  /* k_col_fft: y pencils, padded FFT / cropped inverse FFT (any length) */
-  SGSPM_KC_FFT512 = 6,   /* k_fft512: the same for length 512, in registers */
-  SGSPM_KC_CONV = 7,     /* k_conv: last-axis FFT, demagnetising-tensor multiply, inverse FFT */
-  SGSPM_KC_CONV64 = 8,   /* k_conv64: the same for a padded last axis of 64, in registers */
-  SGSPM_KC_OTHER = 9,    /* point-wise passes, reductions, energies */
-  SGSPM_KC_COUNT = 10
+  SGSPM_KC_ROW_FWD = 0,     /* k_row_fwd: x rows: [c2r] -> right-hand side -> [DCT-II] / [r2c] */
+  SGSPM_KC_ROW_FWD256 = 1,  /* k_row_fwd256: the same for rows of 256, in registers */
+  SGSPM_KC_ROW_INV = 2,     /* k_row_inv: x rows: inverse DCT -> Gauss-Seidel update or projection -> [r2c] */
+  SGSPM_KC_ROW_INV256 = 3,  /* k_row_inv256: the same for rows of 256, in registers */
+  SGSPM_KC_COL_DCT = 4,     /* k_col_dct: y / z pencil DCT passes (grids without the fused solve) */
+  SGSPM_KC_YZ_SOLVE = 5,    /* k_yz_solve: y and z DCTs and the diagonal solve of x-major planes */
+  SGSPM_KC_YZ_REG = 6,      /* k_yz_reg: the same for 256 x 32 planes, z pass in registers */
+  SGSPM_KC_COL_FFT = 7,     /* k_col_fft: y pencils, padded FFT / cropped inverse FFT (any length) */
+  SGSPM_KC_FFT512 = 8,      /* k_fft512: the same for length 512, in registers */
+  SGSPM_KC_CONV = 9,        /* k_conv: last-axis FFT, demagnetising-tensor multiply, inverse FFT */
+  SGSPM_KC_CONV64 = 10,     /* k_conv64: the same for a padded last axis of 64, in registers */
+  SGSPM_KC_OTHER = 11,      /* point-wise passes, reductions, energies */
+  SGSPM_KC_COUNT = 12
 };
 
 /* Enable (1) or disable (0) timing of every later launch with HIP events on

@@ -137,6 +137,37 @@ template <typename T> __device__ __forceinline__ void dft16(cx<T>* v, bool inv) 
   }
 }
 
+// 16-point DFT of a sequence whose entries 8..15 are zero (natural order out)
+template <typename T> __device__ __forceinline__ void dft16_lo8(cx<T>* v, bool inv) {
+  cx<T> u[16];
+#pragma unroll
+  for (int n1 = 0; n1 < 4; ++n1) {
+    const cx<T> a0 = v[n1], r1 = rot(v[n1 + 4], inv);
+    u[4 * n1] = a0 + v[n1 + 4];
+    u[4 * n1 + 1] = a0 + r1;
+    u[4 * n1 + 2] = a0 - v[n1 + 4];
+    u[4 * n1 + 3] = a0 - r1;
+  }
+  u[5] = tw16<T, 1>(u[5], inv);
+  u[6] = tw16<T, 2>(u[6], inv);
+  u[7] = tw16<T, 3>(u[7], inv);
+  u[9] = tw16<T, 2>(u[9], inv);
+  u[10] = tw16<T, 4>(u[10], inv);
+  u[11] = tw16<T, 6>(u[11], inv);
+  u[13] = tw16<T, 3>(u[13], inv);
+  u[14] = tw16<T, 6>(u[14], inv);
+  u[15] = tw16<T, 9>(u[15], inv);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<T> a0 = u[k1], a1 = u[4 + k1], a2 = u[8 + k1], a3 = u[12 + k1];
+    dft4v(a0, a1, a2, a3, inv);
+    v[k1] = a0;
+    v[k1 + 4] = a1;
+    v[k1 + 8] = a2;
+    v[k1 + 12] = a3;
+  }
+}
+
 // 32-point DFT in registers (even / odd halves), natural order
 template <typename T, int K = 0> __device__ __forceinline__ void dft32_merge(cx<T>* v, const cx<T>* e, const cx<T>* o,
                                                                              bool inv) {

@@ -1523,7 +1523,348 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register row kernels for rows of N = 256 (zero-padded transforms of 512).
+// A workgroup of 16 RR_PB threads takes RR_PB complex pencils (two real rows
+// each, rows a in .x and b in .y); a team of 16 threads works on one pencil.
+// Between transforms every thread t holds its pencil at the Makhoul positions
+// p = t + 16 m (m < 16) of the length-256 DCT reordering, x = 2p for p < 128
+// and x = 511 - 2p above; these are also the residues 2t and 31 - 2t modulo 32
+// of the 512-point transforms, so c2r -> pointwise -> DCT-II and inverse
+// DCT -> pointwise -> r2c chain without permutations.  Transforms:
+//  DCT-II (256 = 16 x 16): DFT-16 over m, W_256^{t k1}, transpose, DFT-16 over t.
+//  r2c (512 = 16 x 32): per residue r a DFT-16 over j (x = r + 32 j, j < 8
+//    nonzero), W_512^{r k1}, transpose, DFT-32 over r.
+//  c2r and the inverse DCT: the same steps reversed.
+// Each transpose swaps the role of the thread index; the mapping of threads to
+// (pencil, index) is chosen per phase so that global accesses coalesce:
+// index-fastest for row-major arrays, pencil-fastest for x-major ones.
+constexpr int RR_PB = 8;            // complex pencils (16 rows) per workgroup
+constexpr int RR_NT = 16 * RR_PB;
+constexpr int RR_SP = 545;          // LDS complex per pencil (largest transpose 32 x 17)
+
+__device__ __forceinline__ int rr_minv(int p) { return p < 128 ? 2 * p : 511 - 2 * p; }
+
+// c2r of the x-level half spectra of rows ra, ra + 1 (k <= 256), cropped to
+// x < 256; thread t (index-fastest mapping) receives h[m] at p = t + 16 m.
+template <typename T>
+__device__ __forceinline__ void rr_c2r(const cx<T>* __restrict__ xin, int pitch, int ra, int nrows, int t,
+                                       cx<T>* Sq, const cx<T>* W, cx<T> (&h)[16]) {
+  cx<T> u[32];
+#pragma unroll
+  for (int k2 = 0; k2 < 32; ++k2) {
+    const int k = t + 16 * k2;
+    const int kk = k <= 256 ? k : 512 - k;
+    cx<T> Xa = zero<T>(), Xb = zero<T>();
+    if (ra < nrows) Xa = xin[(long)ra * pitch + kk];
+    if (ra + 1 < nrows) Xb = xin[(long)(ra + 1) * pitch + kk];
+    if (kk == 0 || kk == 256) {
+      Xa.y = (T)0;
+      Xb.y = (T)0;
+    }
+    if (k > 256) {
+      Xa.y = -Xa.y;
+      Xb.y = -Xb.y;
+    }
+    u[k2] = mk<T>(Xa.x - Xb.y, Xa.y + Xb.x);
+  }
+  dft32(u, true);
+#pragma unroll
+  for (int r = 1; r < 32; ++r) u[r] = cmul(u[r], conjg(W[(r * t) & 511]));
+#pragma unroll
+  for (int r = 0; r < 32; ++r) Sq[r * 17 + t] = u[r];
+  __syncthreads();
+  cx<T> w[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) w[k1] = Sq[(2 * t) * 17 + k1];
+  dft16(w, true);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) h[j] = w[j];
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) w[k1] = Sq[(31 - 2 * t) * 17 + k1];
+  dft16(w, true);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) h[15 - j] = w[j];
+  __syncthreads();
+}
+
+// zero-padded r2c of v (Makhoul positions, index-fastest mapping) into the
+// half spectra of rows ra, ra + 1 (k <= 256)
+template <typename T>
+__device__ __forceinline__ void rr_r2c(const cx<T> (&v)[16], int ra, int nrows, int t, cx<T>* Sq, const cx<T>* W,
+                                       cx<T>* __restrict__ xo, int pitch) {
+  {
+    cx<T> e[16];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) e[j] = v[j];
+    dft16_lo8(e, false);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) Sq[k1 * 33 + 2 * t] = k1 ? cmul(e[k1], W[(2 * t * k1) & 511]) : e[0];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) e[j] = v[15 - j];
+    dft16_lo8(e, false);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) Sq[k1 * 33 + 31 - 2 * t] = k1 ? cmul(e[k1], W[((31 - 2 * t) * k1) & 511]) : e[0];
+  }
+  __syncthreads();
+  cx<T> u[32];
+#pragma unroll
+  for (int r = 0; r < 32; ++r) u[r] = Sq[t * 33 + r];
+  dft32(u, false);
+  __syncthreads();
+#pragma unroll
+  for (int k2 = 0; k2 < 32; ++k2) Sq[t + 16 * k2] = u[k2];
+  __syncthreads();
+#pragma unroll
+  for (int k2 = 0; k2 <= 16; ++k2) {
+    const int k = t + 16 * k2;
+    if (k2 == 16 && t) break;
+    const cx<T> Zk = u[k2];
+    const cx<T> Zm = Sq[(512 - k) & 511];
+    const cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+    const cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+    if (ra < nrows) xo[(long)ra * pitch + k] = Xa;
+    if (ra + 1 < nrows) xo[(long)(ra + 1) * pitch + k] = Xb;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(RR_NT) void k_row_fwd256(const RowFwd<T> A) {
+  constexpr int N = 256;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);  // W_512^i
+  cx<T>* S = W + 512;
+  const int tid = threadIdx.x, ch = blockIdx.z;
+  for (int i = tid; i < 512; i += RR_NT) W[i] = A.tw[i << (A.lgTw - 9)];
+  const int row0 = blockIdx.x * 2 * RR_PB;
+  const int t = tid & 15, q = tid >> 4;  // index-fastest mapping
+  const int ra = row0 + 2 * q;
+  cx<T>* Sq = S + q * RR_SP;
+  __syncthreads();
+  cx<T> v[16];
+  if (A.xin[ch]) rr_c2r<T>(A.xin[ch], A.xin_pitch, ra, A.nrows, t, Sq, W, v);
+  else
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m] = zero<T>();
+
+  // v = a u + b (hs + he) + wc w at the Makhoul positions
+  {
+    const T* u = A.u[ch];
+    const T* w = A.w[ch];
+    T* hso = A.hs_out[ch];
+    T* vo = A.val_out[ch];
+    const T ac = A.a[ch], hec = A.he[ch], bc = A.b, wcc = A.wc[ch];
+    const bool oka = ra < A.nrows, okb = ra + 1 < A.nrows;
+    const long ia = (long)ra * N, ib = ia + N;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int x = rr_minv(t + 16 * m);
+      const T hsa = v[m].x, hsb = v[m].y;
+      T va = bc * (hsa + hec), vb = bc * (hsb + hec);
+      if (u) {
+        va += ac * (oka ? u[ia + x] : (T)0);
+        vb += ac * (okb ? u[ib + x] : (T)0);
+      }
+      if (w) {
+        va += wcc * (oka ? w[ia + x] : (T)0);
+        vb += wcc * (okb ? w[ib + x] : (T)0);
+      }
+      if (hso) {
+        if (oka) hso[ia + x] = hsa;
+        if (okb) hso[ib + x] = hsb;
+      }
+      if (vo) {
+        if (oka) vo[ia + x] = va;
+        if (okb) vo[ib + x] = vb;
+      }
+      v[m] = mk<T>(oka ? va : (T)0, okb ? vb : (T)0);
+    }
+  }
+
+  T* dout = A.dct_out[ch];
+  if (dout) {
+    cx<T> d[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) d[m] = v[m];
+    dft16(d, false);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) Sq[k1 * 17 + t] = k1 ? cmul(d[k1], W[(2 * t * k1) & 511]) : d[0];
+    __syncthreads();
+    // second stage: pencil-fastest threads for x-major stores
+    const bool xm = A.dct_xmajor != 0;
+    const int q2 = xm ? (tid % RR_PB) : q, k1 = xm ? (tid / RR_PB) : t;
+    cx<T>* S2 = S + q2 * RR_SP;
+#pragma unroll
+    for (int tt = 0; tt < 16; ++tt) d[tt] = S2[k1 * 17 + tt];
+    dft16(d, false);
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) S2[k1 + 16 * k2] = d[k2];
+    __syncthreads();
+    const int rb2 = row0 + 2 * q2;
+    const long nr = A.nrows;
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) {
+      const int k = k1 + 16 * k2;
+      const cx<T> Zk = d[k2];
+      const cx<T> Zm = S2[(N - k) & (N - 1)];
+      const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+      const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+      const cx<T> wk = A.dtw[k];
+      const T xa = wk.x * Va.x - wk.y * Va.y, xb = wk.x * Vb.x - wk.y * Vb.y;
+      if (xm) {
+        if (rb2 < A.nrows) dout[(long)k * nr + rb2] = xa;
+        if (rb2 + 1 < A.nrows) dout[(long)k * nr + rb2 + 1] = xb;
+      } else {
+        if (rb2 < A.nrows) dout[(long)rb2 * N + k] = xa;
+        if (rb2 + 1 < A.nrows) dout[(long)(rb2 + 1) * N + k] = xb;
+      }
+    }
+    __syncthreads();
+  }
+  if (A.xout[ch]) rr_r2c<T>(v, ra, A.nrows, t, Sq, W, A.xout[ch], A.xout_pitch);
+}
+
+template <typename T>
+__global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
+  constexpr int N = 256;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* S = W + 512;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 512; i += RR_NT) W[i] = A.tw[i << (A.lgTw - 9)];
+  const int row0 = blockIdx.x * 2 * RR_PB;
+  const int t = tid & 15, q = tid >> 4;  // index-fastest mapping
+  const int ra = row0 + 2 * q;
+  cx<T>* Sq = S + q * RR_SP;
+  const bool xm = A.heat_xmajor != 0;
+  const int q1 = xm ? (tid % RR_PB) : q, k1 = xm ? (tid / RR_PB) : t;
+  const int ra1 = row0 + 2 * q1;
+  cx<T>* S1 = S + q1 * RR_SP;
+  const T invn = (T)1 / (T)N;
+  const bool oka = ra < A.nrows, okb = ra + 1 < A.nrows;
+  const long ia = (long)ra * N, ib = ia + N;
+  cx<T> g[3][16];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c < A.nch) {
+      const T* H = A.heat[c];
+      cx<T> u[16];
+#pragma unroll
+      for (int k2 = 0; k2 < 16; ++k2) {
+        const int k = k1 + 16 * k2;
+        T xak = 0, xam = 0, xbk = 0, xbm = 0;
+        if (xm) {
+          const long nr = A.nrows;
+          if (ra1 < A.nrows) {
+            xak = H[(long)k * nr + ra1];
+            if (k) xam = H[(long)(N - k) * nr + ra1];
+          }
+          if (ra1 + 1 < A.nrows) {
+            xbk = H[(long)k * nr + ra1 + 1];
+            if (k) xbm = H[(long)(N - k) * nr + ra1 + 1];
+          }
+        } else {
+          if (ra1 < A.nrows) {
+            xak = H[(long)ra1 * N + k];
+            if (k) xam = H[(long)ra1 * N + N - k];
+          }
+          if (ra1 + 1 < A.nrows) {
+            xbk = H[(long)(ra1 + 1) * N + k];
+            if (k) xbm = H[(long)(ra1 + 1) * N + N - k];
+          }
+        }
+        const cx<T> w = conjg(A.dtw[k]);
+        const cx<T> Va = cmul(w, mk<T>(xak, -xam));
+        const cx<T> Vb = cmul(w, mk<T>(xbk, -xbm));
+        u[k2] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
+      }
+      dft16(u, true);
+#pragma unroll
+      for (int tt = 0; tt < 16; ++tt) S1[tt * 17 + k1] = tt ? cmul(u[tt], conjg(W[(2 * tt * k1) & 511])) : u[0];
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) g[c][kk] = Sq[t * 17 + kk];
+      dft16(g[c], true);
+      T* go = A.gout[c];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        g[c][m] = mk<T>(g[c][m].x * invn, g[c][m].y * invn);
+        if (go) {
+          const int x = rr_minv(t + 16 * m);
+          if (oka) go[ia + x] = g[c][m].x;
+          if (okb) go[ib + x] = g[c][m].y;
+        }
+      }
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) g[c][m] = zero<T>();
+    }
+  }
+
+  if (A.op == ROW_OP_GS) {
+    cx<T> v[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int x = rr_minv(t + 16 * m);
+      T o[2] = {(T)0, (T)0};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool ok = h ? okb : oka;
+        if (!ok) continue;
+        const long idx = (h ? ib : ia) + x;
+        const T g0 = h ? g[0][m].y : g[0][m].x, g1 = h ? g[1][m].y : g[1][m].x;
+        const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : A.Pf[idx]);
+        const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : A.Rf[idx]);
+        T val = A.base[idx] + pv * A.Qf[idx] - rv * A.Sf[idx];
+        if (A.src) val += A.ds * A.src[idx];
+        A.out[idx] = val;
+        o[h] = val;
+      }
+      v[m] = mk<T>(o[0], o[1]);
+    }
+    if (A.xout) rr_r2c<T>(v, ra, A.nrows, t, Sq, W, A.xout, A.xout_pitch);
+  } else if (A.op == ROW_OP_PROJECT) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int x = rr_minv(t + 16 * m);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool ok = h ? okb : oka;
+        if (!ok) continue;
+        const long idx = (h ? ib : ia) + x;
+        const T c0 = h ? g[0][m].y : g[0][m].x, c1 = h ? g[1][m].y : g[1][m].x, c2 = h ? g[2][m].y : g[2][m].x;
+        const T nr = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+        if (!(nr > (T)0) || !isfinite(nr)) A.flag[0] = 1;
+        const T inr = (T)1 / nr;
+        A.mout[0][idx] = c0 * inr;
+        A.mout[1][idx] = c1 * inr;
+        A.mout[2][idx] = c2 * inr;
+        if (A.nrm) A.nrm[idx] = nr;
+      }
+    }
+  }
+}
+
+// the register row kernels serve rows of 256 whose padded transforms have length 512
+template <typename T> bool row256(int lgN, int lgLc, int lgLr, bool c2r, bool r2c) {
+  return lgN == 8 && (!c2r || lgLc == 9) && (!r2c || lgLr == 9);
+}
+
 template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_t s) {
+  bool c2r = false, r2c = false;
+  for (int c = 0; c < nch; ++c) {
+    c2r = c2r || a.xin[c];
+    r2c = r2c || a.xout[c];
+  }
+  if (row256<T>(a.lgN, a.lgLc, a.lgLr, c2r, r2c)) {
+    const size_t lds = (512 + (size_t)RR_PB * RR_SP) * sizeof(cx<T>);
+    hipLaunchKernelGGL(k_row_fwd256<T>, dim3(ceil_div(a.nrows, 2 * RR_PB), 1, nch), dim3(RR_NT), lds, s, a);
+    return SGSPM_KC_ROW_FWD256;
+  }
   const int rows = 2 << a.lgP;
   dim3 grid(ceil_div(a.nrows, rows), 1, nch);
   const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1)) * sizeof(cx<T>);
@@ -1532,6 +1873,11 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
 }
 
 template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
+  if (row256<T>(a.lgN, a.lgLr, a.lgLr, false, a.xout != nullptr)) {
+    const size_t lds = (512 + (size_t)RR_PB * RR_SP) * sizeof(cx<T>);
+    hipLaunchKernelGGL(k_row_inv256<T>, dim3(ceil_div(a.nrows, 2 * RR_PB)), dim3(RR_NT), lds, s, a);
+    return SGSPM_KC_ROW_INV256;
+  }
   const int rows = 2 << a.lgP;
   dim3 grid(ceil_div(a.nrows, rows), 1, 1);
   const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1)) * sizeof(cx<T>);

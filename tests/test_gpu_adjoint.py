@@ -37,7 +37,7 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
-@pytest.mark.parametrize("n", [(16, 8, 4), (32, 16, 1), (8, 1, 8), (16, 1, 1), (4, 4, 4)],
+@pytest.mark.parametrize("n", [(16, 8, 4), (32, 16, 1), (8, 1, 8), (16, 1, 1), (4, 4, 4), (256, 4, 2)],
                          ids=lambda n: "x".join(map(str, n)))
 @pytest.mark.parametrize("terms", [ALL, ("exchange",), ("exchange", "aniso", "zeeman"), ("stray", "zeeman")],
                          ids=lambda t: "+".join(t))

@@ -138,7 +138,8 @@ def test_manufactured_film_32x32(env, prec):
     assert err <= (1e-11 if prec == 1 else 1e-5)
 
 
-@pytest.mark.parametrize("n", [(16, 8, 4), (32, 16, 1), (8, 1, 8), (16, 1, 1)], ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("n", [(16, 8, 4), (32, 16, 1), (8, 1, 8), (16, 1, 1), (256, 4, 2), (256, 1, 1)],
+                         ids=lambda n: "x".join(map(str, n)))
 @pytest.mark.parametrize("method", ["sgspm", "gspm"])
 def test_full_step_fp64(env, n, method):
     torch, sg = env
