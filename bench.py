@@ -41,6 +41,36 @@ WORKLOAD_TEXT = {
 }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_block-256x256x32.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2606_28113_amd", "csrc", f) for f in ("kernels.hip", "kernels.h", "fft_lds.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, dtype, workload):
+    """HBM bytes per launch of `kernel` from the committed hardware-counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when the
+    summary is absent, covers another workload, or the kernel sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    src = kernel_source_hash()
+    for line in open(TRAFFIC_FILE):
+        if not line.startswith("traffic:"):
+            continue
+        f = dict(kv.split("=", 1) for kv in line.split()[1:])
+        if (f.get("kernel") == kernel and f.get("dtype") == dtype and f.get("workload") == workload
+                and f.get("source_sha256") == src):
+            return float(f["bytes_per_launch"])
+    return None
+
+
 def make_plan(sg, c, precision):
     kw = dict(nx=c.n[0], ny=c.n[1], nz=c.n[2], dx=c.h[0], dy=c.h[1], dz=c.h[2], dt=c.dt, precision=precision)
     if c.units == "si":
@@ -125,9 +155,10 @@ def main():
                                           "alg_MB_per_launch": by / cnt / 1e6}
     dom = max(breakdown, key=lambda k: breakdown[k]["ms_per_step"])
     d = breakdown[dom]
+    traffic = measured_traffic(dom, "f32", c.name)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["GBps"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(d["GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_launch_us": round(d["avg_us"], 3)}
+                "unit": "GB/s", "frac": round(d["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "avg_launch_us": round(d["avg_us"], 3), "alg_bytes_per_launch": round(d["alg_MB_per_launch"] * 1e6)}
     alg_step_bytes = sum(stats[k][1] for k in stats) / K
     e32 = p32.energy(torch.tensor(m1_32, dtype=torch.float32, device="cuda"), B[0])
     del p32, m

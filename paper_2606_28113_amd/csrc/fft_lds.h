@@ -199,6 +199,41 @@ template <typename T, int N> __device__ __forceinline__ void dft_reg(cx<T>* v, b
   else if constexpr (N == 32) dft32(v, inv);
 }
 
+// 8-point DFT of a sequence whose entries 4..7 are zero (natural order out)
+template <typename T> __device__ __forceinline__ void dft8_lo4(cx<T>* v, bool inv) {
+  const cx<T> r2 = rot(v[2], inv), r3 = rot(v[3], inv);
+  const cx<T> e0 = v[0] + v[2], e1 = v[0] + r2, e2 = v[0] - v[2], e3 = v[0] - r2;
+  cx<T> o0 = v[1] + v[3], o1 = v[1] + r3, o2 = v[1] - v[3], o3 = v[1] - r3;
+  const T s = (T)0.70710678118654752440084436210485;
+  const cx<T> w1 = inv ? mk(s * (o1.x - o1.y), s * (o1.x + o1.y)) : mk(s * (o1.x + o1.y), s * (o1.y - o1.x));
+  const cx<T> w2 = rot(o2, inv);
+  const cx<T> w3 = inv ? mk(-s * (o3.x + o3.y), s * (o3.x - o3.y)) : mk(s * (o3.y - o3.x), -s * (o3.x + o3.y));
+  v[0] = e0 + o0;
+  v[4] = e0 - o0;
+  v[1] = e1 + w1;
+  v[5] = e1 - w1;
+  v[2] = e2 + w2;
+  v[6] = e2 - w2;
+  v[3] = e3 + w3;
+  v[7] = e3 - w3;
+}
+
+// outputs 0..3 of an 8-point DFT (entries 4..7 of v are left undefined)
+template <typename T> __device__ __forceinline__ void dft8_first4(cx<T>* v, bool inv) {
+  cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4v(e0, e1, e2, e3, inv);
+  dft4v(o0, o1, o2, o3, inv);
+  const T s = (T)0.70710678118654752440084436210485;
+  const cx<T> w1 = inv ? mk(s * (o1.x - o1.y), s * (o1.x + o1.y)) : mk(s * (o1.x + o1.y), s * (o1.y - o1.x));
+  const cx<T> w2 = rot(o2, inv);
+  const cx<T> w3 = inv ? mk(-s * (o3.x + o3.y), s * (o3.x - o3.y)) : mk(s * (o3.y - o3.x), -s * (o3.x + o3.y));
+  v[0] = e0 + o0;
+  v[1] = e1 + w1;
+  v[2] = e2 + w2;
+  v[3] = e3 + w3;
+}
+
 template <typename T, int R> __device__ __forceinline__ void dftR(cx<T>* v, bool inv) {
   if constexpr (R == 2) dft2(v, inv);
   else if constexpr (R == 4) dft4(v, inv);

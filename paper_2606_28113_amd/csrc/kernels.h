@@ -135,8 +135,9 @@ template <typename T> struct Conv {
   long sa, sb;
   const cx<T>* S[3]; // null = component identically zero
   cx<T>* O[3];       // null = output not requested
-  const T* tens;     // [6][Hc][Hb][ni]
+  const T* tens;     // [6][Hc][Hb][tkx]
   long tcs;
+  int tkx;           // kx pitch of the tensor rows (a multiple of 32)
   int nt;            // tensor components used (listed in clist; cpos maps component -> slot)
   int clist[6];
   int cpos[6];
@@ -159,7 +160,7 @@ void launch_newell_fill(double* out, int comp, int nx, int ny, int nz, int Px, i
                         double hz, int rfar, hipStream_t s);
 // Real part of the FP64 spectrum on the folded octant, times scale, as T.
 template <typename T>
-void launch_tensor_pack(const cx<double>* spec, T* out, int Hz, int Hy, int Kx, int Kxp, int Py, double scale,
+void launch_tensor_pack(const cx<double>* spec, T* out, int Hz, int Hy, int Kx, int Kxp, int Kt, int Py, double scale,
                         hipStream_t s);
 
 // Pointwise product terms: for each term t in order,

@@ -18,6 +18,33 @@ namespace sgspm {
 
 template <typename T> __device__ __forceinline__ cx<T> zero() { return mk<T>((T)0, (T)0); }
 
+// Workgroups go to the 8 XCDs round-robin by linear id, and each XCD has its
+// own L2.  Renumber them so that consecutive logical workgroups (neighbours
+// that read the two halves of the same 128-byte lines) run on one XCD.
+// element at a byte offset from a base pointer
+template <typename V> __device__ __forceinline__ V ld_off(const V* base, unsigned byte_off) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename V> __device__ __forceinline__ void st_off(V* base, unsigned byte_off, V v) {
+  *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+struct Blk {
+  int x, y, z;
+};
+__device__ __forceinline__ Blk xcd_block() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int n = gx * gy * (int)gridDim.z;
+  const int L = (int)blockIdx.x + gx * ((int)blockIdx.y + gy * (int)blockIdx.z);
+  const int q = n >> 3, rem = n & 7, xc = L & 7;
+  const int lg = xc * q + min(xc, rem) + (L >> 3);
+  Blk b;
+  b.x = lg % gx;
+  b.y = (lg / gx) % gy;
+  b.z = lg / (gx * gy);
+  return b;
+}
+
 // ---------------------------------------------------------------------------
 // Shared row-kernel helpers (tile: P complex pencils = 2P real rows).
 
@@ -719,11 +746,16 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
   const int q = tid % P;
   const int t = tid / P;  // 0..63
   for (int i = tid; i < 512; i += 64 * P) w[i] = A.tw[i << (A.lgTw - 9)];
-  const int kx = blockIdx.x * P + q;
+  const Blk bk = xcd_block();
+  const int kx = bk.x * P + q;
   const bool act = kx < A.ni;
-  const int b = blockIdx.y;
-  const cx<T>* in = A.in[blockIdx.z] + (long)b * A.sb_in + kx;
-  cx<T>* out = A.out[blockIdx.z] + (long)b * A.sb_out + kx;
+  const int b = bk.y;
+  // byte offsets from the uniform pencil-set bases (inactive lanes read kx = ni - 1)
+  const cx<T>* in = A.in[bk.z];
+  cx<T>* out = A.out[bk.z];
+  constexpr unsigned CB = sizeof(cx<T>);
+  const unsigned ioff = (unsigned)(b * A.sb_in + min(kx, A.ni - 1)) * CB, isa = (unsigned)A.sa_in * CB;
+  const unsigned ooff = (unsigned)(b * A.sb_out + kx) * CB, osa = (unsigned)A.sa_out * CB;
   const bool inv = A.inv != 0;
   auto W = [&](int e) {  // W_512^{e} (conjugated for the inverse)
     cx<T> v = w[e & 511];
@@ -735,7 +767,7 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int row = t + 64 * m;
-      v[m] = (act && row < A.n_in) ? in[(long)row * A.sa_in] : zero<T>();
+      v[m] = row < A.n_in ? ld_off(in, ioff + (unsigned)row * isa) : zero<T>();
     }
     __syncthreads();
     dft8(v, false);
@@ -766,7 +798,7 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
           const int k = k2 + 8 * ka + 64 * kb;
-          if (k < A.n_out) out[(long)k * A.sa_out] = v[kb];
+          if (k < A.n_out) st_off(out, ooff + (unsigned)k * osa, v[kb]);
         }
       }
     }
@@ -775,7 +807,7 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
 #pragma unroll
     for (int kb = 0; kb < 8; ++kb) {
       const int k = k2 + 8 * ka + 64 * kb;
-      v[kb] = (act && k < A.n_in) ? in[(long)k * A.sa_in] : zero<T>();
+      v[kb] = k < A.n_in ? ld_off(in, ioff + (unsigned)k * isa) : zero<T>();
     }
     __syncthreads();
     dft8(v, true);  // index t0
@@ -803,7 +835,7 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const int row = t + 64 * m;
-        if (row < A.n_out) out[(long)row * A.sa_out] = v[m];
+        if (row < A.n_out) st_off(out, ooff + (unsigned)row * osa, v[m]);
       }
     }
   }
@@ -844,7 +876,7 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
     const int kf = (t / P) % LH;
     const int ci = t / (P * LH);
     const int kx = i0 + q;
-    tt[t] = (kx < A.ni) ? A.tens[(long)A.clist[ci] * A.tcs + ((long)kf * A.Hb + bf) * A.ni + kx] : (T)0;
+    tt[t] = (kx < A.ni) ? A.tens[(long)A.clist[ci] * A.tcs + ((long)kf * A.Hb + bf) * A.tkx + kx] : (T)0;
   }
   const bool mirror = A.Pb > 1 && bf != 0 && 2 * bf != A.Pb;
   const int ch = L >> 1;
@@ -949,30 +981,33 @@ __global__ __launch_bounds__(C64_NT) void k_conv64(const Conv<T> A) {
   const int t = (tid >> A.lgP) & 7;
   const int r = tid >> (A.lgP + 3);
   for (int i = tid; i < 64; i += C64_NT) w64[i] = A.tw[i << (A.lgTw - 6)];
-  const int bf = blockIdx.y;
-  const int kx0 = blockIdx.x * P;
+  const Blk bk = xcd_block();
+  const int bf = bk.y;
+  const int kx0 = bk.x * P;
   const bool mirror = A.Pb > 1 && bf != 0 && 2 * bf != A.Pb;
   const int kx = kx0 + q;
   const bool act = kx < A.ni && (r == 0 || mirror);
-  const int b = r ? A.Pb - bf : bf;
-  const long boff = (long)b * A.sb + kx;
+  // inactive lanes read valid addresses and are never stored
+  const int kxc = min(kx, A.ni - 1);
+  const int b = (r && mirror) ? A.Pb - bf : bf;
+  // byte offsets from uniform base pointers (scalar base + 32-bit vector offset)
+  const unsigned soff = (unsigned)(b * A.sb + kxc) * (unsigned)sizeof(cx<T>);
+  const unsigned sa = (unsigned)A.sa * (unsigned)sizeof(cx<T>);
   const int pen = r * P + q;
 
-  // forward: load, DFT-8 over m, twiddle, transpose, DFT-8 over t
+  // forward: load z = t + 8 m (m < 4; the padded half is zero), DFT-8 over m,
+  // twiddle, transpose, DFT-8 over t
   cx<T> v[3][8];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const cx<T>* S = A.S[c];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int z = t + 8 * m;
-      v[c][m] = (act && S && m < 4 && z < A.n) ? S[boff + (long)z * A.sa] : zero<T>();
-    }
+    for (int m = 0; m < 4; ++m) v[c][m] = S ? ld_off(S, soff + (unsigned)(t + 8 * m) * sa) : zero<T>();
   }
   __syncthreads();  // w64 is in LDS
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    dft8(v[c], false);
+    dft8_lo4(v[c], false);
     tw64_apply(v[c], w64, t, false);
 #pragma unroll
     for (int k2 = 0; k2 < 8; ++k2) xb[((c * 8 + k2) * 8 + t) * NP + pen] = v[c][k2];
@@ -985,29 +1020,39 @@ __global__ __launch_bounds__(C64_NT) void k_conv64(const Conv<T> A) {
     dft8(v[c], false);  // v[c][k1] = X[t + 8 k1]
   }
   __syncthreads();
-  // per output: multiply by the folded real tensor spectrum, IDFT-8 over k1,
-  // twiddle, then the transpose slot of that output
+
+  // folded tensor rows: offset and z sign per k1, shared by every component
+  // and output (kz = t + 8 k1 > 32 reads row 64 - kz of a z-odd component negated)
+  unsigned toff[8];
+  T zs[8];
+  const unsigned tstr = (unsigned)(A.Hb * A.tkx) * (unsigned)sizeof(T);
+  const unsigned tb = (unsigned)(bf * A.tkx + kxc) * (unsigned)sizeof(T);
+#pragma unroll
+  for (int k1 = 0; k1 < 8; ++k1) {
+    const int kz = t + 8 * k1;
+    const bool cneg = kz > 32;
+    toff[k1] = tb + (unsigned)(cneg ? 64 - kz : kz) * tstr;
+    zs[k1] = cneg ? (T)-1 : (T)1;
+  }
   const bool bneg = r == 1;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (!A.O[a]) continue;
     cx<T> o[8];
 #pragma unroll
-    for (int k1 = 0; k1 < 8; ++k1) {
-      const int kz = t + 8 * k1;
-      const bool cneg = kz > 32;
-      const int kf = cneg ? 64 - kz : kz;
-      T tv[3];
+    for (int k1 = 0; k1 < 8; ++k1) o[k1] = zero<T>();
 #pragma unroll
-      for (int bb = 0; bb < 3; ++bb) {
-        const int c = comp_index(a, bb);
-        T w = act ? A.tens[(long)c * A.tcs + ((long)kf * A.Hb + bf) * A.ni + kx] : (T)0;
-        if (cneg && ((A.oddc >> c) & 1)) w = -w;
-        if (bneg && ((A.oddb >> c) & 1)) w = -w;
-        tv[bb] = w;
+    for (int bb = 0; bb < 3; ++bb) {
+      const int c = comp_index(a, bb);
+      const T* tc = A.tens + (long)c * A.tcs;
+      const bool zodd = (A.oddc >> c) & 1;
+      const T ys = (bneg && ((A.oddb >> c) & 1)) ? (T)-1 : (T)1;
+#pragma unroll
+      for (int k1 = 0; k1 < 8; ++k1) {
+        T w = ld_off(tc, toff[k1]) * ys;
+        if (zodd) w *= zs[k1];
+        o[k1] = mk<T>(o[k1].x + w * v[bb][k1].x, o[k1].y + w * v[bb][k1].y);
       }
-      o[k1] = mk<T>(tv[0] * v[0][k1].x + tv[1] * v[1][k1].x + tv[2] * v[2][k1].x,
-                    tv[0] * v[0][k1].y + tv[1] * v[1][k1].y + tv[2] * v[2][k1].y);
     }
     dft8(o, true);
     tw64_apply(o, w64, t, true);
@@ -1022,13 +1067,10 @@ __global__ __launch_bounds__(C64_NT) void k_conv64(const Conv<T> A) {
     cx<T> u[8];
 #pragma unroll
     for (int tt2 = 0; tt2 < 8; ++tt2) u[tt2] = xb[((a * 8 + t) * 8 + tt2) * NP + pen];
-    dft8(u, true);  // u[a'] = x[8 a' + t]
+    dft8_first4(u, true);  // u[a'] = x[8 a' + t], a' < 4: z < 32
     if (act) {
 #pragma unroll
-      for (int aa = 0; aa < 4; ++aa) {
-        const int z = 8 * aa + t;
-        if (z < A.n) O[boff + (long)z * A.sa] = u[aa];
-      }
+      for (int aa = 0; aa < 4; ++aa) st_off(O, soff + (unsigned)(8 * aa + t) * sa, u[aa]);
     }
   }
 }
@@ -1115,13 +1157,14 @@ __global__ void k_newell_fill(double* out, int comp, int nx, int ny, int nz, int
 }
 
 template <typename T>
-__global__ void k_tensor_pack(const cx<double>* spec, T* out, int Hz, int Hy, int Kx, int Kxp, int Py, double scale) {
-  const long total = (long)Hz * Hy * Kx;
+__global__ void k_tensor_pack(const cx<double>* spec, T* out, int Hz, int Hy, int Kx, int Kxp, int Kt, int Py,
+                              double scale) {
+  const long total = (long)Hz * Hy * Kt;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    const int kx = (int)(t % Kx);
-    const int ky = (int)((t / Kx) % Hy);
-    const int kz = (int)(t / ((long)Kx * Hy));
-    out[t] = (T)(spec[((long)kz * Py + ky) * Kxp + kx].x * scale);
+    const int kx = (int)(t % Kt);
+    const int ky = (int)((t / Kt) % Hy);
+    const int kz = (int)(t / ((long)Kt * Hy));
+    out[t] = kx < Kx ? (T)(spec[((long)kz * Py + ky) * Kxp + kx].x * scale) : (T)0;
   }
 }
 
@@ -1635,9 +1678,10 @@ __global__ __launch_bounds__(RR_NT) void k_row_fwd256(const RowFwd<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);  // W_512^i
   cx<T>* S = W + 512;
-  const int tid = threadIdx.x, ch = blockIdx.z;
+  const Blk bk = xcd_block();
+  const int tid = threadIdx.x, ch = bk.z;
   for (int i = tid; i < 512; i += RR_NT) W[i] = A.tw[i << (A.lgTw - 9)];
-  const int row0 = blockIdx.x * 2 * RR_PB;
+  const int row0 = bk.x * 2 * RR_PB;
   const int t = tid & 15, q = tid >> 4;  // index-fastest mapping
   const int ra = row0 + 2 * q;
   cx<T>* Sq = S + q * RR_SP;
@@ -1732,9 +1776,10 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* S = W + 512;
+  const Blk bk = xcd_block();
   const int tid = threadIdx.x;
   for (int i = tid; i < 512; i += RR_NT) W[i] = A.tw[i << (A.lgTw - 9)];
-  const int row0 = blockIdx.x * 2 * RR_PB;
+  const int row0 = bk.x * 2 * RR_PB;
   const int t = tid & 15, q = tid >> 4;  // index-fastest mapping
   const int ra = row0 + 2 * q;
   cx<T>* Sq = S + q * RR_SP;
@@ -1944,7 +1989,7 @@ template <typename T> int conv_lgP(int lgL, int ni, int nt) {
 }
 
 template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t s) {
-  if (a.lgL == 6 && a.n <= 32) {
+  if (a.lgL == 6 && a.n == 32) {
     // register four-step kernel: 16 kx x 2 batch rows x 8 threads per pencil
     Conv<T> b = a;
     b.lgP = 4;
@@ -1966,11 +2011,11 @@ void launch_newell_fill(double* out, int comp, int nx, int ny, int nz, int Px, i
 }
 
 template <typename T>
-void launch_tensor_pack(const cx<double>* spec, T* out, int Hz, int Hy, int Kx, int Kxp, int Py, double scale,
+void launch_tensor_pack(const cx<double>* spec, T* out, int Hz, int Hy, int Kx, int Kxp, int Kt, int Py, double scale,
                         hipStream_t s) {
-  const long total = (long)Hz * Hy * Kx;
+  const long total = (long)Hz * Hy * Kt;
   const int blocks = (int)std::min<long>((total + NT - 1) / NT, 65536);
-  hipLaunchKernelGGL(k_tensor_pack<T>, dim3(blocks), dim3(NT), 0, s, spec, out, Hz, Hy, Kx, Kxp, Py, scale);
+  hipLaunchKernelGGL(k_tensor_pack<T>, dim3(blocks), dim3(NT), 0, s, spec, out, Hz, Hy, Kx, Kxp, Kt, Py, scale);
 }
 
 template <typename T>
@@ -2030,7 +2075,7 @@ void launch_adj_damp(const T* lw, const T* u, const T* nrm, const T* const uF[3]
   template int launch_conv<T>(const Conv<T>&, int, hipStream_t);                                                   \
   template int conv_lgP<T>(int, int, int);                                                                          \
   template int launch_yz_solve<T>(const YZSolve<T>&, int, hipStream_t);                                            \
-  template void launch_tensor_pack<T>(const cx<double>*, T*, int, int, int, int, int, double, hipStream_t);         \
+  template void launch_tensor_pack<T>(const cx<double>*, T*, int, int, int, int, int, int, double, hipStream_t);    \
   template void launch_field_assemble<T>(const T*, const T*, T*, int, int, int, double, double, double, double,    \
                                          double, const double*, hipStream_t);                                       \
   template void launch_energy<T>(const T*, const T*, int, int, int, double, double, double, const double*, double*, \

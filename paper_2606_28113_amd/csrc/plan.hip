@@ -117,7 +117,8 @@ struct sgspm_plan_s {
   void* xlev = nullptr;    // 3 x nz*ny*Kxp complex
   void* ylev = nullptr;    // 3 x nz*Py*Kxp complex (3-D) or null
   void* yout = nullptr;    // 3 x conv outputs
-  void* tens = nullptr;    // 6 x Hz*Hy*Kx
+  void* tens = nullptr;    // 6 x Hz*Hy*Kt
+  int Kt = 1;              // tensor kx pitch: Kx rounded up to 32 (128-byte rows in FP32)
   double* partials = nullptr;
   double* eout = nullptr;
   int* flag = nullptr;
@@ -482,7 +483,8 @@ template <typename T> struct Eng {
     }
     A.lgP = conv_lgP<T>(A.lgL, P.Kx, A.nt);
     A.tens = tens;
-    A.tcs = (long)P.Hz * P.Hy * P.Kx;
+    A.tcs = (long)P.Hz * P.Hy * P.Kt;
+    A.tkx = P.Kt;
     A.tw = tw;
     A.lgTw = P.lgTw;
     const int nb = (z && P.has_mid) ? P.Hy : 1;
@@ -910,7 +912,7 @@ int build_tensor(sgspm_plan_s* P) {
   if ((rc = dalloc(P, &spec, speclen * sizeof(cx<double>)))) return rc;
   const double hs = std::max(P->prm.dx, std::max(P->prm.dy, P->prm.dz));
   const double hx = P->prm.dx / hs, hy = P->prm.dy / hs, hz = P->prm.dz / hs;
-  const long tcs = (long)P->Hz * P->Hy * P->Kx;
+  const long tcs = (long)P->Hz * P->Hy * P->Kt;
   const double scale = -1.0 / (double)padded;
   const cx<double>* tw64 = (const cx<double>*)P->tw64;
   for (int comp = 0; comp < 6; ++comp) {
@@ -958,10 +960,10 @@ int build_tensor(sgspm_plan_s* P) {
       launch_col_fft<double>(A, ax == 1 ? P->Pz : P->Py, 1, P->s);
     }
     if (P->fp64)
-      launch_tensor_pack<double>((const cx<double>*)spec, (double*)P->tens + comp * tcs, P->Hz, P->Hy, P->Kx, P->Kxp,
+      launch_tensor_pack<double>((const cx<double>*)spec, (double*)P->tens + comp * tcs, P->Hz, P->Hy, P->Kx, P->Kxp, P->Kt,
                                  P->Py, scale, P->s);
     else
-      launch_tensor_pack<float>((const cx<double>*)spec, (float*)P->tens + comp * tcs, P->Hz, P->Hy, P->Kx, P->Kxp,
+      launch_tensor_pack<float>((const cx<double>*)spec, (float*)P->tens + comp * tcs, P->Hz, P->Hy, P->Kx, P->Kxp, P->Kt,
                                 P->Py, scale, P->s);
   }
   rc = hip_check(hipGetLastError(), "tensor kernels");
@@ -1021,7 +1023,7 @@ template <typename T> int alloc_workspace(sgspm_plan_s* P) {
     } else {
       if ((rc = dalloc(P, &P->yout, 3 * xl * sizeof(cx<T>)))) return rc;
     }
-    if ((rc = dalloc(P, &P->tens, (size_t)6 * P->Hz * P->Hy * P->Kx * sizeof(T)))) return rc;
+    if ((rc = dalloc(P, &P->tens, (size_t)6 * P->Hz * P->Hy * P->Kt * sizeof(T)))) return rc;
   }
   P->nred = (int)std::min<long>(1024, (P->N + NT - 1) / NT);
   if ((rc = dalloc(P, (void**)&P->partials, (size_t)P->nred * 4 * sizeof(double)))) return rc;
@@ -1073,6 +1075,7 @@ int sgspm_plan(const sgspm_params* p, void* hip_stream, sgspm_plan_t* out) {
   P->Pz = p->nz > 1 ? 2 * p->nz : 1;
   P->Kx = P->Px / 2 + 1;
   P->Kxp = (P->Kx + 15) / 16 * 16;
+  P->Kt = (P->Kx + 31) / 32 * 32;
   P->Hy = P->Py / 2 + 1;
   P->Hz = P->Pz / 2 + 1;
   P->stray = p->terms & SGSPM_TERM_STRAY;
