@@ -149,3 +149,32 @@ def test_gradients_vs_finite_differences_fp64(env):
         assert fd == pytest.approx(np.sum(gh * w), rel=1e-6)
     fd = (loss(m0, B, alpha + h) - loss(m0, B, alpha - h)) / (2 * h)
     assert fd == pytest.approx(ga, rel=1e-6)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_adjoint_film_full_length(env, prec):
+    """The adjoint workload at full length: 128x128 film, 500 steps with checkpoints every 50,
+    gradients of the terminal misfit with respect to m0, every step's applied field and alpha.
+    FP64 runs from the workload's random start, whose trajectory is chaotic: the two FP64
+    implementations separate as the rounding differences grow, so the bound is looser than
+    the 20-step one. FP32 cannot follow a chaotic trajectory for 500 steps; it runs from the
+    paper's exchange-test state eq. (m0-1) on the same film, which is well conditioned."""
+    torch, sg = env
+    c = workloads.config("adjoint-film-128x128")
+    S, K = c.steps, 50
+    assert S == 500
+    m0 = workloads.initial_state(c) if prec == 1 else workloads.paper_ic(c.shape)
+    B = workloads.field_schedule(c, S)
+    target = workloads.target_state(c)
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, prec)
+    L, gm, gh, ga = _loss_grads_gpu(torch, sg, plan, m0, B, c.alpha, target, K, prec)
+    P = oracle_problem_si(c.n, c.h, c.dt, ALL)
+    Lr, gmr, ghr, gar = oadj.run_with_grad(P, rounded_like(m0, prec), c.alpha,
+                                           [oracle_field_si(b, ALL) for b in B], rounded_like(target, prec))
+    errs = (_rel(gm, gmr), _rel(gh, ghr * FSCALE), abs(ga - gar) / abs(gar))
+    print(f"adjoint-film {'fp64' if prec else 'fp32'} 500-step gradients (checkpoints every {K}): rel err m0 "
+          f"{errs[0]:.2e}, h_e {errs[1]:.2e}, alpha {errs[2]:.2e}; loss {L:.9e} vs {Lr:.9e}")
+    tol = 1e-6 if prec == 1 else 1e-3
+    assert max(errs) <= tol
+    assert L == pytest.approx(Lr, rel=1e-9 if prec == 1 else 1e-5)
