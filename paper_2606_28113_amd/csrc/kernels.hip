@@ -736,10 +736,14 @@ __global__ __launch_bounds__(NT) void k_col_fft(const ColFft<T> A) {
 // and W_64^{t0 ka}; transpose; thread (k2, ka) finishes with a DFT-8 over t0
 // and owns k = k2 + 8 ka + 64 kb.  The inverse runs the same digits backwards.
 // LDS rows are padded (S = 8P + 1) against bank conflicts.
+template <typename T, int P> constexpr int fft512_stride() { return 8 * P + (sizeof(T) == 4 ? 8 : 4); }
+
 template <typename T, int P>
 __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int S = 8 * P + 1;
+  // row stride of the transposes: 8 mod 32 complex (float) or 4 mod 16 (double), so the
+  // 8 rows x P columns a half-wave touches fall in distinct banks
+  constexpr int S = fft512_stride<T, P>();
   cx<T>* w = reinterpret_cast<cx<T>*>(smem_raw);  // W_512^i
   cx<T>* xb = w + 512;                             // [64][S]
   const int tid = threadIdx.x;
@@ -969,6 +973,14 @@ __device__ __forceinline__ void tw64_apply(cx<T>* v, const cx<T>* w64, int t, bo
   }
 }
 
+// LDS index of pencil pen in transpose row (a, b) of channel c (rows of NP = 32
+// pencils): on odd a + b the two halves of the row swap, so that the two t
+// values of a half-wave fall in distinct banks both when t is the column index
+// (writes) and when it is the row index (reads)
+__device__ __forceinline__ int c64_idx(int c, int a, int b, int NP, int pen) {
+  return ((c * 8 + a) * 8 + b) * NP + (pen ^ (((a + b) & 1) << 4));
+}
+
 template <typename T>
 __global__ __launch_bounds__(C64_NT) void k_conv64(const Conv<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1010,13 +1022,13 @@ __global__ __launch_bounds__(C64_NT) void k_conv64(const Conv<T> A) {
     dft8_lo4(v[c], false);
     tw64_apply(v[c], w64, t, false);
 #pragma unroll
-    for (int k2 = 0; k2 < 8; ++k2) xb[((c * 8 + k2) * 8 + t) * NP + pen] = v[c][k2];
+    for (int k2 = 0; k2 < 8; ++k2) xb[c64_idx(c, k2, t, NP, pen)] = v[c][k2];
   }
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
 #pragma unroll
-    for (int tt2 = 0; tt2 < 8; ++tt2) v[c][tt2] = xb[((c * 8 + t) * 8 + tt2) * NP + pen];
+    for (int tt2 = 0; tt2 < 8; ++tt2) v[c][tt2] = xb[c64_idx(c, t, tt2, NP, pen)];
     dft8(v[c], false);  // v[c][k1] = X[t + 8 k1]
   }
   __syncthreads();
@@ -1057,7 +1069,7 @@ __global__ __launch_bounds__(C64_NT) void k_conv64(const Conv<T> A) {
     dft8(o, true);
     tw64_apply(o, w64, t, true);
 #pragma unroll
-    for (int bb = 0; bb < 8; ++bb) xb[((a * 8 + bb) * 8 + t) * NP + pen] = o[bb];
+    for (int bb = 0; bb < 8; ++bb) xb[c64_idx(a, bb, t, NP, pen)] = o[bb];
   }
   __syncthreads();
 #pragma unroll
@@ -1066,7 +1078,7 @@ __global__ __launch_bounds__(C64_NT) void k_conv64(const Conv<T> A) {
     if (!O) continue;
     cx<T> u[8];
 #pragma unroll
-    for (int tt2 = 0; tt2 < 8; ++tt2) u[tt2] = xb[((a * 8 + t) * 8 + tt2) * NP + pen];
+    for (int tt2 = 0; tt2 < 8; ++tt2) u[tt2] = xb[c64_idx(a, t, tt2, NP, pen)];
     dft8_first4(u, true);  // u[a'] = x[8 a' + t], a' < 4: z < 32
     if (act) {
 #pragma unroll
@@ -1685,6 +1697,18 @@ __global__ __launch_bounds__(RR_NT) void k_row_fwd256(const RowFwd<T> A) {
   const int t = tid & 15, q = tid >> 4;  // index-fastest mapping
   const int ra = row0 + 2 * q;
   cx<T>* Sq = S + q * RR_SP;
+  // the right-hand side's inputs do not depend on the c2r: load them first
+  const bool oka = ra < A.nrows, okb = ra + 1 < A.nrows;
+  const long ia = (long)ra * N, ib = ia + N;
+  const T* u = A.u[ch];
+  const T* w = A.w[ch];
+  cx<T> pre_u[16], pre_w[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int x = rr_minv(t + 16 * m);
+    pre_u[m] = u ? mk<T>(oka ? u[ia + x] : (T)0, okb ? u[ib + x] : (T)0) : zero<T>();
+    pre_w[m] = w ? mk<T>(oka ? w[ia + x] : (T)0, okb ? w[ib + x] : (T)0) : zero<T>();
+  }
   __syncthreads();
   cx<T> v[16];
   if (A.xin[ch]) rr_c2r<T>(A.xin[ch], A.xin_pitch, ra, A.nrows, t, Sq, W, v);
@@ -1694,25 +1718,21 @@ __global__ __launch_bounds__(RR_NT) void k_row_fwd256(const RowFwd<T> A) {
 
   // v = a u + b (hs + he) + wc w at the Makhoul positions
   {
-    const T* u = A.u[ch];
-    const T* w = A.w[ch];
     T* hso = A.hs_out[ch];
     T* vo = A.val_out[ch];
     const T ac = A.a[ch], hec = A.he[ch], bc = A.b, wcc = A.wc[ch];
-    const bool oka = ra < A.nrows, okb = ra + 1 < A.nrows;
-    const long ia = (long)ra * N, ib = ia + N;
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const int x = rr_minv(t + 16 * m);
       const T hsa = v[m].x, hsb = v[m].y;
       T va = bc * (hsa + hec), vb = bc * (hsb + hec);
       if (u) {
-        va += ac * (oka ? u[ia + x] : (T)0);
-        vb += ac * (okb ? u[ib + x] : (T)0);
+        va += ac * pre_u[m].x;
+        vb += ac * pre_u[m].y;
       }
       if (w) {
-        va += wcc * (oka ? w[ia + x] : (T)0);
-        vb += wcc * (okb ? w[ib + x] : (T)0);
+        va += wcc * pre_w[m].x;
+        vb += wcc * pre_w[m].y;
       }
       if (hso) {
         if (oka) hso[ia + x] = hsa;
@@ -1770,7 +1790,7 @@ __global__ __launch_bounds__(RR_NT) void k_row_fwd256(const RowFwd<T> A) {
   if (A.xout[ch]) rr_r2c<T>(v, ra, A.nrows, t, Sq, W, A.xout[ch], A.xout_pitch);
 }
 
-template <typename T>
+template <typename T, int NCH>
 __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
   constexpr int N = 256;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1790,11 +1810,30 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
   const T invn = (T)1 / (T)N;
   const bool oka = ra < A.nrows, okb = ra + 1 < A.nrows;
   const long ia = (long)ra * N, ib = ia + N;
-  cx<T> g[3][16];
+  // The Gauss-Seidel operands do not depend on the transforms: load them first so
+  // their latency overlaps the heat-array loads (rows a in .x, b in .y).  At most
+  // one of Pf / Rf is an array in the sweeps; a second one is read later.  Done in
+  // single precision with one or two channels, where the registers are free.
+  constexpr bool PF = NCH < 3 && sizeof(T) == 4;
+  constexpr int NPF = PF ? 16 : 1;
+  const bool gs = A.op == ROW_OP_GS;
+  const T* PR = A.Pch < 0 ? A.Pf : (A.Rch < 0 ? A.Rf : nullptr);
+  cx<T> pre_b[NPF], pre_q[NPF], pre_s[NPF], pre_pr[NPF];
+  if (PF && gs) {
+#pragma unroll
+    for (int m = 0; m < NPF; ++m) {
+      const int x = rr_minv(t + 16 * m);
+      pre_b[m] = mk<T>(oka ? A.base[ia + x] : (T)0, okb ? A.base[ib + x] : (T)0);
+      pre_q[m] = mk<T>(oka ? A.Qf[ia + x] : (T)0, okb ? A.Qf[ib + x] : (T)0);
+      pre_s[m] = mk<T>(oka ? A.Sf[ia + x] : (T)0, okb ? A.Sf[ib + x] : (T)0);
+      pre_pr[m] = PR ? mk<T>(oka ? PR[ia + x] : (T)0, okb ? PR[ib + x] : (T)0) : zero<T>();
+    }
+  }
+  cx<T> g[NCH][16];
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    if (c < A.nch) {
+  for (int c = 0; c < NCH; ++c) {
+    {
       const T* H = A.heat[c];
       cx<T> u[16];
 #pragma unroll
@@ -1844,13 +1883,11 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
         }
       }
       __syncthreads();
-    } else {
-#pragma unroll
-      for (int m = 0; m < 16; ++m) g[c][m] = zero<T>();
     }
   }
 
-  if (A.op == ROW_OP_GS) {
+  if (gs) {
+    constexpr int C1 = NCH > 1 ? 1 : 0;
     cx<T> v[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
@@ -1861,10 +1898,20 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
         const bool ok = h ? okb : oka;
         if (!ok) continue;
         const long idx = (h ? ib : ia) + x;
-        const T g0 = h ? g[0][m].y : g[0][m].x, g1 = h ? g[1][m].y : g[1][m].x;
-        const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : A.Pf[idx]);
-        const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : A.Rf[idx]);
-        T val = A.base[idx] + pv * A.Qf[idx] - rv * A.Sf[idx];
+        const T g0 = h ? g[0][m].y : g[0][m].x;
+        const T g1 = NCH > 1 ? (h ? g[C1][m].y : g[C1][m].x) : (T)0;
+        T val;
+        if constexpr (PF) {
+          const T prv = h ? pre_pr[m].y : pre_pr[m].x;
+          const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : (A.Pf == PR ? prv : A.Pf[idx]));
+          const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : (A.Rf == PR ? prv : A.Rf[idx]));
+          val = (h ? pre_b[m].y : pre_b[m].x) + pv * (h ? pre_q[m].y : pre_q[m].x) -
+                rv * (h ? pre_s[m].y : pre_s[m].x);
+        } else {
+          const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : A.Pf[idx]);
+          const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : A.Rf[idx]);
+          val = A.base[idx] + pv * A.Qf[idx] - rv * A.Sf[idx];
+        }
         if (A.src) val += A.ds * A.src[idx];
         A.out[idx] = val;
         o[h] = val;
@@ -1872,7 +1919,8 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
       v[m] = mk<T>(o[0], o[1]);
     }
     if (A.xout) rr_r2c<T>(v, ra, A.nrows, t, Sq, W, A.xout, A.xout_pitch);
-  } else if (A.op == ROW_OP_PROJECT) {
+  } else if (NCH == 3 && A.op == ROW_OP_PROJECT) {
+    constexpr int C1 = NCH > 1 ? 1 : 0, C2 = NCH > 2 ? 2 : 0;
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const int x = rr_minv(t + 16 * m);
@@ -1881,7 +1929,7 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
         const bool ok = h ? okb : oka;
         if (!ok) continue;
         const long idx = (h ? ib : ia) + x;
-        const T c0 = h ? g[0][m].y : g[0][m].x, c1 = h ? g[1][m].y : g[1][m].x, c2 = h ? g[2][m].y : g[2][m].x;
+        const T c0 = h ? g[0][m].y : g[0][m].x, c1 = h ? g[C1][m].y : g[C1][m].x, c2 = h ? g[C2][m].y : g[C2][m].x;
         const T nr = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
         if (!(nr > (T)0) || !isfinite(nr)) A.flag[0] = 1;
         const T inr = (T)1 / nr;
@@ -1920,7 +1968,10 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
 template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
   if (row256<T>(a.lgN, a.lgLr, a.lgLr, false, a.xout != nullptr)) {
     const size_t lds = (512 + (size_t)RR_PB * RR_SP) * sizeof(cx<T>);
-    hipLaunchKernelGGL(k_row_inv256<T>, dim3(ceil_div(a.nrows, 2 * RR_PB)), dim3(RR_NT), lds, s, a);
+    const dim3 grid(ceil_div(a.nrows, 2 * RR_PB));
+    if (a.nch == 1) hipLaunchKernelGGL((k_row_inv256<T, 1>), grid, dim3(RR_NT), lds, s, a);
+    else if (a.nch == 2) hipLaunchKernelGGL((k_row_inv256<T, 2>), grid, dim3(RR_NT), lds, s, a);
+    else hipLaunchKernelGGL((k_row_inv256<T, 3>), grid, dim3(RR_NT), lds, s, a);
     return SGSPM_KC_ROW_INV256;
   }
   const int rows = 2 << a.lgP;
@@ -1941,7 +1992,7 @@ template <typename T> int launch_col_fft(const ColFft<T>& a, int nbatch, int nch
   if (a.lgL == 9) {
     constexpr int P = sizeof(T) == 4 ? 8 : 4;
     dim3 grid(ceil_div(a.ni, P), nbatch, nch);
-    const size_t lds = (512 + (size_t)64 * (8 * P + 1)) * sizeof(cx<T>);
+    const size_t lds = (512 + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
     hipLaunchKernelGGL((k_fft512<T, P>), grid, dim3(64 * P), lds, s, a);
     return SGSPM_KC_FFT512;
   }
