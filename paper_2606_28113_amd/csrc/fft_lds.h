@@ -104,6 +104,28 @@ template <typename T, int E> __device__ __forceinline__ cx<T> tw32(cx<T> a, bool
   }
 }
 template <typename T, int E> __device__ __forceinline__ cx<T> tw16(cx<T> a, bool inv) { return tw32<T, 2 * E>(a, inv); }
+// v * W_32^e for an exponent that is a compile-time constant once the caller's
+// loop is unrolled (table lookups then fold into literals)
+template <typename T> __device__ __forceinline__ cx<T> tw32v(cx<T> a, int e, bool inv) {
+  constexpr double C1 = 0.98078528040323044912618223613424163, S1 = 0.19509032201612826784828486847702224;
+  constexpr double C2 = 0.92387953251128675612818318939678829, S2 = 0.38268343236508977172845998403039887;
+  constexpr double C3 = 0.83146961230254523707878837761790760, S3 = 0.55557023301960222474283081394853288;
+  constexpr double R2 = 0.70710678118654752440084436210484904;
+  constexpr double cq[9] = {1, C1, C2, C3, R2, S3, S2, S1, 0};
+  e &= 31;
+  if (e == 0) return a;
+  if (e == 8) return rot(a, inv);
+  if (e == 16) return mk(-a.x, -a.y);
+  if (e == 24) return rot(a, !inv);
+  const int q = e & 15;
+  const double c0 = q <= 8 ? cq[q] : -cq[16 - q];
+  const double s0 = q <= 8 ? cq[8 - q] : cq[q - 8];
+  const T cr = (T)(e < 16 ? c0 : -c0);
+  const T sn = (T)(e < 16 ? s0 : -s0);
+  const T sg = inv ? sn : -sn;
+  return mk(a.x * cr - a.y * sg, a.x * sg + a.y * cr);
+}
+
 
 // 16-point DFT in registers (4 x 4): natural order in and out
 template <typename T> __device__ __forceinline__ void dft16(cx<T>* v, bool inv) {

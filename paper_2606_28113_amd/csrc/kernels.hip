@@ -1407,27 +1407,29 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // ---------------------------------------------------------------------------
 // Register version of the y-z heat solve for one x-major plane [NZ][NY] per
-// workgroup (NY = 16 R2, NZ <= 32), one thread team of R2 threads per pair of
+// workgroup (NY = 16 R2, NZ = 32), one thread team of R2 threads per pair of
 // z rows (a = r, b = r + NZ/2) packed as one complex pencil.
 //  y forward: Makhoul reordering on the load, 16-point DFT in registers over
 //    the stride-R2 digit, twiddle, one padded LDS transpose, length-R2 DFTs:
 //    the pencil's spectrum lands in row r of the LDS array Zs.
-//  z: thread c owns the column pair (c, NY - c) (c = 0 owns 0 and NY/2); it
-//    separates the two rows of every pencil into y-DCT coefficients, packs its
-//    two columns into one complex z pencil and does the z DCT-II, the diagonal
-//    1 / (1 + s (lamX + lamY + lamZ)), and the z DCT-III entirely in registers,
-//    then writes the pre-twiddled y-inverse input of its columns back to Zs.
-//  y inverse: the forward steps mirrored; stores undo the reordering and scale
-//    by 1 / (NY NZ).
+//  z: thread c owns column c.  It separates the two rows of every pencil into
+//    the y-DCT coefficients of its column, then does the z DCT-II of that real
+//    column as a 16-point complex FFT of its even / odd Makhoul samples, the
+//    diagonal 1 / (1 + s (lamX + lamY + lamZ)) and the z DCT-III the same way,
+//    all in registers, and writes the column to LDS (over Zs, as reals).
+//  y inverse: each team forms the pre-twiddled inverse input of its two rows
+//    from that array, then the forward steps mirrored; stores undo the
+//    reordering and scale by 2 / (NY NZ) (the half-length z inverse leaves 2).
 template <typename T, int LGY, int LGZ>
 __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(const YZSolve<T> A) {
   constexpr int NY = 1 << LGY, NZ = 1 << LGZ, HZ = NZ / 2;
   constexpr int R2 = NY / 16, G = 16 / R2, NTH = HZ * R2, RS = NY + 16;
-  static_assert(LGY >= 5 && LGY <= 8 && LGZ >= 1 && LGZ <= 5 && LGZ <= LGY, "unsupported plane");
-  static_assert(NY / 2 <= NTH, "one z thread per column pair");
+  static_assert(LGY >= 5 && LGY <= 8 && LGZ == 5, "unsupported plane");
+  static_assert(NTH == NY, "one z thread per column");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* Wy = reinterpret_cast<cx<T>*>(smem_raw);  // W_NY^i
-  cx<T>* Zs = Wy + NY;                             // [HZ][RS]
+  cx<T>* Zs = Wy + NY;                             // [HZ][RS] complex, reused as [NZ][RS] reals
+  T* Yr = reinterpret_cast<T*>(Zs);
   const int tid = threadIdx.x;
   for (int i = tid; i < NY; i += NTH) Wy[i] = A.tw[i << (A.lgTw - LGY)];
   const int r = tid / R2, t = tid % R2;
@@ -1467,80 +1469,62 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
     __syncthreads();
   }
 
-  // ---- z pass on column pairs
-  if (tid < NY / 2) {
+  // ---- z pass: one real column per thread
+  {
     const int c = tid;
-    const int ca = c, cb = c ? NY - c : NY / 2;
-    const cx<T> wa = A.dtwy[ca], wb = A.dtwy[cb];
-    cx<T> z[NZ];
+    const int cm = (NY - c) & (NY - 1);
+    const cx<T> wy = A.dtwy[c];
+    cx<T> u[HZ];  // u_n = v_2n + i v_2n+1, v the Makhoul order of the column
 #pragma unroll
     for (int q = 0; q < HZ; ++q) {
-      // the partner of column ca is cb, except for c = 0 where 0 and NY/2 pair with themselves
-      const cx<T> Za = Zs[q * RS + ca];
-      const cx<T> Zb = Zs[q * RS + cb];
-      const cx<T> Zam = c ? Zb : Za;
-      const cx<T> Zbm = c ? Za : Zb;
-      const cx<T> Va = mk<T>((Za.x + Zam.x) * (T)0.5, (Za.y - Zam.y) * (T)0.5);
-      const cx<T> Vb = mk<T>((Za.y + Zam.y) * (T)0.5, (Zam.x - Za.x) * (T)0.5);
-      const cx<T> Vc = mk<T>((Zb.x + Zbm.x) * (T)0.5, (Zb.y - Zbm.y) * (T)0.5);
-      const cx<T> Vd = mk<T>((Zb.y + Zbm.y) * (T)0.5, (Zbm.x - Zb.x) * (T)0.5);
-      // element z of the packed z pencil: column ca in .x, column cb in .y,
-      // stored at its Makhoul position
+      const cx<T> Zk = Zs[q * RS + c], Zm = Zs[q * RS + cm];
+      const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+      const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+      // rows q and q + HZ of the column sit at Makhoul positions pa, pb
       const int za = q, zb = q + HZ;
       const int pa = (za & 1) ? NZ - 1 - (za >> 1) : (za >> 1);
       const int pb = (zb & 1) ? NZ - 1 - (zb >> 1) : (zb >> 1);
-      z[pa] = mk<T>(wa.x * Va.x - wa.y * Va.y, wb.x * Vc.x - wb.y * Vc.y);
-      z[pb] = mk<T>(wa.x * Vb.x - wa.y * Vb.y, wb.x * Vd.x - wb.y * Vd.y);
+      const T ya = wy.x * Va.x - wy.y * Va.y, yb = wy.x * Vb.x - wy.y * Vb.y;
+      if (pa & 1) u[pa >> 1].y = ya;
+      else u[pa >> 1].x = ya;
+      if (pb & 1) u[pb >> 1].y = yb;
+      else u[pb >> 1].x = yb;
     }
-    dft_reg<T, NZ>(z, false);
+    dft16(u, false);
     const T lx = A.lamX[blockIdx.x];
-    const T da = (T)1 + A.s * (lx + A.lamY[ca]), db = (T)1 + A.s * (lx + A.lamY[cb]);
-    // z DCT-II coefficients at k and NZ - k come from the same two spectrum
-    // values, and so does the DCT-III input at both: process the pair in place
+    const T dc = (T)1 + A.s * (lx + A.lamY[c]);
+    T X[NZ];
+    // V_k = E_k + W_32^k O_k from U_k and conj U_(16-k); V_(32-k) = conj V_k
 #pragma unroll
-    for (int k = 0; k <= NZ / 2; ++k) {
-      const int m = (NZ - k) & (NZ - 1);
-      const cx<T> Zk = z[k], Zm = z[m];
-      const cx<T> VA = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
-      const cx<T> VB = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+    for (int k = 0; k <= HZ; ++k) {
+      const cx<T> Uk = u[k & (HZ - 1)];
+      const cx<T> Um = conjg(u[(HZ - k) & (HZ - 1)]);
+      const cx<T> E = mk<T>((Uk.x + Um.x) * (T)0.5, (Uk.y + Um.y) * (T)0.5);
+      const cx<T> O = mk<T>((Uk.y - Um.y) * (T)0.5, (Um.x - Uk.x) * (T)0.5);
+      const cx<T> V = E + tw32v(O, k, false);
       const cx<T> wk = A.dtwz[k];
-      const T szk = A.s * A.lamZ[k];
-      const T xak = (wk.x * VA.x - wk.y * VA.y) * recip(da + szk);
-      const T xbk = (wk.x * VB.x - wk.y * VB.y) * recip(db + szk);
-      if (m == k) {
-        // k = 0 pairs with the absent coefficient NZ, k = NZ/2 with itself
-        const T pa = k ? xak : (T)0, pb = k ? xbk : (T)0;
-        const cx<T> ua = cmul(conjg(wk), mk<T>(xak, -pa));
-        const cx<T> ub = cmul(conjg(wk), mk<T>(xbk, -pb));
-        z[k] = mk<T>(ua.x - ub.y, ua.y + ub.x);
-      } else {
-        // the coefficients at m use conj(VA), conj(VB)
-        const cx<T> wm = A.dtwz[m];
-        const T szm = A.s * A.lamZ[m];
-        const T xam = (wm.x * VA.x + wm.y * VA.y) * recip(da + szm);
-        const T xbm = (wm.x * VB.x + wm.y * VB.y) * recip(db + szm);
-        const cx<T> uak = cmul(conjg(wk), mk<T>(xak, -xam));
-        const cx<T> ubk = cmul(conjg(wk), mk<T>(xbk, -xbm));
-        const cx<T> uam = cmul(conjg(wm), mk<T>(xam, -xak));
-        const cx<T> ubm = cmul(conjg(wm), mk<T>(xbm, -xbk));
-        z[k] = mk<T>(uak.x - ubk.y, uak.y + ubk.x);
-        z[m] = mk<T>(uam.x - ubm.y, uam.y + ubm.x);
+      X[k] = (wk.x * V.x - wk.y * V.y) * recip(dc + A.s * A.lamZ[k]);
+      if (k > 0 && k < HZ) {
+        const cx<T> wm = A.dtwz[NZ - k];
+        X[NZ - k] = (wm.x * V.x + wm.y * V.y) * recip(dc + A.s * A.lamZ[NZ - k]);
       }
     }
-    dft_reg<T, NZ>(z, true);
-    const cx<T> ia = conjg(wa), ib = conjg(wb);
+    // DCT-III input V_j = conj(dtwz_j) (X_j - i X_(32-j)), folded to 16 points:
+    // E = (V_k + V_(k+16)) / 2, O = (V_k - V_(k+16)) conj(W_32^k) / 2, u_k = E + i O
 #pragma unroll
-    for (int q = 0; q < HZ; ++q) {
-      const int za = q, zb = q + HZ;
-      const cx<T> A_ = z[(za & 1) ? NZ - 1 - (za >> 1) : (za >> 1)];  // row a: col ca (.x), col cb (.y)
-      const cx<T> B_ = z[(zb & 1) ? NZ - 1 - (zb >> 1) : (zb >> 1)];  // row b
-      // y-inverse input of each row at columns ca and cb
-      const cx<T> a_ca = cmul(ia, mk<T>(A_.x, c ? -A_.y : (T)0));
-      const cx<T> a_cb = cmul(ib, mk<T>(A_.y, c ? -A_.x : -A_.y));
-      const cx<T> b_ca = cmul(ia, mk<T>(B_.x, c ? -B_.y : (T)0));
-      const cx<T> b_cb = cmul(ib, mk<T>(B_.y, c ? -B_.x : -B_.y));
-      Zs[q * RS + ca] = mk<T>(a_ca.x - b_ca.y, a_ca.y + b_ca.x);
-      Zs[q * RS + cb] = mk<T>(a_cb.x - b_cb.y, a_cb.y + b_cb.x);
+    for (int k = 0; k < HZ; ++k) {
+      const cx<T> Vk = cmul(conjg(A.dtwz[k]), mk<T>(X[k], k ? -X[NZ - k] : (T)0));
+      const cx<T> Vj = cmul(conjg(A.dtwz[k + HZ]), mk<T>(X[k + HZ], -X[HZ - k]));
+      const cx<T> E = mk<T>((Vk.x + Vj.x) * (T)0.5, (Vk.y + Vj.y) * (T)0.5);
+      const cx<T> O = tw32v(mk<T>((Vk.x - Vj.x) * (T)0.5, (Vk.y - Vj.y) * (T)0.5), k, true);
+      u[k] = mk<T>(E.x - O.y, E.y + O.x);
+    }
+    dft16(u, true);
+    __syncthreads();  // every thread has read Zs
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) {
+      const int p = (z & 1) ? NZ - 1 - (z >> 1) : (z >> 1);
+      Yr[z * RS + c] = (p & 1) ? u[p >> 1].y : u[p >> 1].x;
     }
   }
   __syncthreads();
@@ -1548,11 +1532,19 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
   // ---- y inverse
   {
     cx<T> v[16];
+    const T* ya = Yr + r * RS;
+    const T* yb = Yr + (r + HZ) * RS;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int k1 = t * G + g;
 #pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) v[g * R2 + k2] = zs[k1 + 16 * k2];
+      for (int k2 = 0; k2 < R2; ++k2) {
+        const int k = k1 + 16 * k2;
+        const cx<T> w = conjg(A.dtwy[k]);
+        const cx<T> Va = cmul(w, mk<T>(ya[k], k ? -ya[NY - k] : (T)0));
+        const cx<T> Vb = cmul(w, mk<T>(yb[k], k ? -yb[NY - k] : (T)0));
+        v[g * R2 + k2] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
+      }
       dft_reg<T, R2>(v + g * R2, true);
 #pragma unroll
       for (int q = 1; q < R2; ++q) v[g * R2 + q] = cmul(v[g * R2 + q], conjg(Wy[(q * k1) & (NY - 1)]));
@@ -1568,7 +1560,7 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
 #pragma unroll
     for (int k1 = 0; k1 < 16; ++k1) v[k1] = zs[k1 * (R2 + 1) + t];
     dft16(v, true);
-    const T sc = (T)1 / (T)(NY * NZ);
+    const T sc = (T)2 / (T)(NY * NZ);
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const int y = minv(t + R2 * m);
