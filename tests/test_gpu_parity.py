@@ -61,7 +61,7 @@ def test_heat_solve(env, n, prec):
 
 STRAY_SHAPES = [(8, 4, 2), (16, 8, 1), (4, 4, 4), (32, 1, 1), (1, 1, 1), (2, 2, 2), (1, 8, 4), (4, 1, 4),
                 (128, 64, 1), (64, 32, 8), (512, 32, 4), (128, 128, 1), (16, 8, 32), (16, 32, 1), (4, 1, 32),
-                (256, 4, 32)]
+                (256, 4, 32), (16, 256, 2), (8, 256, 4)]
 
 
 @pytest.mark.parametrize("n", STRAY_SHAPES, ids=lambda n: "x".join(map(str, n)))
