@@ -1670,8 +1670,9 @@ __device__ __forceinline__ void rr_r2c(const cx<T> (&v)[16], int ra, int nrows, 
     const cx<T> Zm = Sq[(512 - k) & 511];
     const cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
     const cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-    if (ra < nrows) xo[(long)ra * pitch + k] = Xa;
-    if (ra + 1 < nrows) xo[(long)(ra + 1) * pitch + k] = Xb;
+    constexpr unsigned CB = sizeof(cx<T>);
+    if (ra < nrows) st_off(xo, ((unsigned)ra * (unsigned)pitch + (unsigned)k) * CB, Xa);
+    if (ra + 1 < nrows) st_off(xo, ((unsigned)(ra + 1) * (unsigned)pitch + (unsigned)k) * CB, Xb);
   }
   __syncthreads();
 }
@@ -1691,15 +1692,17 @@ __global__ __launch_bounds__(RR_NT) void k_row_fwd256(const RowFwd<T> A) {
   cx<T>* Sq = S + q * RR_SP;
   // the right-hand side's inputs do not depend on the c2r: load them first
   const bool oka = ra < A.nrows, okb = ra + 1 < A.nrows;
-  const long ia = (long)ra * N, ib = ia + N;
+  // loads read rows clamped into range (finite data for rows that are never stored)
+  constexpr unsigned TB = sizeof(T);
+  const unsigned la = (unsigned)min(ra, A.nrows - 1) * (N * TB), lb = (unsigned)min(ra + 1, A.nrows - 1) * (N * TB);
   const T* u = A.u[ch];
   const T* w = A.w[ch];
   cx<T> pre_u[16], pre_w[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
-    const int x = rr_minv(t + 16 * m);
-    pre_u[m] = u ? mk<T>(oka ? u[ia + x] : (T)0, okb ? u[ib + x] : (T)0) : zero<T>();
-    pre_w[m] = w ? mk<T>(oka ? w[ia + x] : (T)0, okb ? w[ib + x] : (T)0) : zero<T>();
+    const unsigned xo = (unsigned)rr_minv(t + 16 * m) * TB;
+    pre_u[m] = u ? mk<T>(ld_off(u, la + xo), ld_off(u, lb + xo)) : zero<T>();
+    pre_w[m] = w ? mk<T>(ld_off(w, la + xo), ld_off(w, lb + xo)) : zero<T>();
   }
   __syncthreads();
   cx<T> v[16];
@@ -1727,14 +1730,14 @@ __global__ __launch_bounds__(RR_NT) void k_row_fwd256(const RowFwd<T> A) {
         vb += wcc * pre_w[m].y;
       }
       if (hso) {
-        if (oka) hso[ia + x] = hsa;
-        if (okb) hso[ib + x] = hsb;
+        if (oka) st_off(hso, la + (unsigned)x * TB, hsa);
+        if (okb) st_off(hso, lb + (unsigned)x * TB, hsb);
       }
       if (vo) {
-        if (oka) vo[ia + x] = va;
-        if (okb) vo[ib + x] = vb;
+        if (oka) st_off(vo, la + (unsigned)x * TB, va);
+        if (okb) st_off(vo, lb + (unsigned)x * TB, vb);
       }
-      v[m] = mk<T>(oka ? va : (T)0, okb ? vb : (T)0);
+      v[m] = mk<T>(va, vb);
     }
   }
 
@@ -1770,11 +1773,11 @@ __global__ __launch_bounds__(RR_NT) void k_row_fwd256(const RowFwd<T> A) {
       const cx<T> wk = A.dtw[k];
       const T xa = wk.x * Va.x - wk.y * Va.y, xb = wk.x * Vb.x - wk.y * Vb.y;
       if (xm) {
-        if (rb2 < A.nrows) dout[(long)k * nr + rb2] = xa;
-        if (rb2 + 1 < A.nrows) dout[(long)k * nr + rb2 + 1] = xb;
+        if (rb2 < A.nrows) st_off(dout, ((unsigned)k * (unsigned)nr + (unsigned)rb2) * (unsigned)sizeof(T), xa);
+        if (rb2 + 1 < A.nrows) st_off(dout, ((unsigned)k * (unsigned)nr + (unsigned)rb2 + 1) * (unsigned)sizeof(T), xb);
       } else {
-        if (rb2 < A.nrows) dout[(long)rb2 * N + k] = xa;
-        if (rb2 + 1 < A.nrows) dout[(long)(rb2 + 1) * N + k] = xb;
+        if (rb2 < A.nrows) st_off(dout, ((unsigned)rb2 * N + (unsigned)k) * (unsigned)sizeof(T), xa);
+        if (rb2 + 1 < A.nrows) st_off(dout, ((unsigned)(rb2 + 1) * N + (unsigned)k) * (unsigned)sizeof(T), xb);
       }
     }
     __syncthreads();
@@ -1801,7 +1804,9 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
   cx<T>* S1 = S + q1 * RR_SP;
   const T invn = (T)1 / (T)N;
   const bool oka = ra < A.nrows, okb = ra + 1 < A.nrows;
-  const long ia = (long)ra * N, ib = ia + N;
+  // loads read rows clamped into range (finite data for rows that are never stored)
+  constexpr unsigned TB = sizeof(T);
+  const unsigned la = (unsigned)min(ra, A.nrows - 1) * (N * TB), lb = (unsigned)min(ra + 1, A.nrows - 1) * (N * TB);
   // The Gauss-Seidel operands do not depend on the transforms: load them first so
   // their latency overlaps the heat-array loads (rows a in .x, b in .y).  At most
   // one of Pf / Rf is an array in the sweeps; a second one is read later.  Done in
@@ -1814,11 +1819,11 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
   if (PF && gs) {
 #pragma unroll
     for (int m = 0; m < NPF; ++m) {
-      const int x = rr_minv(t + 16 * m);
-      pre_b[m] = mk<T>(oka ? A.base[ia + x] : (T)0, okb ? A.base[ib + x] : (T)0);
-      pre_q[m] = mk<T>(oka ? A.Qf[ia + x] : (T)0, okb ? A.Qf[ib + x] : (T)0);
-      pre_s[m] = mk<T>(oka ? A.Sf[ia + x] : (T)0, okb ? A.Sf[ib + x] : (T)0);
-      pre_pr[m] = PR ? mk<T>(oka ? PR[ia + x] : (T)0, okb ? PR[ib + x] : (T)0) : zero<T>();
+      const unsigned xo = (unsigned)rr_minv(t + 16 * m) * TB;
+      pre_b[m] = mk<T>(ld_off(A.base, la + xo), ld_off(A.base, lb + xo));
+      pre_q[m] = mk<T>(ld_off(A.Qf, la + xo), ld_off(A.Qf, lb + xo));
+      pre_s[m] = mk<T>(ld_off(A.Sf, la + xo), ld_off(A.Sf, lb + xo));
+      pre_pr[m] = PR ? mk<T>(ld_off(PR, la + xo), ld_off(PR, lb + xo)) : zero<T>();
     }
   }
   cx<T> g[NCH][16];
@@ -1831,26 +1836,27 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
 #pragma unroll
       for (int k2 = 0; k2 < 16; ++k2) {
         const int k = k1 + 16 * k2;
-        T xak = 0, xam = 0, xbk = 0, xbm = 0;
+        // partner N - k; k = 0 has none (its partner slot reads a valid index, unused)
+        const int kp = k ? N - k : 1;
+        T xak, xam, xbk, xbm;
         if (xm) {
-          const long nr = A.nrows;
-          if (ra1 < A.nrows) {
-            xak = H[(long)k * nr + ra1];
-            if (k) xam = H[(long)(N - k) * nr + ra1];
-          }
-          if (ra1 + 1 < A.nrows) {
-            xbk = H[(long)k * nr + ra1 + 1];
-            if (k) xbm = H[(long)(N - k) * nr + ra1 + 1];
-          }
+          // [N][nrows]: the k-dependent part is uniform per unrolled k2
+          const unsigned ra1c = (unsigned)min(ra1, A.nrows - 1), rb1c = (unsigned)min(ra1 + 1, A.nrows - 1);
+          const unsigned nr = (unsigned)A.nrows;
+          xak = ld_off(H, ((unsigned)k * nr + ra1c) * TB);
+          xbk = ld_off(H, ((unsigned)k * nr + rb1c) * TB);
+          xam = ld_off(H, ((unsigned)kp * nr + ra1c) * TB);
+          xbm = ld_off(H, ((unsigned)kp * nr + rb1c) * TB);
         } else {
-          if (ra1 < A.nrows) {
-            xak = H[(long)ra1 * N + k];
-            if (k) xam = H[(long)ra1 * N + N - k];
-          }
-          if (ra1 + 1 < A.nrows) {
-            xbk = H[(long)(ra1 + 1) * N + k];
-            if (k) xbm = H[(long)(ra1 + 1) * N + N - k];
-          }
+          const unsigned ha = (unsigned)min(ra1, A.nrows - 1) * (N * TB), hb = (unsigned)min(ra1 + 1, A.nrows - 1) * (N * TB);
+          xak = ld_off(H, ha + (unsigned)k * TB);
+          xbk = ld_off(H, hb + (unsigned)k * TB);
+          xam = ld_off(H, ha + (unsigned)kp * TB);
+          xbm = ld_off(H, hb + (unsigned)kp * TB);
+        }
+        if (!k) {
+          xam = (T)0;
+          xbm = (T)0;
         }
         const cx<T> w = conjg(A.dtw[k]);
         const cx<T> Va = cmul(w, mk<T>(xak, -xam));
@@ -1870,8 +1876,8 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
         g[c][m] = mk<T>(g[c][m].x * invn, g[c][m].y * invn);
         if (go) {
           const int x = rr_minv(t + 16 * m);
-          if (oka) go[ia + x] = g[c][m].x;
-          if (okb) go[ib + x] = g[c][m].y;
+          if (oka) st_off(go, la + (unsigned)x * TB, g[c][m].x);
+          if (okb) st_off(go, lb + (unsigned)x * TB, g[c][m].y);
         }
       }
       __syncthreads();
@@ -1889,23 +1895,23 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
       for (int h = 0; h < 2; ++h) {
         const bool ok = h ? okb : oka;
         if (!ok) continue;
-        const long idx = (h ? ib : ia) + x;
+        const unsigned bo = (h ? lb : la) + (unsigned)x * TB;  // this row is in range here
         const T g0 = h ? g[0][m].y : g[0][m].x;
         const T g1 = NCH > 1 ? (h ? g[C1][m].y : g[C1][m].x) : (T)0;
         T val;
         if constexpr (PF) {
           const T prv = h ? pre_pr[m].y : pre_pr[m].x;
-          const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : (A.Pf == PR ? prv : A.Pf[idx]));
-          const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : (A.Rf == PR ? prv : A.Rf[idx]));
+          const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : (A.Pf == PR ? prv : ld_off(A.Pf, bo)));
+          const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : (A.Rf == PR ? prv : ld_off(A.Rf, bo)));
           val = (h ? pre_b[m].y : pre_b[m].x) + pv * (h ? pre_q[m].y : pre_q[m].x) -
                 rv * (h ? pre_s[m].y : pre_s[m].x);
         } else {
-          const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : A.Pf[idx]);
-          const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : A.Rf[idx]);
-          val = A.base[idx] + pv * A.Qf[idx] - rv * A.Sf[idx];
+          const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : ld_off(A.Pf, bo));
+          const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : ld_off(A.Rf, bo));
+          val = ld_off(A.base, bo) + pv * ld_off(A.Qf, bo) - rv * ld_off(A.Sf, bo);
         }
-        if (A.src) val += A.ds * A.src[idx];
-        A.out[idx] = val;
+        if (A.src) val += A.ds * ld_off(A.src, bo);
+        st_off(A.out, bo, val);
         o[h] = val;
       }
       v[m] = mk<T>(o[0], o[1]);
@@ -1920,15 +1926,15 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
       for (int h = 0; h < 2; ++h) {
         const bool ok = h ? okb : oka;
         if (!ok) continue;
-        const long idx = (h ? ib : ia) + x;
+        const unsigned bo = (h ? lb : la) + (unsigned)x * TB;
         const T c0 = h ? g[0][m].y : g[0][m].x, c1 = h ? g[C1][m].y : g[C1][m].x, c2 = h ? g[C2][m].y : g[C2][m].x;
         const T nr = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
         if (!(nr > (T)0) || !isfinite(nr)) A.flag[0] = 1;
         const T inr = (T)1 / nr;
-        A.mout[0][idx] = c0 * inr;
-        A.mout[1][idx] = c1 * inr;
-        A.mout[2][idx] = c2 * inr;
-        if (A.nrm) A.nrm[idx] = nr;
+        st_off(A.mout[0], bo, c0 * inr);
+        st_off(A.mout[1], bo, c1 * inr);
+        st_off(A.mout[2], bo, c2 * inr);
+        if (A.nrm) st_off(A.nrm, bo, nr);
       }
     }
   }
