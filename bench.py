@@ -178,6 +178,17 @@ def main():
     ms64 = time_steps(torch, p64, m, alpha, B, 1 + min(W, 5), K64)
     p64.check()
     print(f"[bench] fp64 forward {ms64:.4f} ms/step", file=sys.stderr, flush=True)
+    # per-kernel breakdown of the FP64 step (second pass with per-launch events)
+    p64.timing(True)
+    for n in range(1 + min(W, 5), 1 + min(W, 5) + K64):
+        p64.step(m, alpha, B[n])
+    stats64 = p64.timing_read()
+    p64.timing(False)
+    breakdown64 = {}
+    for k, (ms, by, cnt) in stats64.items():
+        if cnt:
+            breakdown64[KERNEL_NAMES[k]] = {"ms_per_step": ms / K64, "launches_per_step": cnt / K64,
+                                            "avg_us": 1e3 * ms / cnt, "GBps": by / (ms * 1e-3) / 1e9}
 
     # ---- adjoint step (FP32), if the library provides it
     adj = None
@@ -241,7 +252,8 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "fp64": {"value": N / (ms64 * 1e-3), "unit": "cell-updates/s", "ms_per_step": ms64, "steps": K64},
+        "fp64": {"value": N / (ms64 * 1e-3), "unit": "cell-updates/s", "ms_per_step": ms64, "steps": K64,
+                 "kernels": breakdown64},
         "adjoint": adj,
         "error_vs_oracle": err,
         "step_algorithmic_MB": alg_step_bytes / 1e6,

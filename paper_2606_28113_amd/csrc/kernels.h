@@ -127,6 +127,8 @@ template <typename T> struct YZSolve {
 template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStream_t s);
 // largest plane (ny * nz reals) the fused yz solve holds in one workgroup
 template <typename T> constexpr int yz_max_plane() { return sizeof(T) == 4 ? 8192 : 4096; }
+// planes that the register y-z kernel handles in either precision
+inline bool yz_reg_plane(int ny, int nz) { return ny == 256 && nz == 32; }
 
 // Last-axis convolution: FFT of the three component spectra, multiply by the
 // six-component symmetric tensor spectrum, inverse FFT of the requested outputs.

@@ -973,12 +973,12 @@ __device__ __forceinline__ void tw64_apply(cx<T>* v, const cx<T>* w64, int t, bo
   }
 }
 
-// LDS index of pencil pen in transpose row (a, b) of channel c (rows of NP = 32
+// LDS index of pencil pen in transpose row (a, b) of channel c (rows of NP
 // pencils): on odd a + b the two halves of the row swap, so that the two t
 // values of a half-wave fall in distinct banks both when t is the column index
 // (writes) and when it is the row index (reads)
 __device__ __forceinline__ int c64_idx(int c, int a, int b, int NP, int pen) {
-  return ((c * 8 + a) * 8 + b) * NP + (pen ^ (((a + b) & 1) << 4));
+  return ((c * 8 + a) * 8 + b) * NP + (pen ^ (((a + b) & 1) * (NP >> 1)));
 }
 
 template <typename T>
@@ -2007,7 +2007,7 @@ template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStrea
   const size_t nbuf = std::max((size_t)(1 << a.lgNy) * (Hy + 1), (size_t)(1 << a.lgNz) * (Hz + 1));
   const size_t lds = ((size_t)(1 << lgL) + nbuf) * sizeof(cx<T>);
   (void)lgR;
-  if (a.lgNy == 8 && a.lgNz == 5) {
+  if (yz_reg_plane(1 << a.lgNy, 1 << a.lgNz)) {
     constexpr int NY = 256, NZ = 32;
     const size_t lr = (NY + (size_t)(NZ / 2) * (NY + 16)) * sizeof(cx<T>);
     hipLaunchKernelGGL((k_yz_reg<T, 8, 5>), dim3(a.nx, 1, nch), dim3((NZ / 2) * (NY / 16)), lr, s, a);
@@ -2039,12 +2039,14 @@ template <typename T> int conv_lgP(int lgL, int ni, int nt) {
 
 template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t s) {
   if (a.lgL == 6 && a.n == 32) {
-    // register four-step kernel: 16 kx x 2 batch rows x 8 threads per pencil
+    // register four-step kernel: P kx x 2 batch rows x 8 threads per pencil
+    // 16 kx per workgroup in single precision, 8 in double (LDS 48 / 48 KiB)
     Conv<T> b = a;
-    b.lgP = 4;
-    dim3 grid(ceil_div(a.ni, 16), nbatch, 1);
-    const size_t lds = (64 + (size_t)3 * 64 * 32) * sizeof(cx<T>);
-    hipLaunchKernelGGL(k_conv64<T>, grid, dim3(C64_NT), lds, s, b);
+    b.lgP = sizeof(T) == 4 ? 4 : 3;
+    const int P = 1 << b.lgP;
+    dim3 grid(ceil_div(a.ni, P), nbatch, 1);
+    const size_t lds = (64 + (size_t)3 * 64 * 2 * P) * sizeof(cx<T>);
+    hipLaunchKernelGGL(k_conv64<T>, grid, dim3(16 * P), lds, s, b);
     return SGSPM_KC_CONV64;
   }
   dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, 1);

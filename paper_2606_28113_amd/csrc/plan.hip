@@ -1081,7 +1081,8 @@ int sgspm_plan(const sgspm_params* p, void* hip_stream, sgspm_plan_t* out) {
   P->stray = p->terms & SGSPM_TERM_STRAY;
   P->zeeman = p->terms & SGSPM_TERM_ZEEMAN;
   P->has_mid = p->nz > 1 && p->ny > 1;
-  P->yz = (long)p->ny * p->nz <= (P->fp64 ? yz_max_plane<double>() : yz_max_plane<float>());
+  P->yz = yz_reg_plane(p->ny, p->nz) ||
+          (long)p->ny * p->nz <= (P->fp64 ? yz_max_plane<double>() : yz_max_plane<float>());
   double red[5];
   reduce(p, red);
   P->eps = red[0];
