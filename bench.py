@@ -207,8 +207,19 @@ def main():
             pa.adjoint_step(ma, alpha, B[n], lam, grad)
         torch.cuda.synchronize()
         msa = (time.perf_counter() - t0) * 1e3 / KA
+        pa.timing(True)
+        for n in range(KA):
+            pa.adjoint_step(ma, alpha, B[n], lam, grad)
+        stats_a = pa.timing_read()
+        pa.timing(False)
+        breakdown_a = {}
+        for k, (ms, by, cnt) in stats_a.items():
+            if cnt:
+                breakdown_a[KERNEL_NAMES[k]] = {"ms_per_step": ms / KA, "launches_per_step": cnt / KA,
+                                                "avg_us": 1e3 * ms / cnt, "GBps": by / (ms * 1e-3) / 1e9}
         adj = {"value": N / (msa * 1e-3), "unit": "cell-updates/s", "ms_per_step": msa, "steps": KA,
-               "dtype": "f32", "note": "one adjoint step recomputes its forward step internally"}
+               "dtype": "f32", "note": "one adjoint step recomputes its forward step internally",
+               "kernels": breakdown_a}
         del pa, ma, lam
     except sg.SGSPMError as e:
         adj = {"value": None, "note": str(e)}

@@ -774,7 +774,8 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
       v[m] = row < A.n_in ? ld_off(in, ioff + (unsigned)row * isa) : zero<T>();
     }
     __syncthreads();
-    dft8(v, false);
+    if (A.n_in <= 256) dft8_lo4(v, false);  // zero-padded half: rows t + 64 m, m >= 4
+    else dft8(v, false);
     const int t0 = t & 7, t1 = t >> 3;
 #pragma unroll
     for (int k2 = 1; k2 < 8; ++k2) v[k2] = cmul(v[k2], W(t * k2));
@@ -834,7 +835,9 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
     __syncthreads();
 #pragma unroll
     for (int kk2 = 0; kk2 < 8; ++kk2) v[kk2] = xb[t * S + kk2 * P + q];
-    dft8(v, true);  // index m: x[t + 64 m]
+    // index m: x[t + 64 m]; a cropped output keeps m < 4
+    if (A.n_out <= 256) dft8_first4(v, true);
+    else dft8(v, true);
     if (act) {
 #pragma unroll
       for (int m = 0; m < 8; ++m) {

@@ -795,7 +795,8 @@ template <typename T> struct Eng {
     const T* u = mt;
     const T* nrm = f[F_NRM];
     // projection and heat flow
-    launch_adj_project<T>(lam, u, nrm, LW_[0], N, s);
+    // reads lam, u (3 N each) and |c| (N), writes 3 N
+    timed(10.0 * N * TS, [&] { launch_adj_project<T>(lam, u, nrm, LW_[0], N, s); return (int)SGSPM_KC_OTHER; });
     {
       const T* in[3] = {LW_[0], LW_[1], LW_[2]};
       heat_solve_n(3, in, (T)alpha, LW_);
@@ -803,10 +804,15 @@ template <typename T> struct Eng {
     {
       const T* uF[3] = {f[F_B1], f[F_B2], f[F_A3]};
       const double ex = P.eps;
-      launch_adj_damp<T>(LW_[0], u, nrm, uF, P.stray ? f[F_HS0] : nullptr, P.nx, P.ny, P.nz,
-                         P.nx > 1 ? ex / (P.prm.dx * P.prm.dx) : 0.0, P.ny > 1 ? ex / (P.prm.dy * P.prm.dy) : 0.0,
-                         P.nz > 1 ? ex / (P.prm.dz * P.prm.dz) : 0.0, Q, he, dt, alpha * dh, P.partials, P.nred, grad,
-                         s);
+      // reads w, u, the damping operands and h_s (3 N each) and |c| (N)
+      const double by = (P.stray ? 13.0 : 10.0) * N * TS;
+      timed(by, [&] {
+        launch_adj_damp<T>(LW_[0], u, nrm, uF, P.stray ? f[F_HS0] : nullptr, P.nx, P.ny, P.nz,
+                           P.nx > 1 ? ex / (P.prm.dx * P.prm.dx) : 0.0, P.ny > 1 ? ex / (P.prm.dy * P.prm.dy) : 0.0,
+                           P.nz > 1 ? ex / (P.prm.dz * P.prm.dz) : 0.0, Q, he, dt, alpha * dh, P.partials, P.nred,
+                           grad, s);
+        return (int)SGSPM_KC_OTHER;
+      });
     }
     {
       const T* v[3] = {LW_[0], LW_[1], LW_[2]};
