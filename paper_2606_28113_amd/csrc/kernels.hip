@@ -985,12 +985,12 @@ __device__ __forceinline__ int c64_idx(int c, int a, int b, int NP, int pen) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(C64_NT) void k_conv64(const Conv<T> A) {
+__global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const Conv<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int P = 1 << A.lgP;
   const int NP = 2 * P;  // pencils per workgroup (two batch rows)
   cx<T>* w64 = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* xb = w64 + 64;  // [3][8][8][NP]
+  cx<T>* xb = w64 + 64;  // [8][8][NP]: one transpose at a time
   const int tid = threadIdx.x;
   const int q = tid & (P - 1);
   const int t = (tid >> A.lgP) & 7;
@@ -1025,16 +1025,13 @@ __global__ __launch_bounds__(C64_NT) void k_conv64(const Conv<T> A) {
     dft8_lo4(v[c], false);
     tw64_apply(v[c], w64, t, false);
 #pragma unroll
-    for (int k2 = 0; k2 < 8; ++k2) xb[c64_idx(c, k2, t, NP, pen)] = v[c][k2];
-  }
-  __syncthreads();
+    for (int k2 = 0; k2 < 8; ++k2) xb[c64_idx(0, k2, t, NP, pen)] = v[c][k2];
+    __syncthreads();
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-#pragma unroll
-    for (int tt2 = 0; tt2 < 8; ++tt2) v[c][tt2] = xb[c64_idx(c, t, tt2, NP, pen)];
+    for (int tt2 = 0; tt2 < 8; ++tt2) v[c][tt2] = xb[c64_idx(0, t, tt2, NP, pen)];
+    __syncthreads();
     dft8(v[c], false);  // v[c][k1] = X[t + 8 k1]
   }
-  __syncthreads();
 
   // folded tensor rows: offset and z sign per k1, shared by every component
   // and output (kz = t + 8 k1 > 32 reads row 64 - kz of a z-odd component negated)
@@ -1072,16 +1069,13 @@ __global__ __launch_bounds__(C64_NT) void k_conv64(const Conv<T> A) {
     dft8(o, true);
     tw64_apply(o, w64, t, true);
 #pragma unroll
-    for (int bb = 0; bb < 8; ++bb) xb[c64_idx(a, bb, t, NP, pen)] = o[bb];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
+    for (int bb = 0; bb < 8; ++bb) xb[c64_idx(0, bb, t, NP, pen)] = o[bb];
+    __syncthreads();
     cx<T>* O = A.O[a];
-    if (!O) continue;
     cx<T> u[8];
 #pragma unroll
-    for (int tt2 = 0; tt2 < 8; ++tt2) u[tt2] = xb[c64_idx(a, t, tt2, NP, pen)];
+    for (int tt2 = 0; tt2 < 8; ++tt2) u[tt2] = xb[c64_idx(0, t, tt2, NP, pen)];
+    __syncthreads();
     dft8_first4(u, true);  // u[a'] = x[8 a' + t], a' < 4: z < 32
     if (act) {
 #pragma unroll
@@ -2043,12 +2037,12 @@ template <typename T> int conv_lgP(int lgL, int ni, int nt) {
 template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t s) {
   if (a.lgL == 6 && a.n == 32) {
     // register four-step kernel: P kx x 2 batch rows x 8 threads per pencil
-    // 16 kx per workgroup in single precision, 8 in double (LDS 48 / 48 KiB)
+    // 16 kx per workgroup in single precision, 8 in double (LDS 16 / 16 KiB)
     Conv<T> b = a;
     b.lgP = sizeof(T) == 4 ? 4 : 3;
     const int P = 1 << b.lgP;
     dim3 grid(ceil_div(a.ni, P), nbatch, 1);
-    const size_t lds = (64 + (size_t)3 * 64 * 2 * P) * sizeof(cx<T>);
+    const size_t lds = (64 + (size_t)64 * 2 * P) * sizeof(cx<T>);
     hipLaunchKernelGGL(k_conv64<T>, grid, dim3(16 * P), lds, s, b);
     return SGSPM_KC_CONV64;
   }
