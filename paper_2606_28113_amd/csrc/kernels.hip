@@ -1020,10 +1020,15 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const
     for (int m = 0; m < 4; ++m) v[c][m] = S ? ld_off(S, soff + (unsigned)(t + 8 * m) * sa) : zero<T>();
   }
   __syncthreads();  // w64 is in LDS
+  // this thread's twiddles W_64^{t k}, k < 8 (conjugated for the inverse)
+  cx<T> twr[8];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) twr[k] = w64[(t * k) & 63];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     dft8_lo4(v[c], false);
-    tw64_apply(v[c], w64, t, false);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) v[c][k] = cmul(v[c][k], twr[k]);
 #pragma unroll
     for (int k2 = 0; k2 < 8; ++k2) xb[c64_idx(0, k2, t, NP, pen)] = v[c][k2];
     __syncthreads();
@@ -1067,7 +1072,8 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const
       }
     }
     dft8(o, true);
-    tw64_apply(o, w64, t, true);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) o[k] = cmul(o[k], conjg(twr[k]));
 #pragma unroll
     for (int bb = 0; bb < 8; ++bb) xb[c64_idx(0, bb, t, NP, pen)] = o[bb];
     __syncthreads();
@@ -1674,7 +1680,7 @@ __device__ __forceinline__ void rr_r2c(const cx<T> (&v)[16], int ra, int nrows, 
   __syncthreads();
 }
 
-template <typename T>
+template <typename T, bool PF>
 __global__ __launch_bounds__(RR_NT) void k_row_fwd256(const RowFwd<T> A) {
   constexpr int N = 256;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1687,19 +1693,23 @@ __global__ __launch_bounds__(RR_NT) void k_row_fwd256(const RowFwd<T> A) {
   const int t = tid & 15, q = tid >> 4;  // index-fastest mapping
   const int ra = row0 + 2 * q;
   cx<T>* Sq = S + q * RR_SP;
-  // the right-hand side's inputs do not depend on the c2r: load them first
+  // The right-hand side's inputs do not depend on the c2r: load them first (PF).
+  // One-channel launches have registers to spare; wider ones keep their occupancy.
   const bool oka = ra < A.nrows, okb = ra + 1 < A.nrows;
   // loads read rows clamped into range (finite data for rows that are never stored)
   constexpr unsigned TB = sizeof(T);
   const unsigned la = (unsigned)min(ra, A.nrows - 1) * (N * TB), lb = (unsigned)min(ra + 1, A.nrows - 1) * (N * TB);
   const T* u = A.u[ch];
   const T* w = A.w[ch];
-  cx<T> pre_u[16], pre_w[16];
+  constexpr int NPF = PF ? 16 : 1;
+  cx<T> pre_u[NPF], pre_w[NPF];
+  if (PF) {
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const unsigned xo = (unsigned)rr_minv(t + 16 * m) * TB;
-    pre_u[m] = u ? mk<T>(ld_off(u, la + xo), ld_off(u, lb + xo)) : zero<T>();
-    pre_w[m] = w ? mk<T>(ld_off(w, la + xo), ld_off(w, lb + xo)) : zero<T>();
+    for (int m = 0; m < NPF; ++m) {
+      const unsigned xo = (unsigned)rr_minv(t + 16 * m) * TB;
+      pre_u[m] = u ? mk<T>(ld_off(u, la + xo), ld_off(u, lb + xo)) : zero<T>();
+      pre_w[m] = w ? mk<T>(ld_off(w, la + xo), ld_off(w, lb + xo)) : zero<T>();
+    }
   }
   __syncthreads();
   cx<T> v[16];
@@ -1719,12 +1729,22 @@ __global__ __launch_bounds__(RR_NT) void k_row_fwd256(const RowFwd<T> A) {
       const T hsa = v[m].x, hsb = v[m].y;
       T va = bc * (hsa + hec), vb = bc * (hsb + hec);
       if (u) {
-        va += ac * pre_u[m].x;
-        vb += ac * pre_u[m].y;
+        if constexpr (PF) {
+          va += ac * pre_u[m].x;
+          vb += ac * pre_u[m].y;
+        } else {
+          va += ac * ld_off(u, la + (unsigned)x * TB);
+          vb += ac * ld_off(u, lb + (unsigned)x * TB);
+        }
       }
       if (w) {
-        va += wcc * pre_w[m].x;
-        vb += wcc * pre_w[m].y;
+        if constexpr (PF) {
+          va += wcc * pre_w[m].x;
+          vb += wcc * pre_w[m].y;
+        } else {
+          va += wcc * ld_off(w, la + (unsigned)x * TB);
+          vb += wcc * ld_off(w, lb + (unsigned)x * TB);
+        }
       }
       if (hso) {
         if (oka) st_off(hso, la + (unsigned)x * TB, hsa);
@@ -1950,7 +1970,9 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
   }
   if (row256<T>(a.lgN, a.lgLc, a.lgLr, c2r, r2c)) {
     const size_t lds = (512 + (size_t)RR_PB * RR_SP) * sizeof(cx<T>);
-    hipLaunchKernelGGL(k_row_fwd256<T>, dim3(ceil_div(a.nrows, 2 * RR_PB), 1, nch), dim3(RR_NT), lds, s, a);
+    // the prefetching variant measured faster for every channel count
+    const dim3 grid(ceil_div(a.nrows, 2 * RR_PB), 1, nch);
+    hipLaunchKernelGGL((k_row_fwd256<T, true>), grid, dim3(RR_NT), lds, s, a);
     return SGSPM_KC_ROW_FWD256;
   }
   const int rows = 2 << a.lgP;
