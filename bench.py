@@ -27,8 +27,8 @@ sys.path.insert(0, ROOT)
 METRIC = "cell-updates/s per SGSPM step (fwd, adjoint) FP32 vs FP64 at stated error; %HBM"
 HBM_PEAK_GBS = 8000.0
 # timing class -> kernel (rocprofv3 shows the float instance as sgspm::k_...<float>)
-KERNEL_NAMES = {"row_fwd": "k_row_fwd", "row_fwd256": "k_row_fwd256", "row_inv": "k_row_inv",
-                "row_inv256": "k_row_inv256", "col_dct": "k_col_dct",
+KERNEL_NAMES = {"row_fwd": "k_row_fwd", "row_fwd512": "k_row_fwd512", "row_inv": "k_row_inv",
+                "row_inv512": "k_row_inv512", "col_dct": "k_col_dct",
                 "yz_solve": "k_yz_solve", "yz_reg": "k_yz_reg", "col_fft": "k_col_fft", "fft512": "k_fft512",
                 "conv": "k_conv", "conv64": "k_conv64", "other": "point-wise/reduction kernels"}
 WORKLOAD_TEXT = {

@@ -128,9 +128,9 @@ int sgspm_adjoint_step(sgspm_plan_t plan, const void* m_n, double alpha, const d
  * one kernel (its float or double instance): */
 enum {
   SGSPM_KC_ROW_FWD = 0,     /* k_row_fwd: x rows: [c2r] -> right-hand side -> [DCT-II] / [r2c] */
-  SGSPM_KC_ROW_FWD256 = 1,  /* k_row_fwd256: the same for rows of 256, in registers */
+  SGSPM_KC_ROW_FWD512 = 1,  /* k_row_fwd512: the same for rows of 256, 512-point register FFTs */
   SGSPM_KC_ROW_INV = 2,     /* k_row_inv: x rows: inverse DCT -> Gauss-Seidel update or projection -> [r2c] */
-  SGSPM_KC_ROW_INV256 = 3,  /* k_row_inv256: the same for rows of 256, in registers */
+  SGSPM_KC_ROW_INV512 = 3,  /* k_row_inv512: the same for rows of 256, 512-point register FFTs */
   SGSPM_KC_COL_DCT = 4,     /* k_col_dct: y / z pencil DCT passes (grids without the fused solve) */
   SGSPM_KC_YZ_SOLVE = 5,    /* k_yz_solve: y and z DCTs and the diagonal solve of x-major planes */
   SGSPM_KC_YZ_REG = 6,      /* k_yz_reg: the same for 256 x 32 planes, z pass in registers */

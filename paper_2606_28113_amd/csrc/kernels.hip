@@ -1574,377 +1574,339 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
 }
 
 // ---------------------------------------------------------------------------
-// Register row kernels for rows of N = 256 (zero-padded transforms of 512).
-// A workgroup of 16 RR_PB threads takes RR_PB complex pencils (two real rows
-// each, rows a in .x and b in .y); a team of 16 threads works on one pencil.
-// Between transforms every thread t holds its pencil at the Makhoul positions
-// p = t + 16 m (m < 16) of the length-256 DCT reordering, x = 2p for p < 128
-// and x = 511 - 2p above; these are also the residues 2t and 31 - 2t modulo 32
-// of the 512-point transforms, so c2r -> pointwise -> DCT-II and inverse
-// DCT -> pointwise -> r2c chain without permutations.  Transforms:
-//  DCT-II (256 = 16 x 16): DFT-16 over m, W_256^{t k1}, transpose, DFT-16 over t.
-//  r2c (512 = 16 x 32): per residue r a DFT-16 over j (x = r + 32 j, j < 8
-//    nonzero), W_512^{r k1}, transpose, DFT-32 over r.
-//  c2r and the inverse DCT: the same steps reversed.
-// Each transpose swaps the role of the thread index; the mapping of threads to
-// (pencil, index) is chosen per phase so that global accesses coalesce:
-// index-fastest for row-major arrays, pencil-fastest for x-major ones.
-constexpr int RR_PB = 8;            // complex pencils (16 rows) per workgroup
-constexpr int RR_NT = 16 * RR_PB;
-constexpr int RR_SP = 545;          // LDS complex per pencil (largest transpose 32 x 17)
+// Row kernels for rows of N = 256 with 64 threads per pair of rows.  A DCT-II of
+// length N is the real part of the twiddled, zero-padded 2N-point DFT, and the
+// inverse DCT a cropped 2N-point inverse DFT of the Hermitian extension of the
+// pre-twiddled coefficients, so all four row transforms (cropped c2r, DCT-II,
+// inverse DCT, zero-padded r2c) are 512-point FFTs with the same 8 x 8 x 8
+// four-step structure, and between them every thread t holds x = t + 64 m, m < 4.
+// Two real rows share one complex pencil (a in .x, b in .y); P pencils per
+// workgroup, thread (q = tid % P, t = tid / P).
 
-__device__ __forceinline__ int rr_minv(int p) { return p < 128 ? 2 * p : 511 - 2 * p; }
-
-// c2r of the x-level half spectra of rows ra, ra + 1 (k <= 256), cropped to
-// x < 256; thread t (index-fastest mapping) receives h[m] at p = t + 16 m.
-template <typename T>
-__device__ __forceinline__ void rr_c2r(const cx<T>* __restrict__ xin, int pitch, int ra, int nrows, int t,
-                                       cx<T>* Sq, const cx<T>* W, cx<T> (&h)[16]) {
-  cx<T> u[32];
-#pragma unroll
-  for (int k2 = 0; k2 < 32; ++k2) {
-    const int k = t + 16 * k2;
-    const int kk = k <= 256 ? k : 512 - k;
-    cx<T> Xa = zero<T>(), Xb = zero<T>();
-    if (ra < nrows) Xa = xin[(long)ra * pitch + kk];
-    if (ra + 1 < nrows) Xb = xin[(long)(ra + 1) * pitch + kk];
-    if (kk == 0 || kk == 256) {
-      Xa.y = (T)0;
-      Xb.y = (T)0;
-    }
-    if (k > 256) {
-      Xa.y = -Xa.y;
-      Xb.y = -Xb.y;
-    }
-    u[k2] = mk<T>(Xa.x - Xb.y, Xa.y + Xb.x);
-  }
-  dft32(u, true);
-#pragma unroll
-  for (int r = 1; r < 32; ++r) u[r] = cmul(u[r], conjg(W[(r * t) & 511]));
-#pragma unroll
-  for (int r = 0; r < 32; ++r) Sq[r * 17 + t] = u[r];
-  __syncthreads();
-  cx<T> w[16];
-#pragma unroll
-  for (int k1 = 0; k1 < 16; ++k1) w[k1] = Sq[(2 * t) * 17 + k1];
-  dft16(w, true);
-#pragma unroll
-  for (int j = 0; j < 8; ++j) h[j] = w[j];
-#pragma unroll
-  for (int k1 = 0; k1 < 16; ++k1) w[k1] = Sq[(31 - 2 * t) * 17 + k1];
-  dft16(w, true);
-#pragma unroll
-  for (int j = 0; j < 8; ++j) h[15 - j] = w[j];
-  __syncthreads();
-}
-
-// zero-padded r2c of v (Makhoul positions, index-fastest mapping) into the
-// half spectra of rows ra, ra + 1 (k <= 256)
-template <typename T>
-__device__ __forceinline__ void rr_r2c(const cx<T> (&v)[16], int ra, int nrows, int t, cx<T>* Sq, const cx<T>* W,
-                                       cx<T>* __restrict__ xo, int pitch) {
+// forward: v[m] = x[t + 64 m] in, v[kb] = X[(t >> 3) + 8 (t & 7) + 64 kb] out;
+// xb the LDS transpose buffer [64][S], W the table W_512^i in LDS; lo4: x[t + 64 m] = 0 for m >= 4
+template <typename T, int P, int S>
+__device__ __forceinline__ void f512_fwd(cx<T> (&v)[8], int t, int q, cx<T>* xb, const cx<T>* W, bool lo4) {
+  if (lo4) dft8_lo4(v, false);
+  else dft8(v, false);
   {
-    cx<T> e[16];
+    const int t0 = t & 7, t1 = t >> 3;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) e[j] = v[j];
-    dft16_lo8(e, false);
+    for (int k2 = 1; k2 < 8; ++k2) v[k2] = cmul(v[k2], W[(t * k2) & 511]);
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) Sq[k1 * 33 + 2 * t] = k1 ? cmul(e[k1], W[(2 * t * k1) & 511]) : e[0];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) e[j] = v[15 - j];
-    dft16_lo8(e, false);
-#pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) Sq[k1 * 33 + 31 - 2 * t] = k1 ? cmul(e[k1], W[((31 - 2 * t) * k1) & 511]) : e[0];
+    for (int k2 = 0; k2 < 8; ++k2) xb[(k2 * 8 + t0) * S + t1 * P + q] = v[k2];
   }
   __syncthreads();
-  cx<T> u[32];
+  {
+    const int k2 = t >> 3, u0 = t & 7;
 #pragma unroll
-  for (int r = 0; r < 32; ++r) u[r] = Sq[t * 33 + r];
-  dft32(u, false);
-  __syncthreads();
+    for (int u1 = 0; u1 < 8; ++u1) v[u1] = xb[(k2 * 8 + u0) * S + u1 * P + q];
+    dft8(v, false);
 #pragma unroll
-  for (int k2 = 0; k2 < 32; ++k2) Sq[t + 16 * k2] = u[k2];
-  __syncthreads();
+    for (int ka = 1; ka < 8; ++ka) v[ka] = cmul(v[ka], W[(8 * u0 * ka) & 511]);
+    __syncthreads();
 #pragma unroll
-  for (int k2 = 0; k2 <= 16; ++k2) {
-    const int k = t + 16 * k2;
-    if (k2 == 16 && t) break;
-    const cx<T> Zk = u[k2];
-    const cx<T> Zm = Sq[(512 - k) & 511];
-    const cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
-    const cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-    constexpr unsigned CB = sizeof(cx<T>);
-    if (ra < nrows) st_off(xo, ((unsigned)ra * (unsigned)pitch + (unsigned)k) * CB, Xa);
-    if (ra + 1 < nrows) st_off(xo, ((unsigned)(ra + 1) * (unsigned)pitch + (unsigned)k) * CB, Xb);
+    for (int ka = 0; ka < 8; ++ka) xb[(k2 * 8 + ka) * S + u0 * P + q] = v[ka];
   }
   __syncthreads();
+  {
+    const int k2 = t >> 3, ka = t & 7;
+#pragma unroll
+    for (int u0 = 0; u0 < 8; ++u0) v[u0] = xb[(k2 * 8 + ka) * S + u0 * P + q];
+  }
+  __syncthreads();
+  dft8(v, false);
 }
 
-template <typename T, bool PF>
-__global__ __launch_bounds__(RR_NT) void k_row_fwd256(const RowFwd<T> A) {
-  constexpr int N = 256;
+// inverse (unnormalised): v[kb] = X[(t >> 3) + 8 (t & 7) + 64 kb] in, v[m] = x[t + 64 m]
+// out; first4: only m < 4 is needed
+template <typename T, int P, int S>
+__device__ __forceinline__ void f512_inv(cx<T> (&v)[8], int t, int q, cx<T>* xb, const cx<T>* W, bool first4) {
+  {
+    const int k2 = t >> 3, ka = t & 7;
+    dft8(v, true);
+#pragma unroll
+    for (int t0 = 1; t0 < 8; ++t0) v[t0] = cmul(v[t0], conjg(W[(8 * t0 * ka) & 511]));
+#pragma unroll
+    for (int t0 = 0; t0 < 8; ++t0) xb[(k2 * 8 + t0) * S + ka * P + q] = v[t0];
+  }
+  __syncthreads();
+  {
+    const int kk2 = t >> 3, t0 = t & 7;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) v[a] = xb[(kk2 * 8 + t0) * S + a * P + q];
+    dft8(v, true);
+#pragma unroll
+    for (int t1 = 0; t1 < 8; ++t1) v[t1] = cmul(v[t1], conjg(W[((t0 + 8 * t1) * kk2) & 511]));
+    __syncthreads();
+#pragma unroll
+    for (int t1 = 0; t1 < 8; ++t1) xb[(t0 + 8 * t1) * S + kk2 * P + q] = v[t1];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int kk2 = 0; kk2 < 8; ++kk2) v[kk2] = xb[t * S + kk2 * P + q];
+  __syncthreads();
+  if (first4) dft8_first4(v, true);
+  else dft8(v, true);
+}
+
+// the spectrum X[k] of this thread's pencil, after f512_fwd, to its natural slot in xb
+template <typename T, int P, int S>
+__device__ __forceinline__ void f512_spill(const cx<T> (&v)[8], int t, int q, cx<T>* xb) {
+  const int kl = (t >> 3) + 8 * (t & 7);
+#pragma unroll
+  for (int kb = 0; kb < 8; ++kb) xb[kl * S + kb * P + q] = v[kb];
+}
+template <typename T, int P, int S> __device__ __forceinline__ cx<T> f512_at(const cx<T>* xb, int k, int q) {
+  return xb[(k & 63) * S + (k >> 6) * P + q];
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
+  constexpr int N = 256, S = fft512_stride<T, P>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);  // W_512^i
-  cx<T>* S = W + 512;
+  cx<T>* xb = W + 512;
   const Blk bk = xcd_block();
-  const int tid = threadIdx.x, ch = bk.z;
-  for (int i = tid; i < 512; i += RR_NT) W[i] = A.tw[i << (A.lgTw - 9)];
-  const int row0 = bk.x * 2 * RR_PB;
-  const int t = tid & 15, q = tid >> 4;  // index-fastest mapping
-  const int ra = row0 + 2 * q;
-  cx<T>* Sq = S + q * RR_SP;
-  // The right-hand side's inputs do not depend on the c2r: load them first (PF).
-  // One-channel launches have registers to spare; wider ones keep their occupancy.
+  const int tid = threadIdx.x, q = tid % P, t = tid / P, ch = bk.z;
+  for (int i = tid; i < 512; i += 64 * P) W[i] = A.tw[i << (A.lgTw - 9)];
+  const int ra = bk.x * 2 * P + 2 * q;
   const bool oka = ra < A.nrows, okb = ra + 1 < A.nrows;
-  // loads read rows clamped into range (finite data for rows that are never stored)
   constexpr unsigned TB = sizeof(T);
+  // loads read rows clamped into range (finite data for rows that are never stored)
   const unsigned la = (unsigned)min(ra, A.nrows - 1) * (N * TB), lb = (unsigned)min(ra + 1, A.nrows - 1) * (N * TB);
   const T* u = A.u[ch];
   const T* w = A.w[ch];
-  constexpr int NPF = PF ? 16 : 1;
-  cx<T> pre_u[NPF], pre_w[NPF];
-  if (PF) {
+  cx<T> pu[4], pw[4];
 #pragma unroll
-    for (int m = 0; m < NPF; ++m) {
-      const unsigned xo = (unsigned)rr_minv(t + 16 * m) * TB;
-      pre_u[m] = u ? mk<T>(ld_off(u, la + xo), ld_off(u, lb + xo)) : zero<T>();
-      pre_w[m] = w ? mk<T>(ld_off(w, la + xo), ld_off(w, lb + xo)) : zero<T>();
-    }
+  for (int m = 0; m < 4; ++m) {
+    const unsigned xo = (unsigned)(t + 64 * m) * TB;
+    pu[m] = u ? mk<T>(ld_off(u, la + xo), ld_off(u, lb + xo)) : zero<T>();
+    pw[m] = w ? mk<T>(ld_off(w, la + xo), ld_off(w, lb + xo)) : zero<T>();
   }
-  __syncthreads();
-  cx<T> v[16];
-  if (A.xin[ch]) rr_c2r<T>(A.xin[ch], A.xin_pitch, ra, A.nrows, t, Sq, W, v);
-  else
+  __syncthreads();  // W
+  cx<T> v[8];
+  const cx<T>* xin = A.xin[ch];
+  if (xin) {
+    // cropped c2r of the x-level half spectra (k <= 256, Hermitian completion above)
+    const int kl = (t >> 3) + 8 * (t & 7);
+    constexpr unsigned CB = sizeof(cx<T>);
+    const unsigned pa = (unsigned)min(ra, A.nrows - 1) * (unsigned)A.xin_pitch * CB;
+    const unsigned pb = (unsigned)min(ra + 1, A.nrows - 1) * (unsigned)A.xin_pitch * CB;
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = zero<T>();
-
-  // v = a u + b (hs + he) + wc w at the Makhoul positions
+    for (int kb = 0; kb < 8; ++kb) {
+      const int k = kl + 64 * kb;
+      const int kk = k <= 256 ? k : 512 - k;
+      cx<T> Xa = ld_off(xin, pa + (unsigned)kk * CB), Xb = ld_off(xin, pb + (unsigned)kk * CB);
+      if (kk == 0 || kk == 256) {
+        Xa.y = (T)0;
+        Xb.y = (T)0;
+      }
+      if (k > 256) {
+        Xa.y = -Xa.y;
+        Xb.y = -Xb.y;
+      }
+      v[kb] = mk<T>(Xa.x - Xb.y, Xa.y + Xb.x);
+    }
+    f512_inv<T, P, S>(v, t, q, xb, W, true);
+  } else {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = zero<T>();
+  }
+  // v = a u + b (hs + he) + wc w at x = t + 64 m
   {
     T* hso = A.hs_out[ch];
     T* vo = A.val_out[ch];
     const T ac = A.a[ch], hec = A.he[ch], bc = A.b, wcc = A.wc[ch];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int x = rr_minv(t + 16 * m);
+    for (int m = 0; m < 4; ++m) {
+      const unsigned xo = (unsigned)(t + 64 * m) * TB;
       const T hsa = v[m].x, hsb = v[m].y;
       T va = bc * (hsa + hec), vb = bc * (hsb + hec);
       if (u) {
-        if constexpr (PF) {
-          va += ac * pre_u[m].x;
-          vb += ac * pre_u[m].y;
-        } else {
-          va += ac * ld_off(u, la + (unsigned)x * TB);
-          vb += ac * ld_off(u, lb + (unsigned)x * TB);
-        }
+        va += ac * pu[m].x;
+        vb += ac * pu[m].y;
       }
       if (w) {
-        if constexpr (PF) {
-          va += wcc * pre_w[m].x;
-          vb += wcc * pre_w[m].y;
-        } else {
-          va += wcc * ld_off(w, la + (unsigned)x * TB);
-          vb += wcc * ld_off(w, lb + (unsigned)x * TB);
-        }
+        va += wcc * pw[m].x;
+        vb += wcc * pw[m].y;
       }
       if (hso) {
-        if (oka) st_off(hso, la + (unsigned)x * TB, hsa);
-        if (okb) st_off(hso, lb + (unsigned)x * TB, hsb);
+        if (oka) st_off(hso, la + xo, hsa);
+        if (okb) st_off(hso, lb + xo, hsb);
       }
       if (vo) {
-        if (oka) st_off(vo, la + (unsigned)x * TB, va);
-        if (okb) st_off(vo, lb + (unsigned)x * TB, vb);
+        if (oka) st_off(vo, la + xo, va);
+        if (okb) st_off(vo, lb + xo, vb);
       }
       v[m] = mk<T>(va, vb);
     }
   }
-
   T* dout = A.dct_out[ch];
-  if (dout) {
-    cx<T> d[16];
+  cx<T>* xo = A.xout[ch];
+  if (dout || xo) {
+    // one zero-padded forward transform serves the DCT-II and the r2c
 #pragma unroll
-    for (int m = 0; m < 16; ++m) d[m] = v[m];
-    dft16(d, false);
-#pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) Sq[k1 * 17 + t] = k1 ? cmul(d[k1], W[(2 * t * k1) & 511]) : d[0];
+    for (int m = 4; m < 8; ++m) v[m] = zero<T>();
+    f512_fwd<T, P, S>(v, t, q, xb, W, true);
+    f512_spill<T, P, S>(v, t, q, xb);
     __syncthreads();
-    // second stage: pencil-fastest threads for x-major stores
-    const bool xm = A.dct_xmajor != 0;
-    const int q2 = xm ? (tid % RR_PB) : q, k1 = xm ? (tid / RR_PB) : t;
-    cx<T>* S2 = S + q2 * RR_SP;
+    if (dout) {
+      const unsigned nr = (unsigned)A.nrows;
 #pragma unroll
-    for (int tt = 0; tt < 16; ++tt) d[tt] = S2[k1 * 17 + tt];
-    dft16(d, false);
-    __syncthreads();
-#pragma unroll
-    for (int k2 = 0; k2 < 16; ++k2) S2[k1 + 16 * k2] = d[k2];
-    __syncthreads();
-    const int rb2 = row0 + 2 * q2;
-    const long nr = A.nrows;
-#pragma unroll
-    for (int k2 = 0; k2 < 16; ++k2) {
-      const int k = k1 + 16 * k2;
-      const cx<T> Zk = d[k2];
-      const cx<T> Zm = S2[(N - k) & (N - 1)];
-      const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
-      const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-      const cx<T> wk = A.dtw[k];
-      const T xa = wk.x * Va.x - wk.y * Va.y, xb = wk.x * Vb.x - wk.y * Vb.y;
-      if (xm) {
-        if (rb2 < A.nrows) st_off(dout, ((unsigned)k * (unsigned)nr + (unsigned)rb2) * (unsigned)sizeof(T), xa);
-        if (rb2 + 1 < A.nrows) st_off(dout, ((unsigned)k * (unsigned)nr + (unsigned)rb2 + 1) * (unsigned)sizeof(T), xb);
-      } else {
-        if (rb2 < A.nrows) st_off(dout, ((unsigned)rb2 * N + (unsigned)k) * (unsigned)sizeof(T), xa);
-        if (rb2 + 1 < A.nrows) st_off(dout, ((unsigned)(rb2 + 1) * N + (unsigned)k) * (unsigned)sizeof(T), xb);
+      for (int j = 0; j < 4; ++j) {
+        const int k = t + 64 * j;
+        const cx<T> Zk = f512_at<T, P, S>(xb, k, q), Zm = f512_at<T, P, S>(xb, (512 - k) & 511, q);
+        const cx<T> Fa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+        const cx<T> Fb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+        const cx<T> wk = A.dtw[k];
+        const T xa = wk.x * Fa.x - wk.y * Fa.y, xbv = wk.x * Fb.x - wk.y * Fb.y;
+        if (A.dct_xmajor) {
+          if (oka) st_off(dout, ((unsigned)k * nr + (unsigned)ra) * TB, xa);
+          if (okb) st_off(dout, ((unsigned)k * nr + (unsigned)ra + 1) * TB, xbv);
+        } else {
+          if (oka) st_off(dout, la + (unsigned)k * TB, xa);
+          if (okb) st_off(dout, lb + (unsigned)k * TB, xbv);
+        }
       }
     }
-    __syncthreads();
+    if (xo) {
+      constexpr unsigned CB = sizeof(cx<T>);
+      const unsigned pitch = (unsigned)A.xout_pitch;
+#pragma unroll
+      for (int j = 0; j <= 4; ++j) {
+        const int k = t + 64 * j;
+        if (j == 4 && t) break;
+        const cx<T> Zk = f512_at<T, P, S>(xb, k, q), Zm = f512_at<T, P, S>(xb, (512 - k) & 511, q);
+        const cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+        const cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+        if (oka) st_off(xo, ((unsigned)ra * pitch + (unsigned)k) * CB, Xa);
+        if (okb) st_off(xo, ((unsigned)(ra + 1) * pitch + (unsigned)k) * CB, Xb);
+      }
+    }
   }
-  if (A.xout[ch]) rr_r2c<T>(v, ra, A.nrows, t, Sq, W, A.xout[ch], A.xout_pitch);
 }
 
-template <typename T, int NCH>
-__global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
-  constexpr int N = 256;
+template <typename T, int P, int NCH, bool XM, int OP>
+__global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
+  constexpr int N = 256, S = fft512_stride<T, P>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* S = W + 512;
+  cx<T>* xb = W + 512;
   const Blk bk = xcd_block();
-  const int tid = threadIdx.x;
-  for (int i = tid; i < 512; i += RR_NT) W[i] = A.tw[i << (A.lgTw - 9)];
-  const int row0 = bk.x * 2 * RR_PB;
-  const int t = tid & 15, q = tid >> 4;  // index-fastest mapping
-  const int ra = row0 + 2 * q;
-  cx<T>* Sq = S + q * RR_SP;
-  const bool xm = A.heat_xmajor != 0;
-  const int q1 = xm ? (tid % RR_PB) : q, k1 = xm ? (tid / RR_PB) : t;
-  const int ra1 = row0 + 2 * q1;
-  cx<T>* S1 = S + q1 * RR_SP;
-  const T invn = (T)1 / (T)N;
+  const int tid = threadIdx.x, q = tid % P, t = tid / P;
+  for (int i = tid; i < 512; i += 64 * P) W[i] = A.tw[i << (A.lgTw - 9)];
+  const int ra = bk.x * 2 * P + 2 * q;
   const bool oka = ra < A.nrows, okb = ra + 1 < A.nrows;
-  // loads read rows clamped into range (finite data for rows that are never stored)
   constexpr unsigned TB = sizeof(T);
   const unsigned la = (unsigned)min(ra, A.nrows - 1) * (N * TB), lb = (unsigned)min(ra + 1, A.nrows - 1) * (N * TB);
-  // The Gauss-Seidel operands do not depend on the transforms: load them first so
-  // their latency overlaps the heat-array loads (rows a in .x, b in .y).  At most
-  // one of Pf / Rf is an array in the sweeps; a second one is read later.  Done in
-  // single precision with one or two channels, where the registers are free.
-  constexpr bool PF = NCH < 3 && sizeof(T) == 4;
-  constexpr int NPF = PF ? 16 : 1;
-  const bool gs = A.op == ROW_OP_GS;
+  constexpr bool gs = OP == ROW_OP_GS;
+  // Gauss-Seidel operands first (they do not depend on the transforms)
   const T* PR = A.Pch < 0 ? A.Pf : (A.Rch < 0 ? A.Rf : nullptr);
-  cx<T> pre_b[NPF], pre_q[NPF], pre_s[NPF], pre_pr[NPF];
-  if (PF && gs) {
+  cx<T> pre_b[4], pre_q[4], pre_s[4], pre_pr[4];
+  if (gs) {
 #pragma unroll
-    for (int m = 0; m < NPF; ++m) {
-      const unsigned xo = (unsigned)rr_minv(t + 16 * m) * TB;
+    for (int m = 0; m < 4; ++m) {
+      const unsigned xo = (unsigned)(t + 64 * m) * TB;
       pre_b[m] = mk<T>(ld_off(A.base, la + xo), ld_off(A.base, lb + xo));
       pre_q[m] = mk<T>(ld_off(A.Qf, la + xo), ld_off(A.Qf, lb + xo));
       pre_s[m] = mk<T>(ld_off(A.Sf, la + xo), ld_off(A.Sf, lb + xo));
       pre_pr[m] = PR ? mk<T>(ld_off(PR, la + xo), ld_off(PR, lb + xo)) : zero<T>();
     }
   }
-  cx<T> g[NCH][16];
-  __syncthreads();
+  __syncthreads();  // W
+  const T invn = (T)1 / (T)N;
+  const int kl = (t >> 3) + 8 * (t & 7);
+  const unsigned ra1c = (unsigned)min(ra, A.nrows - 1), rb1c = (unsigned)min(ra + 1, A.nrows - 1);
+  cx<T> g[NCH][4];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
-    {
-      const T* H = A.heat[c];
-      cx<T> u[16];
+    const T* H = A.heat[c];
+    cx<T> v[8];
 #pragma unroll
-      for (int k2 = 0; k2 < 16; ++k2) {
-        const int k = k1 + 16 * k2;
-        // partner N - k; k = 0 has none (its partner slot reads a valid index, unused)
-        const int kp = k ? N - k : 1;
-        T xak, xam, xbk, xbm;
-        if (xm) {
-          // [N][nrows]: the k-dependent part is uniform per unrolled k2
-          const unsigned ra1c = (unsigned)min(ra1, A.nrows - 1), rb1c = (unsigned)min(ra1 + 1, A.nrows - 1);
-          const unsigned nr = (unsigned)A.nrows;
-          xak = ld_off(H, ((unsigned)k * nr + ra1c) * TB);
-          xbk = ld_off(H, ((unsigned)k * nr + rb1c) * TB);
-          xam = ld_off(H, ((unsigned)kp * nr + ra1c) * TB);
-          xbm = ld_off(H, ((unsigned)kp * nr + rb1c) * TB);
-        } else {
-          const unsigned ha = (unsigned)min(ra1, A.nrows - 1) * (N * TB), hb = (unsigned)min(ra1 + 1, A.nrows - 1) * (N * TB);
-          xak = ld_off(H, ha + (unsigned)k * TB);
-          xbk = ld_off(H, hb + (unsigned)k * TB);
-          xam = ld_off(H, ha + (unsigned)kp * TB);
-          xbm = ld_off(H, hb + (unsigned)kp * TB);
-        }
-        if (!k) {
-          xam = (T)0;
-          xbm = (T)0;
-        }
-        const cx<T> w = conjg(A.dtw[k]);
-        const cx<T> Va = cmul(w, mk<T>(xak, -xam));
-        const cx<T> Vb = cmul(w, mk<T>(xbk, -xbm));
-        u[k2] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
+    for (int kb = 0; kb < 8; ++kb) {
+      // Hermitian extension of G_k = conj(dtw_k) X_k (k < 256), G_256 = 0
+      const int k = kl + 64 * kb;
+      const int kk = k < 256 ? k : (k == 256 ? 0 : 512 - k);
+      T xa, xbv;
+      if (XM) {
+        const unsigned nr = (unsigned)A.nrows;
+        xa = ld_off(H, ((unsigned)kk * nr + ra1c) * TB);
+        xbv = ld_off(H, ((unsigned)kk * nr + rb1c) * TB);
+      } else {
+        xa = ld_off(H, la + (unsigned)kk * TB);
+        xbv = ld_off(H, lb + (unsigned)kk * TB);
       }
-      dft16(u, true);
+      cx<T> wk = A.dtw[kk];
+      if (k < 256) wk.y = -wk.y;  // conj(dtw_k) below 256, dtw_(512-k) above
+      cx<T> ga = mk<T>(wk.x * xa, wk.y * xa), gb = mk<T>(wk.x * xbv, wk.y * xbv);
+      if (k == 256) ga = gb = zero<T>();
+      v[kb] = mk<T>(ga.x - gb.y, ga.y + gb.x);
+    }
+    f512_inv<T, P, S>(v, t, q, xb, W, true);
+    T* go = A.gout[c];
 #pragma unroll
-      for (int tt = 0; tt < 16; ++tt) S1[tt * 17 + k1] = tt ? cmul(u[tt], conjg(W[(2 * tt * k1) & 511])) : u[0];
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < 16; ++kk) g[c][kk] = Sq[t * 17 + kk];
-      dft16(g[c], true);
-      T* go = A.gout[c];
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        g[c][m] = mk<T>(g[c][m].x * invn, g[c][m].y * invn);
-        if (go) {
-          const int x = rr_minv(t + 16 * m);
-          if (oka) st_off(go, la + (unsigned)x * TB, g[c][m].x);
-          if (okb) st_off(go, lb + (unsigned)x * TB, g[c][m].y);
-        }
+    for (int m = 0; m < 4; ++m) {
+      g[c][m] = mk<T>(v[m].x * invn, v[m].y * invn);
+      if (go) {
+        const unsigned xo = (unsigned)(t + 64 * m) * TB;
+        if (oka) st_off(go, la + xo, g[c][m].x);
+        if (okb) st_off(go, lb + xo, g[c][m].y);
       }
-      __syncthreads();
     }
   }
-
-  if (gs) {
+  if constexpr (gs) {
     constexpr int C1 = NCH > 1 ? 1 : 0;
-    cx<T> v[16];
+    cx<T> v[8];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int x = rr_minv(t + 16 * m);
-      T o[2] = {(T)0, (T)0};
+    for (int m = 0; m < 4; ++m) {
+      const unsigned xo = (unsigned)(t + 64 * m) * TB;
+      T o[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const bool ok = h ? okb : oka;
-        if (!ok) continue;
-        const unsigned bo = (h ? lb : la) + (unsigned)x * TB;  // this row is in range here
+        const unsigned bo = (h ? lb : la) + xo;
         const T g0 = h ? g[0][m].y : g[0][m].x;
         const T g1 = NCH > 1 ? (h ? g[C1][m].y : g[C1][m].x) : (T)0;
-        T val;
-        if constexpr (PF) {
-          const T prv = h ? pre_pr[m].y : pre_pr[m].x;
-          const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : (A.Pf == PR ? prv : ld_off(A.Pf, bo)));
-          const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : (A.Rf == PR ? prv : ld_off(A.Rf, bo)));
-          val = (h ? pre_b[m].y : pre_b[m].x) + pv * (h ? pre_q[m].y : pre_q[m].x) -
+        const T prv = h ? pre_pr[m].y : pre_pr[m].x;
+        const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : (A.Pf == PR ? prv : ld_off(A.Pf, bo)));
+        const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : (A.Rf == PR ? prv : ld_off(A.Rf, bo)));
+        T val = (h ? pre_b[m].y : pre_b[m].x) + pv * (h ? pre_q[m].y : pre_q[m].x) -
                 rv * (h ? pre_s[m].y : pre_s[m].x);
-        } else {
-          const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : ld_off(A.Pf, bo));
-          const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : ld_off(A.Rf, bo));
-          val = ld_off(A.base, bo) + pv * ld_off(A.Qf, bo) - rv * ld_off(A.Sf, bo);
-        }
         if (A.src) val += A.ds * ld_off(A.src, bo);
-        st_off(A.out, bo, val);
+        if (h ? okb : oka) st_off(A.out, bo, val);
         o[h] = val;
       }
       v[m] = mk<T>(o[0], o[1]);
     }
-    if (A.xout) rr_r2c<T>(v, ra, A.nrows, t, Sq, W, A.xout, A.xout_pitch);
-  } else if (NCH == 3 && A.op == ROW_OP_PROJECT) {
-    constexpr int C1 = NCH > 1 ? 1 : 0, C2 = NCH > 2 ? 2 : 0;
+    if (A.xout) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int x = rr_minv(t + 16 * m);
+      for (int m = 4; m < 8; ++m) v[m] = zero<T>();
+      f512_fwd<T, P, S>(v, t, q, xb, W, true);
+      f512_spill<T, P, S>(v, t, q, xb);
+      __syncthreads();
+      constexpr unsigned CB = sizeof(cx<T>);
+      const unsigned pitch = (unsigned)A.xout_pitch;
+#pragma unroll
+      for (int j = 0; j <= 4; ++j) {
+        const int k = t + 64 * j;
+        if (j == 4 && t) break;
+        const cx<T> Zk = f512_at<T, P, S>(xb, k, q), Zm = f512_at<T, P, S>(xb, (512 - k) & 511, q);
+        const cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+        const cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+        if (oka) st_off(A.xout, ((unsigned)ra * pitch + (unsigned)k) * CB, Xa);
+        if (okb) st_off(A.xout, ((unsigned)(ra + 1) * pitch + (unsigned)k) * CB, Xb);
+      }
+    }
+  } else if constexpr (NCH == 3 && OP == ROW_OP_PROJECT) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const unsigned xo = (unsigned)(t + 64 * m) * TB;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const bool ok = h ? okb : oka;
-        if (!ok) continue;
-        const unsigned bo = (h ? lb : la) + (unsigned)x * TB;
-        const T c0 = h ? g[0][m].y : g[0][m].x, c1 = h ? g[C1][m].y : g[C1][m].x, c2 = h ? g[C2][m].y : g[C2][m].x;
+        if (!(h ? okb : oka)) continue;
+        const unsigned bo = (h ? lb : la) + xo;
+        const T c0 = h ? g[0][m].y : g[0][m].x, c1 = h ? g[NCH > 1 ? 1 : 0][m].y : g[NCH > 1 ? 1 : 0][m].x,
+                c2 = h ? g[NCH > 2 ? 2 : 0][m].y : g[NCH > 2 ? 2 : 0][m].x;
         const T nr = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
         if (!(nr > (T)0) || !isfinite(nr)) A.flag[0] = 1;
         const T inr = (T)1 / nr;
@@ -1957,7 +1919,10 @@ __global__ __launch_bounds__(RR_NT) void k_row_inv256(const RowInv<T> A) {
   }
 }
 
-// the register row kernels serve rows of 256 whose padded transforms have length 512
+// pencils (pairs of rows) per workgroup of the 512-point row kernels (16 measured
+// slower in single precision: larger barriers, one workgroup per CU)
+template <typename T> constexpr int row512_pencils() { return sizeof(T) == 4 ? 8 : 4; }
+
 template <typename T> bool row256(int lgN, int lgLc, int lgLr, bool c2r, bool r2c) {
   return lgN == 8 && (!c2r || lgLc == 9) && (!r2c || lgLr == 9);
 }
@@ -1969,11 +1934,11 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
     r2c = r2c || a.xout[c];
   }
   if (row256<T>(a.lgN, a.lgLc, a.lgLr, c2r, r2c)) {
-    const size_t lds = (512 + (size_t)RR_PB * RR_SP) * sizeof(cx<T>);
-    // the prefetching variant measured faster for every channel count
-    const dim3 grid(ceil_div(a.nrows, 2 * RR_PB), 1, nch);
-    hipLaunchKernelGGL((k_row_fwd256<T, true>), grid, dim3(RR_NT), lds, s, a);
-    return SGSPM_KC_ROW_FWD256;
+    constexpr int P = row512_pencils<T>();
+    const size_t lds = (512 + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
+    const dim3 grid(ceil_div(a.nrows, 2 * P), 1, nch);
+    hipLaunchKernelGGL((k_row_fwd512<T, P>), grid, dim3(64 * P), lds, s, a);
+    return SGSPM_KC_ROW_FWD512;
   }
   const int rows = 2 << a.lgP;
   dim3 grid(ceil_div(a.nrows, rows), 1, nch);
@@ -1982,14 +1947,41 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
   return SGSPM_KC_ROW_FWD;
 }
 
+template <typename T, int NCH, bool XM>
+void launch_row_inv512_op(const RowInv<T>& a, dim3 grid, size_t lds, hipStream_t s) {
+  constexpr int P = row512_pencils<T>();
+  const dim3 blk(64 * P);
+  if constexpr (NCH < 3) {
+    if (a.op == ROW_OP_GS) {
+      hipLaunchKernelGGL((k_row_inv512<T, P, NCH, XM, ROW_OP_GS>), grid, blk, lds, s, a);
+      return;
+    }
+  } else {
+    if (a.op == ROW_OP_PROJECT) {
+      hipLaunchKernelGGL((k_row_inv512<T, P, NCH, XM, ROW_OP_PROJECT>), grid, blk, lds, s, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_row_inv512<T, P, NCH, XM, ROW_OP_NONE>), grid, blk, lds, s, a);
+}
+template <typename T> void launch_row_inv512_mode(const RowInv<T>& a, dim3 grid, size_t lds, hipStream_t s) {
+  const bool xm = a.heat_xmajor != 0;
+  if (a.nch == 1) xm ? launch_row_inv512_op<T, 1, true>(a, grid, lds, s) : launch_row_inv512_op<T, 1, false>(a, grid, lds, s);
+  else if (a.nch == 2) xm ? launch_row_inv512_op<T, 2, true>(a, grid, lds, s) : launch_row_inv512_op<T, 2, false>(a, grid, lds, s);
+  else xm ? launch_row_inv512_op<T, 3, true>(a, grid, lds, s) : launch_row_inv512_op<T, 3, false>(a, grid, lds, s);
+}
+
 template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
-  if (row256<T>(a.lgN, a.lgLr, a.lgLr, false, a.xout != nullptr)) {
-    const size_t lds = (512 + (size_t)RR_PB * RR_SP) * sizeof(cx<T>);
-    const dim3 grid(ceil_div(a.nrows, 2 * RR_PB));
-    if (a.nch == 1) hipLaunchKernelGGL((k_row_inv256<T, 1>), grid, dim3(RR_NT), lds, s, a);
-    else if (a.nch == 2) hipLaunchKernelGGL((k_row_inv256<T, 2>), grid, dim3(RR_NT), lds, s, a);
-    else hipLaunchKernelGGL((k_row_inv256<T, 3>), grid, dim3(RR_NT), lds, s, a);
-    return SGSPM_KC_ROW_INV256;
+  // the register kernel covers the sweeps (update with one or two channels), the
+  // projection (three) and plain inverse transforms (one to three)
+  const bool mode_ok = (a.op == ROW_OP_GS && a.nch < 3) || (a.op == ROW_OP_PROJECT && a.nch == 3) ||
+                       a.op == ROW_OP_NONE;
+  if (mode_ok && row256<T>(a.lgN, a.lgLr, a.lgLr, false, a.xout != nullptr)) {
+    constexpr int P = row512_pencils<T>();
+    const size_t lds = (512 + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
+    const dim3 grid(ceil_div(a.nrows, 2 * P));
+    launch_row_inv512_mode<T>(a, grid, lds, s);
+    return SGSPM_KC_ROW_INV512;
   }
   const int rows = 2 << a.lgP;
   dim3 grid(ceil_div(a.nrows, rows), 1, 1);
