@@ -18,9 +18,6 @@ namespace sgspm {
 
 template <typename T> __device__ __forceinline__ cx<T> zero() { return mk<T>((T)0, (T)0); }
 
-// Workgroups go to the 8 XCDs round-robin by linear id, and each XCD has its
-// own L2.  Renumber them so that consecutive logical workgroups (neighbours
-// that read the two halves of the same 128-byte lines) run on one XCD.
 // element at a byte offset from a base pointer
 template <typename V> __device__ __forceinline__ V ld_off(const V* base, unsigned byte_off) {
   return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
@@ -29,6 +26,9 @@ template <typename V> __device__ __forceinline__ void st_off(V* base, unsigned b
   *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
+// Workgroups go to the 8 XCDs round-robin by linear id, and each XCD has its
+// own L2.  Renumber them so that consecutive logical workgroups (neighbours
+// that read the two halves of the same 128-byte lines) run on one XCD.
 struct Blk {
   int x, y, z;
 };
@@ -749,7 +749,6 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
   const int tid = threadIdx.x;
   const int q = tid % P;
   const int t = tid / P;  // 0..63
-  for (int i = tid; i < 512; i += 64 * P) w[i] = A.tw[i << (A.lgTw - 9)];
   const Blk bk = xcd_block();
   const int kx = bk.x * P + q;
   const bool act = kx < A.ni;
@@ -766,6 +765,7 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
     if (inv) v.y = -v.y;
     return v;
   };
+  // the pencil first, then the W table: one round trip to memory
   cx<T> v[8];
   if (!inv) {
 #pragma unroll
@@ -773,7 +773,16 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
       const int row = t + 64 * m;
       v[m] = row < A.n_in ? ld_off(in, ioff + (unsigned)row * isa) : zero<T>();
     }
-    __syncthreads();
+  } else {
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      const int k = (t >> 3) + 8 * (t & 7) + 64 * kb;
+      v[kb] = k < A.n_in ? ld_off(in, ioff + (unsigned)k * isa) : zero<T>();
+    }
+  }
+  for (int i = tid; i < 512; i += 64 * P) w[i] = A.tw[i << (A.lgTw - 9)];
+  __syncthreads();
+  if (!inv) {
     if (A.n_in <= 256) dft8_lo4(v, false);  // zero-padded half: rows t + 64 m, m >= 4
     else dft8(v, false);
     const int t0 = t & 7, t1 = t >> 3;
@@ -809,12 +818,6 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
     }
   } else {
     const int k2 = t >> 3, ka = t & 7;
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
-      const int k = k2 + 8 * ka + 64 * kb;
-      v[kb] = k < A.n_in ? ld_off(in, ioff + (unsigned)k * isa) : zero<T>();
-    }
-    __syncthreads();
     dft8(v, true);  // index t0
 #pragma unroll
     for (int t0 = 1; t0 < 8; ++t0) v[t0] = cmul(v[t0], W(8 * t0 * ka));
@@ -995,7 +998,6 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const
   const int q = tid & (P - 1);
   const int t = (tid >> A.lgP) & 7;
   const int r = tid >> (A.lgP + 3);
-  for (int i = tid; i < 64; i += C64_NT) w64[i] = A.tw[i << (A.lgTw - 6)];
   const Blk bk = xcd_block();
   const int bf = bk.y;
   const int kx0 = bk.x * P;
@@ -1019,6 +1021,8 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const
 #pragma unroll
     for (int m = 0; m < 4; ++m) v[c][m] = S ? ld_off(S, soff + (unsigned)(t + 8 * m) * sa) : zero<T>();
   }
+  // the W table after the pencils: one round trip to memory
+  for (int i = tid; i < 64; i += C64_NT) w64[i] = A.tw[i << (A.lgTw - 6)];
   __syncthreads();  // w64 is in LDS
   // this thread's twiddles W_64^{t k}, k < 8 (conjugated for the inverse)
   cx<T> twr[8];
@@ -1431,23 +1435,42 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
   static_assert(NTH == NY, "one z thread per column");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* Wy = reinterpret_cast<cx<T>*>(smem_raw);  // W_NY^i
-  cx<T>* Zs = Wy + NY;                             // [HZ][RS] complex, reused as [NZ][RS] reals
+  cx<T>* Dy = Wy + NY;                             // y DCT twiddles
+  cx<T>* Dz = Dy + NY;                             // z DCT twiddles
+  cx<T>* Zs = Dz + NZ;                             // [HZ][RS] complex, reused as [NZ][RS] reals
+  T* Ly = reinterpret_cast<T*>(Zs + HZ * RS);      // y eigenvalues
+  T* Lz = Ly + NY;                                 // z eigenvalues
   T* Yr = reinterpret_cast<T*>(Zs);
   const int tid = threadIdx.x;
-  for (int i = tid; i < NY; i += NTH) Wy[i] = A.tw[i << (A.lgTw - LGY)];
   const int r = tid / R2, t = tid % R2;
   T* D = A.data[blockIdx.z] + (long)blockIdx.x * (NY * NZ);
   cx<T>* zs = Zs + r * RS;
   auto minv = [](int p) { return p < NY / 2 ? 2 * p : 2 * (NY - 1 - p) + 1; };
+  T lx;
 
   // ---- y forward
   {
+    // the plane first, then the tables into LDS: one round trip to memory
     cx<T> v[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const int y = minv(t + R2 * m);
       v[m] = mk<T>(D[r * NY + y], D[(r + HZ) * NY + y]);
     }
+    // one table entry per thread (NTH = NY)
+    const cx<T> w_i = A.tw[tid << (A.lgTw - LGY)], dy_i = A.dtwy[tid];
+    const T ly_i = A.lamY[tid];
+    const int iz = min(tid, NZ - 1);
+    const cx<T> dz_i = A.dtwz[iz];
+    const T lz_i = A.lamZ[iz];
+    lx = A.lamX[blockIdx.x];
+    Wy[tid] = w_i;
+    Dy[tid] = dy_i;
+    Ly[tid] = ly_i;
+    // threads past NZ repeat entry NZ - 1 (same value, same slot): no branch for the
+    // compiler to sink these loads into
+    Dz[iz] = dz_i;
+    Lz[iz] = lz_i;
     __syncthreads();
     dft16(v, false);
 #pragma unroll
@@ -1476,7 +1499,7 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
   {
     const int c = tid;
     const int cm = (NY - c) & (NY - 1);
-    const cx<T> wy = A.dtwy[c];
+    const cx<T> wy = Dy[c];
     cx<T> u[HZ];  // u_n = v_2n + i v_2n+1, v the Makhoul order of the column
 #pragma unroll
     for (int q = 0; q < HZ; ++q) {
@@ -1494,8 +1517,7 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
       else u[pb >> 1].x = yb;
     }
     dft16(u, false);
-    const T lx = A.lamX[blockIdx.x];
-    const T dc = (T)1 + A.s * (lx + A.lamY[c]);
+    const T dc = (T)1 + A.s * (lx + Ly[c]);
     T X[NZ];
     // V_k = E_k + W_32^k O_k from U_k and conj U_(16-k); V_(32-k) = conj V_k
 #pragma unroll
@@ -1505,19 +1527,19 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
       const cx<T> E = mk<T>((Uk.x + Um.x) * (T)0.5, (Uk.y + Um.y) * (T)0.5);
       const cx<T> O = mk<T>((Uk.y - Um.y) * (T)0.5, (Um.x - Uk.x) * (T)0.5);
       const cx<T> V = E + tw32v(O, k, false);
-      const cx<T> wk = A.dtwz[k];
-      X[k] = (wk.x * V.x - wk.y * V.y) * recip(dc + A.s * A.lamZ[k]);
+      const cx<T> wk = Dz[k];
+      X[k] = (wk.x * V.x - wk.y * V.y) * recip(dc + A.s * Lz[k]);
       if (k > 0 && k < HZ) {
-        const cx<T> wm = A.dtwz[NZ - k];
-        X[NZ - k] = (wm.x * V.x + wm.y * V.y) * recip(dc + A.s * A.lamZ[NZ - k]);
+        const cx<T> wm = Dz[NZ - k];
+        X[NZ - k] = (wm.x * V.x + wm.y * V.y) * recip(dc + A.s * Lz[NZ - k]);
       }
     }
     // DCT-III input V_j = conj(dtwz_j) (X_j - i X_(32-j)), folded to 16 points:
     // E = (V_k + V_(k+16)) / 2, O = (V_k - V_(k+16)) conj(W_32^k) / 2, u_k = E + i O
 #pragma unroll
     for (int k = 0; k < HZ; ++k) {
-      const cx<T> Vk = cmul(conjg(A.dtwz[k]), mk<T>(X[k], k ? -X[NZ - k] : (T)0));
-      const cx<T> Vj = cmul(conjg(A.dtwz[k + HZ]), mk<T>(X[k + HZ], -X[HZ - k]));
+      const cx<T> Vk = cmul(conjg(Dz[k]), mk<T>(X[k], k ? -X[NZ - k] : (T)0));
+      const cx<T> Vj = cmul(conjg(Dz[k + HZ]), mk<T>(X[k + HZ], -X[HZ - k]));
       const cx<T> E = mk<T>((Vk.x + Vj.x) * (T)0.5, (Vk.y + Vj.y) * (T)0.5);
       const cx<T> O = tw32v(mk<T>((Vk.x - Vj.x) * (T)0.5, (Vk.y - Vj.y) * (T)0.5), k, true);
       u[k] = mk<T>(E.x - O.y, E.y + O.x);
@@ -1543,7 +1565,7 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) {
         const int k = k1 + 16 * k2;
-        const cx<T> w = conjg(A.dtwy[k]);
+        const cx<T> w = conjg(Dy[k]);
         const cx<T> Va = cmul(w, mk<T>(ya[k], k ? -ya[NY - k] : (T)0));
         const cx<T> Vb = cmul(w, mk<T>(yb[k], k ? -yb[NY - k] : (T)0));
         v[g * R2 + k2] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
@@ -1661,6 +1683,10 @@ template <typename T, int P, int S> __device__ __forceinline__ cx<T> f512_at(con
   return xb[(k & 63) * S + (k >> 6) * P + q];
 }
 
+// Memory order in both kernels: every global load (operands, spectra, DCT
+// twiddles, then the W table) is issued before the first wait, and no load
+// follows a store.  The hardware counts loads and stores in one in-order
+// counter, so a load issued after a store would make its wait cover the store.
 template <typename T, int P>
 __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
   constexpr int N = 256, S = fft512_stride<T, P>();
@@ -1669,44 +1695,58 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
   cx<T>* xb = W + 512;
   const Blk bk = xcd_block();
   const int tid = threadIdx.x, q = tid % P, t = tid / P, ch = bk.z;
-  for (int i = tid; i < 512; i += 64 * P) W[i] = A.tw[i << (A.lgTw - 9)];
   const int ra = bk.x * 2 * P + 2 * q;
   const bool oka = ra < A.nrows, okb = ra + 1 < A.nrows;
-  constexpr unsigned TB = sizeof(T);
+  constexpr unsigned TB = sizeof(T), CB = sizeof(cx<T>);
   // loads read rows clamped into range (finite data for rows that are never stored)
-  const unsigned la = (unsigned)min(ra, A.nrows - 1) * (N * TB), lb = (unsigned)min(ra + 1, A.nrows - 1) * (N * TB);
+  const unsigned ra1c = (unsigned)min(ra, A.nrows - 1), rb1c = (unsigned)min(ra + 1, A.nrows - 1);
+  const unsigned la = ra1c * (N * TB), lb = rb1c * (N * TB);
   const T* u = A.u[ch];
   const T* w = A.w[ch];
-  cx<T> pu[4], pw[4];
+  const cx<T>* xin = A.xin[ch];
+  T* dout = A.dct_out[ch];
+  cx<T>* xo = A.xout[ch];
+  // this thread's spectral slots k = kl + 64 kb of the 512-point transforms
+  const int kl = (t >> 3) + 8 * (t & 7);
+  cx<T> Xa[8], Xb[8];
+  if (xin) {
+    // x-level half spectra (k <= 256) of both rows
+    const unsigned pa = ra1c * (unsigned)A.xin_pitch * CB, pb = rb1c * (unsigned)A.xin_pitch * CB;
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      const int k = kl + 64 * kb;
+      const unsigned kk = (unsigned)(k <= 256 ? k : 512 - k);
+      Xa[kb] = ld_off(xin, pa + kk * CB);
+      Xb[kb] = ld_off(xin, pb + kk * CB);
+    }
+  }
+  cx<T> pu[4], pw[4], wk[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    const unsigned xo = (unsigned)(t + 64 * m) * TB;
-    pu[m] = u ? mk<T>(ld_off(u, la + xo), ld_off(u, lb + xo)) : zero<T>();
-    pw[m] = w ? mk<T>(ld_off(w, la + xo), ld_off(w, lb + xo)) : zero<T>();
+    const unsigned xo4 = (unsigned)(t + 64 * m) * TB;
+    pu[m] = u ? mk<T>(ld_off(u, la + xo4), ld_off(u, lb + xo4)) : zero<T>();
+    pw[m] = w ? mk<T>(ld_off(w, la + xo4), ld_off(w, lb + xo4)) : zero<T>();
+    wk[m] = dout ? A.dtw[t + 64 * m] : zero<T>();
   }
-  __syncthreads();  // W
+  for (int i = tid; i < 512; i += 64 * P) W[i] = A.tw[i << (A.lgTw - 9)];
+  __syncthreads();
   cx<T> v[8];
-  const cx<T>* xin = A.xin[ch];
   if (xin) {
-    // cropped c2r of the x-level half spectra (k <= 256, Hermitian completion above)
-    const int kl = (t >> 3) + 8 * (t & 7);
-    constexpr unsigned CB = sizeof(cx<T>);
-    const unsigned pa = (unsigned)min(ra, A.nrows - 1) * (unsigned)A.xin_pitch * CB;
-    const unsigned pb = (unsigned)min(ra + 1, A.nrows - 1) * (unsigned)A.xin_pitch * CB;
+    // cropped c2r: Hermitian completion above k = 256, both rows packed as a + i b
 #pragma unroll
     for (int kb = 0; kb < 8; ++kb) {
       const int k = kl + 64 * kb;
       const int kk = k <= 256 ? k : 512 - k;
-      cx<T> Xa = ld_off(xin, pa + (unsigned)kk * CB), Xb = ld_off(xin, pb + (unsigned)kk * CB);
+      cx<T> xa = Xa[kb], xbb = Xb[kb];
       if (kk == 0 || kk == 256) {
-        Xa.y = (T)0;
-        Xb.y = (T)0;
+        xa.y = (T)0;
+        xbb.y = (T)0;
       }
       if (k > 256) {
-        Xa.y = -Xa.y;
-        Xb.y = -Xb.y;
+        xa.y = -xa.y;
+        xbb.y = -xbb.y;
       }
-      v[kb] = mk<T>(Xa.x - Xb.y, Xa.y + Xb.x);
+      v[kb] = mk<T>(xa.x - xbb.y, xa.y + xbb.x);
     }
     f512_inv<T, P, S>(v, t, q, xb, W, true);
   } else {
@@ -1720,7 +1760,7 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
     const T ac = A.a[ch], hec = A.he[ch], bc = A.b, wcc = A.wc[ch];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const unsigned xo = (unsigned)(t + 64 * m) * TB;
+      const unsigned xo4 = (unsigned)(t + 64 * m) * TB;
       const T hsa = v[m].x, hsb = v[m].y;
       T va = bc * (hsa + hec), vb = bc * (hsb + hec);
       if (u) {
@@ -1732,18 +1772,16 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
         vb += wcc * pw[m].y;
       }
       if (hso) {
-        if (oka) st_off(hso, la + xo, hsa);
-        if (okb) st_off(hso, lb + xo, hsb);
+        if (oka) st_off(hso, la + xo4, hsa);
+        if (okb) st_off(hso, lb + xo4, hsb);
       }
       if (vo) {
-        if (oka) st_off(vo, la + xo, va);
-        if (okb) st_off(vo, lb + xo, vb);
+        if (oka) st_off(vo, la + xo4, va);
+        if (okb) st_off(vo, lb + xo4, vb);
       }
       v[m] = mk<T>(va, vb);
     }
   }
-  T* dout = A.dct_out[ch];
-  cx<T>* xo = A.xout[ch];
   if (dout || xo) {
     // one zero-padded forward transform serves the DCT-II and the r2c
 #pragma unroll
@@ -1759,11 +1797,10 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
         const cx<T> Zk = f512_at<T, P, S>(xb, k, q), Zm = f512_at<T, P, S>(xb, (512 - k) & 511, q);
         const cx<T> Fa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
         const cx<T> Fb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-        const cx<T> wk = A.dtw[k];
-        const T xa = wk.x * Fa.x - wk.y * Fa.y, xbv = wk.x * Fb.x - wk.y * Fb.y;
+        const T xa = wk[j].x * Fa.x - wk[j].y * Fa.y, xbv = wk[j].x * Fb.x - wk[j].y * Fb.y;
         if (A.dct_xmajor) {
-          if (oka) st_off(dout, ((unsigned)k * nr + (unsigned)ra) * TB, xa);
-          if (okb) st_off(dout, ((unsigned)k * nr + (unsigned)ra + 1) * TB, xbv);
+          // [N][nrows] with nrows even: the pair (ra, ra + 1) is one aligned vector
+          if (oka) st_off(reinterpret_cast<cx<T>*>(dout), ((unsigned)k * nr + (unsigned)ra) * TB, mk<T>(xa, xbv));
         } else {
           if (oka) st_off(dout, la + (unsigned)k * TB, xa);
           if (okb) st_off(dout, lb + (unsigned)k * TB, xbv);
@@ -1771,17 +1808,16 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
       }
     }
     if (xo) {
-      constexpr unsigned CB = sizeof(cx<T>);
       const unsigned pitch = (unsigned)A.xout_pitch;
 #pragma unroll
       for (int j = 0; j <= 4; ++j) {
         const int k = t + 64 * j;
         if (j == 4 && t) break;
         const cx<T> Zk = f512_at<T, P, S>(xb, k, q), Zm = f512_at<T, P, S>(xb, (512 - k) & 511, q);
-        const cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
-        const cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-        if (oka) st_off(xo, ((unsigned)ra * pitch + (unsigned)k) * CB, Xa);
-        if (okb) st_off(xo, ((unsigned)(ra + 1) * pitch + (unsigned)k) * CB, Xb);
+        const cx<T> Xa2 = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+        const cx<T> Xb2 = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+        if (oka) st_off(xo, ((unsigned)ra * pitch + (unsigned)k) * CB, Xa2);
+        if (okb) st_off(xo, ((unsigned)(ra + 1) * pitch + (unsigned)k) * CB, Xb2);
       }
     }
   }
@@ -1795,15 +1831,42 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
   cx<T>* xb = W + 512;
   const Blk bk = xcd_block();
   const int tid = threadIdx.x, q = tid % P, t = tid / P;
-  for (int i = tid; i < 512; i += 64 * P) W[i] = A.tw[i << (A.lgTw - 9)];
   const int ra = bk.x * 2 * P + 2 * q;
   const bool oka = ra < A.nrows, okb = ra + 1 < A.nrows;
   constexpr unsigned TB = sizeof(T);
-  const unsigned la = (unsigned)min(ra, A.nrows - 1) * (N * TB), lb = (unsigned)min(ra + 1, A.nrows - 1) * (N * TB);
+  const unsigned ra1c = (unsigned)min(ra, A.nrows - 1), rb1c = (unsigned)min(ra + 1, A.nrows - 1);
+  const unsigned la = ra1c * (N * TB), lb = rb1c * (N * TB);
   constexpr bool gs = OP == ROW_OP_GS;
-  // Gauss-Seidel operands first (they do not depend on the transforms)
+  const int kl = (t >> 3) + 8 * (t & 7);
+  // heat coefficients of every channel at this thread's slots k = kl + 64 kb
+  // (their Hermitian-extension index kk), and the DCT twiddles of those slots
+  T ha[NCH][8], hb[NCH][8];
+  cx<T> wq[8];
+  {
+    // x-major arrays [N][nrows] (nrows even): rows ra, ra + 1 are one aligned vector
+    const unsigned rp = XM ? (unsigned)min(ra, A.nrows - 2) : 0u, nr = (unsigned)A.nrows;
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      const int k = kl + 64 * kb;
+      const unsigned kk = (unsigned)(k < 256 ? k : (k == 256 ? 0 : 512 - k));
+      wq[kb] = A.dtw[kk];
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        if (XM) {
+          const cx<T> h2 = ld_off(reinterpret_cast<const cx<T>*>(A.heat[c]), (kk * nr + rp) * TB);
+          ha[c][kb] = h2.x;
+          hb[c][kb] = h2.y;
+        } else {
+          ha[c][kb] = ld_off(A.heat[c], la + kk * TB);
+          hb[c][kb] = ld_off(A.heat[c], lb + kk * TB);
+        }
+      }
+    }
+  }
+  // Gauss-Seidel operands: at most one of P, R is an array (the other an inverted
+  // channel), the caller guarantees it
   const T* PR = A.Pch < 0 ? A.Pf : (A.Rch < 0 ? A.Rf : nullptr);
-  cx<T> pre_b[4], pre_q[4], pre_s[4], pre_pr[4];
+  cx<T> pre_b[4], pre_q[4], pre_s[4], pre_pr[4], pre_src[4];
   if (gs) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -1812,34 +1875,23 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
       pre_q[m] = mk<T>(ld_off(A.Qf, la + xo), ld_off(A.Qf, lb + xo));
       pre_s[m] = mk<T>(ld_off(A.Sf, la + xo), ld_off(A.Sf, lb + xo));
       pre_pr[m] = PR ? mk<T>(ld_off(PR, la + xo), ld_off(PR, lb + xo)) : zero<T>();
+      pre_src[m] = A.src ? mk<T>(ld_off(A.src, la + xo), ld_off(A.src, lb + xo)) : zero<T>();
     }
   }
-  __syncthreads();  // W
+  for (int i = tid; i < 512; i += 64 * P) W[i] = A.tw[i << (A.lgTw - 9)];
+  __syncthreads();
   const T invn = (T)1 / (T)N;
-  const int kl = (t >> 3) + 8 * (t & 7);
-  const unsigned ra1c = (unsigned)min(ra, A.nrows - 1), rb1c = (unsigned)min(ra + 1, A.nrows - 1);
   cx<T> g[NCH][4];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
-    const T* H = A.heat[c];
     cx<T> v[8];
 #pragma unroll
     for (int kb = 0; kb < 8; ++kb) {
       // Hermitian extension of G_k = conj(dtw_k) X_k (k < 256), G_256 = 0
       const int k = kl + 64 * kb;
-      const int kk = k < 256 ? k : (k == 256 ? 0 : 512 - k);
-      T xa, xbv;
-      if (XM) {
-        const unsigned nr = (unsigned)A.nrows;
-        xa = ld_off(H, ((unsigned)kk * nr + ra1c) * TB);
-        xbv = ld_off(H, ((unsigned)kk * nr + rb1c) * TB);
-      } else {
-        xa = ld_off(H, la + (unsigned)kk * TB);
-        xbv = ld_off(H, lb + (unsigned)kk * TB);
-      }
-      cx<T> wk = A.dtw[kk];
+      cx<T> wk = wq[kb];
       if (k < 256) wk.y = -wk.y;  // conj(dtw_k) below 256, dtw_(512-k) above
-      cx<T> ga = mk<T>(wk.x * xa, wk.y * xa), gb = mk<T>(wk.x * xbv, wk.y * xbv);
+      cx<T> ga = mk<T>(wk.x * ha[c][kb], wk.y * ha[c][kb]), gb = mk<T>(wk.x * hb[c][kb], wk.y * hb[c][kb]);
       if (k == 256) ga = gb = zero<T>();
       v[kb] = mk<T>(ga.x - gb.y, ga.y + gb.x);
     }
@@ -1857,6 +1909,7 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
   }
   if constexpr (gs) {
     constexpr int C1 = NCH > 1 ? 1 : 0;
+    const T ds = A.ds;
     cx<T> v[8];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -1864,18 +1917,16 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
       T o[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const unsigned bo = (h ? lb : la) + xo;
         const T g0 = h ? g[0][m].y : g[0][m].x;
         const T g1 = NCH > 1 ? (h ? g[C1][m].y : g[C1][m].x) : (T)0;
         const T prv = h ? pre_pr[m].y : pre_pr[m].x;
-        const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : (A.Pf == PR ? prv : ld_off(A.Pf, bo)));
-        const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : (A.Rf == PR ? prv : ld_off(A.Rf, bo)));
-        T val = (h ? pre_b[m].y : pre_b[m].x) + pv * (h ? pre_q[m].y : pre_q[m].x) -
-                rv * (h ? pre_s[m].y : pre_s[m].x);
-        if (A.src) val += A.ds * ld_off(A.src, bo);
-        if (h ? okb : oka) st_off(A.out, bo, val);
-        o[h] = val;
+        const T pv = A.Pch == 0 ? g0 : (A.Pch == 1 ? g1 : prv);
+        const T rv = A.Rch == 0 ? g0 : (A.Rch == 1 ? g1 : prv);
+        o[h] = (h ? pre_b[m].y : pre_b[m].x) + pv * (h ? pre_q[m].y : pre_q[m].x) -
+               rv * (h ? pre_s[m].y : pre_s[m].x) + ds * (h ? pre_src[m].y : pre_src[m].x);
       }
+      if (oka) st_off(A.out, la + xo, o[0]);
+      if (okb) st_off(A.out, lb + xo, o[1]);
       v[m] = mk<T>(o[0], o[1]);
     }
     if (A.xout) {
@@ -1937,7 +1988,9 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
     constexpr int P = row512_pencils<T>();
     const size_t lds = (512 + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
     const dim3 grid(ceil_div(a.nrows, 2 * P), 1, nch);
-    hipLaunchKernelGGL((k_row_fwd512<T, P>), grid, dim3(64 * P), lds, s, a);
+    RowFwd<T> b = a;
+    b.dct_xmajor = a.dct_xmajor && a.nrows > 1;  // one row: both layouts coincide
+    hipLaunchKernelGGL((k_row_fwd512<T, P>), grid, dim3(64 * P), lds, s, b);
     return SGSPM_KC_ROW_FWD512;
   }
   const int rows = 2 << a.lgP;
@@ -1965,7 +2018,7 @@ void launch_row_inv512_op(const RowInv<T>& a, dim3 grid, size_t lds, hipStream_t
   hipLaunchKernelGGL((k_row_inv512<T, P, NCH, XM, ROW_OP_NONE>), grid, blk, lds, s, a);
 }
 template <typename T> void launch_row_inv512_mode(const RowInv<T>& a, dim3 grid, size_t lds, hipStream_t s) {
-  const bool xm = a.heat_xmajor != 0;
+  const bool xm = a.heat_xmajor != 0 && a.nrows > 1;  // one row: both layouts coincide
   if (a.nch == 1) xm ? launch_row_inv512_op<T, 1, true>(a, grid, lds, s) : launch_row_inv512_op<T, 1, false>(a, grid, lds, s);
   else if (a.nch == 2) xm ? launch_row_inv512_op<T, 2, true>(a, grid, lds, s) : launch_row_inv512_op<T, 2, false>(a, grid, lds, s);
   else xm ? launch_row_inv512_op<T, 3, true>(a, grid, lds, s) : launch_row_inv512_op<T, 3, false>(a, grid, lds, s);
@@ -1974,8 +2027,8 @@ template <typename T> void launch_row_inv512_mode(const RowInv<T>& a, dim3 grid,
 template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
   // the register kernel covers the sweeps (update with one or two channels), the
   // projection (three) and plain inverse transforms (one to three)
-  const bool mode_ok = (a.op == ROW_OP_GS && a.nch < 3) || (a.op == ROW_OP_PROJECT && a.nch == 3) ||
-                       a.op == ROW_OP_NONE;
+  const bool mode_ok = (a.op == ROW_OP_GS && a.nch < 3 && !(a.Pch < 0 && a.Rch < 0)) ||
+                       (a.op == ROW_OP_PROJECT && a.nch == 3) || a.op == ROW_OP_NONE;
   if (mode_ok && row256<T>(a.lgN, a.lgLr, a.lgLr, false, a.xout != nullptr)) {
     constexpr int P = row512_pencils<T>();
     const size_t lds = (512 + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
@@ -2020,7 +2073,8 @@ template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStrea
   (void)lgR;
   if (yz_reg_plane(1 << a.lgNy, 1 << a.lgNz)) {
     constexpr int NY = 256, NZ = 32;
-    const size_t lr = (NY + (size_t)(NZ / 2) * (NY + 16)) * sizeof(cx<T>);
+    // W, y and z DCT twiddles, the [NZ/2][NY + 16] buffer, y and z eigenvalues
+    const size_t lr = (2 * NY + NZ + (size_t)(NZ / 2) * (NY + 16)) * sizeof(cx<T>) + (NY + NZ) * sizeof(T);
     hipLaunchKernelGGL((k_yz_reg<T, 8, 5>), dim3(a.nx, 1, nch), dim3((NZ / 2) * (NY / 16)), lr, s, a);
     return SGSPM_KC_YZ_REG;
   }
