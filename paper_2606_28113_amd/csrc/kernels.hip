@@ -1605,16 +1605,24 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
 // Two real rows share one complex pencil (a in .x, b in .y); P pencils per
 // workgroup, thread (q = tid % P, t = tid / P).
 
-// forward: v[m] = x[t + 64 m] in, v[kb] = X[(t >> 3) + 8 (t & 7) + 64 kb] out;
-// xb the LDS transpose buffer [64][S], W the table W_512^i in LDS; lo4: x[t + 64 m] = 0 for m >= 4
-template <typename T, int P, int S>
-__device__ __forceinline__ void f512_fwd(cx<T> (&v)[8], int t, int q, cx<T>* xb, const cx<T>* W, bool lo4) {
-  if (lo4) dft8_lo4(v, false);
-  else dft8(v, false);
+// natural order in: v[m] = x[t + 64 m]; digit order out: v[kb] = X[(t >> 3) + 8 (t & 7) + 64 kb],
+// the forward DFT, or with INV the unnormalised inverse (conjugate twiddles);
+// xb the LDS transpose buffer [64][S], W the table W_512^i in LDS;
+// lo4: x[t + 64 m] = 0 for m >= 4; first4: only kb < 4 is needed
+template <typename T, int P, int S, bool INV>
+__device__ __forceinline__ void f512_dif(cx<T> (&v)[8], int t, int q, cx<T>* xb, const cx<T>* W, bool lo4,
+                                         bool first4) {
+  auto tw = [&](int e) {
+    cx<T> w = W[e & 511];
+    if (INV) w.y = -w.y;
+    return w;
+  };
+  if (lo4) dft8_lo4(v, INV);
+  else dft8(v, INV);
   {
     const int t0 = t & 7, t1 = t >> 3;
 #pragma unroll
-    for (int k2 = 1; k2 < 8; ++k2) v[k2] = cmul(v[k2], W[(t * k2) & 511]);
+    for (int k2 = 1; k2 < 8; ++k2) v[k2] = cmul(v[k2], tw(t * k2));
 #pragma unroll
     for (int k2 = 0; k2 < 8; ++k2) xb[(k2 * 8 + t0) * S + t1 * P + q] = v[k2];
   }
@@ -1623,9 +1631,9 @@ __device__ __forceinline__ void f512_fwd(cx<T> (&v)[8], int t, int q, cx<T>* xb,
     const int k2 = t >> 3, u0 = t & 7;
 #pragma unroll
     for (int u1 = 0; u1 < 8; ++u1) v[u1] = xb[(k2 * 8 + u0) * S + u1 * P + q];
-    dft8(v, false);
+    dft8(v, INV);
 #pragma unroll
-    for (int ka = 1; ka < 8; ++ka) v[ka] = cmul(v[ka], W[(8 * u0 * ka) & 511]);
+    for (int ka = 1; ka < 8; ++ka) v[ka] = cmul(v[ka], tw(8 * u0 * ka));
     __syncthreads();
 #pragma unroll
     for (int ka = 0; ka < 8; ++ka) xb[(k2 * 8 + ka) * S + u0 * P + q] = v[ka];
@@ -1637,7 +1645,12 @@ __device__ __forceinline__ void f512_fwd(cx<T> (&v)[8], int t, int q, cx<T>* xb,
     for (int u0 = 0; u0 < 8; ++u0) v[u0] = xb[(k2 * 8 + ka) * S + u0 * P + q];
   }
   __syncthreads();
-  dft8(v, false);
+  if (first4) dft8_first4(v, INV);
+  else dft8(v, INV);
+}
+template <typename T, int P, int S>
+__device__ __forceinline__ void f512_fwd(cx<T> (&v)[8], int t, int q, cx<T>* xb, const cx<T>* W, bool lo4) {
+  f512_dif<T, P, S, false>(v, t, q, xb, W, lo4, false);
 }
 
 // inverse (unnormalised): v[kb] = X[(t >> 3) + 8 (t & 7) + 64 kb] in, v[m] = x[t + 64 m]
@@ -1706,18 +1719,17 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
   const cx<T>* xin = A.xin[ch];
   T* dout = A.dct_out[ch];
   cx<T>* xo = A.xout[ch];
-  // this thread's spectral slots k = kl + 64 kb of the 512-point transforms
-  const int kl = (t >> 3) + 8 * (t & 7);
   cx<T> Xa[8], Xb[8];
   if (xin) {
-    // x-level half spectra (k <= 256) of both rows
+    // x-level half spectra (k <= 256) of both rows at k = t + 64 m (consecutive
+    // lanes read consecutive k; above 256 the mirrored 512 - k)
     const unsigned pa = ra1c * (unsigned)A.xin_pitch * CB, pb = rb1c * (unsigned)A.xin_pitch * CB;
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
-      const int k = kl + 64 * kb;
+    for (int m = 0; m < 8; ++m) {
+      const int k = t + 64 * m;
       const unsigned kk = (unsigned)(k <= 256 ? k : 512 - k);
-      Xa[kb] = ld_off(xin, pa + kk * CB);
-      Xb[kb] = ld_off(xin, pb + kk * CB);
+      Xa[m] = ld_off(xin, pa + kk * CB);
+      Xb[m] = ld_off(xin, pb + kk * CB);
     }
   }
   cx<T> pu[4], pw[4], wk[4];
@@ -1734,10 +1746,10 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
   if (xin) {
     // cropped c2r: Hermitian completion above k = 256, both rows packed as a + i b
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
-      const int k = kl + 64 * kb;
+    for (int m = 0; m < 8; ++m) {
+      const int k = t + 64 * m;
       const int kk = k <= 256 ? k : 512 - k;
-      cx<T> xa = Xa[kb], xbb = Xb[kb];
+      cx<T> xa = Xa[m], xbb = Xb[m];
       if (kk == 0 || kk == 256) {
         xa.y = (T)0;
         xbb.y = (T)0;
@@ -1746,9 +1758,19 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
         xa.y = -xa.y;
         xbb.y = -xbb.y;
       }
-      v[kb] = mk<T>(xa.x - xbb.y, xa.y + xbb.x);
+      v[m] = mk<T>(xa.x - xbb.y, xa.y + xbb.x);
     }
-    f512_inv<T, P, S>(v, t, q, xb, W, true);
+    // x in digit order, only x < 256 (kb < 4); back to x = t + 64 m through LDS
+    f512_dif<T, P, S, true>(v, t, q, xb, W, false, true);
+    {
+      const int kl = (t >> 3) + 8 * (t & 7);
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) xb[kl * S + kb * P + q] = v[kb];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = f512_at<T, P, S>(xb, t + 64 * m, q);
+    __syncthreads();  // xb is reused by the forward transform
   } else {
 #pragma unroll
     for (int m = 0; m < 4; ++m) v[m] = zero<T>();
