@@ -61,7 +61,7 @@ def test_heat_solve(env, n, prec):
 
 STRAY_SHAPES = [(8, 4, 2), (16, 8, 1), (4, 4, 4), (32, 1, 1), (1, 1, 1), (2, 2, 2), (1, 8, 4), (4, 1, 4),
                 (128, 64, 1), (64, 32, 8), (512, 32, 4), (128, 128, 1), (16, 8, 32), (16, 32, 1), (4, 1, 32),
-                (256, 4, 32), (16, 256, 2), (8, 256, 4)]
+                (256, 4, 32), (16, 256, 2), (8, 256, 4), (32, 256, 32), (8, 2, 32)]
 
 
 @pytest.mark.parametrize("n", STRAY_SHAPES, ids=lambda n: "x".join(map(str, n)))
@@ -73,8 +73,13 @@ def test_stray_field(env, n, prec):
     plan = gpu_plan_si(sg, n, CELL, DT, ALL, prec)
     hs = plan.stray(to_dev(torch, m, prec)).cpu().numpy()
     ref = demag.stray_field(rounded_like(m, prec), demag.kernel_spectra(shape, CELL))
-    tol = 1e-10 if prec == 1 else 2e-6
-    assert np.abs(hs - ref).max() <= tol
+    # FP64: the two Newell tensors agree to ~1e-12 per entry (cancellation in the
+    # 27-point sum up to the dipole cut-off); summed over N source cells with random
+    # signs that grows like sqrt(N), so the bar widens past 32768 cells
+    tol = 1e-10 * max(1.0, np.sqrt(m[0].size / 32768)) if prec == 1 else 2e-6
+    err = np.abs(hs - ref).max()
+    print(f"stray {'fp64' if prec else 'fp32'} {n}: max abs err {err:.3e} (bar {tol:.1e})")
+    assert err <= tol
 
 
 @pytest.mark.parametrize("n", [(16, 8, 4), (32, 32, 1), (64, 1, 1), (8, 8, 8)], ids=lambda n: "x".join(map(str, n)))
