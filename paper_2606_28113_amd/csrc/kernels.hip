@@ -968,6 +968,8 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
 // mirrors the forward and leaves thread b with z = 8 a + b.  A workgroup covers
 // P consecutive kx and the batch rows b and Pb - b that share a tensor row.
 constexpr int C64_NT = 256;
+// tensor tile entries per thread and component: 33 rows x P kx over 16 P threads
+constexpr int C64_TILE_PT = (33 + 15) / 16;
 
 template <typename T>
 __device__ __forceinline__ void tw64_apply(cx<T>* v, const cx<T>* w64, int t, bool inv) {
@@ -993,7 +995,8 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const
   const int P = 1 << A.lgP;
   const int NP = 2 * P;  // pencils per workgroup (two batch rows)
   cx<T>* w64 = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* xb = w64 + 64;  // [8][8][NP]: one transpose at a time
+  cx<T>* xb = w64 + 64;                          // [8][8][NP]: one transpose at a time
+  T* tt = reinterpret_cast<T*>(xb + 64 * NP);    // tensor tile [nt][33 folded kz][P kx]
   const int tid = threadIdx.x;
   const int q = tid & (P - 1);
   const int t = (tid >> A.lgP) & 7;
@@ -1021,9 +1024,38 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const
 #pragma unroll
     for (int m = 0; m < 4; ++m) v[c][m] = S ? ld_off(S, soff + (unsigned)(t + 8 * m) * sa) : zero<T>();
   }
-  // the W table after the pencils: one round trip to memory
-  for (int i = tid; i < 64; i += C64_NT) w64[i] = A.tw[i << (A.lgTw - 6)];
-  __syncthreads();  // w64 is in LDS
+  // the tensor tile of this workgroup (the used components, the 33 folded kz rows
+  // of batch row bf, its P kx) and the W table into LDS, loaded with the pencils:
+  // one round trip to memory, and no tensor load in the output loop
+  {
+    const int nth = 16 * P, ncp = 33 * P;  // entries per component: 33 rows x P kx
+    // 32-bit byte offsets from the uniform tensor base
+    const unsigned rowb = (unsigned)(bf * A.tkx) * (unsigned)sizeof(T), kzb = (unsigned)(A.Hb * A.tkx) * (unsigned)sizeof(T);
+    T tv[6][C64_TILE_PT];
+#pragma unroll
+    for (int cp = 0; cp < 6; ++cp) {
+      if (cp >= A.nt) break;
+      const unsigned cb = (unsigned)A.clist[cp] * (unsigned)A.tcs * (unsigned)sizeof(T) + rowb;
+#pragma unroll
+      for (int j = 0; j < C64_TILE_PT; ++j) {
+        const int i = min(tid + j * nth, ncp - 1);
+        const unsigned off = cb + (unsigned)(i >> A.lgP) * kzb + (unsigned)min(kx0 + (i & (P - 1)), A.ni - 1) * (unsigned)sizeof(T);
+        tv[cp][j] = ld_off(A.tens, off);
+      }
+    }
+    const cx<T> wv = A.tw[min(tid, 63) << (A.lgTw - 6)];
+    // every load above is issued before the first LDS store waits for one
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int cp = 0; cp < 6; ++cp) {
+      if (cp >= A.nt) break;
+#pragma unroll
+      for (int j = 0; j < C64_TILE_PT; ++j)
+        if (tid + j * nth < ncp) tt[cp * ncp + tid + j * nth] = tv[cp][j];
+    }
+    if (tid < 64) w64[tid] = wv;
+  }
+  __syncthreads();  // w64 and the tile are in LDS
   // this thread's twiddles W_64^{t k}, k < 8 (conjugated for the inverse)
   cx<T> twr[8];
 #pragma unroll
@@ -1042,19 +1074,11 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const
     dft8(v[c], false);  // v[c][k1] = X[t + 8 k1]
   }
 
-  // folded tensor rows: offset and z sign per k1, shared by every component
-  // and output (kz = t + 8 k1 > 32 reads row 64 - kz of a z-odd component negated)
-  unsigned toff[8];
-  T zs[8];
-  const unsigned tstr = (unsigned)(A.Hb * A.tkx) * (unsigned)sizeof(T);
-  const unsigned tb = (unsigned)(bf * A.tkx + kxc) * (unsigned)sizeof(T);
-#pragma unroll
-  for (int k1 = 0; k1 < 8; ++k1) {
-    const int kz = t + 8 * k1;
-    const bool cneg = kz > 32;
-    toff[k1] = tb + (unsigned)(cneg ? 64 - kz : kz) * tstr;
-    zs[k1] = cneg ? (T)-1 : (T)1;
-  }
+  // folded tensor rows, shared by every component and output: kz = t + 8 k1 reads
+  // row kz up to 32, above that row 64 - kz of a z-odd component negated (with
+  // t < 8 that is k1 > 4, and k1 = 4 for t > 0)
+  auto kzf = [&](int k1) { return k1 < 4 ? t + 8 * k1 : (k1 > 4 ? 64 - t - 8 * k1 : (t ? 32 - t : 32)); };
+  auto zsg = [&](int k1) -> T { return k1 < 4 ? (T)1 : (k1 > 4 ? (T)-1 : (t ? (T)-1 : (T)1)); };
   const bool bneg = r == 1;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -1065,13 +1089,13 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const
 #pragma unroll
     for (int bb = 0; bb < 3; ++bb) {
       const int c = comp_index(a, bb);
-      const T* tc = A.tens + (long)c * A.tcs;
+      const T* tc = tt + A.cpos[c] * 33 * P + q;
       const bool zodd = (A.oddc >> c) & 1;
       const T ys = (bneg && ((A.oddb >> c) & 1)) ? (T)-1 : (T)1;
 #pragma unroll
       for (int k1 = 0; k1 < 8; ++k1) {
-        T w = ld_off(tc, toff[k1]) * ys;
-        if (zodd) w *= zs[k1];
+        T w = tc[kzf(k1) * P] * ys;
+        if (zodd) w *= zsg(k1);
         o[k1] = mk<T>(o[k1].x + w * v[bb][k1].x, o[k1].y + w * v[bb][k1].y);
       }
     }
@@ -2132,7 +2156,8 @@ template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t 
     b.lgP = sizeof(T) == 4 ? 4 : 3;
     const int P = 1 << b.lgP;
     dim3 grid(ceil_div(a.ni, P), nbatch, 1);
-    const size_t lds = (64 + (size_t)64 * 2 * P) * sizeof(cx<T>);
+    // W_64, the transpose buffer, the tensor tile
+    const size_t lds = (64 + (size_t)64 * 2 * P) * sizeof(cx<T>) + (size_t)a.nt * 33 * P * sizeof(T);
     hipLaunchKernelGGL(k_conv64<T>, grid, dim3(16 * P), lds, s, b);
     return SGSPM_KC_CONV64;
   }
