@@ -1316,15 +1316,30 @@ template <typename T> struct PwPack {
   int n;
 };
 
-template <typename T> __global__ void k_pw(const PwPack<T> A, long N) {
-  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < N; idx += (long)gridDim.x * blockDim.x) {
-    for (int k = 0; k < A.n; ++k) {
-      const PwTerm<T>& t = A.t[k];
-      double v = t.acc ? (double)t.out[idx] : 0.0;
-      if (t.x0) v += t.c0 * (double)t.x0[idx] * (t.y0 ? (double)t.y0[idx] : 1.0);
-      if (t.x1) v += t.c1 * (double)t.x1[idx] * (t.y1 ? (double)t.y1[idx] : 1.0);
-      t.out[idx] = (T)v;
-    }
+// One element per thread.  No term reads an array that an earlier term of the pack
+// writes (the launcher splits packs that would), so the kernel issues every load of
+// the pack, then computes, then stores: one round trip to memory.
+template <typename T> __global__ __launch_bounds__(NT) void k_pw(const PwPack<T> A, int N) {
+  const int idx = blockIdx.x * NT + threadIdx.x;
+  if (idx >= N) return;
+  T ro[PW_MAX], ra0[PW_MAX], rb0[PW_MAX], ra1[PW_MAX], rb1[PW_MAX];
+#pragma unroll
+  for (int k = 0; k < PW_MAX; ++k) {
+    if (k >= A.n) break;
+    const PwTerm<T>& t = A.t[k];
+    ro[k] = t.acc ? t.out[idx] : (T)0;
+    ra0[k] = t.x0 ? t.x0[idx] : (T)0;
+    rb0[k] = t.y0 ? t.y0[idx] : (T)1;
+    ra1[k] = t.x1 ? t.x1[idx] : (T)0;
+    rb1[k] = t.y1 ? t.y1[idx] : (T)1;
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < PW_MAX; ++k) {
+    if (k >= A.n) break;
+    const PwTerm<T>& t = A.t[k];
+    const double v = (double)ro[k] + t.c0 * (double)ra0[k] * (double)rb0[k] + t.c1 * (double)ra1[k] * (double)rb1[k];
+    t.out[idx] = (T)v;
   }
 }
 
@@ -1397,17 +1412,16 @@ __global__ __launch_bounds__(NT) void k_adj_damp(const T* lw, const T* u, const 
                                                   const T* uF2, const T* hsF, int nx, int ny, int nz, double ecx,
                                                   double ecy, double ecz, double Q, double he0, double he1, double he2,
                                                   double* partials) {
-  const long N = (long)nx * ny * nz;
+  // power-of-two extents, N <= 2^28: 32-bit indices, coordinates by shifts
+  const int N = nx * ny * nz, lx = __builtin_ctz(nx), lxy = lx + __builtin_ctz(ny), nxy = nx * ny;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const T* uF[3] = {uF0, uF1, uF2};
   const double he[3] = {he0, he1, he2};
-  for (long idx = blockIdx.x * (long)NT + threadIdx.x; idx < N; idx += (long)gridDim.x * NT) {
-    const int x = (int)(idx % nx);
-    const int y = (int)((idx / nx) % ny);
-    const int z = (int)(idx / ((long)nx * ny));
-    const long xm = x > 0 ? idx - 1 : idx, xp = x < nx - 1 ? idx + 1 : idx;
-    const long ym = y > 0 ? idx - nx : idx, yp = y < ny - 1 ? idx + nx : idx;
-    const long zm = z > 0 ? idx - (long)nx * ny : idx, zp = z < nz - 1 ? idx + (long)nx * ny : idx;
+  for (int idx = blockIdx.x * NT + threadIdx.x; idx < N; idx += gridDim.x * NT) {
+    const int x = idx & (nx - 1), y = (idx >> lx) & (ny - 1), z = idx >> lxy;
+    const int xm = x > 0 ? idx - 1 : idx, xp = x < nx - 1 ? idx + 1 : idx;
+    const int ym = y > 0 ? idx - nx : idx, yp = y < ny - 1 ? idx + nx : idx;
+    const int zm = z > 0 ? idx - nxy : idx, zp = z < nz - 1 ? idx + nxy : idx;
     double t = 0.0;
     for (int c = 0; c < 3; ++c) {
       const T* uc = u + c * N;
@@ -2199,11 +2213,25 @@ void launch_energy(const T* m, const T* hs, int nx, int ny, int nz, double cxx, 
 }
 
 template <typename T> void launch_pw(const PwTerm<T>* terms, int nterms, long N, hipStream_t s) {
-  PwPack<T> A{};
-  for (int k = 0; k < nterms; ++k) A.t[k] = terms[k];
-  A.n = nterms;
-  const int blocks = (int)std::min<long>((N + NT - 1) / NT, 8192);
-  hipLaunchKernelGGL(k_pw<T>, dim3(blocks), dim3(NT), 0, s, A, N);
+  // a term that reads what an earlier term of the pack writes starts a new pack
+  int k0 = 0;
+  while (k0 < nterms) {
+    int k1 = k0 + 1;
+    for (; k1 < nterms; ++k1) {
+      const PwTerm<T>& t = terms[k1];
+      bool dep = false;
+      for (int j = k0; j < k1; ++j) {
+        const T* w = terms[j].out;
+        dep = dep || w == t.x0 || w == t.y0 || w == t.x1 || w == t.y1 || w == t.out;
+      }
+      if (dep) break;
+    }
+    PwPack<T> A{};
+    for (int k = k0; k < k1; ++k) A.t[k - k0] = terms[k];
+    A.n = k1 - k0;
+    hipLaunchKernelGGL(k_pw<T>, dim3(ceil_div(N, NT)), dim3(NT), 0, s, A, (int)N);
+    k0 = k1;
+  }
 }
 
 template <typename T> void launch_adj_project(const T* lam, const T* u, const T* nrm, T* lc, long N, hipStream_t s) {
