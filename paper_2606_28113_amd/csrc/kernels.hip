@@ -90,48 +90,85 @@ __device__ __forceinline__ void row_r2c_store(cx<T>* buf, const cx<T>* tw, const
   __syncthreads();
 }
 
+// the FFT twiddles W_Lmax^i and the DCT twiddles of length n <= Lmax into LDS, both
+// loads of an index issued before either store; the DCT table is optional (a plain
+// r2c launch, such as the tensor build's, passes none)
+template <typename T>
+__device__ __forceinline__ void load_row_tables(cx<T>* tw, cx<T>* dtl, const RowFwd<T>* fa, const RowInv<T>* ia,
+                                                int lgLmax, int n) {
+  const cx<T>* gtw = fa ? fa->tw : ia->tw;
+  const cx<T>* gdt = fa ? fa->dtw : ia->dtw;
+  const int sh = (fa ? fa->lgTw : ia->lgTw) - lgLmax;
+  for (int i = threadIdx.x; i < (1 << lgLmax); i += NT) {
+    const cx<T> a = gtw[i << sh];
+    const cx<T> d = gdt ? gdt[min(i, n - 1)] : zero<T>();
+    tw[i] = a;
+    if (i < n) dtl[i] = d;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Row forward kernel: [c2r of x-level hs] -> v = a u + b (hs + he) ->
 // [DCT-II along x] and/or [zero-padded r2c along x].
 template <typename T>
 __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int NV = 2 * Tile<T>::VPT;
+  constexpr int NV = 2 * Tile<T>::VPT, VPT = Tile<T>::VPT;
   const int ch = blockIdx.z;
   const int Lmax = 1 << A.lgLmax;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + Lmax;
-  load_twiddles(tw, A.tw, A.lgLmax, A.lgTw);
   const int P = 1 << A.lgP;
   const int row0 = blockIdx.x * 2 * P;
   const int n = 1 << A.lgN;
   const int tot = (2 * P) << A.lgN;
+  // the DCT twiddles in LDS after the tile (no global load among the stores)
+  cx<T>* dtl = buf + P * (Lmax + 1);
   T hs[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) hs[i] = (T)0;
-  __syncthreads();
 
   const cx<T>* xin = A.xin[ch];
+  const int Lc = 1 << A.lgLc;
+  const int half = Lc >> 1;
+  // the spectra first (at most VPT per thread: P Lc fits the tile), then the tables,
+  // then the LDS stores: one round trip to memory
+  cx<T> Ra[VPT], Rb[VPT];
   if (xin) {
-    const int Lc = 1 << A.lgLc;
-    const int half = Lc >> 1;
-    for (int t = threadIdx.x; t < (P << A.lgLc); t += NT) {
-      const int q = t >> A.lgLc, k = t & (Lc - 1);
-      const int ra = row0 + 2 * q;
-      const bool cj = k > half;
-      const int kk = cj ? Lc - k : k;
-      cx<T> Xa = zero<T>(), Xb = zero<T>();
-      if (ra < A.nrows) Xa = xin[(long)ra * A.xin_pitch + kk];
-      if (ra + 1 < A.nrows) Xb = xin[(long)(ra + 1) * A.xin_pitch + kk];
-      if (kk == 0 || kk == half) {
-        Xa.y = (T)0;
-        Xb.y = (T)0;
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int t = threadIdx.x + j * NT;
+      Ra[j] = Rb[j] = zero<T>();
+      if (t < (P << A.lgLc)) {
+        const int q = t >> A.lgLc, k = t & (Lc - 1);
+        const int ra = row0 + 2 * q;
+        const int kk = k > half ? Lc - k : k;
+        if (ra < A.nrows) Ra[j] = xin[(long)ra * A.xin_pitch + kk];
+        if (ra + 1 < A.nrows) Rb[j] = xin[(long)(ra + 1) * A.xin_pitch + kk];
       }
-      if (cj) {
-        Xa.y = -Xa.y;
-        Xb.y = -Xb.y;
+    }
+  }
+  load_row_tables<T>(tw, dtl, &A, nullptr, A.lgLmax, n);
+  __syncthreads();
+  if (xin) {
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+      const int t = threadIdx.x + j * NT;
+      if (t < (P << A.lgLc)) {
+        const int q = t >> A.lgLc, k = t & (Lc - 1);
+        const bool cj = k > half;
+        const int kk = cj ? Lc - k : k;
+        cx<T> Xa = Ra[j], Xb = Rb[j];
+        if (kk == 0 || kk == half) {
+          Xa.y = (T)0;
+          Xb.y = (T)0;
+        }
+        if (cj) {
+          Xa.y = -Xa.y;
+          Xb.y = -Xb.y;
+        }
+        buf[q * (Lc + 1) + k] = mk<T>(Xa.x - Xb.y, Xa.y + Xb.x);
       }
-      buf[q * (Lc + 1) + k] = mk<T>(Xa.x - Xb.y, Xa.y + Xb.x);
     }
     __syncthreads();
     FftGeom g{A.lgLc, A.lgP, 1, false, Lc + 1, 1, A.lgLmax - A.lgLc};
@@ -154,19 +191,37 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
   T* hso = A.hs_out[ch];
   T* vo = A.val_out[ch];
   const T ac = A.a[ch], hec = A.he[ch], bc = A.b, wcc = A.wc[ch];
+  // loads of every element first (clamped indices, no branch between them), stores
+  // after (loads and stores share one in-order counter)
+  auto cidx = [&](int i) {
+    const int e = min((int)threadIdx.x + i * NT, tot - 1);
+    return ((long)min(row0 + (e >> A.lgN), A.nrows - 1) << A.lgN) + (e & (n - 1));
+  };
+#pragma unroll
+  for (int i = 0; i < NV; ++i) val[i] = bc * (hs[i] + hec);
+  if (u) {
+    T pu[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) pu[i] = u[cidx(i)];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) val[i] += ac * pu[i];
+  }
+  if (w) {
+    T pw[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) pw[i] = w[cidx(i)];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) val[i] += wcc * pw[i];
+  }
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const int e = threadIdx.x + i * NT;
-    val[i] = (T)0;
     if (e < tot) {
       const int row = e >> A.lgN, x = e & (n - 1);
       const int grow = row0 + row;
       if (grow < A.nrows) {
         const long idx = ((long)grow << A.lgN) + x;
-        const T uu = u ? u[idx] : (T)0;
         if (hso) hso[idx] = hs[i];
-        val[i] = ac * uu + bc * (hs[i] + hec);
-        if (w) val[i] += wcc * w[idx];
         if (vo) vo[idx] = val[i];
       }
     }
@@ -195,7 +250,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
       const cx<T> Zm = buf[q * ps + ((n - k) & (n - 1))];
       const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
       const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-      const cx<T> w = A.dtw[k];
+      const cx<T> w = dtl[k];
       const int ra = row0 + 2 * q;
       const T xa = w.x * Va.x - w.y * Va.y, xb = w.x * Vb.x - w.y * Vb.y;
       if (A.dct_xmajor) {
@@ -220,15 +275,16 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
 template <typename T>
 __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int NV = 2 * Tile<T>::VPT;
+  constexpr int NV = 2 * Tile<T>::VPT, VPT = Tile<T>::VPT;
   const int Lmax = 1 << A.lgLmax;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + Lmax;
-  load_twiddles(tw, A.tw, A.lgLmax, A.lgTw);
   const int P = 1 << A.lgP;
   const int row0 = blockIdx.x * 2 * P;
   const int n = 1 << A.lgN;
   const int tot = (2 * P) << A.lgN;
+  cx<T>* dtl = buf + P * (Lmax + 1);  // DCT twiddles
+  load_row_tables<T>(tw, dtl, nullptr, &A, A.lgLmax, n);
   const T invn = (T)1 / (T)n;
   T g[3][NV];
 #pragma unroll
@@ -242,35 +298,54 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
       __syncthreads();
       const T* H = A.heat[c];
       const int ps = n + 1;
-      for (int t = threadIdx.x; t < (P << A.lgN); t += NT) {
-        const int q = A.heat_xmajor ? (t & (P - 1)) : (t >> A.lgN);
-        const int k = A.heat_xmajor ? (t >> A.lgP) : (t & (n - 1));
-        const int ra = row0 + 2 * q;
-        T xak = 0, xam = 0, xbk = 0, xbm = 0;
-        if (A.heat_xmajor) {
-          const long nr = A.nrows;
-          if (ra < A.nrows) {
-            xak = H[(long)k * nr + ra];
-            if (k) xam = H[(long)(n - k) * nr + ra];
-          }
-          if (ra + 1 < A.nrows) {
-            xbk = H[(long)k * nr + ra + 1];
-            if (k) xbm = H[(long)(n - k) * nr + ra + 1];
-          }
-        } else {
-          if (ra < A.nrows) {
-            xak = H[((long)ra << A.lgN) + k];
-            if (k) xam = H[((long)ra << A.lgN) + n - k];
-          }
-          if (ra + 1 < A.nrows) {
-            xbk = H[((long)(ra + 1) << A.lgN) + k];
-            if (k) xbm = H[((long)(ra + 1) << A.lgN) + n - k];
+      // loads in groups of four rows of the loop (at most VPT per thread), each
+      // group issued before its LDS stores
+      constexpr int CH = 4;
+#pragma unroll
+      for (int j0 = 0; j0 < VPT; j0 += CH) {
+        T rak[CH], ram[CH], rbk[CH], rbm[CH];
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) {
+          const int t = threadIdx.x + (j0 + jj) * NT;
+          rak[jj] = ram[jj] = rbk[jj] = rbm[jj] = (T)0;
+          if (t < (P << A.lgN)) {
+            const int q = A.heat_xmajor ? (t & (P - 1)) : (t >> A.lgN);
+            const int k = A.heat_xmajor ? (t >> A.lgP) : (t & (n - 1));
+            const int ra = row0 + 2 * q;
+            if (A.heat_xmajor) {
+              const long nr = A.nrows;
+              if (ra < A.nrows) {
+                rak[jj] = H[(long)k * nr + ra];
+                if (k) ram[jj] = H[(long)(n - k) * nr + ra];
+              }
+              if (ra + 1 < A.nrows) {
+                rbk[jj] = H[(long)k * nr + ra + 1];
+                if (k) rbm[jj] = H[(long)(n - k) * nr + ra + 1];
+              }
+            } else {
+              if (ra < A.nrows) {
+                rak[jj] = H[((long)ra << A.lgN) + k];
+                if (k) ram[jj] = H[((long)ra << A.lgN) + n - k];
+              }
+              if (ra + 1 < A.nrows) {
+                rbk[jj] = H[((long)(ra + 1) << A.lgN) + k];
+                if (k) rbm[jj] = H[((long)(ra + 1) << A.lgN) + n - k];
+              }
+            }
           }
         }
-        const cx<T> w = conjg(A.dtw[k]);
-        const cx<T> Va = cmul(w, mk<T>(xak, -xam));
-        const cx<T> Vb = cmul(w, mk<T>(xbk, -xbm));
-        buf[q * ps + k] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) {
+          const int t = threadIdx.x + (j0 + jj) * NT;
+          if (t < (P << A.lgN)) {
+            const int q = A.heat_xmajor ? (t & (P - 1)) : (t >> A.lgN);
+            const int k = A.heat_xmajor ? (t >> A.lgP) : (t & (n - 1));
+            const cx<T> w = conjg(dtl[k]);
+            const cx<T> Va = cmul(w, mk<T>(rak[jj], -ram[jj]));
+            const cx<T> Vb = cmul(w, mk<T>(rbk[jj], -rbm[jj]));
+            buf[q * ps + k] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
+          }
+        }
       }
       __syncthreads();
       FftGeom gm{A.lgN, A.lgP, 1, false, ps, 1, A.lgLmax - A.lgN};
@@ -291,6 +366,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
   __syncthreads();
 
   if (A.op == ROW_OP_GS) {
+    // loads of every element first, stores after
     T val[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -304,9 +380,16 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
           const T rv = A.Rch == 0 ? g[0][i] : (A.Rch == 1 ? g[1][i] : A.Rf[idx]);
           T o = A.base[idx] + pv * A.Qf[idx] - rv * A.Sf[idx];
           if (A.src) o += A.ds * A.src[idx];
-          A.out[idx] = o;
           val[i] = o;
         }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e = threadIdx.x + i * NT;
+      if (e < tot) {
+        const int row = e >> A.lgN, x = e & (n - 1);
+        if (row0 + row < A.nrows) A.out[((long)(row0 + row) << A.lgN) + x] = val[i];
       }
     }
     if (A.xout)
@@ -2055,7 +2138,8 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
   }
   const int rows = 2 << a.lgP;
   dim3 grid(ceil_div(a.nrows, rows), 1, nch);
-  const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1)) * sizeof(cx<T>);
+  // twiddles, the tile, the DCT twiddles
+  const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1) + ((size_t)1 << a.lgN)) * sizeof(cx<T>);
   hipLaunchKernelGGL(k_row_fwd<T>, grid, dim3(NT), lds, s, a);
   return SGSPM_KC_ROW_FWD;
 }
@@ -2098,7 +2182,8 @@ template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
   }
   const int rows = 2 << a.lgP;
   dim3 grid(ceil_div(a.nrows, rows), 1, 1);
-  const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1)) * sizeof(cx<T>);
+  // twiddles, the tile, the DCT twiddles
+  const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1) + ((size_t)1 << a.lgN)) * sizeof(cx<T>);
   hipLaunchKernelGGL(k_row_inv<T>, grid, dim3(NT), lds, s, a);
   return SGSPM_KC_ROW_INV;
 }

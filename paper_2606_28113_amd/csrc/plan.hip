@@ -173,6 +173,14 @@ int cap_lgP(int lgP, long count_pencils) {
   return std::max(0, std::min(lgP, need));
 }
 
+// the same for the row kernels, whose grid is the row pairs alone: fewer pencils per
+// workgroup until the launch has about 256 workgroups (small grids are latency-bound;
+// a full tile per workgroup would leave most of the chip idle)
+int row_lgP(int lgP, long count_pencils) {
+  const int need = ilog2(std::max<long>(1, count_pencils));
+  return std::max(0, std::min(cap_lgP(lgP, count_pencils), need - 8));
+}
+
 // ---------------------------------------------------------------------------
 template <typename T> struct Eng {
   sgspm_plan_s& P;
@@ -263,7 +271,7 @@ template <typename T> struct Eng {
     }
     if (any_x) lgL = std::max(lgL, A.lgLr);
     A.lgLmax = lgL;
-    A.lgP = cap_lgP(lg_tile<T>() - lgL, (A.nrows + 1) / 2);
+    A.lgP = row_lgP(lg_tile<T>() - lgL, (A.nrows + 1) / 2);
     A.lgTw = P.lgTw;
     A.tw = tw;
     A.dtw = dtw[0];
@@ -299,7 +307,7 @@ template <typename T> struct Eng {
     A.lgN = ilog2(P.nx);
     A.lgLr = ilog2(P.Px);
     A.lgLmax = r2c ? std::max(A.lgN, A.lgLr) : A.lgN;
-    A.lgP = cap_lgP(lg_tile<T>() - A.lgLmax, (A.nrows + 1) / 2);
+    A.lgP = row_lgP(lg_tile<T>() - A.lgLmax, (A.nrows + 1) / 2);
     A.lgTw = P.lgTw;
     A.tw = tw;
     A.dtw = dtw[0];
@@ -482,6 +490,11 @@ template <typename T> struct Eng {
       }
     }
     A.lgP = conv_lgP<T>(A.lgL, P.Kx, A.nt);
+    {
+      // small grids: fewer kx per workgroup until the launch has ~256 workgroups
+      const long nbw = (z && P.has_mid) ? P.Hy : 1;
+      while (A.lgP > 0 && ((P.Kx + (1L << A.lgP) - 1) >> A.lgP) * nbw < 256) --A.lgP;
+    }
     A.tens = tens;
     A.tcs = (long)P.Hz * P.Hy * P.Kt;
     A.tkx = P.Kt;
