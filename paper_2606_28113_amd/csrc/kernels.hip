@@ -550,25 +550,52 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
   const int lgR = lgM + A.lgPP;
   const int R = 1 << lgR;
   const int lgL = max(A.lgNy, A.lgNz);
-  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* buf = tw + (1 << lgL);
-  T* bufr = reinterpret_cast<T*>(buf);
-  load_twiddles<T, NTH>(tw, A.tw, lgL, A.lgTw);
-  const int p0 = blockIdx.x << A.lgPP;
-  const int nplanes = min(1 << A.lgPP, A.nx - p0);
-  T* D = A.data[blockIdx.z] + ((long)p0 << lgM);
-  T v[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const int e = threadIdx.x + i * NTH;
-    v[i] = (e < R && (e >> lgM) < nplanes) ? D[e] : (T)0;
-  }
   // y pass: real pencils rho = (p, z), 2^lgPy of them, paired rho <-> rho + Hy
   const int lgPy = A.lgPP + A.lgNz;
   const int lgHy = max(0, lgPy - 1), Hy = 1 << lgHy, esy = Hy + 1;
   // z pass: real pencils rho' = (p, ky)
   const int lgPz = A.lgPP + A.lgNy;
   const int lgHz = max(0, lgPz - 1), Hz = 1 << lgHz, esz = Hz + 1;
+  const int PP = 1 << A.lgPP;
+  // LDS: twiddles, the transpose buffer, then the DCT twiddles and eigenvalues
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* buf = tw + (1 << lgL);
+  T* bufr = reinterpret_cast<T*>(buf);
+  cx<T>* Dy = buf + max(ny * esy, nz * esz);
+  cx<T>* Dz = Dy + ny;
+  T* Ly = reinterpret_cast<T*>(Dz + nz);
+  T* Lz = Ly + ny;
+  T* Lx = Lz + nz;
+  const int p0 = blockIdx.x << A.lgPP;
+  const int nplanes = min(PP, A.nx - p0);
+  T* D = A.data[blockIdx.z] + ((long)p0 << lgM);
+  // one round trip to memory: the planes, then the tables (each table loop loads
+  // before it stores)
+  T v[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const int e = threadIdx.x + i * NTH;
+    v[i] = (e < R && (e >> lgM) < nplanes) ? D[e] : (T)0;
+  }
+  {
+    const int L = 1 << lgL, sh = A.lgTw - lgL, nt = max(L, PP);
+    for (int i = threadIdx.x; i < nt; i += NTH) {
+      const cx<T> a = A.tw[min(i, L - 1) << sh];
+      const cx<T> dy = A.dtwy[min(i, ny - 1)], dz = A.dtwz[min(i, nz - 1)];
+      const T ly = A.lamY[min(i, ny - 1)], lz = A.lamZ[min(i, nz - 1)];
+      const T lx = A.lamX[min(p0 + min(i, PP - 1), A.nx - 1)];
+      if (i < L) tw[i] = a;
+      if (i < ny) {
+        Dy[i] = dy;
+        Ly[i] = ly;
+      }
+      if (i < nz) {
+        Dz[i] = dz;
+        Lz[i] = lz;
+      }
+      if (i < PP) Lx[i] = p0 + i < A.nx ? lx : (T)0;
+    }
+  }
   // current order of v[]: 0 plane order (e = tid + i NTH), 1 after the y pass, 2 after the z pass
   int order = 0;
   auto decode = [&](int i, int& p, int& z, int& y) -> bool {
@@ -624,7 +651,7 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
         const cx<T> Zm = buf[((ny - k) & (ny - 1)) * esy + q];
         const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
         const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-        const cx<T> w = A.dtwy[k];
+        const cx<T> w = Dy[k];
         v[2 * s2] = w.x * Va.x - w.y * Va.y;
         v[2 * s2 + 1] = w.x * Vb.x - w.y * Vb.y;
       }
@@ -659,13 +686,12 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
         const cx<T> Zm = buf[((nz - k) & (nz - 1)) * esz + q];
         const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
         const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-        const cx<T> w = A.dtwz[k];
+        const cx<T> w = Dz[k];
         const int ra = q, rb = q + Hz;
         const int pa = ra >> A.lgNy, pb = rb >> A.lgNy;
-        const T lx_a = (p0 + pa < A.nx) ? A.lamX[p0 + pa] : (T)0;
-        const T lx_b = (p0 + pb < A.nx) ? A.lamX[p0 + pb] : (T)0;
-        xa[s2] = (w.x * Va.x - w.y * Va.y) / ((T)1 + A.s * (lx_a + A.lamY[ra & (ny - 1)] + A.lamZ[k]));
-        xb[s2] = (w.x * Vb.x - w.y * Vb.y) / ((T)1 + A.s * (lx_b + A.lamY[rb & (ny - 1)] + A.lamZ[k]));
+        const T lx_a = Lx[pa], lx_b = Lx[pb];
+        xa[s2] = (w.x * Va.x - w.y * Va.y) / ((T)1 + A.s * (lx_a + Ly[ra & (ny - 1)] + Lz[k]));
+        xb[s2] = (w.x * Vb.x - w.y * Vb.y) / ((T)1 + A.s * (lx_b + Ly[rb & (ny - 1)] + Lz[k]));
       }
     }
     __syncthreads();
@@ -684,7 +710,7 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
         const int k = t >> lgHz, q = t & (Hz - 1);
         const cx<T> Xk = buf[k * esz + q];
         const cx<T> Xm = k ? buf[(nz - k) * esz + q] : zero<T>();
-        const cx<T> w = conjg(A.dtwz[k]);
+        const cx<T> w = conjg(Dz[k]);
         const cx<T> Va = cmul(w, mk<T>(Xk.x, -Xm.x));
         const cx<T> Vb = cmul(w, mk<T>(Xk.y, -Xm.y));
         zz[s2] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
@@ -717,8 +743,7 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
     for (int i = 0; i < NV; ++i) {
       int p, z, y;
       if (decode(i, p, z, y)) {
-        const T lx = (p0 + p < A.nx) ? A.lamX[p0 + p] : (T)0;
-        v[i] /= (T)1 + A.s * (lx + A.lamY[y] + A.lamZ[0]);
+        v[i] /= (T)1 + A.s * (Lx[p] + Ly[y] + Lz[0]);
       }
     }
   }
@@ -745,7 +770,7 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
         const int k = t >> lgHy, q = t & (Hy - 1);
         const cx<T> Xk = buf[k * esy + q];
         const cx<T> Xm = k ? buf[(ny - k) * esy + q] : zero<T>();
-        const cx<T> w = conjg(A.dtwy[k]);
+        const cx<T> w = conjg(Dy[k]);
         const cx<T> Va = cmul(w, mk<T>(Xk.x, -Xm.x));
         const cx<T> Vb = cmul(w, mk<T>(Xk.y, -Xm.y));
         zz[s2] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
@@ -790,16 +815,27 @@ __global__ __launch_bounds__(NT) void k_col_fft(const ColFft<T> A) {
   const int L = 1 << A.lgL;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + L;
-  load_twiddles(tw, A.tw, A.lgL, A.lgTw);
   const int P = 1 << A.lgP;
   const int i0 = blockIdx.x * P;
   const int b = blockIdx.y;
   const cx<T>* in = A.in[blockIdx.z] + (long)b * A.sb_in;
   cx<T>* out = A.out[blockIdx.z] + (long)b * A.sb_out;
-  for (int t = threadIdx.x; t < (P << A.lgL); t += NT) {
+  // the tile's loads first (at most VPT per thread), then the twiddles, then the LDS
+  // stores: one round trip to memory
+  constexpr int VPT = Tile<T>::VPT;
+  cx<T> r[VPT];
+#pragma unroll
+  for (int u = 0; u < VPT; ++u) {
+    const int t = threadIdx.x + u * NT;
     const int j = t >> A.lgP, q = t & (P - 1);
     const int i = i0 + q;
-    buf[t] = (j < A.n_in && i < A.ni) ? in[(long)j * A.sa_in + i] : zero<T>();
+    r[u] = (t < (P << A.lgL) && j < A.n_in && i < A.ni) ? in[(long)j * A.sa_in + i] : zero<T>();
+  }
+  load_twiddles(tw, A.tw, A.lgL, A.lgTw);
+#pragma unroll
+  for (int u = 0; u < VPT; ++u) {
+    const int t = threadIdx.x + u * NT;
+    if (t < (P << A.lgL)) buf[t] = r[u];
   }
   __syncthreads();
   FftGeom g{A.lgL, A.lgP, 1, true, 1, P, 0};
@@ -963,13 +999,23 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
   load_twiddles<T, CONV_NT>(tw, A.tw, A.lgL, A.lgTw);
   const int i0 = blockIdx.x * P;
   const int bf = blockIdx.y;
-  // folded tensor tile
-  for (int t = threadIdx.x; t < A.nt * LH * P; t += CONV_NT) {
-    const int q = t % P;
-    const int kf = (t / P) % LH;
-    const int ci = t / (P * LH);
-    const int kx = i0 + q;
-    tt[t] = (kx < A.ni) ? A.tens[(long)A.clist[ci] * A.tcs + ((long)kf * A.Hb + bf) * A.tkx + kx] : (T)0;
+  // folded tensor tile: per chunk of the [LH][P] tile, every used component's entry
+  // loaded before any is stored (one round trip per chunk, component lists read as
+  // uniform values)
+  for (int t0 = 0; t0 < LH * P; t0 += CONV_NT) {
+    const int t = t0 + threadIdx.x;
+    const int tc = min(t, LH * P - 1);
+    const int q = tc % P, kf = tc / P;
+    const int kx = min(i0 + q, A.ni - 1);
+    T tv[6];
+#pragma unroll
+    for (int ci = 0; ci < 6; ++ci)
+      tv[ci] = ci < A.nt ? A.tens[(long)A.clist[ci] * A.tcs + ((long)kf * A.Hb + bf) * A.tkx + kx] : (T)0;
+    if (t < LH * P) {
+#pragma unroll
+      for (int ci = 0; ci < 6; ++ci)
+        if (ci < A.nt) tt[ci * LH * P + t] = (i0 + q < A.ni) ? tv[ci] : (T)0;
+    }
   }
   const bool mirror = A.Pb > 1 && bf != 0 && 2 * bf != A.Pb;
   const int ch = L >> 1;
@@ -978,15 +1024,29 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
     const bool bneg = pass == 1;
     const long boff = (long)b * A.sb;
     __syncthreads();
+    // the three components' loads first, then the LDS stores.  The kx tile keeps
+    // 3 (P << lgL) <= CONV_VPT CONV_NT with P << lgL a power of two, so P << lgL is at
+    // most 2 CONV_NT: two loads per component and thread
+    static_assert(3 * 4 * CONV_NT > CONV_VPT * CONV_NT, "at most two loads per component and thread");
+    cx<T> r[3][2];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const cx<T>* S = A.S[c];
-      for (int t = threadIdx.x; t < (P << A.lgL); t += CONV_NT) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int t = threadIdx.x + u * CONV_NT;
         const int j = t >> A.lgP, q = t & (P - 1);
         const int i = i0 + q;
-        buf[j * es + c * P + q] = (S && j < A.n && i < A.ni) ? S[boff + (long)j * A.sa + i] : zero<T>();
+        r[c][u] = (S && t < (P << A.lgL) && j < A.n && i < A.ni) ? S[boff + (long)j * A.sa + i] : zero<T>();
       }
     }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int t = threadIdx.x + u * CONV_NT;
+        if (t < (P << A.lgL)) buf[(t >> A.lgP) * es + c * P + (t & (P - 1))] = r[c][u];
+      }
     __syncthreads();
     {
       FftGeom g{A.lgL, A.lgP, 3, true, 1, es, 0};
@@ -2214,7 +2274,9 @@ template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStrea
   const int lgR = a.lgNy + a.lgNz + a.lgPP;
   const int Hy = 1 << std::max(0, a.lgPP + a.lgNz - 1), Hz = 1 << std::max(0, a.lgPP + a.lgNy - 1);
   const size_t nbuf = std::max((size_t)(1 << a.lgNy) * (Hy + 1), (size_t)(1 << a.lgNz) * (Hz + 1));
-  const size_t lds = ((size_t)(1 << lgL) + nbuf) * sizeof(cx<T>);
+  // twiddles, buffer, DCT twiddles of y and z, eigenvalues of y, z and the planes
+  const size_t ny = (size_t)1 << a.lgNy, nz = (size_t)1 << a.lgNz;
+  const size_t lds = ((size_t)(1 << lgL) + nbuf + ny + nz) * sizeof(cx<T>) + (ny + nz + ((size_t)1 << a.lgPP)) * sizeof(T);
   (void)lgR;
   if (yz_reg_plane(1 << a.lgNy, 1 << a.lgNz)) {
     constexpr int NY = 256, NZ = 32;
