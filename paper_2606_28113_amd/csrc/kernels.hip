@@ -1111,6 +1111,10 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
 // mirrors the forward and leaves thread b with z = 8 a + b.  A workgroup covers
 // P consecutive kx and the batch rows b and Pb - b that share a tensor row.
 constexpr int C64_NT = 256;
+// log2 of the kx per workgroup: 16 in single precision, 8 in double (16 KiB of
+// transpose buffer either way); a compile-time constant, so that every LDS
+// offset of the transposes and the tile is an immediate
+template <typename T> constexpr int c64_lgP() { return sizeof(T) == 4 ? 4 : 3; }
 // tensor tile entries per thread and component: 33 rows x P kx over 16 P threads
 constexpr int C64_TILE_PT = (33 + 15) / 16;
 
@@ -1133,17 +1137,17 @@ __device__ __forceinline__ int c64_idx(int c, int a, int b, int NP, int pen) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const Conv<T> A) {
+__global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 5 : 1) void k_conv64(const Conv<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int P = 1 << A.lgP;
-  const int NP = 2 * P;  // pencils per workgroup (two batch rows)
+  constexpr int LGP = c64_lgP<T>(), P = 1 << LGP;
+  constexpr int NP = 2 * P;  // pencils per workgroup (two batch rows)
   cx<T>* w64 = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* xb = w64 + 64;                          // [8][8][NP]: one transpose at a time
   T* tt = reinterpret_cast<T*>(xb + 64 * NP);    // tensor tile [nt][33 folded kz][P kx]
   const int tid = threadIdx.x;
   const int q = tid & (P - 1);
-  const int t = (tid >> A.lgP) & 7;
-  const int r = tid >> (A.lgP + 3);
+  const int t = (tid >> LGP) & 7;
+  const int r = tid >> (LGP + 3);
   const Blk bk = xcd_block();
   const int bf = bk.y;
   const int kx0 = bk.x * P;
@@ -1182,7 +1186,7 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const
 #pragma unroll
       for (int j = 0; j < C64_TILE_PT; ++j) {
         const int i = min(tid + j * nth, ncp - 1);
-        const unsigned off = cb + (unsigned)(i >> A.lgP) * kzb + (unsigned)min(kx0 + (i & (P - 1)), A.ni - 1) * (unsigned)sizeof(T);
+        const unsigned off = cb + (unsigned)(i >> LGP) * kzb + (unsigned)min(kx0 + (i & (P - 1)), A.ni - 1) * (unsigned)sizeof(T);
         tv[cp][j] = ld_off(A.tens, off);
       }
     }
@@ -1199,15 +1203,12 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const
     if (tid < 64) w64[tid] = wv;
   }
   __syncthreads();  // w64 and the tile are in LDS
-  // this thread's twiddles W_64^{t k}, k < 8 (conjugated for the inverse)
-  cx<T> twr[8];
-#pragma unroll
-  for (int k = 1; k < 8; ++k) twr[k] = w64[(t * k) & 63];
+  // this thread's twiddles W_64^{t k}, k < 8 (conjugated for the inverse), read
+  // from LDS at each use: held in registers they would cost a wave per SIMD
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     dft8_lo4(v[c], false);
-#pragma unroll
-    for (int k = 1; k < 8; ++k) v[c][k] = cmul(v[c][k], twr[k]);
+    tw64_apply(v[c], w64, t, false);
 #pragma unroll
     for (int k2 = 0; k2 < 8; ++k2) xb[c64_idx(0, k2, t, NP, pen)] = v[c][k2];
     __syncthreads();
@@ -1243,8 +1244,7 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 4 : 1) void k_conv64(const
       }
     }
     dft8(o, true);
-#pragma unroll
-    for (int k = 1; k < 8; ++k) o[k] = cmul(o[k], conjg(twr[k]));
+    tw64_apply(o, w64, t, true);
 #pragma unroll
     for (int bb = 0; bb < 8; ++bb) xb[c64_idx(0, bb, t, NP, pen)] = o[bb];
     __syncthreads();
@@ -2314,7 +2314,7 @@ template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t 
     // register four-step kernel: P kx x 2 batch rows x 8 threads per pencil
     // 16 kx per workgroup in single precision, 8 in double (LDS 16 / 16 KiB)
     Conv<T> b = a;
-    b.lgP = sizeof(T) == 4 ? 4 : 3;
+    b.lgP = c64_lgP<T>();
     const int P = 1 << b.lgP;
     dim3 grid(ceil_div(a.ni, P), nbatch, 1);
     // W_64, the transpose buffer, the tensor tile
