@@ -10,6 +10,12 @@
 //                    along some of its axes
 // A "channel" is one of up to three independent arrays handled by one launch
 // (grid.z); each argument block carries one pointer per channel.
+//
+// Blocked Nyquist layout (spectra whose Nyquist bin N = Kx - 1 is a multiple of
+// 16, with Kxp = N + 16, in planes whose row count is a multiple of 16): the
+// Nyquist bin of row r is not at (r, N) but at (r & ~15, N + (r & 15)), in the
+// row padding.  A pass along the rows then reads or writes the Nyquist bins of
+// 16 consecutive rows as one 128-byte line instead of 16 lines of 8 bytes.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -17,6 +23,11 @@
 #include "../../include/sgspm.h"
 
 namespace sgspm {
+
+// element offset of the Nyquist bin `nyq` of row `row` (rows of `pitch` complex)
+__host__ __device__ inline long nyq_off(long row, long pitch, int nyq, bool blocked) {
+  return blocked ? (row & ~15L) * pitch + nyq + (row & 15) : row * pitch + nyq;
+}
 
 // Row kernels (pencils along x; two real rows share one complex FFT).
 template <typename T> struct RowFwd {
@@ -45,6 +56,7 @@ template <typename T> struct RowFwd {
   cx<T>* xout[3];   // optional zero-padded real-to-complex transform of v
   int lgLr;
   int xout_pitch;
+  int nyqb;         // xin and xout hold their Nyquist bins in the blocked layout (nyq_off)
 };
 
 enum { ROW_OP_NONE = 0, ROW_OP_GS = 1, ROW_OP_PROJECT = 2 };
@@ -77,6 +89,7 @@ template <typename T> struct RowInv {
   cx<T>* xout;
   int lgLr;
   int xout_pitch;
+  int nyqb;            // xout holds its Nyquist bins in the blocked layout (nyq_off)
 };
 
 // Column kernels (pencils along a strided axis; tiles of consecutive inner indices).
@@ -107,6 +120,11 @@ template <typename T> struct ColFft {
   int inv;
   const cx<T>* tw;
   int lgTw;
+  // set by the caller when columns 0 and ni - 1 are the x-level DC and Nyquist
+  // columns of real rows (real before the forward transform, real again after
+  // the inverse one) and the Nyquist column of in and out is in the blocked
+  // layout (nyq_off): the 512-point kernel then carries both in one pencil
+  int pack;
 };
 
 // Heat solve across y and z of x-major planes [nx][nz][ny] (after the x DCT-II):
@@ -147,6 +165,7 @@ template <typename T> struct Conv {
   int oddc, oddb;    // bitmask of components odd along the pencil / batch axis
   const cx<T>* tw;
   int lgTw;
+  int nyqb;          // S and O hold the Nyquist column ni - 1 in the blocked layout over the batch rows
 };
 
 template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_t s);

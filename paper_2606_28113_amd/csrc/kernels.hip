@@ -52,7 +52,8 @@ __device__ __forceinline__ Blk xcd_block() {
 // (element e = tid + i NT of the tile) and store of bins 0..Lr/2.
 template <typename T, int NV>
 __device__ __forceinline__ void row_r2c_store(cx<T>* buf, const cx<T>* tw, const T (&val)[NV], int tot, int lgN, int lgLr,
-                                              int lgLmax, int lgP, int row0, int nrows, cx<T>* xout, int pitch) {
+                                              int lgLmax, int lgP, int row0, int nrows, cx<T>* xout, int pitch,
+                                              bool nyqb) {
   const int n = 1 << lgN;
   const int Lr = 1 << lgLr;
   const int P = 1 << lgP;
@@ -84,8 +85,9 @@ __device__ __forceinline__ void row_r2c_store(cx<T>* buf, const cx<T>* tw, const
     const cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
     const cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
     const int ra = row0 + 2 * q;
-    if (ra < nrows) xout[(long)ra * pitch + k] = Xa;
-    if (ra + 1 < nrows) xout[(long)(ra + 1) * pitch + k] = Xb;
+    const bool nq = k == half;
+    if (ra < nrows) xout[nq ? nyq_off(ra, pitch, half, nyqb) : (long)ra * pitch + k] = Xa;
+    if (ra + 1 < nrows) xout[nq ? nyq_off(ra + 1, pitch, half, nyqb) : (long)(ra + 1) * pitch + k] = Xb;
   }
   __syncthreads();
 }
@@ -143,8 +145,10 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
         const int q = t >> A.lgLc, k = t & (Lc - 1);
         const int ra = row0 + 2 * q;
         const int kk = k > half ? Lc - k : k;
-        if (ra < A.nrows) Ra[j] = xin[(long)ra * A.xin_pitch + kk];
-        if (ra + 1 < A.nrows) Rb[j] = xin[(long)(ra + 1) * A.xin_pitch + kk];
+        const bool nq = kk == half, nb = A.nyqb != 0;
+        if (ra < A.nrows) Ra[j] = xin[nq ? nyq_off(ra, A.xin_pitch, half, nb) : (long)ra * A.xin_pitch + kk];
+        if (ra + 1 < A.nrows)
+          Rb[j] = xin[nq ? nyq_off(ra + 1, A.xin_pitch, half, nb) : (long)(ra + 1) * A.xin_pitch + kk];
       }
     }
   }
@@ -265,7 +269,9 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
   }
 
   cx<T>* xo = A.xout[ch];
-  if (xo) row_r2c_store<T, NV>(buf, tw, val, tot, A.lgN, A.lgLr, A.lgLmax, A.lgP, row0, A.nrows, xo, A.xout_pitch);
+  if (xo)
+    row_r2c_store<T, NV>(buf, tw, val, tot, A.lgN, A.lgLr, A.lgLmax, A.lgP, row0, A.nrows, xo, A.xout_pitch,
+                         A.nyqb != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -393,7 +399,8 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
       }
     }
     if (A.xout)
-      row_r2c_store<T, NV>(buf, tw, val, tot, A.lgN, A.lgLr, A.lgLmax, A.lgP, row0, A.nrows, A.xout, A.xout_pitch);
+      row_r2c_store<T, NV>(buf, tw, val, tot, A.lgN, A.lgLr, A.lgLmax, A.lgP, row0, A.nrows, A.xout, A.xout_pitch,
+                           A.nyqb != 0);
   } else if (A.op == ROW_OP_PROJECT) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -871,6 +878,17 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
   const Blk bk = xcd_block();
   const int kx = bk.x * P + q;
   const bool act = kx < A.ni;
+  // A.pack: columns 0 and A.ni (the x-level DC and Nyquist columns, the latter
+  // in the blocked layout) share the pencil of tile 0, lane q = 0, as c0 + i cN.
+  // Both are real on input to the forward transform, whose result splits by
+  // Hermitian symmetry; the inverse takes C0 + i CN and returns c0 + i cN with
+  // c0 and cN real.  So ni / 8 workgroups cover ni + 1 columns: at 257 columns,
+  // 1024 workgroups, one round at four per CU, instead of 1056.  Single
+  // precision only: in double precision (three workgroups per CU) no round is
+  // saved.
+  constexpr bool CAN_PACK = sizeof(T) == 4;
+  const bool pk = CAN_PACK && A.pack && bk.x == 0;
+  const bool pkl = pk && q == 0;
   const int b = bk.y;
   // byte offsets from the uniform pencil-set bases (inactive lanes read kx = ni - 1)
   const cx<T>* in = A.in[bk.z];
@@ -878,6 +896,15 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
   constexpr unsigned CB = sizeof(cx<T>);
   const unsigned ioff = (unsigned)(b * A.sb_in + min(kx, A.ni - 1)) * CB, isa = (unsigned)A.sa_in * CB;
   const unsigned ooff = (unsigned)(b * A.sb_out + kx) * CB, osa = (unsigned)A.sa_out * CB;
+  // the Nyquist column (blocked layout: row r at (r & ~15, ni + (r & 15))),
+  // staged through LDS for the packed lane, one entry per thread.  Entry i sits
+  // in the padding of transpose row i % 64 (columns 8 P + i / 64, which no
+  // transpose touches), so no barrier separates it from the transposes.
+  const unsigned nbase_in = (unsigned)(b * A.sb_in + A.ni) * CB, nbase_out = (unsigned)(b * A.sb_out + A.ni) * CB;
+  auto noff_in = [&](int r) { return nbase_in + (unsigned)(r & ~15) * isa + (unsigned)(r & 15) * CB; };
+  auto noff_out = [&](int r) { return nbase_out + (unsigned)(r & ~15) * osa + (unsigned)(r & 15) * CB; };
+  static_assert(!CAN_PACK || S - 8 * P >= 8, "8 padding entries per transpose row");
+  auto xn = [&](int i) -> cx<T>& { return xb[(i & 63) * S + 8 * P + (i >> 6)]; };
   const bool inv = A.inv != 0;
   auto W = [&](int e) {  // W_512^{e} (conjugated for the inverse)
     cx<T> v = w[e & 511];
@@ -899,8 +926,35 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
       v[kb] = k < A.n_in ? ld_off(in, ioff + (unsigned)k * isa) : zero<T>();
     }
   }
-  for (int i = tid; i < 512; i += 64 * P) w[i] = A.tw[i << (A.lgTw - 9)];
+  if constexpr (CAN_PACK) {
+    static_assert(64 * P == 512, "one table entry per thread");
+    // the staging load is unconditional: other workgroups re-read their own
+    // first element (a valid address, the value unused), since a branch around
+    // the load makes the compiler wait for it there.  Rows past n_in are masked
+    // where the packed lane reads them.
+    const cx<T> nq = ld_off(in, pk ? noff_in(min(tid, A.n_in - 1)) : ioff);
+    const cx<T> wv = A.tw[tid << (A.lgTw - 9)];
+    // every load above is issued before the first LDS store waits for one
+    __builtin_amdgcn_sched_barrier(0);
+    w[tid] = wv;
+    if (pk) xn(tid) = nq;
+  } else {
+    for (int i = tid; i < 512; i += 64 * P) w[i] = A.tw[i << (A.lgTw - 9)];
+  }
   __syncthreads();
+  if (pkl) {
+    if (!inv) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) v[m].y = t + 64 * m < A.n_in ? xn(t + 64 * m).x : (T)0;
+    } else {
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) {
+        const int k = (t >> 3) + 8 * (t & 7) + 64 * kb;
+        const cx<T> cn = k < A.n_in ? xn(k) : zero<T>();
+        v[kb] = mk<T>(v[kb].x - cn.y, v[kb].y + cn.x);
+      }
+    }
+  }
   if (!inv) {
     if (A.n_in <= 256) dft8_lo4(v, false);  // zero-padded half: rows t + 64 m, m >= 4
     else dft8(v, false);
@@ -927,7 +981,29 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
 #pragma unroll
       for (int u0 = 0; u0 < 8; ++u0) v[u0] = xb[(k2 * 8 + ka) * S + u0 * P + q];
       dft8(v, false);
-      if (act) {
+      if (pk) {
+        // Z = FFT(c0 + i cN): FFT(c0)[k] = (Z[k] + conj Z[-k]) / 2 and
+        // FFT(cN)[k] = (Z[k] - conj Z[-k]) / 2i, Z[-k] from the lane that owns it
+        if (q == 0) {
+#pragma unroll
+          for (int kb = 0; kb < 8; ++kb) xn(k2 + 8 * ka + 64 * kb) = v[kb];
+        }
+        __syncthreads();
+        if (q == 0) {
+#pragma unroll
+          for (int kb = 0; kb < 8; ++kb) {
+            const int k = k2 + 8 * ka + 64 * kb;
+            const cx<T> Z = v[kb], Zm = xn((512 - k) & 511);
+            const cx<T> c0 = mk<T>((Z.x + Zm.x) * (T)0.5, (Z.y - Zm.y) * (T)0.5);
+            const cx<T> cN = mk<T>((Z.y + Zm.y) * (T)0.5, (Zm.x - Z.x) * (T)0.5);
+            if (k < A.n_out) {
+              st_off(out, ooff + (unsigned)k * osa, c0);
+              st_off(out, noff_out(k), cN);
+            }
+          }
+        }
+      }
+      if (act && !pkl) {
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
           const int k = k2 + 8 * ka + 64 * kb;
@@ -960,7 +1036,17 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
     // index m: x[t + 64 m]; a cropped output keeps m < 4
     if (A.n_out <= 256) dft8_first4(v, true);
     else dft8(v, true);
-    if (act) {
+    if (pkl) {
+      // c0 + i cN with c0, cN real: the real part is column 0, the imaginary part column ni
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int row = t + 64 * m;
+        if (row < A.n_out) {
+          st_off(out, ooff + (unsigned)row * osa, mk<T>(v[m].x, (T)0));
+          st_off(out, noff_out(row), mk<T>(v[m].y, (T)0));
+        }
+      }
+    } else if (act) {
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const int row = t + 64 * m;
@@ -1157,8 +1243,11 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 5 : 1) void k_conv64(const
   // inactive lanes read valid addresses and are never stored
   const int kxc = min(kx, A.ni - 1);
   const int b = (r && mirror) ? A.Pb - bf : bf;
-  // byte offsets from uniform base pointers (scalar base + 32-bit vector offset)
-  const unsigned soff = (unsigned)(b * A.sb + kxc) * (unsigned)sizeof(cx<T>);
+  // byte offsets from uniform base pointers (scalar base + 32-bit vector offset);
+  // the Nyquist column may be in the blocked layout over the batch rows
+  const unsigned soff =
+      (unsigned)(A.nyqb && kxc == A.ni - 1 ? nyq_off(b, A.sb, kxc, true) : (long)b * A.sb + kxc) *
+      (unsigned)sizeof(cx<T>);
   const unsigned sa = (unsigned)A.sa * (unsigned)sizeof(cx<T>);
   const int pen = r * P + q;
 
@@ -1909,8 +1998,13 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
     for (int m = 0; m < 8; ++m) {
       const int k = t + 64 * m;
       const unsigned kk = (unsigned)(k <= 256 ? k : 512 - k);
-      Xa[m] = ld_off(xin, pa + kk * CB);
-      Xb[m] = ld_off(xin, pb + kk * CB);
+      unsigned oa = pa + kk * CB, ob = pb + kk * CB;
+      if (m == 4 && A.nyqb && kk == 256u) {  // the Nyquist bin (thread 0)
+        oa = (unsigned)nyq_off(ra1c, A.xin_pitch, 256, true) * CB;
+        ob = (unsigned)nyq_off(rb1c, A.xin_pitch, 256, true) * CB;
+      }
+      Xa[m] = ld_off(xin, oa);
+      Xb[m] = ld_off(xin, ob);
     }
   }
   cx<T> pu[4], pw[4], wk[4];
@@ -2019,8 +2113,11 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
         const cx<T> Zk = f512_at<T, P, S>(xb, k, q), Zm = f512_at<T, P, S>(xb, (512 - k) & 511, q);
         const cx<T> Xa2 = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
         const cx<T> Xb2 = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-        if (oka) st_off(xo, ((unsigned)ra * pitch + (unsigned)k) * CB, Xa2);
-        if (okb) st_off(xo, ((unsigned)(ra + 1) * pitch + (unsigned)k) * CB, Xb2);
+        const bool nb = j == 4 && A.nyqb;  // the Nyquist bin
+        const unsigned oa = nb ? (unsigned)nyq_off(ra, pitch, 256, true) : (unsigned)ra * pitch + (unsigned)k;
+        const unsigned ob = nb ? (unsigned)nyq_off(ra + 1, pitch, 256, true) : (unsigned)(ra + 1) * pitch + (unsigned)k;
+        if (oka) st_off(xo, oa * CB, Xa2);
+        if (okb) st_off(xo, ob * CB, Xb2);
       }
     }
   }
@@ -2147,8 +2244,11 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
         const cx<T> Zk = f512_at<T, P, S>(xb, k, q), Zm = f512_at<T, P, S>(xb, (512 - k) & 511, q);
         const cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
         const cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-        if (oka) st_off(A.xout, ((unsigned)ra * pitch + (unsigned)k) * CB, Xa);
-        if (okb) st_off(A.xout, ((unsigned)(ra + 1) * pitch + (unsigned)k) * CB, Xb);
+        const bool nb = j == 4 && A.nyqb;  // the Nyquist bin
+        const unsigned oa = nb ? (unsigned)nyq_off(ra, pitch, 256, true) : (unsigned)ra * pitch + (unsigned)k;
+        const unsigned ob = nb ? (unsigned)nyq_off(ra + 1, pitch, 256, true) : (unsigned)(ra + 1) * pitch + (unsigned)k;
+        if (oka) st_off(A.xout, oa * CB, Xa);
+        if (okb) st_off(A.xout, ob * CB, Xb);
       }
     }
   } else if constexpr (NCH == 3 && OP == ROW_OP_PROJECT) {
@@ -2258,9 +2358,16 @@ template <typename T> int launch_col_dct(const ColDct<T>& a, int nbatch, int nch
 template <typename T> int launch_col_fft(const ColFft<T>& a, int nbatch, int nch, hipStream_t s) {
   if (a.lgL == 9) {
     constexpr int P = sizeof(T) == 4 ? 8 : 4;
-    dim3 grid(ceil_div(a.ni, P), nbatch, nch);
+    // packed DC and Nyquist columns: the kernel's ni counts the columns before
+    // the Nyquist column, which is column ni
+    ColFft<T> b = a;
+    // (the plan requests packing, and the blocked Nyquist layout it implies, in
+    // single precision only)
+    b.pack = sizeof(T) == 4 && a.pack && a.ni > 1;
+    if (b.pack) b.ni = a.ni - 1;
+    dim3 grid(ceil_div(b.ni, P), nbatch, nch);
     const size_t lds = (512 + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
-    hipLaunchKernelGGL((k_fft512<T, P>), grid, dim3(64 * P), lds, s, a);
+    hipLaunchKernelGGL((k_fft512<T, P>), grid, dim3(64 * P), lds, s, b);
     return SGSPM_KC_FFT512;
   }
   dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, nch);

@@ -86,6 +86,29 @@ def test_adjoint_step_fp32(env):
     assert e_l <= 1e-5 and e_h <= 1e-5 and e_a <= 1e-5
 
 
+def test_adjoint_step_fp32_blocked_nyquist(env):
+    """FP32 adjoint step on a 16x256x32 block, whose stray-field passes keep the
+    Nyquist column in the blocked layout and pack it with the DC column."""
+    torch, sg = env
+    n = (16, 256, 32)
+    rng = np.random.default_rng(203)
+    m0 = workloads.random_unit((n[2], n[1], n[0]), 204)
+    lam = rng.normal(size=m0.shape)
+    B = (5e-3, 1e-3, 0.0)
+    alpha = 0.02
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, 0)
+    lam_d = to_dev(torch, lam, 0)
+    grad = torch.zeros(4, dtype=torch.float64, device="cuda")
+    plan.adjoint_step(to_dev(torch, m0, 0), alpha, B, lam_d, grad)
+    torch.cuda.synchronize()
+    P = oracle_problem_si(n, CELL, DT, ALL)
+    lref, dh, da = oadj.adjoint_step(P, rounded_like(m0, 0), alpha, oracle_field_si(B, ALL), rounded_like(lam, 0))
+    g = grad.cpu().numpy()
+    e_l, e_h, e_a = _rel(lam_d.cpu().numpy(), lref), _rel(g[:3], dh * FSCALE), abs(g[3] - da) / abs(da)
+    print(f"16x256x32 fp32 adjoint step: rel err lam {e_l:.2e}, dh_e {e_h:.2e}, dalpha {e_a:.2e}")
+    assert e_l <= 1e-5 and e_h <= 1e-5 and e_a <= 1e-5
+
+
 def _loss_grads_gpu(torch, sg, plan, m0, B, alpha, target, ckpt, prec):
     dt_ = torch.float64 if prec == 1 else torch.float32
     m = torch.tensor(m0, dtype=dt_, device="cuda", requires_grad=True)
