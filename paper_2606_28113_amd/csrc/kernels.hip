@@ -981,25 +981,26 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
 #pragma unroll
       for (int u0 = 0; u0 < 8; ++u0) v[u0] = xb[(k2 * 8 + ka) * S + u0 * P + q];
       dft8(v, false);
-      if (pk) {
+      if (pkl) {
         // Z = FFT(c0 + i cN): FFT(c0)[k] = (Z[k] + conj Z[-k]) / 2 and
-        // FFT(cN)[k] = (Z[k] - conj Z[-k]) / 2i, Z[-k] from the lane that owns it
-        if (q == 0) {
+        // FFT(cN)[k] = (Z[k] - conj Z[-k]) / 2i.  With s = k2 + 8 ka, Z[-k] is
+        // output 7 - kb of the thread with s' = 64 - s (output (8 - kb) % 8 of this
+        // thread for s = 0); this lane repeats that thread's last DFT from the
+        // same LDS rows instead of waiting for it at a barrier.
+        const int s0 = k2 + 8 * ka, s1 = (64 - s0) & 63;
+        cx<T> u[8];
 #pragma unroll
-          for (int kb = 0; kb < 8; ++kb) xn(k2 + 8 * ka + 64 * kb) = v[kb];
-        }
-        __syncthreads();
-        if (q == 0) {
+        for (int u0 = 0; u0 < 8; ++u0) u[u0] = xb[((s1 & 7) * 8 + (s1 >> 3)) * S + u0 * P + q];
+        dft8(u, false);
 #pragma unroll
-          for (int kb = 0; kb < 8; ++kb) {
-            const int k = k2 + 8 * ka + 64 * kb;
-            const cx<T> Z = v[kb], Zm = xn((512 - k) & 511);
-            const cx<T> c0 = mk<T>((Z.x + Zm.x) * (T)0.5, (Z.y - Zm.y) * (T)0.5);
-            const cx<T> cN = mk<T>((Z.y + Zm.y) * (T)0.5, (Zm.x - Z.x) * (T)0.5);
-            if (k < A.n_out) {
-              st_off(out, ooff + (unsigned)k * osa, c0);
-              st_off(out, noff_out(k), cN);
-            }
+        for (int kb = 0; kb < 8; ++kb) {
+          const int k = s0 + 64 * kb;
+          const cx<T> Z = v[kb], Zm = s0 ? u[7 - kb] : v[(8 - kb) & 7];
+          const cx<T> c0 = mk<T>((Z.x + Zm.x) * (T)0.5, (Z.y - Zm.y) * (T)0.5);
+          const cx<T> cN = mk<T>((Z.y + Zm.y) * (T)0.5, (Zm.x - Z.x) * (T)0.5);
+          if (k < A.n_out) {
+            st_off(out, ooff + (unsigned)k * osa, c0);
+            st_off(out, noff_out(k), cN);
           }
         }
       }
