@@ -11,11 +11,15 @@
 // A "channel" is one of up to three independent arrays handled by one launch
 // (grid.z); each argument block carries one pointer per channel.
 //
-// Blocked Nyquist layout (spectra whose Nyquist bin N = Kx - 1 is a multiple of
-// 16, with Kxp = N + 16, in planes whose row count is a multiple of 16): the
-// Nyquist bin of row r is not at (r, N) but at (r & ~15, N + (r & 15)), in the
-// row padding.  A pass along the rows then reads or writes the Nyquist bins of
-// 16 consecutive rows as one 128-byte line instead of 16 lines of 8 bytes.
+// Packed DC and Nyquist bins (x-level spectra of real rows): both bins are real,
+// so bin 0 holds X[0] + i X[N] and bin N is not stored; the y pass transforms
+// that column like any other.  At the y level the forward pass splits it again:
+// the DC column in column 0, the Nyquist column in the blocked layout (spectra
+// whose Nyquist bin N = Kx - 1 is a multiple of 16, with Kxp = N + 16, in planes
+// whose row count is a multiple of 16): the Nyquist bin of row r is not at
+// (r, N) but at (r & ~15, N + (r & 15)), in the row padding, so that the Nyquist
+// bins of 16 consecutive rows form one 128-byte line.  The convolution keeps
+// that layout, and the inverse y pass packs the two columns again.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -56,7 +60,7 @@ template <typename T> struct RowFwd {
   cx<T>* xout[3];   // optional zero-padded real-to-complex transform of v
   int lgLr;
   int xout_pitch;
-  int nyqb;         // xin and xout hold their Nyquist bins in the blocked layout (nyq_off)
+  int xpk;          // xin and xout hold the Nyquist bin in the imaginary part of bin 0
 };
 
 enum { ROW_OP_NONE = 0, ROW_OP_GS = 1, ROW_OP_PROJECT = 2 };
@@ -89,7 +93,7 @@ template <typename T> struct RowInv {
   cx<T>* xout;
   int lgLr;
   int xout_pitch;
-  int nyqb;            // xout holds its Nyquist bins in the blocked layout (nyq_off)
+  int xpk;             // xout holds the Nyquist bin in the imaginary part of bin 0
 };
 
 // Column kernels (pencils along a strided axis; tiles of consecutive inner indices).
@@ -120,10 +124,9 @@ template <typename T> struct ColFft {
   int inv;
   const cx<T>* tw;
   int lgTw;
-  // set by the caller when columns 0 and ni - 1 are the x-level DC and Nyquist
-  // columns of real rows (real before the forward transform, real again after
-  // the inverse one) and the Nyquist column of in and out is in the blocked
-  // layout (nyq_off): the 512-point kernel then carries both in one pencil
+  // the x-level side packs the DC and Nyquist columns in column 0 (ni - 1
+  // columns are transformed); the y-level side holds them apart, the Nyquist
+  // column ni - 1 in the blocked layout (nyq_off)
   int pack;
 };
 

@@ -53,7 +53,7 @@ __device__ __forceinline__ Blk xcd_block() {
 template <typename T, int NV>
 __device__ __forceinline__ void row_r2c_store(cx<T>* buf, const cx<T>* tw, const T (&val)[NV], int tot, int lgN, int lgLr,
                                               int lgLmax, int lgP, int row0, int nrows, cx<T>* xout, int pitch,
-                                              bool nyqb) {
+                                              bool xpk) {
   const int n = 1 << lgN;
   const int Lr = 1 << lgLr;
   const int P = 1 << lgP;
@@ -77,17 +77,23 @@ __device__ __forceinline__ void row_r2c_store(cx<T>* buf, const cx<T>* tw, const
   const int half = Lr >> 1;
   for (int t = threadIdx.x; t < (P << lgLr); t += NT) {
     const int k = t & (Lr - 1);
-    if (k > half) continue;
+    if (k > half || (xpk && k == half)) continue;
     const int q = t >> lgLr;
     const cx<T> Zk = buf[q * ps + k];
     const cx<T> Zm = buf[q * ps + ((Lr - k) & (Lr - 1))];
     // X_a = (Z_k + conj Z_{-k}) / 2 ; X_b = (Z_k - conj Z_{-k}) / (2i)
-    const cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
-    const cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+    cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+    cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+    if (xpk && k == 0) {
+      // packed: X_a[half] = Re Z_half and X_b[half] = Im Z_half (both real) in the
+      // imaginary part of bin 0
+      const cx<T> Zh = buf[q * ps + half];
+      Xa.y = Zh.x;
+      Xb.y = Zh.y;
+    }
     const int ra = row0 + 2 * q;
-    const bool nq = k == half;
-    if (ra < nrows) xout[nq ? nyq_off(ra, pitch, half, nyqb) : (long)ra * pitch + k] = Xa;
-    if (ra + 1 < nrows) xout[nq ? nyq_off(ra + 1, pitch, half, nyqb) : (long)(ra + 1) * pitch + k] = Xb;
+    if (ra < nrows) xout[(long)ra * pitch + k] = Xa;
+    if (ra + 1 < nrows) xout[(long)(ra + 1) * pitch + k] = Xb;
   }
   __syncthreads();
 }
@@ -145,10 +151,9 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
         const int q = t >> A.lgLc, k = t & (Lc - 1);
         const int ra = row0 + 2 * q;
         const int kk = k > half ? Lc - k : k;
-        const bool nq = kk == half, nb = A.nyqb != 0;
-        if (ra < A.nrows) Ra[j] = xin[nq ? nyq_off(ra, A.xin_pitch, half, nb) : (long)ra * A.xin_pitch + kk];
-        if (ra + 1 < A.nrows)
-          Rb[j] = xin[nq ? nyq_off(ra + 1, A.xin_pitch, half, nb) : (long)(ra + 1) * A.xin_pitch + kk];
+        const int kl = A.xpk && kk == half ? 0 : kk;  // packed: the Nyquist bin is in bin 0
+        if (ra < A.nrows) Ra[j] = xin[(long)ra * A.xin_pitch + kl];
+        if (ra + 1 < A.nrows) Rb[j] = xin[(long)(ra + 1) * A.xin_pitch + kl];
       }
     }
   }
@@ -164,6 +169,10 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
         const int kk = cj ? Lc - k : k;
         cx<T> Xa = Ra[j], Xb = Rb[j];
         if (kk == 0 || kk == half) {
+          if (A.xpk && kk == half) {
+            Xa.x = Xa.y;
+            Xb.x = Xb.y;
+          }
           Xa.y = (T)0;
           Xb.y = (T)0;
         }
@@ -271,7 +280,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
   cx<T>* xo = A.xout[ch];
   if (xo)
     row_r2c_store<T, NV>(buf, tw, val, tot, A.lgN, A.lgLr, A.lgLmax, A.lgP, row0, A.nrows, xo, A.xout_pitch,
-                         A.nyqb != 0);
+                         A.xpk != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -400,7 +409,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
     }
     if (A.xout)
       row_r2c_store<T, NV>(buf, tw, val, tot, A.lgN, A.lgLr, A.lgLmax, A.lgP, row0, A.nrows, A.xout, A.xout_pitch,
-                           A.nyqb != 0);
+                           A.xpk != 0);
   } else if (A.op == ROW_OP_PROJECT) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
@@ -864,7 +873,7 @@ __global__ __launch_bounds__(NT) void k_col_fft(const ColFft<T> A) {
 // LDS rows are padded (S = 8P + 1) against bank conflicts.
 template <typename T, int P> constexpr int fft512_stride() { return 8 * P + (sizeof(T) == 4 ? 8 : 4); }
 
-template <typename T, int P>
+template <typename T, int P, bool INV>
 __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // row stride of the transposes: 8 mod 32 complex (float) or 4 mod 16 (double), so the
@@ -878,14 +887,14 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
   const Blk bk = xcd_block();
   const int kx = bk.x * P + q;
   const bool act = kx < A.ni;
-  // A.pack: columns 0 and A.ni (the x-level DC and Nyquist columns, the latter
-  // in the blocked layout) share the pencil of tile 0, lane q = 0, as c0 + i cN.
-  // Both are real on input to the forward transform, whose result splits by
-  // Hermitian symmetry; the inverse takes C0 + i CN and returns c0 + i cN with
-  // c0 and cN real.  So ni / 8 workgroups cover ni + 1 columns: at 257 columns,
-  // 1024 workgroups, one round at four per CU, instead of 1056.  Single
-  // precision only: in double precision (three workgroups per CU) no round is
-  // saved.
+  // A.pack: the x-level DC and Nyquist columns (both real) share the pencil of
+  // tile 0, lane q = 0, as c0 + i cN, packed so in column 0 of the x-level side;
+  // the y-level side holds them apart, C0 in column 0 and CN in column A.ni in
+  // the blocked layout.  The forward output splits by Hermitian symmetry; the
+  // inverse packs C0 + i CN on input and returns c0 + i cN.  So ni / 8
+  // workgroups cover ni + 1 columns: 1024 instead of 1056 for 257 columns, one
+  // round at four per CU.  Single precision only: in double precision (three
+  // workgroups per CU) no round is saved.
   constexpr bool CAN_PACK = sizeof(T) == 4;
   const bool pk = CAN_PACK && A.pack && bk.x == 0;
   const bool pkl = pk && q == 0;
@@ -896,16 +905,17 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
   constexpr unsigned CB = sizeof(cx<T>);
   const unsigned ioff = (unsigned)(b * A.sb_in + min(kx, A.ni - 1)) * CB, isa = (unsigned)A.sa_in * CB;
   const unsigned ooff = (unsigned)(b * A.sb_out + kx) * CB, osa = (unsigned)A.sa_out * CB;
-  // the Nyquist column (blocked layout: row r at (r & ~15, ni + (r & 15))),
-  // staged through LDS for the packed lane, one entry per thread.  Entry i sits
-  // in the padding of transpose row i % 64 (columns 8 P + i / 64, which no
-  // transpose touches), so no barrier separates it from the transposes.
+  // the y-level Nyquist column (blocked layout: row r at (r & ~15, ni + (r & 15))),
+  // for the inverse staged through LDS for the packed lane, one entry per
+  // thread.  Entry i sits in the padding of transpose row i % 64 (columns 8 P +
+  // i / 64, which no transpose touches), so no barrier separates it from the
+  // transposes.
   const unsigned nbase_in = (unsigned)(b * A.sb_in + A.ni) * CB, nbase_out = (unsigned)(b * A.sb_out + A.ni) * CB;
   auto noff_in = [&](int r) { return nbase_in + (unsigned)(r & ~15) * isa + (unsigned)(r & 15) * CB; };
   auto noff_out = [&](int r) { return nbase_out + (unsigned)(r & ~15) * osa + (unsigned)(r & 15) * CB; };
   static_assert(!CAN_PACK || S - 8 * P >= 8, "8 padding entries per transpose row");
   auto xn = [&](int i) -> cx<T>& { return xb[(i & 63) * S + 8 * P + (i >> 6)]; };
-  const bool inv = A.inv != 0;
+  constexpr bool inv = INV;
   auto W = [&](int e) {  // W_512^{e} (conjugated for the inverse)
     cx<T> v = w[e & 511];
     if (inv) v.y = -v.y;
@@ -926,7 +936,7 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
       v[kb] = k < A.n_in ? ld_off(in, ioff + (unsigned)k * isa) : zero<T>();
     }
   }
-  if constexpr (CAN_PACK) {
+  if constexpr (CAN_PACK && INV) {
     static_assert(64 * P == 512, "one table entry per thread");
     // the staging load is unconditional: other workgroups re-read their own
     // first element (a valid address, the value unused), since a branch around
@@ -942,17 +952,12 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
     for (int i = tid; i < 512; i += 64 * P) w[i] = A.tw[i << (A.lgTw - 9)];
   }
   __syncthreads();
-  if (pkl) {
-    if (!inv) {
+  if (INV && pkl) {
 #pragma unroll
-      for (int m = 0; m < 8; ++m) v[m].y = t + 64 * m < A.n_in ? xn(t + 64 * m).x : (T)0;
-    } else {
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb) {
-        const int k = (t >> 3) + 8 * (t & 7) + 64 * kb;
-        const cx<T> cn = k < A.n_in ? xn(k) : zero<T>();
-        v[kb] = mk<T>(v[kb].x - cn.y, v[kb].y + cn.x);
-      }
+    for (int kb = 0; kb < 8; ++kb) {
+      const int k = (t >> 3) + 8 * (t & 7) + 64 * kb;
+      const cx<T> cn = k < A.n_in ? xn(k) : zero<T>();
+      v[kb] = mk<T>(v[kb].x - cn.y, v[kb].y + cn.x);
     }
   }
   if (!inv) {
@@ -986,30 +991,35 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
         // FFT(cN)[k] = (Z[k] - conj Z[-k]) / 2i.  With s = k2 + 8 ka, Z[-k] is
         // output 7 - kb of the thread with s' = 64 - s (output (8 - kb) % 8 of this
         // thread for s = 0); this lane repeats that thread's last DFT from the
-        // same LDS rows instead of waiting for it at a barrier.
+        // same LDS rows instead of waiting for it at a barrier.  FFT(c0) leaves
+        // with the other lanes' outputs, FFT(cN) through LDS.
         const int s0 = k2 + 8 * ka, s1 = (64 - s0) & 63;
         cx<T> u[8];
 #pragma unroll
         for (int u0 = 0; u0 < 8; ++u0) u[u0] = xb[((s1 & 7) * 8 + (s1 >> 3)) * S + u0 * P + q];
         dft8(u, false);
+        cx<T> c0[8];
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
-          const int k = s0 + 64 * kb;
           const cx<T> Z = v[kb], Zm = s0 ? u[7 - kb] : v[(8 - kb) & 7];
-          const cx<T> c0 = mk<T>((Z.x + Zm.x) * (T)0.5, (Z.y - Zm.y) * (T)0.5);
-          const cx<T> cN = mk<T>((Z.y + Zm.y) * (T)0.5, (Zm.x - Z.x) * (T)0.5);
-          if (k < A.n_out) {
-            st_off(out, ooff + (unsigned)k * osa, c0);
-            st_off(out, noff_out(k), cN);
-          }
+          c0[kb] = mk<T>((Z.x + Zm.x) * (T)0.5, (Z.y - Zm.y) * (T)0.5);
+          xn(s0 + 64 * kb) = mk<T>((Z.y + Zm.y) * (T)0.5, (Zm.x - Z.x) * (T)0.5);
         }
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) v[kb] = c0[kb];
       }
-      if (act && !pkl) {
+      if (act) {
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
           const int k = k2 + 8 * ka + 64 * kb;
           if (k < A.n_out) st_off(out, ooff + (unsigned)k * osa, v[kb]);
         }
+      }
+      if (pk) {
+        // the Nyquist column, one row per thread: whole lines of the blocked
+        // layout instead of scattered 8-byte stores
+        __syncthreads();
+        if (tid < A.n_out) st_off(out, noff_out(tid), xn(tid));
       }
     }
   } else {
@@ -1037,17 +1047,7 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
     // index m: x[t + 64 m]; a cropped output keeps m < 4
     if (A.n_out <= 256) dft8_first4(v, true);
     else dft8(v, true);
-    if (pkl) {
-      // c0 + i cN with c0, cN real: the real part is column 0, the imaginary part column ni
-#pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const int row = t + 64 * m;
-        if (row < A.n_out) {
-          st_off(out, ooff + (unsigned)row * osa, mk<T>(v[m].x, (T)0));
-          st_off(out, noff_out(row), mk<T>(v[m].y, (T)0));
-        }
-      }
-    } else if (act) {
+    if (act) {
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const int row = t + 64 * m;
@@ -1999,13 +1999,10 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
     for (int m = 0; m < 8; ++m) {
       const int k = t + 64 * m;
       const unsigned kk = (unsigned)(k <= 256 ? k : 512 - k);
-      unsigned oa = pa + kk * CB, ob = pb + kk * CB;
-      if (m == 4 && A.nyqb && kk == 256u) {  // the Nyquist bin (thread 0)
-        oa = (unsigned)nyq_off(ra1c, A.xin_pitch, 256, true) * CB;
-        ob = (unsigned)nyq_off(rb1c, A.xin_pitch, 256, true) * CB;
-      }
-      Xa[m] = ld_off(xin, oa);
-      Xb[m] = ld_off(xin, ob);
+      // packed: the Nyquist bin (thread 0, m = 4) is the imaginary part of bin 0
+      const unsigned kl = m == 4 && A.xpk && kk == 256u ? 0u : kk;
+      Xa[m] = ld_off(xin, pa + kl * CB);
+      Xb[m] = ld_off(xin, pb + kl * CB);
     }
   }
   cx<T> pu[4], pw[4], wk[4];
@@ -2027,6 +2024,10 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
       const int kk = k <= 256 ? k : 512 - k;
       cx<T> xa = Xa[m], xbb = Xb[m];
       if (kk == 0 || kk == 256) {
+        if (A.xpk && kk == 256) {
+          xa.x = xa.y;
+          xbb.x = xbb.y;
+        }
         xa.y = (T)0;
         xbb.y = (T)0;
       }
@@ -2110,15 +2111,18 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
 #pragma unroll
       for (int j = 0; j <= 4; ++j) {
         const int k = t + 64 * j;
-        if (j == 4 && t) break;
+        if (j == 4 && (t || A.xpk)) break;  // packed: the Nyquist bin goes with bin 0
         const cx<T> Zk = f512_at<T, P, S>(xb, k, q), Zm = f512_at<T, P, S>(xb, (512 - k) & 511, q);
-        const cx<T> Xa2 = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
-        const cx<T> Xb2 = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-        const bool nb = j == 4 && A.nyqb;  // the Nyquist bin
-        const unsigned oa = nb ? (unsigned)nyq_off(ra, pitch, 256, true) : (unsigned)ra * pitch + (unsigned)k;
-        const unsigned ob = nb ? (unsigned)nyq_off(ra + 1, pitch, 256, true) : (unsigned)(ra + 1) * pitch + (unsigned)k;
-        if (oka) st_off(xo, oa * CB, Xa2);
-        if (okb) st_off(xo, ob * CB, Xb2);
+        cx<T> Xa2 = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+        cx<T> Xb2 = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+        if (j == 0 && A.xpk && t == 0) {
+          // X[256] of both rows (real: Re Z_256, Im Z_256) as bin 0's imaginary part
+          const cx<T> Zn = f512_at<T, P, S>(xb, 256, q);
+          Xa2.y = Zn.x;
+          Xb2.y = Zn.y;
+        }
+        if (oka) st_off(xo, ((unsigned)ra * pitch + (unsigned)k) * CB, Xa2);
+        if (okb) st_off(xo, ((unsigned)(ra + 1) * pitch + (unsigned)k) * CB, Xb2);
       }
     }
   }
@@ -2241,15 +2245,18 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
 #pragma unroll
       for (int j = 0; j <= 4; ++j) {
         const int k = t + 64 * j;
-        if (j == 4 && t) break;
+        if (j == 4 && (t || A.xpk)) break;  // packed: the Nyquist bin goes with bin 0
         const cx<T> Zk = f512_at<T, P, S>(xb, k, q), Zm = f512_at<T, P, S>(xb, (512 - k) & 511, q);
-        const cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
-        const cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-        const bool nb = j == 4 && A.nyqb;  // the Nyquist bin
-        const unsigned oa = nb ? (unsigned)nyq_off(ra, pitch, 256, true) : (unsigned)ra * pitch + (unsigned)k;
-        const unsigned ob = nb ? (unsigned)nyq_off(ra + 1, pitch, 256, true) : (unsigned)(ra + 1) * pitch + (unsigned)k;
-        if (oka) st_off(A.xout, oa * CB, Xa);
-        if (okb) st_off(A.xout, ob * CB, Xb);
+        cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+        cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+        if (j == 0 && A.xpk && t == 0) {
+          // X[256] of both rows (real: Re Z_256, Im Z_256) as bin 0's imaginary part
+          const cx<T> Zn = f512_at<T, P, S>(xb, 256, q);
+          Xa.y = Zn.x;
+          Xb.y = Zn.y;
+        }
+        if (oka) st_off(A.xout, ((unsigned)ra * pitch + (unsigned)k) * CB, Xa);
+        if (okb) st_off(A.xout, ((unsigned)(ra + 1) * pitch + (unsigned)k) * CB, Xb);
       }
     }
   } else if constexpr (NCH == 3 && OP == ROW_OP_PROJECT) {
@@ -2368,7 +2375,8 @@ template <typename T> int launch_col_fft(const ColFft<T>& a, int nbatch, int nch
     if (b.pack) b.ni = a.ni - 1;
     dim3 grid(ceil_div(b.ni, P), nbatch, nch);
     const size_t lds = (512 + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
-    hipLaunchKernelGGL((k_fft512<T, P>), grid, dim3(64 * P), lds, s, b);
+    if (a.inv) hipLaunchKernelGGL((k_fft512<T, P, true>), grid, dim3(64 * P), lds, s, b);
+    else hipLaunchKernelGGL((k_fft512<T, P, false>), grid, dim3(64 * P), lds, s, b);
     return SGSPM_KC_FFT512;
   }
   dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, nch);

@@ -101,9 +101,9 @@ struct sgspm_plan_s {
   long N = 0;
   int Px = 1, Py = 1, Pz = 1, Kx = 1, Kxp = 1, Hy = 1, Hz = 1;
   bool stray = false, zeeman = false, has_mid = false;
-  // x- and y-level spectra keep their Nyquist column in the blocked layout
-  // (nyq_off), and the 512-point y pass packs it with the DC column
-  bool nyqb = false;
+  // the x-level spectra carry their (real) Nyquist bin in bin 0, and the y
+  // level holds the DC column and the Nyquist column (blocked layout) apart
+  bool dcnq = false;
   bool yz = false;  // heat arrays x-major and solved across y, z by one fused kernel
   double eps = 0, Q = 0, dt = 0, fscale = 1, escale = 1;
   double cxx = 0, cyy = 0, czz = 0;  // eps / h^2 per axis (reduced)
@@ -281,7 +281,7 @@ template <typename T> struct Eng {
     A.b = io.b;
     A.xin_pitch = P.Kxp;
     A.xout_pitch = P.Kxp;
-    A.nyqb = P.nyqb ? 1 : 0;
+    A.xpk = P.dcnq ? 1 : 0;
     A.dct_xmajor = P.yz ? 1 : 0;
     for (int c = 0; c < nch; ++c) {
       A.u[c] = io.u[c];
@@ -316,7 +316,7 @@ template <typename T> struct Eng {
     A.tw = tw;
     A.dtw = dtw[0];
     A.xout_pitch = P.Kxp;
-    A.nyqb = P.nyqb ? 1 : 0;
+    A.xpk = P.dcnq ? 1 : 0;
     A.heat_xmajor = P.yz ? 1 : 0;
     if (!r2c) A.xout = nullptr;
     double by = A.nch * P.N * TS;
@@ -426,7 +426,7 @@ template <typename T> struct Eng {
     A.inv = 0;
     A.tw = tw;
     A.lgTw = P.lgTw;
-    A.pack = P.nyqb ? 1 : 0;  // the x-level spectra of real rows
+    A.pack = P.dcnq ? 1 : 0;
     const double cb = (double)P.Kx * P.nz * 2 * TS;
     timed(k * cb * (P.ny + P.Py), [&] { return launch_col_fft<T>(A, P.nz, k, s); });
   }
@@ -452,7 +452,7 @@ template <typename T> struct Eng {
     A.inv = 1;
     A.tw = tw;
     A.lgTw = P.lgTw;
-    A.pack = P.nyqb ? 1 : 0;  // the stray field is real
+    A.pack = P.dcnq ? 1 : 0;
     const double cb = (double)P.Kx * P.nz * 2 * TS;
     timed(k * cb * (P.ny + P.Py), [&] { return launch_col_fft<T>(A, P.nz, k, s); });
   }
@@ -503,7 +503,7 @@ template <typename T> struct Eng {
       while (A.lgP > 0 && ((P.Kx + (1L << A.lgP) - 1) >> A.lgP) * nbw < 256) --A.lgP;
     }
     A.tens = tens;
-    A.nyqb = P.nyqb ? 1 : 0;
+    A.nyqb = P.dcnq ? 1 : 0;
     A.tcs = (long)P.Hz * P.Hy * P.Kt;
     A.tkx = P.Kt;
     A.tw = tw;
@@ -1109,9 +1109,9 @@ int sgspm_plan(const sgspm_params* p, void* hip_stream, sgspm_plan_t* out) {
   P->zeeman = p->terms & SGSPM_TERM_ZEEMAN;
   P->has_mid = p->nz > 1 && p->ny > 1;
   // only where every pass over the spectra supports it: the single-precision
-  // 512-point y pass (ny = 256) and the 64-point z convolution (nz = 32), rows of
-  // x bins with 16 slots of padding (nx a multiple of 16)
-  P->nyqb = !P->fp64 && P->has_mid && p->ny == 256 && p->nz == 32 && p->nx >= 16 && p->nx % 16 == 0 &&
+  // 512-point y pass (ny = 256) and the 64-point z convolution (nz = 32), rows
+  // of x bins with 16 slots of padding (nx a multiple of 16)
+  P->dcnq = !P->fp64 && P->has_mid && p->ny == 256 && p->nz == 32 && p->nx >= 16 && p->nx % 16 == 0 &&
             P->Kxp == P->Kx - 1 + 16;
   P->yz = yz_reg_plane(p->ny, p->nz) ||
           (long)p->ny * p->nz <= (P->fp64 ? yz_max_plane<double>() : yz_max_plane<float>());
