@@ -870,7 +870,7 @@ __global__ __launch_bounds__(NT) void k_col_fft(const ColFft<T> A) {
 // W_512^{t k2}; transpose; thread (k2, t0) takes t = t0 + 8 t1, DFT-8 over t1
 // and W_64^{t0 ka}; transpose; thread (k2, ka) finishes with a DFT-8 over t0
 // and owns k = k2 + 8 ka + 64 kb.  The inverse runs the same digits backwards.
-// LDS rows are padded (S = 8P + 1) against bank conflicts.
+// LDS rows are padded (fft512_stride) against bank conflicts.
 template <typename T, int P> constexpr int fft512_stride() { return 8 * P + (sizeof(T) == 4 ? 8 : 4); }
 
 template <typename T, int P, bool INV>
@@ -879,8 +879,12 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
   // row stride of the transposes: 8 mod 32 complex (float) or 4 mod 16 (double), so the
   // 8 rows x P columns a half-wave touches fall in distinct banks
   constexpr int S = fft512_stride<T, P>();
-  cx<T>* w = reinterpret_cast<cx<T>*>(smem_raw);  // W_512^i
-  cx<T>* xb = w + 512;                             // [64][S]
+  // double precision takes its twiddles as powers of one or two table entries
+  // (W^k by repeated products: k - 1 roundings of 2^-53), so that without the
+  // 8 KiB table in LDS four workgroups fit a CU
+  constexpr bool TWR = sizeof(T) == 8;
+  cx<T>* w = reinterpret_cast<cx<T>*>(smem_raw);  // W_512^i (single precision)
+  cx<T>* xb = TWR ? w : w + 512;                   // [64][S]
   const int tid = threadIdx.x;
   const int q = tid % P;
   const int t = tid / P;  // 0..63
@@ -893,10 +897,9 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
   // the blocked layout.  The forward output splits by Hermitian symmetry; the
   // inverse packs C0 + i CN on input and returns c0 + i cN.  So ni / 8
   // workgroups cover ni + 1 columns: 1024 instead of 1056 for 257 columns, one
-  // round at four per CU.  Single precision only: in double precision (three
-  // workgroups per CU) no round is saved.
-  constexpr bool CAN_PACK = sizeof(T) == 4;
-  const bool pk = CAN_PACK && A.pack && bk.x == 0;
+  // round at four per CU (two rounds of 1024 instead of three in double
+  // precision, with P = 4).
+  const bool pk = A.pack && bk.x == 0;
   const bool pkl = pk && q == 0;
   const int b = bk.y;
   // byte offsets from the uniform pencil-set bases (inactive lanes read kx = ni - 1)
@@ -906,20 +909,36 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
   const unsigned ioff = (unsigned)(b * A.sb_in + min(kx, A.ni - 1)) * CB, isa = (unsigned)A.sa_in * CB;
   const unsigned ooff = (unsigned)(b * A.sb_out + kx) * CB, osa = (unsigned)A.sa_out * CB;
   // the y-level Nyquist column (blocked layout: row r at (r & ~15, ni + (r & 15))),
-  // for the inverse staged through LDS for the packed lane, one entry per
-  // thread.  Entry i sits in the padding of transpose row i % 64 (columns 8 P +
-  // i / 64, which no transpose touches), so no barrier separates it from the
-  // transposes.
+  // staged through LDS for or from the packed lane, 512 / (64 P) entries per
+  // thread.  With 8 padding entries per transpose row (single precision), entry
+  // i sits in the padding of row i % 64 (columns 8 P + i / 64, which no
+  // transpose touches), so no barrier separates it from the transposes;
+  // otherwise it sits in the transpose buffer, behind a barrier each way.
   const unsigned nbase_in = (unsigned)(b * A.sb_in + A.ni) * CB, nbase_out = (unsigned)(b * A.sb_out + A.ni) * CB;
   auto noff_in = [&](int r) { return nbase_in + (unsigned)(r & ~15) * isa + (unsigned)(r & 15) * CB; };
   auto noff_out = [&](int r) { return nbase_out + (unsigned)(r & ~15) * osa + (unsigned)(r & 15) * CB; };
-  static_assert(!CAN_PACK || S - 8 * P >= 8, "8 padding entries per transpose row");
-  auto xn = [&](int i) -> cx<T>& { return xb[(i & 63) * S + 8 * P + (i >> 6)]; };
+  constexpr bool PADST = S - 8 * P >= 8;
+  constexpr int NPT = 512 / (64 * P);
+  static_assert(NPT == 1 || NPT == 2, "one or two staged entries per thread");
+  auto xn = [&](int i) -> cx<T>& { return PADST ? xb[(i & 63) * S + 8 * P + (i >> 6)] : xb[i]; };
   constexpr bool inv = INV;
-  auto W = [&](int e) {  // W_512^{e} (conjugated for the inverse)
+  auto W = [&](int e) {  // W_512^{e} (conjugated for the inverse), from the LDS table
     cx<T> v = w[e & 511];
     if (inv) v.y = -v.y;
     return v;
+  };
+  auto G = [&](int e) {  // the same from the global table
+    cx<T> v = A.tw[(e & 511) << (A.lgTw - 9)];
+    if (inv) v.y = -v.y;
+    return v;
+  };
+  // v[j] *= a b^j for j = j0..7 (b^j by repeated products)
+  auto tw_pow = [](cx<T>(&v)[8], cx<T> a, cx<T> b, int j0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j >= j0) v[j] = cmul(v[j], a);
+      a = cmul(a, b);
+    }
   };
   // the pencil first, then the W table: one round trip to memory
   cx<T> v[8];
@@ -936,19 +955,35 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
       v[kb] = k < A.n_in ? ld_off(in, ioff + (unsigned)k * isa) : zero<T>();
     }
   }
-  if constexpr (CAN_PACK && INV) {
-    static_assert(64 * P == 512, "one table entry per thread");
-    // the staging load is unconditional: other workgroups re-read their own
+  // twiddle bases of this thread (double precision): forward W^t and W^(8 (t & 7)),
+  // inverse W^(8 (t & 7)), W^((t & 7) (t >> 3)) and W^(8 (t >> 3))
+  cx<T> tb0{}, tb1{}, tb2{};
+  if constexpr (TWR) {
+    tb0 = inv ? G(8 * (t & 7)) : G(t);
+    tb1 = inv ? G((t & 7) * (t >> 3)) : G(8 * (t & 7));
+    if (inv) tb2 = G(8 * (t >> 3));
+  }
+  if constexpr (INV) {
+    // the staging loads are unconditional: other workgroups re-read their own
     // first element (a valid address, the value unused), since a branch around
-    // the load makes the compiler wait for it there.  Rows past n_in are masked
+    // a load makes the compiler wait for it there.  Rows past n_in are masked
     // where the packed lane reads them.
-    const cx<T> nq = ld_off(in, pk ? noff_in(min(tid, A.n_in - 1)) : ioff);
-    const cx<T> wv = A.tw[tid << (A.lgTw - 9)];
+    const int r1 = tid + 64 * P;
+    const cx<T> nq0 = ld_off(in, pk ? noff_in(min(tid, A.n_in - 1)) : ioff);
+    const cx<T> nq1 = NPT == 2 ? ld_off(in, pk ? noff_in(min(r1, A.n_in - 1)) : ioff) : zero<T>();
+    cx<T> wv{};
+    if constexpr (!TWR) wv = A.tw[tid << (A.lgTw - 9)];
     // every load above is issued before the first LDS store waits for one
     __builtin_amdgcn_sched_barrier(0);
-    w[tid] = wv;
-    if (pk) xn(tid) = nq;
-  } else {
+    if constexpr (!TWR) {
+      static_assert(TWR || 64 * P == 512, "one table entry per thread");
+      w[tid] = wv;
+    }
+    if (pk) {
+      xn(tid) = nq0;
+      if (NPT == 2) xn(r1) = nq1;
+    }
+  } else if constexpr (!TWR) {
     for (int i = tid; i < 512; i += 64 * P) w[i] = A.tw[i << (A.lgTw - 9)];
   }
   __syncthreads();
@@ -960,12 +995,16 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
       v[kb] = mk<T>(v[kb].x - cn.y, v[kb].y + cn.x);
     }
   }
+  if (INV && !PADST && pk) __syncthreads();  // the first transpose overwrites the staging
   if (!inv) {
     if (A.n_in <= 256) dft8_lo4(v, false);  // zero-padded half: rows t + 64 m, m >= 4
     else dft8(v, false);
     const int t0 = t & 7, t1 = t >> 3;
+    if constexpr (TWR) tw_pow(v, mk<T>((T)1, (T)0), tb0, 1);
+    else {
 #pragma unroll
-    for (int k2 = 1; k2 < 8; ++k2) v[k2] = cmul(v[k2], W(t * k2));
+      for (int k2 = 1; k2 < 8; ++k2) v[k2] = cmul(v[k2], W(t * k2));
+    }
 #pragma unroll
     for (int k2 = 0; k2 < 8; ++k2) xb[(k2 * 8 + t0) * S + t1 * P + q] = v[k2];
     __syncthreads();
@@ -974,8 +1013,11 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
 #pragma unroll
       for (int u1 = 0; u1 < 8; ++u1) v[u1] = xb[(k2 * 8 + u0) * S + u1 * P + q];
       dft8(v, false);
+      if constexpr (TWR) tw_pow(v, mk<T>((T)1, (T)0), tb1, 1);
+      else {
 #pragma unroll
-      for (int ka = 1; ka < 8; ++ka) v[ka] = cmul(v[ka], W(8 * u0 * ka));
+        for (int ka = 1; ka < 8; ++ka) v[ka] = cmul(v[ka], W(8 * u0 * ka));
+      }
       __syncthreads();
 #pragma unroll
       for (int ka = 0; ka < 8; ++ka) xb[(k2 * 8 + ka) * S + u0 * P + q] = v[ka];
@@ -986,6 +1028,8 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
 #pragma unroll
       for (int u0 = 0; u0 < 8; ++u0) v[u0] = xb[(k2 * 8 + ka) * S + u0 * P + q];
       dft8(v, false);
+      const int s0 = k2 + 8 * ka, s1 = (64 - s0) & 63;
+      cx<T> cn[8];  // the packed lane's FFT(cN)
       if (pkl) {
         // Z = FFT(c0 + i cN): FFT(c0)[k] = (Z[k] + conj Z[-k]) / 2 and
         // FFT(cN)[k] = (Z[k] - conj Z[-k]) / 2i.  With s = k2 + 8 ka, Z[-k] is
@@ -993,7 +1037,6 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
         // thread for s = 0); this lane repeats that thread's last DFT from the
         // same LDS rows instead of waiting for it at a barrier.  FFT(c0) leaves
         // with the other lanes' outputs, FFT(cN) through LDS.
-        const int s0 = k2 + 8 * ka, s1 = (64 - s0) & 63;
         cx<T> u[8];
 #pragma unroll
         for (int u0 = 0; u0 < 8; ++u0) u[u0] = xb[((s1 & 7) * 8 + (s1 >> 3)) * S + u0 * P + q];
@@ -1002,8 +1045,9 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
           const cx<T> Z = v[kb], Zm = s0 ? u[7 - kb] : v[(8 - kb) & 7];
+          cn[kb] = mk<T>((Z.y + Zm.y) * (T)0.5, (Zm.x - Z.x) * (T)0.5);
           c0[kb] = mk<T>((Z.x + Zm.x) * (T)0.5, (Z.y - Zm.y) * (T)0.5);
-          xn(s0 + 64 * kb) = mk<T>((Z.y + Zm.y) * (T)0.5, (Zm.x - Z.x) * (T)0.5);
+          if (PADST) xn(s0 + 64 * kb) = cn[kb];
         }
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) v[kb] = c0[kb];
@@ -1018,15 +1062,27 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
       if (pk) {
         // the Nyquist column, one row per thread: whole lines of the blocked
         // layout instead of scattered 8-byte stores
+        if constexpr (!PADST) {
+          __syncthreads();  // every thread has read the transpose buffer
+          if (pkl) {
+#pragma unroll
+            for (int kb = 0; kb < 8; ++kb) xn(s0 + 64 * kb) = cn[kb];
+          }
+        }
         __syncthreads();
-        if (tid < A.n_out) st_off(out, noff_out(tid), xn(tid));
+#pragma unroll
+        for (int j = 0; j < NPT; ++j)
+          if (tid + j * 64 * P < A.n_out) st_off(out, noff_out(tid + j * 64 * P), xn(tid + j * 64 * P));
       }
     }
   } else {
     const int k2 = t >> 3, ka = t & 7;
     dft8(v, true);  // index t0
+    if constexpr (TWR) tw_pow(v, mk<T>((T)1, (T)0), tb0, 1);
+    else {
 #pragma unroll
-    for (int t0 = 1; t0 < 8; ++t0) v[t0] = cmul(v[t0], W(8 * t0 * ka));
+      for (int t0 = 1; t0 < 8; ++t0) v[t0] = cmul(v[t0], W(8 * t0 * ka));
+    }
 #pragma unroll
     for (int t0 = 0; t0 < 8; ++t0) xb[(k2 * 8 + t0) * S + ka * P + q] = v[t0];
     __syncthreads();
@@ -1035,8 +1091,11 @@ __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
 #pragma unroll
       for (int a = 0; a < 8; ++a) v[a] = xb[(kk2 * 8 + t0) * S + a * P + q];
       dft8(v, true);  // index t1
+      if constexpr (TWR) tw_pow(v, tb1, tb2, 0);
+      else {
 #pragma unroll
-      for (int t1 = 0; t1 < 8; ++t1) v[t1] = cmul(v[t1], W((t0 + 8 * t1) * kk2));
+        for (int t1 = 0; t1 < 8; ++t1) v[t1] = cmul(v[t1], W((t0 + 8 * t1) * kk2));
+      }
       __syncthreads();
 #pragma unroll
       for (int t1 = 0; t1 < 8; ++t1) xb[(t0 + 8 * t1) * S + kk2 * P + q] = v[t1];
@@ -2369,12 +2428,11 @@ template <typename T> int launch_col_fft(const ColFft<T>& a, int nbatch, int nch
     // packed DC and Nyquist columns: the kernel's ni counts the columns before
     // the Nyquist column, which is column ni
     ColFft<T> b = a;
-    // (the plan requests packing, and the blocked Nyquist layout it implies, in
-    // single precision only)
-    b.pack = sizeof(T) == 4 && a.pack && a.ni > 1;
+    b.pack = a.pack && a.ni > 1;
     if (b.pack) b.ni = a.ni - 1;
     dim3 grid(ceil_div(b.ni, P), nbatch, nch);
-    const size_t lds = (512 + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
+    // the twiddle table (single precision) and the transpose buffer
+    const size_t lds = ((sizeof(T) == 4 ? 512 : 0) + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
     if (a.inv) hipLaunchKernelGGL((k_fft512<T, P, true>), grid, dim3(64 * P), lds, s, b);
     else hipLaunchKernelGGL((k_fft512<T, P, false>), grid, dim3(64 * P), lds, s, b);
     return SGSPM_KC_FFT512;

@@ -1108,10 +1108,10 @@ int sgspm_plan(const sgspm_params* p, void* hip_stream, sgspm_plan_t* out) {
   P->stray = p->terms & SGSPM_TERM_STRAY;
   P->zeeman = p->terms & SGSPM_TERM_ZEEMAN;
   P->has_mid = p->nz > 1 && p->ny > 1;
-  // only where every pass over the spectra supports it: the single-precision
-  // 512-point y pass (ny = 256) and the 64-point z convolution (nz = 32), rows
-  // of x bins with 16 slots of padding (nx a multiple of 16)
-  P->dcnq = !P->fp64 && P->has_mid && p->ny == 256 && p->nz == 32 && p->nx >= 16 && p->nx % 16 == 0 &&
+  // only where every pass over the spectra supports it: the 512-point y pass
+  // (ny = 256) and the 64-point z convolution (nz = 32), rows of x bins with 16
+  // slots of padding (nx a multiple of 16)
+  P->dcnq = P->has_mid && p->ny == 256 && p->nz == 32 && p->nx >= 16 && p->nx % 16 == 0 &&
             P->Kxp == P->Kx - 1 + 16;
   P->yz = yz_reg_plane(p->ny, p->nz) ||
           (long)p->ny * p->nz <= (P->fp64 ? yz_max_plane<double>() : yz_max_plane<float>());
