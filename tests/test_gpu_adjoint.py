@@ -86,9 +86,11 @@ def test_adjoint_step_fp32(env):
     assert e_l <= 1e-5 and e_h <= 1e-5 and e_a <= 1e-5
 
 
-def test_adjoint_step_fp32_blocked_nyquist(env):
-    """FP32 adjoint step on a 16x256x32 block, whose stray-field passes keep the
-    Nyquist column in the blocked layout and pack it with the DC column."""
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_adjoint_step_blocked_nyquist(env, prec):
+    """Adjoint step on a 16x256x32 block, whose stray-field passes carry the DC and
+    Nyquist columns packed at the x level and the Nyquist column of the y level
+    in the blocked layout."""
     torch, sg = env
     n = (16, 256, 32)
     rng = np.random.default_rng(203)
@@ -96,17 +98,20 @@ def test_adjoint_step_fp32_blocked_nyquist(env):
     lam = rng.normal(size=m0.shape)
     B = (5e-3, 1e-3, 0.0)
     alpha = 0.02
-    plan = gpu_plan_si(sg, n, CELL, DT, ALL, 0)
-    lam_d = to_dev(torch, lam, 0)
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, prec)
+    lam_d = to_dev(torch, lam, prec)
     grad = torch.zeros(4, dtype=torch.float64, device="cuda")
-    plan.adjoint_step(to_dev(torch, m0, 0), alpha, B, lam_d, grad)
+    plan.adjoint_step(to_dev(torch, m0, prec), alpha, B, lam_d, grad)
     torch.cuda.synchronize()
     P = oracle_problem_si(n, CELL, DT, ALL)
-    lref, dh, da = oadj.adjoint_step(P, rounded_like(m0, 0), alpha, oracle_field_si(B, ALL), rounded_like(lam, 0))
+    lref, dh, da = oadj.adjoint_step(P, rounded_like(m0, prec), alpha, oracle_field_si(B, ALL),
+                                     rounded_like(lam, prec))
     g = grad.cpu().numpy()
     e_l, e_h, e_a = _rel(lam_d.cpu().numpy(), lref), _rel(g[:3], dh * FSCALE), abs(g[3] - da) / abs(da)
-    print(f"16x256x32 fp32 adjoint step: rel err lam {e_l:.2e}, dh_e {e_h:.2e}, dalpha {e_a:.2e}")
-    assert e_l <= 1e-5 and e_h <= 1e-5 and e_a <= 1e-5
+    print(f"16x256x32 {'fp64' if prec else 'fp32'} adjoint step: rel err lam {e_l:.2e}, dh_e {e_h:.2e}, "
+          f"dalpha {e_a:.2e}")
+    bar = 1e-10 if prec == 1 else 1e-5
+    assert e_l <= bar and e_h <= bar and e_a <= bar
 
 
 def _loss_grads_gpu(torch, sg, plan, m0, B, alpha, target, ckpt, prec):
