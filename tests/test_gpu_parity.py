@@ -61,12 +61,14 @@ def test_heat_solve(env, n, prec):
         assert np.abs(g - ref).max() <= tol * np.abs(r).max(), (n, s)
 
 
-# (16|32|256, 256, 32) in FP32 keep the Nyquist column of their spectra in the
-# blocked layout and pack it with the DC column in the 512-point y pass
+# (16|32|256, 256, 32) pack the real DC and Nyquist x bins into bin 0 and keep the
+# y-level Nyquist column in the blocked layout; (8, 256, 32) runs the same
+# 512-point y pass and 64-point convolution without that packing (nx not a
+# multiple of 16)
 STRAY_SHAPES = [(8, 4, 2), (16, 8, 1), (4, 4, 4), (32, 1, 1), (1, 1, 1), (2, 2, 2), (1, 8, 4), (4, 1, 4),
                 (128, 64, 1), (64, 32, 8), (512, 32, 4), (128, 128, 1), (16, 8, 32), (16, 32, 1), (4, 1, 32),
                 (256, 4, 32), (16, 256, 2), (8, 256, 4), (32, 256, 32), (8, 2, 32), (16, 256, 32),
-                (256, 256, 32)]
+                (256, 256, 32), (8, 256, 32)]
 
 
 @functools.lru_cache(maxsize=2)
