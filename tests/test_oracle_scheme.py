@@ -108,6 +108,46 @@ def test_macrospin_closed_form_first_order():
     assert np.all((orders > 0.9) & (orders < 1.1)), (errs, orders)
 
 
+def _ll_rhs(P, m, alpha, he):
+    """Semi-discrete Landau-Lifshitz right-hand side of §2 in the form the macrospin
+    test fixes: m_t = -m x h - alpha m x (m x h), h = h_eff(m)."""
+    h = scheme.effective_field(P, m, he)
+    mxh = np.cross(m, h, axis=0)
+    return -mxh - alpha * np.cross(m, mxh, axis=0)
+
+
+def test_first_order_with_all_fields_against_rk4():
+    """SGSPM with exchange, anisotropy, stray field and applied field on a small block
+    converges at first order in dt to the semi-discrete equation, integrated here by
+    classical RK4 with a small step (an integrator that shares nothing with the
+    method's stages).  This pins the order in which the stray field enters the sweeps
+    (latest-state reading) against the equation itself, which the paper's printed
+    (exchange-only) numbers cannot."""
+    n = (4, 4, 2)
+    he = (0.05, -0.02, 0.1)
+    alpha, T = 0.1, 0.4
+    m0 = _random_unit(n[::-1], 7)
+    Pref = scheme.Problem(n=n, h=(1.0, 1.0, 1.0), eps=0.5, dt=1.0, Q=0.3, stray=True)
+    m = m0.copy()
+    dtr = 1e-3
+    for _ in range(int(round(T / dtr))):
+        k1 = _ll_rhs(Pref, m, alpha, he)
+        k2 = _ll_rhs(Pref, m + 0.5 * dtr * k1, alpha, he)
+        k3 = _ll_rhs(Pref, m + 0.5 * dtr * k2, alpha, he)
+        k4 = _ll_rhs(Pref, m + dtr * k3, alpha, he)
+        m = m + dtr / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+    ref = m
+    errs = []
+    for dt in (0.02, 0.01, 0.005):
+        P = scheme.Problem(n=n, h=(1.0, 1.0, 1.0), eps=0.5, dt=dt, Q=0.3, stray=True)
+        mm = m0.copy()
+        for _ in range(int(round(T / dt))):
+            mm = scheme.sgspm_step(P, mm, alpha, he)
+        errs.append(float(np.abs(mm - ref).max()))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all((orders > 0.85) & (orders < 1.2)), (errs, orders)
+
+
 def test_fixed_points():
     shape = (2, 3, 4)
     P = scheme.Problem(n=shape[::-1], h=(1.0, 1.0, 1.0), eps=1.0, dt=0.1)
