@@ -68,7 +68,7 @@ def test_heat_solve(env, n, prec):
 STRAY_SHAPES = [(8, 4, 2), (16, 8, 1), (4, 4, 4), (32, 1, 1), (1, 1, 1), (2, 2, 2), (1, 8, 4), (4, 1, 4),
                 (128, 64, 1), (64, 32, 8), (512, 32, 4), (128, 128, 1), (16, 8, 32), (16, 32, 1), (4, 1, 32),
                 (256, 4, 32), (16, 256, 2), (8, 256, 4), (32, 256, 32), (8, 2, 32), (16, 256, 32),
-                (256, 256, 32), (8, 256, 32)]
+                (256, 256, 32), (8, 256, 32), (256, 256, 1), (256, 128, 1)]
 
 
 @functools.lru_cache(maxsize=2)
@@ -174,6 +174,25 @@ def test_full_step_fp64(env, n, method):
     P = oracle_problem_si(n, CELL, DT, ALL)
     ref = _run_oracle(P, m0, 0.02, [oracle_field_si(b, ALL) for b in B], method)
     assert np.abs(got - ref).max() <= 1e-10
+
+
+# rows of 256 (the 512-point row kernels), the 512-point y pass with and without
+# the DC/Nyquist packing, the 64-point convolution and the 256x32 register y-z
+# solve, through whole steps from a random start
+@pytest.mark.parametrize("n", [(16, 256, 32), (256, 256, 1), (256, 8, 32)], ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_steps_512_paths(env, n, prec):
+    torch, sg = env
+    shape = (n[2], n[1], n[0])
+    m0 = workloads.random_unit(shape, 106)
+    B = [(5e-3, 1e-3, -2e-3)] * 5
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, prec)
+    got = _run_gpu(plan, torch, m0, 0.02, B, prec)
+    P = oracle_problem_si(n, CELL, DT, ALL)
+    ref = _run_oracle(P, rounded_like(m0, prec), 0.02, [oracle_field_si(b, ALL) for b in B])
+    err = np.abs(got - ref).max()
+    print(f"steps {'fp64' if prec else 'fp32'} {n}: max|m - m_oracle| after 5 steps = {err:.3e}")
+    assert err <= (1e-10 if prec == 1 else 1e-5)
 
 
 @pytest.mark.parametrize("terms", [("exchange",), ("exchange", "aniso"), ("stray",), ("exchange", "zeeman"),
