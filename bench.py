@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (hardware-counter calibration)")
+    ap.add_argument("--copy-bw-mb", type=int, default=0,
+                    help="first time 20 plain device copies of this many MiB (a practical HBM ceiling)")
     ap.add_argument("--skip-fp64", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -119,6 +121,22 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(f"[bench] copy calibration: {nb} bytes read, {nb} bytes written", file=sys.stderr, flush=True)
+        del src, dst
+    if args.copy_bw_mb:
+        nb = args.copy_bw_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 20
+        print(f"[bench] device copy of {args.copy_bw_mb} MiB: {us:.1f} us, {2 * nb / us / 1e3:.0f} GB/s read + write",
+              file=sys.stderr, flush=True)
         del src, dst
     c = workloads.config(args.config)
     N = c.cells
