@@ -42,7 +42,7 @@ WORKLOAD_TEXT = {
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_block-256x256x32.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2606_28113_amd", "csrc", f) for f in ("kernels.hip", "kernels.h", "fft_lds.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2606_28113_amd", "csrc", f) for f in ("kernels.hip", "kernels.h", "fft_lds.h", "plan.hip")]
 
 
 def kernel_source_hash():
@@ -57,7 +57,8 @@ def kernel_source_hash():
 def measured_traffic(kernel, dtype, workload):
     """HBM bytes per launch of `kernel` from the committed hardware-counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by the copy calibration), or None when the
-    summary is absent, covers another workload, or the kernel sources changed since."""
+    summary is absent, covers another workload, or the device sources (kernels, their
+    launchers and the plan that sets their launch parameters) changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     src = kernel_source_hash()
