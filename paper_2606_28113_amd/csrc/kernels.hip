@@ -2340,9 +2340,13 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
   }
 }
 
-// pencils (pairs of rows) per workgroup of the 512-point row kernels (16 measured
-// slower in single precision: larger barriers, one workgroup per CU)
-template <typename T> constexpr int row512_pencils() { return sizeof(T) == 4 ? 8 : 4; }
+// pencils (pairs of rows) per workgroup of the 512-point row kernels.  Single
+// precision: 8 for the forward kernel (16 measured slower: larger barriers, one
+// workgroup per CU), 4 for the inverse kernel, whose Gauss-Seidel variants hold
+// 110-142 VGPRs: smaller workgroups pack the CU more finely (8 measured 8% slower
+// for one channel, 25% for two)
+template <typename T> constexpr int row_fwd512_pencils() { return sizeof(T) == 4 ? 8 : 4; }
+template <typename T> constexpr int row_inv512_pencils() { return 4; }
 
 template <typename T> bool row256(int lgN, int lgLc, int lgLr, bool c2r, bool r2c) {
   return lgN == 8 && (!c2r || lgLc == 9) && (!r2c || lgLr == 9);
@@ -2355,7 +2359,7 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
     r2c = r2c || a.xout[c];
   }
   if (row256<T>(a.lgN, a.lgLc, a.lgLr, c2r, r2c)) {
-    constexpr int P = row512_pencils<T>();
+    constexpr int P = row_fwd512_pencils<T>();
     const size_t lds = (512 + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
     const dim3 grid(ceil_div(a.nrows, 2 * P), 1, nch);
     RowFwd<T> b = a;
@@ -2373,7 +2377,7 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
 
 template <typename T, int NCH, bool XM>
 void launch_row_inv512_op(const RowInv<T>& a, dim3 grid, size_t lds, hipStream_t s) {
-  constexpr int P = row512_pencils<T>();
+  constexpr int P = row_inv512_pencils<T>();
   const dim3 blk(64 * P);
   if constexpr (NCH < 3) {
     if (a.op == ROW_OP_GS) {
@@ -2401,7 +2405,7 @@ template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
   const bool mode_ok = (a.op == ROW_OP_GS && a.nch < 3 && !(a.Pch < 0 && a.Rch < 0)) ||
                        (a.op == ROW_OP_PROJECT && a.nch == 3) || a.op == ROW_OP_NONE;
   if (mode_ok && row256<T>(a.lgN, a.lgLr, a.lgLr, false, a.xout != nullptr)) {
-    constexpr int P = row512_pencils<T>();
+    constexpr int P = row_inv512_pencils<T>();
     const size_t lds = (512 + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
     const dim3 grid(ceil_div(a.nrows, 2 * P));
     launch_row_inv512_mode<T>(a, grid, lds, s);
