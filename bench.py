@@ -7,11 +7,16 @@ alpha = 1e-3, dt = 0.05 ps), FP32 bulk.  One "step" is one whole SGSPM step
 (both Gauss-Seidel sweeps, damping, projection) over the grid; the metric is
 cell-updates per second (cells x steps / wall) with inputs resident in HBM.
 
-Also reported: the FP64 comparator on the same GPU, the adjoint step, the
-per-kernel-class time and algorithmic bandwidth of the timed steps (HIP events
-around every launch, a second timed pass), the dominant kernel against the HBM
-roofline, the FP64 CPU oracle timed on the host, and the max |m - m_oracle| of
-the first step.
+The forward step is timed over 5 passes of K steps each (HIP-stream
+synchronisation around each pass); ms_per_step is the median pass.  Also
+reported: the FP64 comparator on the same GPU, the adjoint step (FP32 and
+FP64), the full checkpointed backward pass of the workload's adjoint length
+(segment recompute included), the per-kernel-class time and launch-level
+bandwidth of the timed steps (HIP events around every launch, a further timed
+pass), the dominant kernel and the whole step against the HBM roofline on the
+algorithmic byte count (each field read and written once per Gauss-Seidel
+stage plus the demagnetising-tensor spectrum reads), the FP64 CPU oracle timed
+on the host, and the max |m - m_oracle| of the first step.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config block-256x256x32]
 """
@@ -35,7 +40,7 @@ WORKLOAD_TEXT = {
     "block-256x256x32": "256x256x32 block, 4 nm cells, exchange+anisotropy+stray (padded 512x512x64 FFT)+rotating 10 mT, "
           "alpha 1e-3, dt 0.05 ps",
     "adjoint-film-128x128": "128x128x1 film, 4 nm cells, all fields, alpha 0.01, dt 0.1 ps",
-    "wall-strip-512x32x4": "512x32x4 Neel-wall strip, 4 nm cells, all fields, 10 mT, alpha 1e-3, dt 0.1 ps",
+    "wall-strip-512x32x4": "512x32x4 Neel-wall strip, 4 nm cells, all fields, 5 mT, alpha 0.01, dt 0.1 ps",
     "film-128x64": "128x64x1 film, 4 nm cells, all fields, 5 mT, alpha 0.01, dt 0.1 ps",
     "mf-film-32x32": "32x32x1 exchange-only film, manufactured forcing off, alpha 0.01, dt 1e-3",
 }
@@ -72,6 +77,26 @@ def measured_traffic(kernel, dtype, workload):
     return None
 
 
+# Algorithmic bytes of one SGSPM step in single precision (double: twice): every
+# field read once and written once per Gauss-Seidel stage A-F (stage A reads m2,
+# m3 and writes g2, g3 and ... : 20 B per cell; B-E 28 each; F 32), 164 B per
+# cell, plus the demagnetising-tensor spectrum: each output of a convolution
+# reads its three tensor components once, 23 component reads per step (A: the
+# outputs 2 and 3, five distinct components; B, C, D, E: one output, three; F:
+# all six), each over the folded octant (nx+1)(ny+1)(nz+1).
+FIELD_BYTES_PER_CELL = 164
+TENSOR_READS_PER_STEP = 23
+CONV_LAUNCHES_PER_STEP = 6
+
+
+def algorithmic_step_bytes(c, dbytes):
+    nx, ny, nz = c.n
+    octant = (nx + 1) * (ny + 1) * (nz + 1 if nz > 1 else 1)
+    field = FIELD_BYTES_PER_CELL * c.cells * dbytes // 4
+    tensor = TENSOR_READS_PER_STEP * octant * dbytes
+    return field, tensor
+
+
 def make_plan(sg, c, precision):
     kw = dict(nx=c.n[0], ny=c.n[1], nz=c.n[2], dx=c.h[0], dy=c.h[1], dz=c.h[2], dt=c.dt, precision=precision)
     if c.units == "si":
@@ -85,9 +110,71 @@ def time_steps(torch, plan, m, alpha, B, first, count):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for n in range(first, first + count):
-        plan.step(m, alpha, B[n])
+        plan.step(m, alpha, B[n % len(B)])
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3 / count
+
+
+def kernel_breakdown(stats, steps):
+    out = {}
+    for k, (ms, by, cnt) in stats.items():
+        if cnt:
+            out[KERNEL_NAMES[k]] = {"ms_per_step": ms / steps, "launches_per_step": cnt / steps,
+                                    "avg_us": 1e3 * ms / cnt, "launch_level_GBps": by / (ms * 1e-3) / 1e9,
+                                    "launch_level_MB_per_launch": by / cnt / 1e6}
+    return out
+
+
+def time_adjoint(torch, sg, c, precision, m0, B, alpha, KA):
+    """ms per adjoint step (each recomputes its forward step) and its kernel breakdown."""
+    pa = make_plan(sg, c, precision)
+    dt_ = torch.float32 if precision == sg.FP32 else torch.float64
+    ma = torch.tensor(m0, dtype=dt_, device="cuda")
+    lam = torch.zeros_like(ma)
+    grad = torch.zeros(4, dtype=torch.float64, device="cuda")
+    pa.adjoint_step(ma, alpha, B[0], lam, grad)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(KA):
+        pa.adjoint_step(ma, alpha, B[n], lam, grad)
+    torch.cuda.synchronize()
+    msa = (time.perf_counter() - t0) * 1e3 / KA
+    pa.timing(True)
+    for n in range(KA):
+        pa.adjoint_step(ma, alpha, B[n], lam, grad)
+    stats = pa.timing_read()
+    pa.timing(False)
+    pa.close()
+    return msa, kernel_breakdown(stats, KA)
+
+
+def time_backward(torch, sg, c, precision, m0, alpha, S, K):
+    """Forward with checkpoints every K steps and the full backward pass (segment
+    recompute plus S adjoint steps) of the terminal misfit L = mean (m_S - target)^2."""
+    plan = make_plan(sg, c, precision)
+    dt_ = torch.float32 if precision == sg.FP32 else torch.float64
+    B = workloads.field_schedule(c, S)
+    target = torch.tensor(workloads.target_state(c) if c.name in ("adjoint-film-128x128", "block-256x256x32")
+                          else workloads.random_unit(c.shape, 51), dtype=dt_, device="cuda")
+    m = torch.tensor(m0, dtype=dt_, device="cuda", requires_grad=True)
+    he = torch.tensor(B, dtype=torch.float64, requires_grad=True)
+    a = torch.tensor(alpha, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = sg.SGSPMFunction.apply(m, he, a, plan, K)
+    L = torch.mean((out - target) ** 2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    plan.close()
+    ok = bool(torch.isfinite(m.grad).all()) and bool(np.isfinite(float(a.grad)))
+    return {"steps": S, "ckpt_every": K, "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
+            "backward_value": c.cells * S / (t2 - t1), "unit": "cell-updates/s",
+            "note": "backward = recompute of every segment from its checkpoint plus S adjoint steps "
+                    "(each recomputing its forward step); value = cells x S / backward wall",
+            "grads_finite": ok}
 
 
 def main():
@@ -98,6 +185,9 @@ def main():
     ap.add_argument("--config", default="block-256x256x32")
     ap.add_argument("--fp64-steps", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=20)
+    ap.add_argument("--passes", type=int, default=5, help="timed passes of K steps (median reported)")
+    ap.add_argument("--backward-steps", type=int, default=-1,
+                    help="steps of the timed checkpointed backward pass (-1: the workload's adjoint length, 0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (hardware-counter calibration)")
@@ -110,6 +200,7 @@ def main():
               "(sharding across GPUs is described in DESIGN.md, not built)", file=sys.stderr)
         sys.exit(2)
 
+    global np, workloads
     import numpy as np
     import torch
     import paper_2606_28113_amd as sg
@@ -157,28 +248,49 @@ def main():
     m1_32 = m.detach().cpu().numpy().astype(np.float64)
     for n in range(1, 1 + W):
         p32.step(m, alpha, B[n])
-    ms32 = time_steps(torch, p32, m, alpha, B, 1 + W, K)
+    passes = []
+    for _ in range(max(1, args.passes)):
+        passes.append(time_steps(torch, p32, m, alpha, B, 1 + W, K))
+    ms32 = float(np.median(passes))
     p32.check()
-    print(f"[bench] fp32 forward {ms32:.4f} ms/step", file=sys.stderr, flush=True)
-    # second timed pass with per-launch events
+    print(f"[bench] fp32 forward {ms32:.4f} ms/step (median of {len(passes)} passes: "
+          + ", ".join(f"{t:.4f}" for t in passes) + ")", file=sys.stderr, flush=True)
+    # a further timed pass with per-launch events
     p32.timing(True)
     for n in range(1 + W, 1 + W + K):
         p32.step(m, alpha, B[n])
     stats = p32.timing_read()
     p32.timing(False)
-    breakdown = {}
-    for k, (ms, by, cnt) in stats.items():
-        if cnt:
-            breakdown[KERNEL_NAMES[k]] = {"ms_per_step": ms / K, "launches_per_step": cnt / K,
-                                          "avg_us": 1e3 * ms / cnt, "GBps": by / (ms * 1e-3) / 1e9,
-                                          "alg_MB_per_launch": by / cnt / 1e6}
+    breakdown = kernel_breakdown(stats, K)
     dom = max(breakdown, key=lambda k: breakdown[k]["ms_per_step"])
     d = breakdown[dom]
     traffic = measured_traffic(dom, "f32", c.name)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(d["GBps"], 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(d["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "avg_launch_us": round(d["avg_us"], 3), "alg_bytes_per_launch": round(d["alg_MB_per_launch"] * 1e6)}
-    alg_step_bytes = sum(stats[k][1] for k in stats) / K
+    field_b, tensor_b = algorithmic_step_bytes(c, 4)
+    launch_step_bytes = sum(stats[k][1] for k in stats) / K
+    # the dominant kernel's share of the algorithmic bytes: the convolution reads
+    # the tensor spectrum (its spectra are transform intermediates, not counted);
+    # the other kernels move only intermediates or fields counted per stage
+    if dom in ("k_conv64", "k_conv"):
+        alg_launch = tensor_b / CONV_LAUNCHES_PER_STEP
+    else:
+        alg_launch = None
+    avg_s = d["avg_us"] * 1e-6
+    roofline = {"bound": "hbm", "kernel": dom,
+                "achieved": round(alg_launch / avg_s / 1e9, 1) if alg_launch else None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(alg_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4) if alg_launch else None,
+                "traffic": traffic,
+                "avg_launch_us": round(d["avg_us"], 3),
+                "algorithmic_bytes_per_launch": round(alg_launch) if alg_launch else None,
+                "launch_level_bytes_per_launch": round(d["launch_level_MB_per_launch"] * 1e6),
+                "launch_level_GBps": round(d["launch_level_GBps"], 1),
+                "launch_level_frac": round(d["launch_level_GBps"] / HBM_PEAK_GBS, 4),
+                "step": {"algorithmic_bytes": field_b + tensor_b, "field_bytes": field_b, "tensor_bytes": tensor_b,
+                         "GBps": round((field_b + tensor_b) / (ms32 * 1e-3) / 1e9, 1),
+                         "frac": round((field_b + tensor_b) / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "launch_level_bytes": round(launch_step_bytes),
+                         "launch_level_GBps": round(launch_step_bytes / (ms32 * 1e-3) / 1e9, 1),
+                         "launch_level_frac": round(launch_step_bytes / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
     e32 = p32.energy(torch.tensor(m1_32, dtype=torch.float32, device="cuda"), B[0])
     del p32, m
     torch.cuda.empty_cache()
@@ -203,45 +315,36 @@ def main():
         p64.step(m, alpha, B[n])
     stats64 = p64.timing_read()
     p64.timing(False)
-    breakdown64 = {}
-    for k, (ms, by, cnt) in stats64.items():
-        if cnt:
-            breakdown64[KERNEL_NAMES[k]] = {"ms_per_step": ms / K64, "launches_per_step": cnt / K64,
-                                            "avg_us": 1e3 * ms / cnt, "GBps": by / (ms * 1e-3) / 1e9}
+    breakdown64 = kernel_breakdown(stats64, K64)
+    p64.close()
+    del m
+    torch.cuda.empty_cache()
 
-    # ---- adjoint step (FP32), if the library provides it
+    # ---- adjoint steps (FP32 and FP64) from a random cotangent at the workload's start
     adj = None
-    try:
-        if args.adjoint_steps <= 0:
-            raise sg.SGSPMError(0, "adjoint timing skipped (--adjoint-steps 0)")
-        pa = make_plan(sg, c, sg.FP32)
-        ma = torch.tensor(m0, dtype=torch.float32, device="cuda")
-        lam = torch.zeros_like(ma)
-        grad = torch.zeros(4, dtype=torch.float64, device="cuda")
-        pa.adjoint_step(ma, alpha, B[0], lam, grad)
-        torch.cuda.synchronize()
+    if args.adjoint_steps > 0:
         KA = args.adjoint_steps
-        t0 = time.perf_counter()
-        for n in range(KA):
-            pa.adjoint_step(ma, alpha, B[n], lam, grad)
-        torch.cuda.synchronize()
-        msa = (time.perf_counter() - t0) * 1e3 / KA
-        pa.timing(True)
-        for n in range(KA):
-            pa.adjoint_step(ma, alpha, B[n], lam, grad)
-        stats_a = pa.timing_read()
-        pa.timing(False)
-        breakdown_a = {}
-        for k, (ms, by, cnt) in stats_a.items():
-            if cnt:
-                breakdown_a[KERNEL_NAMES[k]] = {"ms_per_step": ms / KA, "launches_per_step": cnt / KA,
-                                                "avg_us": 1e3 * ms / cnt, "GBps": by / (ms * 1e-3) / 1e9}
-        adj = {"value": N / (msa * 1e-3), "unit": "cell-updates/s", "ms_per_step": msa, "steps": KA,
-               "dtype": "f32", "note": "one adjoint step recomputes its forward step internally",
-               "kernels": breakdown_a}
-        del pa, ma, lam
-    except sg.SGSPMError as e:
-        adj = {"value": None, "note": str(e)}
+        adj = {"unit": "cell-updates/s", "steps": KA,
+               "note": "one adjoint step recomputes its forward step internally; cotangent = 0, "
+                       "state = the workload's initial state (the step's work does not depend on the values)"}
+        for name, prec in (("f32", sg.FP32), ("f64", sg.FP64)):
+            msa, bd = time_adjoint(torch, sg, c, prec, m0, B, alpha, KA)
+            adj[name] = {"value": N / (msa * 1e-3), "ms_per_step": msa, "kernels": bd}
+            print(f"[bench] {name} adjoint {msa:.4f} ms/step", file=sys.stderr, flush=True)
+        adj["value"] = adj["f32"]["value"]
+        adj["ms_per_step"] = adj["f32"]["ms_per_step"]
+
+    # ---- full checkpointed backward pass over the workload's adjoint length
+    backward = None
+    SB = args.backward_steps if args.backward_steps >= 0 else (c.adjoint_steps or 0)
+    if SB > 0:
+        KB = c.ckpt_every or max(1, SB // 10)
+        backward = {}
+        for name, prec in (("f32", sg.FP32), ("f64", sg.FP64)):
+            backward[name] = time_backward(torch, sg, c, prec, m0, alpha, SB, KB)
+            torch.cuda.empty_cache()
+            print(f"[bench] {name} backward pass, {SB} steps, checkpoints every {KB}: "
+                  f"{backward[name]['backward_ms']:.1f} ms", file=sys.stderr, flush=True)
 
     # ---- CPU oracle baseline and first-step error
     cpu = None
@@ -285,9 +388,9 @@ def main():
         "fp64": {"value": N / (ms64 * 1e-3), "unit": "cell-updates/s", "ms_per_step": ms64, "steps": K64,
                  "kernels": breakdown64},
         "adjoint": adj,
+        "backward_pass": backward,
         "error_vs_oracle": err,
-        "step_algorithmic_MB": alg_step_bytes / 1e6,
-        "step_algorithmic_GBps": alg_step_bytes / (ms32 * 1e-3) / 1e9,
+        "passes_ms_per_step": passes,
         "kernels": breakdown,
     }
     print(json.dumps(out), flush=True)

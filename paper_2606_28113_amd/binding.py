@@ -13,7 +13,8 @@ FP32, FP64 = 0, 1
 SCHEME_SGS, SCHEME_GS = 0, 1
 
 EXPORTS = ("sgspm_validate", "sgspm_reduced_constants", "sgspm_plan", "sgspm_step", "sgspm_energy",
-           "sgspm_field", "sgspm_stray", "sgspm_heat_solve", "sgspm_adjoint_step", "sgspm_timing",
+           "sgspm_field", "sgspm_stray", "sgspm_heat_solve", "sgspm_adjoint_step",
+           "sgspm_timing",
            "sgspm_timing_read", "sgspm_check", "sgspm_destroy", "sgspm_last_error")
 KERNEL_CLASSES = ("row_fwd", "row_fwd512", "row_inv", "row_inv512", "col_dct", "yz_solve", "yz_reg",
                   "col_fft", "fft512", "conv", "conv64", "other")

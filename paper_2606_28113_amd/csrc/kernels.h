@@ -171,6 +171,15 @@ template <typename T> struct Conv {
   int nyqb;          // S and O hold the Nyquist column ni - 1 in the blocked layout over the batch rows
 };
 
+// Launch-geometry errors.  Every launcher checks, before it launches, the
+// invariants its kernel's indexing relies on (tile capacity, LDS bytes, table
+// lengths, pencil lengths); when one fails it launches nothing and returns
+// LAUNCH_EGEOM, and launch_geom_error() names the kernel and the invariant.
+constexpr int LAUNCH_EGEOM = -100;
+const char* launch_geom_error();
+// LDS of one workgroup on gfx950 (160 KiB per CU)
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
 template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_t s);
 template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s);
 template <typename T> int launch_col_dct(const ColDct<T>& a, int nbatch, int nch, hipStream_t s);

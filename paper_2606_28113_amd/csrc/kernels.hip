@@ -1737,6 +1737,18 @@ __global__ __launch_bounds__(NT) void k_adj_damp(const T* lw, const T* u, const 
 // Launchers
 static inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
+namespace {
+thread_local const char* g_geom = "";
+int geom_fail(const char* what) {
+  g_geom = what;
+  return LAUNCH_EGEOM;
+}
+constexpr int lg2c(int n) { return n <= 1 ? 0 : 1 + lg2c(n >> 1); }
+template <typename T> constexpr int lg_tile_elems() { return lg2c(tile_elems<T>()); }
+}  // namespace
+
+const char* launch_geom_error() { return g_geom; }
+
 // 1 / x: the hardware reciprocal in single precision (within 1 ulp), a correctly
 // rounded division in double
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -2371,6 +2383,15 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
   dim3 grid(ceil_div(a.nrows, rows), 1, nch);
   // twiddles, the tile, the DCT twiddles
   const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1) + ((size_t)1 << a.lgN)) * sizeof(cx<T>);
+  // every transform length and the row length within Lmax (the LDS pitch), and
+  // P Lmax complex values within the tile: each thread then holds its 2 VPT row
+  // values and VPT spectrum values, and every FFT stage its butterflies
+  if (nch < 1 || nch > 3) return geom_fail("k_row_fwd: 1 to 3 channels");
+  if (a.lgLmax < a.lgN || (c2r && a.lgLmax < a.lgLc) || (r2c && a.lgLmax < a.lgLr))
+    return geom_fail("k_row_fwd: a row or transform longer than Lmax");
+  if (a.lgP < 0 || a.lgP + a.lgLmax > lg_tile_elems<T>()) return geom_fail("k_row_fwd: P Lmax beyond the tile");
+  if (a.lgTw < a.lgLmax) return geom_fail("k_row_fwd: twiddle table shorter than Lmax");
+  if (lds > LDS_LIMIT) return geom_fail("k_row_fwd: LDS beyond the limit");
   hipLaunchKernelGGL(k_row_fwd<T>, grid, dim3(NT), lds, s, a);
   return SGSPM_KC_ROW_FWD;
 }
@@ -2415,6 +2436,11 @@ template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
   dim3 grid(ceil_div(a.nrows, rows), 1, 1);
   // twiddles, the tile, the DCT twiddles
   const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1) + ((size_t)1 << a.lgN)) * sizeof(cx<T>);
+  if (a.nch < 1 || a.nch > 3) return geom_fail("k_row_inv: 1 to 3 channels");
+  if (a.lgLmax < a.lgN || (a.xout && a.lgLmax < a.lgLr)) return geom_fail("k_row_inv: a row or transform longer than Lmax");
+  if (a.lgP < 0 || a.lgP + a.lgLmax > lg_tile_elems<T>()) return geom_fail("k_row_inv: P Lmax beyond the tile");
+  if (a.lgTw < a.lgLmax) return geom_fail("k_row_inv: twiddle table shorter than Lmax");
+  if (lds > LDS_LIMIT) return geom_fail("k_row_inv: LDS beyond the limit");
   hipLaunchKernelGGL(k_row_inv<T>, grid, dim3(NT), lds, s, a);
   return SGSPM_KC_ROW_INV;
 }
@@ -2422,11 +2448,19 @@ template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
 template <typename T> int launch_col_dct(const ColDct<T>& a, int nbatch, int nch, hipStream_t s) {
   dim3 grid(ceil_div(a.ni, 2 << a.lgP), nbatch, nch);
   const size_t lds = ((size_t)(1 << a.lgN) + ((size_t)1 << (a.lgP + a.lgN))) * sizeof(cx<T>);
+  if (nch < 1 || nch > 3) return geom_fail("k_col_dct: 1 to 3 channels");
+  if (a.lgP < 0 || a.lgP + a.lgN > lg_tile_elems<T>()) return geom_fail("k_col_dct: P n beyond the tile");
+  if (a.lgTw < a.lgN) return geom_fail("k_col_dct: twiddle table shorter than n");
+  if (lds > LDS_LIMIT) return geom_fail("k_col_dct: LDS beyond the limit");
   hipLaunchKernelGGL(k_col_dct<T>, grid, dim3(NT), lds, s, a);
   return SGSPM_KC_COL_DCT;
 }
 
 template <typename T> int launch_col_fft(const ColFft<T>& a, int nbatch, int nch, hipStream_t s) {
+  if (nch < 1 || nch > 3) return geom_fail("k_col_fft: 1 to 3 channels");
+  if (a.n_in < 1 || a.n_out < 1 || a.n_in > (1 << a.lgL) || a.n_out > (1 << a.lgL))
+    return geom_fail("k_col_fft: input or output longer than the transform");
+  if (a.lgTw < a.lgL) return geom_fail("k_col_fft: twiddle table shorter than the transform");
   if (a.lgL == 9) {
     constexpr int P = sizeof(T) == 4 ? 8 : 4;
     // packed DC and Nyquist columns: the kernel's ni counts the columns before
@@ -2443,6 +2477,8 @@ template <typename T> int launch_col_fft(const ColFft<T>& a, int nbatch, int nch
   }
   dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, nch);
   const size_t lds = ((size_t)(1 << a.lgL) + ((size_t)1 << (a.lgP + a.lgL))) * sizeof(cx<T>);
+  if (a.lgP < 0 || a.lgP + a.lgL > lg_tile_elems<T>()) return geom_fail("k_col_fft: P L beyond the tile");
+  if (lds > LDS_LIMIT) return geom_fail("k_col_fft: LDS beyond the limit");
   hipLaunchKernelGGL(k_col_fft<T>, grid, dim3(NT), lds, s, a);
   return SGSPM_KC_COL_FFT;
 }
@@ -2455,7 +2491,8 @@ template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStrea
   // twiddles, buffer, DCT twiddles of y and z, eigenvalues of y, z and the planes
   const size_t ny = (size_t)1 << a.lgNy, nz = (size_t)1 << a.lgNz;
   const size_t lds = ((size_t)(1 << lgL) + nbuf + ny + nz) * sizeof(cx<T>) + (ny + nz + ((size_t)1 << a.lgPP)) * sizeof(T);
-  (void)lgR;
+  if (nch < 1 || nch > 3) return geom_fail("k_yz_solve: 1 to 3 channels");
+  if (a.lgTw < lgL) return geom_fail("k_yz_solve: twiddle table shorter than the longest axis");
   if (yz_reg_plane(1 << a.lgNy, 1 << a.lgNz)) {
     constexpr int NY = 256, NZ = 32;
     // W, y and z DCT twiddles, the [NZ/2][NY + 16] buffer, y and z eigenvalues
@@ -2463,6 +2500,10 @@ template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStrea
     hipLaunchKernelGGL((k_yz_reg<T, 8, 5>), dim3(a.nx, 1, nch), dim3((NZ / 2) * (NY / 16)), lr, s, a);
     return SGSPM_KC_YZ_REG;
   }
+  // the planes of a workgroup within the 2 YZ_VPT reals each thread holds (the
+  // half-plane FFT tiles then hold YZ_VPT complex values per thread)
+  if (a.lgPP < 0 || lgR > lg2c(2 * YZ_VPT * YZ_NT)) return geom_fail("k_yz_solve: planes beyond the tile");
+  if (lds > LDS_LIMIT) return geom_fail("k_yz_solve: LDS beyond the limit");
   dim3 grid(ceil_div(a.nx, 1 << a.lgPP), 1, nch);
   hipLaunchKernelGGL(k_yz_solve<T>, grid, dim3(YZ_NT), lds, s, a);
   return SGSPM_KC_YZ_SOLVE;
@@ -2488,6 +2529,9 @@ template <typename T> int conv_lgP(int lgL, int ni, int nt) {
 }
 
 template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t s) {
+  if (a.n < 1 || a.n > (1 << a.lgL)) return geom_fail("k_conv: pencil longer than the padded transform");
+  if (a.nt < 0 || a.nt > 6) return geom_fail("k_conv: at most six tensor components");
+  if (a.lgTw < a.lgL) return geom_fail("k_conv: twiddle table shorter than the transform");
   if (a.lgL == 6 && a.n == 32) {
     // register four-step kernel: P kx x 2 batch rows x 8 threads per pencil
     // 16 kx per workgroup in single precision, 8 in double (LDS 16 / 16 KiB)
@@ -2500,6 +2544,11 @@ template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t 
     hipLaunchKernelGGL(k_conv64<T>, grid, dim3(16 * P), lds, s, b);
     return SGSPM_KC_CONV64;
   }
+  // three components' P L values within the FFT capacity, and at most two loads
+  // per component and thread
+  const long pl = 1L << (a.lgP + a.lgL);
+  if (a.lgP < 0 || 3 * pl > (long)CONV_VPT * CONV_NT || pl > 2L * CONV_NT) return geom_fail("k_conv: P L beyond the tile");
+  if (conv_lds<T>(a.lgL, a.lgP, a.nt) > LDS_LIMIT) return geom_fail("k_conv: LDS beyond the limit");
   dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, 1);
   hipLaunchKernelGGL(k_conv<T>, grid, dim3(CONV_NT), conv_lds<T>(a.lgL, a.lgP, a.nt), s, a);
   return SGSPM_KC_CONV;

@@ -14,6 +14,8 @@
 
 using namespace sgspm;
 
+static constexpr int ADJ_FIELDS = 16;  // fields of the adjoint workspace
+
 namespace {
 
 thread_local std::string g_err;
@@ -135,6 +137,9 @@ struct sgspm_plan_s {
     double bytes;
   };
   bool timing = false;
+  // first launch-geometry error of the current call (0: none)
+  int geom_err = 0;
+  std::string geom_msg;
   std::vector<hipEvent_t> evpool;
   size_t evnext = 0;
   std::vector<Rec> recs;
@@ -228,14 +233,23 @@ template <typename T> struct Eng {
   // fn launches one kernel and returns its class (SGSPM_KC_*)
   template <class F> void timed(double bytes, F&& fn) {
     if (!P.timing) {
-      (void)fn();
+      (void)note(fn());
       return;
     }
     hipEvent_t a = ev(), b = ev();
     (void)hipEventRecord(a, s);
     const int cls = fn();
     (void)hipEventRecord(b, s);
-    P.recs.push_back({cls, a, b, bytes});
+    if (note(cls)) P.recs.push_back({cls, a, b, bytes});
+  }
+  // keeps the first launch-geometry error of the call; true for a launch that ran
+  bool note(int cls) {
+    if (cls >= 0) return true;
+    if (!P.geom_err) {
+      P.geom_err = cls;
+      P.geom_msg = launch_geom_error();
+    }
+    return false;
   }
   static constexpr double TS = sizeof(T);
 
@@ -273,6 +287,10 @@ template <typename T> struct Eng {
       if (io.dct_out[c]) lgL = std::max(lgL, A.lgN);
     }
     if (any_x) lgL = std::max(lgL, A.lgLr);
+    // the tile holds 2P rows of nx values whether or not a transform runs (a pass
+    // with no transform, such as the accumulation of a plan without the stray
+    // field, still carries its rows), so the row length bounds it too
+    lgL = std::max(lgL, A.lgN);
     A.lgLmax = lgL;
     A.lgP = row_lgP(lg_tile<T>() - lgL, (A.nrows + 1) / 2);
     A.lgTw = P.lgTw;
@@ -792,9 +810,9 @@ template <typename T> struct Eng {
   }
 
   // Adjoint of one SGSPM step (reverse of step(), latest-state reading).
-  void adjoint(const T* m_n, double alpha, const double he_in[3], T* lam, double* grad) {
+  void adjoint(const T* m_n, double alpha, const double he_in[3], T* lam, double* grad, void* work) {
     const long N = P.N;
-    T* J = (T*)P.adj;
+    T* J = (T*)work;
     enum { LA1, LA2, LA3, LB1, LB2, LG1, LG3, LG3N, TMP, MU, LW, MT = LW + 3, NJ = MT + 3 };
     T* LW_[3] = {J + (long)LW * N, J + (long)(LW + 1) * N, J + (long)(LW + 2) * N};
     T* mt = J + (long)MT * N;
@@ -923,11 +941,19 @@ template <typename T> struct Eng {
       const T wc[3] = {0, cq, cq};
       stray_accumulate(v, dtt, acc, ai, w, wc);
     }
-    (void)NJ;
+    static_assert(NJ == ADJ_FIELDS, "adjoint workspace fields");
   }
 };
 
 // ---------------------------------------------------------------------------
+// cell edges in units of the largest (the tensor is scale free)
+void cell_ratios(const sgspm_plan_s* P, double& hx, double& hy, double& hz) {
+  const double hs = std::max(P->prm.dx, std::max(P->prm.dy, P->prm.dz));
+  hx = P->prm.dx / hs;
+  hy = P->prm.dy / hs;
+  hz = P->prm.dz / hs;
+}
+
 // Plan-time FP64 demagnetising tensor spectrum.
 int build_tensor(sgspm_plan_s* P) {
   const long padded = (long)P->Px * P->Py * P->Pz;
@@ -937,8 +963,8 @@ int build_tensor(sgspm_plan_s* P) {
   int rc;
   if ((rc = dalloc(P, &real, padded * sizeof(double)))) return rc;
   if ((rc = dalloc(P, &spec, speclen * sizeof(cx<double>)))) return rc;
-  const double hs = std::max(P->prm.dx, std::max(P->prm.dy, P->prm.dz));
-  const double hx = P->prm.dx / hs, hy = P->prm.dy / hs, hz = P->prm.dz / hs;
+  double hx, hy, hz;
+  cell_ratios(P, hx, hy, hz);
   const long tcs = (long)P->Hz * P->Hy * P->Kt;
   const double scale = -1.0 / (double)padded;
   const cx<double>* tw64 = (const cx<double>*)P->tw64;
@@ -960,7 +986,7 @@ int build_tensor(sgspm_plan_s* P) {
       A.b = 0.0;
       A.xout[0] = (cx<double>*)spec;
       A.xout_pitch = P->Kxp;
-      launch_row_fwd<double>(A, 1, P->s);
+      if (launch_row_fwd<double>(A, 1, P->s) < 0) return fail(SGSPM_EUNSUPPORTED, launch_geom_error());
     }
     // y and z: complex, full length, in place
     for (int ax = 1; ax <= 2; ++ax) {
@@ -984,7 +1010,8 @@ int build_tensor(sgspm_plan_s* P) {
       A.inv = 0;
       A.tw = tw64;
       A.lgTw = P->lgTw;
-      launch_col_fft<double>(A, ax == 1 ? P->Pz : P->Py, 1, P->s);
+      if (launch_col_fft<double>(A, ax == 1 ? P->Pz : P->Py, 1, P->s) < 0)
+        return fail(SGSPM_EUNSUPPORTED, launch_geom_error());
     }
     if (P->fp64)
       launch_tensor_pack<double>((const cx<double>*)spec, (double*)P->tens + comp * tcs, P->Hz, P->Hy, P->Kx, P->Kxp, P->Kt,
@@ -1061,10 +1088,21 @@ template <typename T> int alloc_workspace(sgspm_plan_s* P) {
   return make_tables<T>(P);
 }
 
+// status of the launches of one call: a launch-geometry error first (nothing was
+// launched for it), then the runtime's launch error; clears the geometry error
+int launch_status(sgspm_plan_s* P, const char* what) {
+  if (P->geom_err) {
+    P->geom_err = 0;
+    (void)hipGetLastError();
+    return fail(SGSPM_EUNSUPPORTED, std::string(what) + ": " + P->geom_msg);
+  }
+  return hip_check(hipGetLastError(), what);
+}
+
 template <typename T> int dispatch_step(sgspm_plan_s* P, void* m, double alpha, const double he[3], const void* src) {
   Eng<T> e(*P);
   e.step((T*)m, alpha, he, (const T*)src);
-  return hip_check(hipGetLastError(), "sgspm_step launch");
+  return launch_status(P, "sgspm_step launch");
 }
 
 }  // namespace
@@ -1155,7 +1193,7 @@ int sgspm_stray(sgspm_plan_t P, const void* m, void* hs_out) {
   }
   if (P->fp64) Eng<double>(*P).stray_to((const double*)m, (double*)hs_out);
   else Eng<float>(*P).stray_to((const float*)m, (float*)hs_out);
-  return hip_check(hipGetLastError(), "sgspm_stray launch");
+  return launch_status(P, "sgspm_stray launch");
 }
 
 int sgspm_field(sgspm_plan_t P, const void* m, const double h_e[3], void* h_out) {
@@ -1178,7 +1216,7 @@ int sgspm_field(sgspm_plan_t P, const void* m, const double h_e[3], void* h_out)
                                  ex ? 1.0 / (P->prm.dx * P->prm.dx) : 0.0, ex ? 1.0 / (P->prm.dy * P->prm.dy) : 0.0,
                                  ex ? 1.0 / (P->prm.dz * P->prm.dz) : 0.0, P->eps, P->Q, he, P->s);
   }
-  return hip_check(hipGetLastError(), "sgspm_field launch");
+  return launch_status(P, "sgspm_field launch");
 }
 
 int sgspm_heat_solve(sgspm_plan_t P, const void* r, double s, void* g) {
@@ -1186,7 +1224,7 @@ int sgspm_heat_solve(sgspm_plan_t P, const void* r, double s, void* g) {
   if (!(s >= 0.0) || !std::isfinite(s)) return fail(SGSPM_EINVAL, "s must be >= 0 and finite");
   if (P->fp64) Eng<double>(*P).heat_solve((const double*)r, s, (double*)g);
   else Eng<float>(*P).heat_solve((const float*)r, (float)s, (float*)g);
-  return hip_check(hipGetLastError(), "sgspm_heat_solve launch");
+  return launch_status(P, "sgspm_heat_solve launch");
 }
 
 int sgspm_energy(sgspm_plan_t P, const void* m, const double h_e[3], double e_out[5]) {
@@ -1209,7 +1247,7 @@ int sgspm_energy(sgspm_plan_t P, const void* m, const double h_e[3], double e_ou
     launch_energy<float>((const float*)m, hs, P->nx, P->ny, P->nz, cx_, cy_, cz_, he, P->partials, P->nred, P->eout,
                          P->s);
   }
-  int rc = hip_check(hipGetLastError(), "sgspm_energy launch");
+  int rc = launch_status(P, "sgspm_energy launch");
   if (rc) return rc;
   double acc[4];
   rc = hip_check(hipMemcpyAsync(acc, P->eout, sizeof(acc), hipMemcpyDeviceToHost, P->s), "energy copy");
@@ -1236,12 +1274,12 @@ int sgspm_adjoint_step(sgspm_plan_t P, const void* m_n, double alpha, const doub
   if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SGSPM_EINVAL, "alpha must be >= 0 and finite");
   if (P->prm.scheme != SGSPM_SCHEME_SGS) return fail(SGSPM_EUNSUPPORTED, "the adjoint covers the SGS scheme only");
   if (!P->adj) {
-    int rc = dalloc(P, &P->adj, (size_t)16 * P->N * (P->fp64 ? 8 : 4));
+    int rc = dalloc(P, &P->adj, (size_t)ADJ_FIELDS * P->N * (P->fp64 ? 8 : 4));
     if (rc) return rc;
   }
-  if (P->fp64) Eng<double>(*P).adjoint((const double*)m_n, alpha, h_e, (double*)lam, grad_dev);
-  else Eng<float>(*P).adjoint((const float*)m_n, alpha, h_e, (float*)lam, grad_dev);
-  return hip_check(hipGetLastError(), "sgspm_adjoint_step launch");
+  if (P->fp64) Eng<double>(*P).adjoint((const double*)m_n, alpha, h_e, (double*)lam, grad_dev, P->adj);
+  else Eng<float>(*P).adjoint((const float*)m_n, alpha, h_e, (float*)lam, grad_dev, P->adj);
+  return launch_status(P, "sgspm_adjoint_step launch");
 }
 
 int sgspm_timing(sgspm_plan_t P, int enable) {

@@ -37,6 +37,11 @@ def _rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
+def _rel_inf(a, b):
+    """Element-wise: max |a - b| over max |b|."""
+    return float(np.abs(np.ravel(a) - np.ravel(b)).max() / max(np.abs(np.ravel(b)).max(), 1e-300))
+
+
 @pytest.mark.parametrize("n", [(16, 8, 4), (32, 16, 1), (8, 1, 8), (16, 1, 1), (4, 4, 4), (256, 4, 2)],
                          ids=lambda n: "x".join(map(str, n)))
 @pytest.mark.parametrize("terms", [ALL, ("exchange",), ("exchange", "aniso", "zeeman"), ("stray", "zeeman")],
@@ -57,7 +62,7 @@ def test_adjoint_step_fp64(env, n, terms):
     P = oracle_problem_si(n, CELL, DT, terms)
     lref, dh, da = oadj.adjoint_step(P, m0, alpha, oracle_field_si(B, terms), lam)
     g = grad.cpu().numpy()
-    assert _rel(lam_d.cpu().numpy(), lref) <= 1e-11
+    assert _rel_inf(lam_d.cpu().numpy(), lref) <= 1e-11
     if "zeeman" in terms:
         assert np.allclose(g[:3], dh * FSCALE, rtol=1e-10, atol=1e-12 * np.abs(dh * FSCALE).max())
     else:
@@ -112,6 +117,52 @@ def test_adjoint_step_blocked_nyquist(env, prec):
           f"dalpha {e_a:.2e}")
     bar = 1e-10 if prec == 1 else 1e-5
     assert e_l <= bar and e_h <= bar and e_a <= bar
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_adjoint_step_block_256x256x32(env, prec):
+    """One adjoint step at the benchmark's full size and launch shapes (512-point row
+    kernels, packed DC/Nyquist y pass, 64-point convolution, register y-z solve),
+    element by element against the oracle adjoint."""
+    torch, sg = env
+    c = workloads.config("block-256x256x32")
+    m0 = workloads.initial_state(c)
+    lam = np.random.default_rng(205).normal(size=m0.shape)
+    B = tuple(workloads.field_schedule(c, 1)[0])
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, prec)
+    lam_d = to_dev(torch, lam, prec)
+    grad = torch.zeros(4, dtype=torch.float64, device="cuda")
+    plan.adjoint_step(to_dev(torch, m0, prec), c.alpha, B, lam_d, grad)
+    torch.cuda.synchronize()
+    P = oracle_problem_si(c.n, c.h, c.dt, ALL)
+    lref, dh, da = oadj.adjoint_step(P, rounded_like(m0, prec), c.alpha, oracle_field_si(B, ALL),
+                                     rounded_like(lam, prec))
+    g = grad.cpu().numpy()
+    e_l, e_h, e_a = _rel_inf(lam_d.cpu().numpy(), lref), _rel_inf(g[:3], dh * FSCALE), abs(g[3] - da) / abs(da)
+    print(f"block {'fp64' if prec else 'fp32'} adjoint step: max-abs rel err lam {e_l:.2e}, dh_e {e_h:.2e}, "
+          f"dalpha {e_a:.2e}")
+    bar = 1e-10 if prec == 1 else 1e-5
+    assert e_l <= bar and e_h <= bar and e_a <= bar
+
+
+def test_block_checkpointed_adjoint_k20(env):
+    """The block's checkpointed backward pass (checkpoints every 20 steps, each segment
+    recomputed from its checkpoint) gives bit for bit the gradients of a pass that keeps
+    every state (checkpoints every step), over 40 steps in single precision."""
+    torch, sg = env
+    c = workloads.config("block-256x256x32")
+    S = 40
+    m0 = workloads.initial_state(c)
+    B = workloads.field_schedule(c, S)
+    target = workloads.target_state(c)
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 0)
+    r20 = _loss_grads_gpu(torch, sg, plan, m0, B, c.alpha, target, c.ckpt_every, 0)
+    r1 = _loss_grads_gpu(torch, sg, plan, m0, B, c.alpha, target, 1, 0)
+    print(f"block fp32 {S} steps: loss {r20[0]:.9e}, |dL/dalpha| {abs(r20[3]):.3e}")
+    assert c.ckpt_every == 20
+    assert r20[0] == r1[0]
+    assert np.array_equal(r20[1], r1[1]) and np.array_equal(r20[2], r1[2]) and r20[3] == r1[3]
+    assert np.all(np.isfinite(r20[1])) and abs(r20[3]) > 0
 
 
 def _loss_grads_gpu(torch, sg, plan, m0, B, alpha, target, ckpt, prec):

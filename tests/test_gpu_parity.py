@@ -305,6 +305,60 @@ def test_block_256x256x32_one_step(env, prec):
     assert err <= (1e-10 if prec == 1 else 2e-6)
 
 
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_wall_strip_512x32x4_50_steps(env, prec):
+    """The strip workload's grid and Neel-wall start, all fields, 50 steps at its stated
+    alpha and field, in both precisions against the FP64 oracle (FP32 from FP32-rounded inputs)."""
+    torch, sg = env
+    c = workloads.config("wall-strip-512x32x4")
+    m0 = workloads.initial_state(c)
+    B = workloads.field_schedule(c, 50)
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, prec)
+    got = _run_gpu(plan, torch, m0, c.alpha, B, prec)
+    P = oracle_problem_si(c.n, c.h, c.dt, ALL)
+    ref = _run_oracle(P, rounded_like(m0, prec), c.alpha, [oracle_field_si(b, ALL) for b in B])
+    err = np.abs(got - ref).max()
+    print(f"wall-strip {'fp64' if prec else 'fp32'} 50 steps: max|m - m_oracle| = {err:.3e}")
+    assert err <= (1e-10 if prec == 1 else 1e-5)
+
+
+# GSPM (paper §3.1) in single precision, on the generic kernels and on the
+# 512-point / register paths of the block
+@pytest.mark.parametrize("n", [(16, 8, 4), (32, 16, 1), (256, 4, 2), (16, 256, 32)],
+                         ids=lambda n: "x".join(map(str, n)))
+def test_gspm_fp32(env, n):
+    torch, sg = env
+    shape = (n[2], n[1], n[0])
+    m0 = workloads.paper_ic(shape)
+    B = [(5e-3, 1e-3, -2e-3)] * 10
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, 0, scheme_=1)
+    got = _run_gpu(plan, torch, m0, 0.02, B, 0)
+    P = oracle_problem_si(n, CELL, DT, ALL)
+    ref = _run_oracle(P, rounded_like(m0, 0), 0.02, [oracle_field_si(b, ALL) for b in B], "gspm")
+    err = np.abs(got - ref).max()
+    print(f"gspm fp32 {n}: max|m - m_oracle| after 10 steps = {err:.3e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_energies_block_256x256x32(env, prec):
+    """Per-term FP64 energies at the benchmark's full size (the stray term through the
+    512-point y pass and the 64-point convolution)."""
+    torch, sg = env
+    c = workloads.config("block-256x256x32")
+    m = workloads.initial_state(c)
+    B = (7e-3, -4e-3, 1e-3)
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, prec)
+    e = plan.energy(to_dev(torch, m, prec), B)
+    P = oracle_problem_si(c.n, c.h, c.dt, ALL)
+    eref = scheme.energies(P, rounded_like(m, prec), oracle_field_si(B, ALL))
+    mu0ms2 = 4e-7 * np.pi * workloads.MS_PY ** 2
+    erel = {k: abs(e[k] / mu0ms2 - eref[k]) / (abs(eref["total"]) + abs(eref[k]) + 1e-30) for k in eref}
+    print(f"block energies {'fp64' if prec else 'fp32'}: " + ", ".join(f"{k} {v:.1e}" for k, v in erel.items()))
+    for k in eref:
+        assert erel[k] <= (1e-11 if prec == 1 else 1e-6), k
+
+
 def test_projection_flags_non_finite(env):
     torch, sg = env
     n = (8, 4, 1)
