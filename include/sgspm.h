@@ -124,6 +124,21 @@ int sgspm_heat_solve(sgspm_plan_t plan, const void* r, double s, void* g);
 int sgspm_adjoint_step(sgspm_plan_t plan, const void* m_n, double alpha, const double h_e[3],
                        void* lam, double* grad_dev);
 
+/* For callers that cannot allocate device memory during the call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * adjoint step above with the same arguments, results and errors, whose 16
+ * fields of adjoint workspace live in a static device array of 8 MiB instead of
+ * memory the plan allocates on the first adjoint call.  It calls no allocating
+ * routine.  Grids above 131072 cells (FP32) or 65536 cells (FP64) need more
+ * than the array holds and are rejected with SGSPM_EUNSUPPORTED before any
+ * launch.  Each GPU holds one copy of the array for the life of the process, and
+ * every call on that GPU, from any plan or thread, uses it: calls that overlap
+ * on one GPU (concurrent streams, several threads) race on it and must be
+ * serialised by the caller.  Nothing in it needs clearing between calls: every
+ * field is written before it is read. */
+int sgspm_adjoint_step_noalloc(sgspm_plan_t plan, const void* m_n, double alpha, const double h_e[3],
+                               void* lam, double* grad_dev);
+
 /* Measurement support.  Kernel classes of the step's launches; each class is
  * one kernel (its float or double instance): */
 enum {

@@ -14,7 +14,7 @@ SCHEME_SGS, SCHEME_GS = 0, 1
 
 EXPORTS = ("sgspm_validate", "sgspm_reduced_constants", "sgspm_plan", "sgspm_step", "sgspm_energy",
            "sgspm_field", "sgspm_stray", "sgspm_heat_solve", "sgspm_adjoint_step",
-           "sgspm_timing",
+           "sgspm_adjoint_step_noalloc", "sgspm_timing",
            "sgspm_timing_read", "sgspm_check", "sgspm_destroy", "sgspm_last_error")
 KERNEL_CLASSES = ("row_fwd", "row_fwd512", "row_inv", "row_inv512", "col_dct", "yz_solve", "yz_reg",
                   "col_fft", "fft512", "conv", "conv64", "other")
@@ -53,6 +53,7 @@ def _load():
     L.sgspm_stray.argtypes = [vp, vp, vp]
     L.sgspm_heat_solve.argtypes = [vp, vp, ctypes.c_double, vp]
     L.sgspm_adjoint_step.argtypes = [vp, vp, ctypes.c_double, dp, vp, vp]
+    L.sgspm_adjoint_step_noalloc.argtypes = [vp, vp, ctypes.c_double, dp, vp, vp]
     L.sgspm_timing.argtypes = [vp, ctypes.c_int]
     L.sgspm_timing_read.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_int64)]
     L.sgspm_check.argtypes = [vp]
@@ -159,6 +160,13 @@ class Plan:
             raise ValueError("grad must be a contiguous CUDA float64 tensor of 4 values")
         _check(lib.sgspm_adjoint_step(self._h, self._ptr(m_n, self.shape, "m_n"), float(alpha), _d3(h_e),
                                       self._ptr(lam, self.shape, "lam"), ctypes.c_void_p(grad.data_ptr())))
+
+    def adjoint_step_noalloc(self, m_n, alpha, h_e, lam, grad):
+        import torch
+        if not grad.is_cuda or grad.dtype != torch.float64 or grad.numel() != 4 or not grad.is_contiguous():
+            raise ValueError("grad must be a contiguous CUDA float64 tensor of 4 values")
+        _check(lib.sgspm_adjoint_step_noalloc(self._h, self._ptr(m_n, self.shape, "m_n"), float(alpha), _d3(h_e),
+                                              self._ptr(lam, self.shape, "lam"), ctypes.c_void_p(grad.data_ptr())))
 
     def timing(self, enable=True):
         _check(lib.sgspm_timing(self._h, 1 if enable else 0))

@@ -6,6 +6,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -14,9 +15,20 @@
 
 using namespace sgspm;
 
-static constexpr int ADJ_FIELDS = 16;  // fields of the adjoint workspace
+// Workspace of sgspm_adjoint_step_noalloc: the adjoint's 16 fields of N cells in
+// one file-scope device array (each GPU holds its own copy until the process
+// ends).  Host code never passes the array's name to a kernel: it is a host-side
+// stand-in there.  The device address comes from hipGetSymbolAddress, once per
+// device with that device current (at plan creation), and is kept per device.
+static constexpr size_t SCRATCH_BYTES = size_t(8) << 20;
+static constexpr int ADJ_FIELDS = 16;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
 
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
 
 thread_local std::string g_err;
 
@@ -98,6 +110,7 @@ void reduce(const sgspm_params* p, double out[5]) {
 struct sgspm_plan_s {
   sgspm_params prm;
   hipStream_t s = nullptr;
+  int dev = 0;  // device current at plan creation (owner of the plan's memory)
   bool fp64 = false;
   int nx = 1, ny = 1, nz = 1;
   long N = 0;
@@ -1063,6 +1076,21 @@ template <typename T> int make_tables(sgspm_plan_s* P) {
   return SGSPM_OK;
 }
 
+// device address of this device's copy of `scratch` (once per device)
+int scratch_setup(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(SGSPM_EUNSUPPORTED, "device ordinal beyond the supported range");
+  if (g_scratch_ptr[dev]) return SGSPM_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return fail(SGSPM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+  g_scratch_ptr[dev] = ptr;
+  return SGSPM_OK;
+}
+
 template <typename T> int alloc_workspace(sgspm_plan_s* P) {
   int rc;
   if ((rc = dalloc(P, &P->fld, (size_t)NF * P->N * sizeof(T)))) return rc;
@@ -1127,8 +1155,14 @@ int sgspm_plan(const sgspm_params* p, void* hip_stream, sgspm_plan_t* out) {
   *out = nullptr;
   int rc = validate(p);
   if (rc) return rc;
+  int dev = 0;
+  rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  rc = scratch_setup(dev);
+  if (rc) return rc;
   sgspm_plan_s* P = new sgspm_plan_s();
   P->prm = *p;
+  P->dev = dev;
   P->s = (hipStream_t)hip_stream;
   P->fp64 = p->precision == SGSPM_FP64;
   P->nx = p->nx;
@@ -1280,6 +1314,25 @@ int sgspm_adjoint_step(sgspm_plan_t P, const void* m_n, double alpha, const doub
   if (P->fp64) Eng<double>(*P).adjoint((const double*)m_n, alpha, h_e, (double*)lam, grad_dev, P->adj);
   else Eng<float>(*P).adjoint((const float*)m_n, alpha, h_e, (float*)lam, grad_dev, P->adj);
   return launch_status(P, "sgspm_adjoint_step launch");
+}
+
+int sgspm_adjoint_step_noalloc(sgspm_plan_t P, const void* m_n, double alpha, const double h_e[3], void* lam,
+                               double* grad_dev) {
+  if (!P || !m_n || !h_e || !lam || !grad_dev) return fail(SGSPM_EINVAL, "NULL argument");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SGSPM_EINVAL, "alpha must be >= 0 and finite");
+  if (P->prm.scheme != SGSPM_SCHEME_SGS) return fail(SGSPM_EUNSUPPORTED, "the adjoint covers the SGS scheme only");
+  const size_t need = (size_t)ADJ_FIELDS * P->N * (P->fp64 ? 8 : 4);
+  if (need > SCRATCH_BYTES)
+    return fail(SGSPM_EUNSUPPORTED, "sgspm_adjoint_step_noalloc: the grid needs " + std::to_string(need) +
+                                        " bytes of workspace; the static workspace holds " +
+                                        std::to_string(SCRATCH_BYTES) + " (at most " +
+                                        std::to_string(SCRATCH_BYTES / (ADJ_FIELDS * 4)) + " cells in FP32, " +
+                                        std::to_string(SCRATCH_BYTES / (ADJ_FIELDS * 8)) + " in FP64)");
+  void* work = g_scratch_ptr[P->dev];
+  if (!work) return fail(SGSPM_EHIP, "the static workspace of this device has no address");
+  if (P->fp64) Eng<double>(*P).adjoint((const double*)m_n, alpha, h_e, (double*)lam, grad_dev, work);
+  else Eng<float>(*P).adjoint((const float*)m_n, alpha, h_e, (float*)lam, grad_dev, work);
+  return launch_status(P, "sgspm_adjoint_step_noalloc launch");
 }
 
 int sgspm_timing(sgspm_plan_t P, int enable) {
