@@ -97,8 +97,9 @@ def algorithmic_step_bytes(c, dbytes):
     return field, tensor
 
 
-def make_plan(sg, c, precision):
-    kw = dict(nx=c.n[0], ny=c.n[1], nz=c.n[2], dx=c.h[0], dy=c.h[1], dz=c.h[2], dt=c.dt, precision=precision)
+def make_plan(sg, c, precision, scheme=0):
+    kw = dict(nx=c.n[0], ny=c.n[1], nz=c.n[2], dx=c.h[0], dy=c.h[1], dz=c.h[2], dt=c.dt, precision=precision,
+              scheme=scheme)
     if c.units == "si":
         kw.update(units=sg.UNITS_SI, A=c.A, Ms=c.Ms, Ku=c.Ku, terms=sg.TERM_ALL)
     else:
@@ -186,6 +187,11 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=50)
     ap.add_argument("--adjoint-steps", type=int, default=20)
     ap.add_argument("--passes", type=int, default=5, help="timed passes of K steps (median reported)")
+    ap.add_argument("--sweep-steps", type=int, default=5000,
+                    help="steps per run of the strip workload's 15-run field/damping sweep (0: skip)")
+    ap.add_argument("--metrics-log", default="",
+                    help="write the sweep's per-run records (energies per term every 10 steps, max ||m| - 1|) "
+                         "to this JSONL file")
     ap.add_argument("--backward-steps", type=int, default=-1,
                     help="steps of the timed checkpointed backward pass (-1: the workload's adjoint length, 0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -320,6 +326,22 @@ def main():
     del m
     torch.cuda.empty_cache()
 
+    # ---- the frozen-field reading of the sweeps (two stray-field evaluations per step), FP32
+    ff = None
+    if c.units == "si":
+        pf = make_plan(sg, c, sg.FP32, scheme=sg.SCHEME_SGS_FF)
+        m = torch.tensor(m0, dtype=torch.float32, device="cuda")
+        for n in range(1, 1 + min(W, 5)):
+            pf.step(m, alpha, B[n])
+        msf = float(np.median([time_steps(torch, pf, m, alpha, B, 1 + min(W, 5), K) for _ in range(3)]))
+        pf.check()
+        ff = {"value": N / (msf * 1e-3), "unit": "cell-updates/s", "ms_per_step": msf, "dtype": "f32",
+              "note": "SGSPM with f frozen at m^n through both sweeps (stray field evaluated twice per step)"}
+        print(f"[bench] fp32 frozen-field step {msf:.4f} ms/step", file=sys.stderr, flush=True)
+        pf.close()
+        del m
+        torch.cuda.empty_cache()
+
     # ---- adjoint steps (FP32 and FP64) from a random cotangent at the workload's start
     adj = None
     if args.adjoint_steps > 0:
@@ -345,6 +367,46 @@ def main():
             torch.cuda.empty_cache()
             print(f"[bench] {name} backward pass, {SB} steps, checkpoints every {KB}: "
                   f"{backward[name]['backward_ms']:.1f} ms", file=sys.stderr, flush=True)
+
+    # ---- the strip workload as specified: 5 fields x 3 dampings, 15 independent runs,
+    # FP64 energies every 10 steps (graph-replayed steps between the records)
+    sweep = None
+    if args.sweep_steps > 0:
+        from paper_2606_28113_amd import runs as runs_mod
+        cs = workloads.config("wall-strip-512x32x4")
+        ps = make_plan(sg, cs, sg.FP32)
+        m0s = workloads.initial_state(cs)
+        log = open(args.metrics_log, "w") if args.metrics_log else None
+        detail = []
+        step_s = 0.0
+        t0 = time.perf_counter()
+        for b_mT in cs.extra["fields_mT"]:
+            for a in cs.extra["alphas"]:
+                ms = torch.tensor(m0s, dtype=torch.float32, device="cuda")
+                r = runs_mod.run_logged(ps, ms, args.sweep_steps, a, (b_mT * 1e-3, 0.0, 0.0), log_every=10,
+                                        sink=log, run_id=len(detail), extra={"B_mT": float(b_mT)})
+                step_s += r["step_seconds"]
+                rec = r["records"]
+                detail.append({"B_mT": float(b_mT), "alpha": a, "monotone_energy": r["monotone"],
+                               "E0": rec[0]["energy"]["total"], "E_end": rec[-1]["energy"]["total"],
+                               "max_unit_error": max(x["unit_error"] for x in rec)})
+        wall = time.perf_counter() - t0
+        if log:
+            log.close()
+        ps.close()
+        cu = cs.cells * args.sweep_steps * len(detail)
+        sweep = {"workload": f"{cs.name}: {WORKLOAD_TEXT[cs.name].split(', 5 mT')[0]}, fields "
+                             f"{', '.join(f'{b:g}' for b in cs.extra['fields_mT'])} mT x alpha "
+                             f"{', '.join(f'{a:g}' for a in cs.extra['alphas'])}, dt 0.1 ps",
+                 "runs": len(detail), "steps_per_run": args.sweep_steps, "dtype": "f32",
+                 "value": cu / step_s, "unit": "cell-updates/s", "step_seconds": step_s,
+                 "value_incl_logging": cu / wall, "wall_s": wall,
+                 "note": "steps replayed from a captured HIP graph; FP64 energies per term and max ||m| - 1| "
+                         "every 10 steps (synchronising); value counts the stepping alone",
+                 "runs_with_monotone_energy": sum(1 for d in detail if d["monotone_energy"]),
+                 "detail": detail}
+        print(f"[bench] strip sweep: {len(detail)} runs x {args.sweep_steps} steps, stepping {step_s:.2f} s "
+              f"({cu / step_s:.3e} cell-updates/s), wall {wall:.2f} s", file=sys.stderr, flush=True)
 
     # ---- CPU oracle baseline and first-step error
     cpu = None
@@ -387,6 +449,8 @@ def main():
         "cpu_baseline": cpu,
         "fp64": {"value": N / (ms64 * 1e-3), "unit": "cell-updates/s", "ms_per_step": ms64, "steps": K64,
                  "kernels": breakdown64},
+        "frozen_field": ff,
+        "wall_sweep": sweep,
         "adjoint": adj,
         "backward_pass": backward,
         "error_vs_oracle": err,

@@ -52,7 +52,12 @@ enum {
 enum { SGSPM_TERM_EXCHANGE = 1, SGSPM_TERM_ANISO = 2, SGSPM_TERM_STRAY = 4, SGSPM_TERM_ZEEMAN = 8 };
 enum { SGSPM_UNITS_SI = 0, SGSPM_UNITS_REDUCED = 1 };
 enum { SGSPM_FP32 = 0, SGSPM_FP64 = 1 };
-enum { SGSPM_SCHEME_SGS = 0, SGSPM_SCHEME_GS = 1 };
+/* SGS: SGSPM (§3.2) with every f of the sweeps at the latest component values;
+ * GS: GSPM (§3.1), same reading; SGS_FF: SGSPM with f frozen at m^n through
+ * both sweeps and evaluated once more at m** for Step 2 (two stray-field
+ * evaluations per step instead of six; the efficiency direction of the
+ * Conclusion and the §3.1 remark on where h_s is evaluated). */
+enum { SGSPM_SCHEME_SGS = 0, SGSPM_SCHEME_GS = 1, SGSPM_SCHEME_SGS_FF = 2 };
 
 /* Problem statement (paper §2 and §3): grid, cell size, constants, time step. */
 typedef struct {
@@ -65,7 +70,7 @@ typedef struct {
   double dt;            /* seconds (SI) or reduced time */
   uint32_t terms;       /* bitmask of SGSPM_TERM_* */
   int32_t precision;    /* SGSPM_FP32 or SGSPM_FP64 */
-  int32_t scheme;       /* SGSPM_SCHEME_SGS (default) or SGSPM_SCHEME_GS */
+  int32_t scheme;       /* SGSPM_SCHEME_SGS (default), SGSPM_SCHEME_GS or SGSPM_SCHEME_SGS_FF */
 } sgspm_params;
 
 typedef struct sgspm_plan_s* sgspm_plan_t;
@@ -97,11 +102,35 @@ int sgspm_plan(const sgspm_params* p, void* hip_stream, sgspm_plan_t* out);
  * A zero or non-finite |m***| sets a device flag reported by sgspm_check. */
 int sgspm_step(sgspm_plan_t plan, void* m, double alpha, const double h_e[3], const void* src);
 
+/* nsteps steps of sgspm_step with the same alpha and h_e and no source, in place,
+ * asynchronous: the first call for a given (m, alpha, h_e) captures one step as a
+ * HIP graph (on a private stream of the plan) and every step replays it, which
+ * removes the host's launch overhead from launch-bound grids (films, strips).
+ * A call with another m, alpha or h_e captures again.  Results equal nsteps
+ * calls of sgspm_step bit for bit. */
+int sgspm_steps(sgspm_plan_t plan, void* m, int nsteps, double alpha, const double h_e[3]);
+
+/* sgspm_step, and the spectral radii of that step's sweep matrices (paper §4,
+ * eqs. GS-matrix and SGS-matrix: G_GS = (D - L)^{-1} U and
+ * G_SGS = (D - U)^{-1} L (D - L)^{-1} U).  Their entries are the coefficients
+ * c_i^s = eps dt Lap_h g_i^s of the step's precession solves, acting cell by
+ * cell, so each cell has its own 3x3 matrices; rho_out (host double[2]) =
+ * {max over cells of rho(G_GS), max over cells of rho(G_SGS)}, computed in FP64
+ * from the solves as stored.  D - U takes the signs of the splitting of the
+ * matrix of eq. M (the printed matrix has its off-diagonal signs flipped).  For
+ * a GSPM plan rho_out[1] is NaN.  Synchronises the stream. */
+int sgspm_step_spectral_radius(sgspm_plan_t plan, void* m, double alpha, const double h_e[3], const void* src,
+                               double rho_out[2]);
+
 /* Energies of m (paper §2, with the 1/2 factors that make h = -dE/dm):
  * e_out = {total, exchange, anisotropy, stray, zeeman}, host double[5], in
  * joules (SI) or reduced energy x volume.  FP64 accumulation with a fixed
  * reduction tree (deterministic).  Synchronises the stream. */
 int sgspm_energy(sgspm_plan_t plan, const void* m, const double h_e[3], double e_out[5]);
+
+/* max over cells of | |m| - 1 | (the unit-length constraint that the projection
+ * of Step 3 restores), FP64, into host *out.  Synchronises the stream. */
+int sgspm_unit_error(sgspm_plan_t plan, const void* m, double* out);
 
 /* Effective field h_eff = eps Lap_h m - Q(m2 e2 + m3 e3) + h_s + h_e (paper §2)
  * of m into h_out (device [3][nz][ny][nx], reduced units). */
@@ -114,6 +143,16 @@ int sgspm_stray(sgspm_plan_t plan, const void* m, void* hs_out);
  * g = (I - s eps dt Lap_h)^{-1} r for one scalar field r (device [nz][ny][nx]);
  * r and g may alias. */
 int sgspm_heat_solve(sgspm_plan_t plan, const void* r, double s, void* g);
+
+/* The demagnetising tensor the stray field uses, component comp (0..5 = xx,
+ * yy, zz, xy, xz, yz), in real space and FP64, exactly as the plan computes it
+ * before transforming it: the Newell-Williams-Dunlop cell-averaged tensor for
+ * offsets up to 20 cells in max norm, the point-dipole tensor beyond, on the
+ * zero-padded grid out = device double [Pz][Py][Px] (P_a = 2 n_a for n_a > 1,
+ * else 1), offset d stored at d mod P, zero where |d_a| > n_a - 1.  Lengths in
+ * units of the largest cell edge (the tensor is scale free).  For checking the
+ * plan-time precomputation; SGSPM_EINVAL if the plan has no stray field. */
+int sgspm_demag_tensor(sgspm_plan_t plan, int comp, void* out);
 
 /* Adjoint of one step (the chain rule of the step above; the paper has none):
  * given m_n (the state the step starts from) and lam = dL/dm^{n+1}, overwrite

@@ -19,14 +19,18 @@ Modules
   units         SI -> the paper's non-dimensional form
   operators     Neumann Laplacian and the heat-type solve (I - c Lap_h)^-1
   demag         Newell cell-averaged demagnetising tensor and the stray field
-  scheme        one SGSPM step, one GSPM step, energies
+  scheme        one SGSPM step (latest-state and frozen-field readings), one GSPM step, energies
+  spectral      spectral radius of the Gauss-Seidel / symmetric Gauss-Seidel sweep matrices
   adjoint       reverse (adjoint) and tangent-linear SGSPM step
   manufactured  exact solutions with forcing from the accuracy section
 
 Pinned functions: all (see tests/test_oracle_*.py).  The stray field update
-points inside the sweeps (the "latest state" reading) are pinned only by self-
-consistency: the paper prints no number with the stray field on, so that
-reading is "parity unpinned" beyond the invariants the tests check.
+points inside the sweeps (the "latest state" reading, and the frozen-field
+reading) are pinned only by self-consistency and by first-order convergence to
+the semi-discrete equation: the paper prints no number with the stray field
+on, so those readings are "parity unpinned" beyond the invariants the tests
+check.  The paper's printed spectral radii are not reproduced (see spectral);
+the sweep matrices are pinned by reproducing the step itself.
 """
-from . import units, operators, demag, scheme, adjoint, manufactured  # noqa: F401
-from .scheme import Problem, sgspm_step, gspm_step, energies, effective_field  # noqa: F401
+from . import units, operators, demag, scheme, adjoint, manufactured, spectral  # noqa: F401
+from .scheme import Problem, sgspm_step, sgspm_ff_step, gspm_step, energies, effective_field  # noqa: F401

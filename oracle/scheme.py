@@ -147,6 +147,43 @@ def sgspm_step(P, m, alpha, h_e, src=None, tape=None):
     return m_next
 
 
+def sgspm_ff_step(P, m, alpha, h_e, src=None):
+    """m^{n+1} from m^n by one SGSPM step under the frozen-field reading of Step 1.
+
+    The sweeps of §3.2 as in sgspm_step, but every f^s of Step 1 (both sweeps)
+    is the field of the state at the start of the step, f(m^n), evaluated once;
+    Step 2 evaluates f once more, at m**.  This is the other reading of where the
+    stray field is computed (the remark after eq. projection in §3.1 ties h_s to
+    the intermediate values rather than to each partial update), and the
+    efficiency direction the Conclusion points to (the improved GSPM variants
+    that cut field evaluations): two stray-field evaluations per step instead of
+    six.  The source term is placed as in sgspm_step.
+    """
+    m = np.asarray(m, dtype=np.float64)
+    dt = P.dt
+    m1, m2, m3 = m
+    s = _source_terms(src, dt, m.shape[1:])
+    f_n = P.f((m1, m2, m3), h_e)
+    # Step 1, forward sweep with f frozen at m^n
+    g2n = P.H(m2 + dt * f_n[1])
+    g3n = P.H(m3 + dt * f_n[2])
+    m1s = m1 + (g2n * m3 - g3n * m2) + s[0]
+    g1s = P.H(m1s + dt * f_n[0])
+    m2s = m2 + (g3n * m1s - g1s * m3) + s[1]
+    g2s = P.H(m2s + dt * f_n[1])
+    m3s = m3 + (g1s * m2s - g2s * m1s) + s[2]
+    # Step 1, backward sweep (m3** = m3*, rebased on m^n), same frozen f
+    g3ss = P.H(m3s + dt * f_n[2])
+    m2ss = m2 + (g3ss * m1s - g1s * m3s) + s[1]
+    g2ss = P.H(m2ss + dt * f_n[1])
+    m1ss = m1 + (g2ss * m3s - g3ss * m2ss) + s[0]
+    mss = np.stack([m1ss, m2ss, m3s])
+    # Steps 2 and 3 as in sgspm_step
+    rhs = mss + alpha * dt * P.f(mss, h_e)
+    msss = np.stack([P.H_alpha(rhs[i], alpha) for i in range(3)])
+    return project(msss)[0]
+
+
 def gspm_step(P, m, alpha, h_e, src=None):
     """m^{n+1} from m^n by one GSPM step (§3.1): forward sweep, heat flow, projection."""
     m = np.asarray(m, dtype=np.float64)

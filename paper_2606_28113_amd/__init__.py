@@ -10,7 +10,7 @@ import ctypes
 import os
 
 from .binding import (  # noqa: F401
-    FP32, FP64, SCHEME_GS, SCHEME_SGS, TERM_ALL, TERM_ANISO, TERM_EXCHANGE, TERM_STRAY, TERM_ZEEMAN,
+    FP32, FP64, SCHEME_GS, SCHEME_SGS, SCHEME_SGS_FF, TERM_ALL, TERM_ANISO, TERM_EXCHANGE, TERM_STRAY, TERM_ZEEMAN,
     UNITS_REDUCED, UNITS_SI, Plan, SGSPMError, lib, lib_path, reduced_constants, validate,
 )
 from .autograd import SGSPMFunction, run_steps  # noqa: F401

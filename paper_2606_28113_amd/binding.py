@@ -10,11 +10,13 @@ TERM_EXCHANGE, TERM_ANISO, TERM_STRAY, TERM_ZEEMAN = 1, 2, 4, 8
 TERM_ALL = 15
 UNITS_SI, UNITS_REDUCED = 0, 1
 FP32, FP64 = 0, 1
-SCHEME_SGS, SCHEME_GS = 0, 1
+SCHEME_SGS, SCHEME_GS, SCHEME_SGS_FF = 0, 1, 2
 
-EXPORTS = ("sgspm_validate", "sgspm_reduced_constants", "sgspm_plan", "sgspm_step", "sgspm_energy",
+EXPORTS = ("sgspm_validate", "sgspm_reduced_constants", "sgspm_plan", "sgspm_step", "sgspm_steps",
+           "sgspm_step_spectral_radius",
+           "sgspm_energy", "sgspm_unit_error",
            "sgspm_field", "sgspm_stray", "sgspm_heat_solve", "sgspm_adjoint_step",
-           "sgspm_adjoint_step_noalloc", "sgspm_timing",
+           "sgspm_adjoint_step_noalloc", "sgspm_demag_tensor", "sgspm_timing",
            "sgspm_timing_read", "sgspm_check", "sgspm_destroy", "sgspm_last_error")
 KERNEL_CLASSES = ("row_fwd", "row_fwd512", "row_inv", "row_inv512", "col_dct", "yz_solve", "yz_reg",
                   "col_fft", "fft512", "conv", "conv64", "other")
@@ -48,12 +50,16 @@ def _load():
     L.sgspm_reduced_constants.argtypes = [ctypes.POINTER(Params), dp]
     L.sgspm_plan.argtypes = [ctypes.POINTER(Params), vp, ctypes.POINTER(vp)]
     L.sgspm_step.argtypes = [vp, vp, ctypes.c_double, dp, vp]
+    L.sgspm_step_spectral_radius.argtypes = [vp, vp, ctypes.c_double, dp, vp, dp]
+    L.sgspm_steps.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, dp]
     L.sgspm_energy.argtypes = [vp, vp, dp, dp]
+    L.sgspm_unit_error.argtypes = [vp, vp, dp]
     L.sgspm_field.argtypes = [vp, vp, dp, vp]
     L.sgspm_stray.argtypes = [vp, vp, vp]
     L.sgspm_heat_solve.argtypes = [vp, vp, ctypes.c_double, vp]
     L.sgspm_adjoint_step.argtypes = [vp, vp, ctypes.c_double, dp, vp, vp]
     L.sgspm_adjoint_step_noalloc.argtypes = [vp, vp, ctypes.c_double, dp, vp, vp]
+    L.sgspm_demag_tensor.argtypes = [vp, ctypes.c_int, vp]
     L.sgspm_timing.argtypes = [vp, ctypes.c_int]
     L.sgspm_timing_read.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_int64)]
     L.sgspm_check.argtypes = [vp]
@@ -130,10 +136,27 @@ class Plan:
         s = None if src is None else self._ptr(src, self.shape, "src")
         _check(lib.sgspm_step(self._h, self._ptr(m, self.shape, "m"), float(alpha), _d3(h_e), s))
 
+    def steps(self, m, nsteps, alpha, h_e):
+        """nsteps steps with constant alpha and h_e, replayed from a captured HIP graph."""
+        _check(lib.sgspm_steps(self._h, self._ptr(m, self.shape, "m"), int(nsteps), float(alpha), _d3(h_e)))
+
+    def step_spectral_radius(self, m, alpha, h_e, src=None):
+        """One step (as step) and (rho(G_GS), rho(G_SGS)) of its sweep matrices."""
+        s = None if src is None else self._ptr(src, self.shape, "src")
+        out = (ctypes.c_double * 2)()
+        _check(lib.sgspm_step_spectral_radius(self._h, self._ptr(m, self.shape, "m"), float(alpha), _d3(h_e), s, out))
+        return out[0], out[1]
+
     def energy(self, m, h_e):
         out = (ctypes.c_double * 5)()
         _check(lib.sgspm_energy(self._h, self._ptr(m, self.shape, "m"), _d3(h_e), out))
         return dict(zip(("total", "exchange", "anisotropy", "stray", "zeeman"), list(out)))
+
+    def unit_error(self, m):
+        """max over cells of | |m| - 1 |."""
+        out = ctypes.c_double()
+        _check(lib.sgspm_unit_error(self._h, self._ptr(m, self.shape, "m"), ctypes.byref(out)))
+        return out.value
 
     def field(self, m, h_e, out=None):
         import torch
@@ -167,6 +190,17 @@ class Plan:
             raise ValueError("grad must be a contiguous CUDA float64 tensor of 4 values")
         _check(lib.sgspm_adjoint_step_noalloc(self._h, self._ptr(m_n, self.shape, "m_n"), float(alpha), _d3(h_e),
                                               self._ptr(lam, self.shape, "lam"), ctypes.c_void_p(grad.data_ptr())))
+
+    def demag_tensor(self, comp, out=None):
+        """Real-space FP64 tensor component comp (0..5 = xx yy zz xy xz yz) on the padded grid (Pz, Py, Px)."""
+        import torch
+        P = tuple(2 * n if n > 1 else 1 for n in self.n)
+        shp = (P[2], P[1], P[0])
+        out = torch.empty(shp, dtype=torch.float64, device="cuda") if out is None else out
+        if not out.is_cuda or out.dtype != torch.float64 or not out.is_contiguous() or tuple(out.shape) != shp:
+            raise ValueError(f"out must be a contiguous CUDA float64 tensor of shape {shp}")
+        _check(lib.sgspm_demag_tensor(self._h, int(comp), ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def timing(self, enable=True):
         _check(lib.sgspm_timing(self._h, 1 if enable else 0))

@@ -223,6 +223,17 @@ void launch_adj_damp(const T* lw, const T* u, const T* nrm, const T* const uF[3]
                      int nz, double ecx, double ecy, double ecz, double Q, const double he[3], double dt, double wdh,
                      double* partials, int nblocks, double* grad, hipStream_t s);
 
+// Spectral radii of the sweep matrices of the last step from its precession
+// solves g = {g2^n, g3^n, g1*, g2*, g3**, g2**} (coefficients eps dt Lap_h g,
+// k_a = eps dt / h_a^2, 0 for an axis of one cell): out[0] = rho(G_GS),
+// out[1] = rho(G_SGS) (only if sgs; else 0).  Power-of-two extents.
+template <typename T>
+void launch_rho(const T* const g[6], int nx, int ny, int nz, double kx, double ky, double kz, int sgs,
+                double* partials, int nblocks, double* out, hipStream_t s);
+
+// out[0] = max over cells of | |m| - 1 | in FP64 (out[1] is overwritten).
+template <typename T> void launch_unit_error(const T* m, long N, double* partials, int nblocks, double* out, hipStream_t s);
+
 // Pointwise and reduction kernels.
 template <typename T>
 void launch_field_assemble(const T* m, const T* hs, T* out, int nx, int ny, int nz, double cxx, double cyy, double czz,

@@ -1602,6 +1602,108 @@ __global__ __launch_bounds__(NT) void k_energy_final(const double* partials, int
 }
 
 // ---------------------------------------------------------------------------
+// Spectral radius of the sweep matrices (paper §4, eqs. GS-matrix and SGS-matrix):
+// per cell the coefficients c = eps dt Lap_h g of the step's six precession
+// solves (7-point stencil, mirror ghosts), the 3x3 iteration matrices
+// G_GS = (D - L)^{-1} U and G_SGS = (D - U)^{-1} L G_GS, whose first columns
+// vanish, so that rho is the larger modulus of the eigenvalues of the trailing
+// 2x2 block; block maxima into partials[4 b], partials[4 b + 1].
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ double rho2(double p, double q, double r, double s) {
+  const double tr = p + s, det = p * s - q * r, disc = tr * tr - 4.0 * det;
+  return disc >= 0.0 ? 0.5 * (fabs(tr) + sqrt(disc)) : sqrt(det);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_rho(const T* g2n, const T* g3n, const T* g1s, const T* g2s, const T* g3ss,
+                                            const T* g2ss, int nx, int ny, int nz, double kx, double ky, double kz,
+                                            int sgs, double* partials) {
+  const int N = nx * ny * nz, lx = __builtin_ctz(nx), lxy = lx + __builtin_ctz(ny), nxy = nx * ny;
+  double rg = 0.0, rs = 0.0;
+  for (int idx = blockIdx.x * NT + threadIdx.x; idx < N; idx += gridDim.x * NT) {
+    const int x = idx & (nx - 1), y = (idx >> lx) & (ny - 1), z = idx >> lxy;
+    const int xm = x > 0 ? idx - 1 : idx, xp = x < nx - 1 ? idx + 1 : idx;
+    const int ym = y > 0 ? idx - nx : idx, yp = y < ny - 1 ? idx + nx : idx;
+    const int zm = z > 0 ? idx - nxy : idx, zp = z < nz - 1 ? idx + nxy : idx;
+    auto lap = [&](const T* g) {
+      const double c = g[idx];
+      return kx * ((double)g[xm] + (double)g[xp] - 2.0 * c) + ky * ((double)g[ym] + (double)g[yp] - 2.0 * c) +
+             kz * ((double)g[zm] + (double)g[zp] - 2.0 * c);
+    };
+    const double a = lap(g3n), b = lap(g2n), c = lap(g1s), d = lap(g2s);
+    // G_GS by forward substitution of (D - L) with D - L = [[1,0,0],[-a,1,0],[d,-c,1]]
+    // and U = [[0,-a,b],[0,0,-c],[0,0,0]]: columns 1 and 2
+    const double g01 = -a, g02 = b;
+    const double g11 = -a * a, g12 = a * b - c;
+    const double g21 = a * d - a * a * c, g22 = a * b * c - b * d - c * c;
+    rg = fmax(rg, rho2(g11, g12, g21, g22));
+    if (sgs) {
+      const double e = lap(g3ss), f = lap(g2ss);
+      // Y = L G_GS with L = [[0,0,0],[e,0,0],[-d,c,0]], then back substitution of
+      // D - U = [[1,e,-f],[0,1,c],[0,0,1]]: rows 1 and 2
+      const double y11 = e * g01, y12 = e * g02;
+      const double y21 = -d * g01 + c * g11, y22 = -d * g02 + c * g12;
+      const double x21 = y21, x22 = y22;
+      const double x11 = y11 - c * x21, x12 = y12 - c * x22;
+      rs = fmax(rs, rho2(x11, x12, x21, x22));
+    }
+  }
+  __shared__ double red[2][NT / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double mg = wave_max(rg), ms = wave_max(rs);
+  if (lane == 0) {
+    red[0][wv] = mg;
+    red[1][wv] = ms;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double v = 0.0;
+    for (int w = 0; w < NT / 64; ++w) v = fmax(v, red[threadIdx.x][w]);
+    partials[(long)blockIdx.x * 4 + threadIdx.x] = v;
+  }
+}
+
+// max over cells of | |m| - 1 | (FP64), block maxima into partials[4 b]
+template <typename T>
+__global__ __launch_bounds__(NT) void k_unit_error(const T* m, long N, double* partials) {
+  double v = 0.0;
+  for (long idx = blockIdx.x * (long)NT + threadIdx.x; idx < N; idx += (long)gridDim.x * NT) {
+    const double a = m[idx], b = m[N + idx], c = m[2 * N + idx];
+    v = fmax(v, fabs(sqrt(a * a + b * b + c * c) - 1.0));
+  }
+  __shared__ double red[NT / 64];
+  const double w = wave_max(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int k = 0; k < NT / 64; ++k) r = fmax(r, red[k]);
+    partials[(long)blockIdx.x * 4] = r;
+    partials[(long)blockIdx.x * 4 + 1] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_rho_final(const double* partials, int nblocks, double* out) {
+  __shared__ double red[2][NT];
+  for (int k = 0; k < 2; ++k) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += NT) v = fmax(v, partials[(long)b * 4 + k]);
+    red[k][threadIdx.x] = v;
+  }
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < 2; ++k) red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 2) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint helpers
 template <typename T> struct PwPack {
   PwTerm<T> t[PW_MAX];
@@ -2632,6 +2734,19 @@ void launch_adj_damp(const T* lw, const T* u, const T* nrm, const T* const uF[3]
                      grad);
 }
 
+template <typename T>
+void launch_rho(const T* const g[6], int nx, int ny, int nz, double kx, double ky, double kz, int sgs,
+                double* partials, int nblocks, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rho<T>, dim3(nblocks), dim3(NT), 0, s, g[0], g[1], g[2], g[3], g[4], g[5], nx, ny, nz, kx, ky,
+                     kz, sgs, partials);
+  hipLaunchKernelGGL(k_rho_final, dim3(1), dim3(NT), 0, s, partials, nblocks, out);
+}
+
+template <typename T> void launch_unit_error(const T* m, long N, double* partials, int nblocks, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_unit_error<T>, dim3(nblocks), dim3(NT), 0, s, m, N, partials);
+  hipLaunchKernelGGL(k_rho_final, dim3(1), dim3(NT), 0, s, partials, nblocks, out);
+}
+
 #define SGSPM_INSTANTIATE(T)                                                                                          \
   template int launch_row_fwd<T>(const RowFwd<T>&, int, hipStream_t);                                              \
   template int launch_row_inv<T>(const RowInv<T>&, hipStream_t);                                                   \
@@ -2651,7 +2766,10 @@ void launch_adj_damp(const T* lw, const T* u, const T* nrm, const T* const uF[3]
                                hipStream_t);                                                                        \
   template void launch_adj_damp<T>(const T*, const T*, const T*, const T* const*, const T*, int, int, int, double,  \
                                    double, double, double, const double*, double, double, double*, int, double*,   \
-                                   hipStream_t);
+                                   hipStream_t);                                                                    \
+  template void launch_rho<T>(const T* const*, int, int, int, double, double, double, int, double*, int, double*,   \
+                              hipStream_t);                                                                         \
+  template void launch_unit_error<T>(const T*, long, double*, int, double*, hipStream_t);
 
 SGSPM_INSTANTIATE(float)
 SGSPM_INSTANTIATE(double)

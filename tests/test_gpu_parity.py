@@ -2,8 +2,9 @@
 element by element, on the same seeded inputs.
 
 Tolerances: FP64 plans agree with the oracle to rounding (1e-12 relative on
-the linear operators; the stray field to 1e-10, bounded by the FP64 Newell
-cancellation of ~1e-12 per tensor entry); FP32 plans to a few FP32 ulps scaled
+the linear operators; the stray field to the classical FFT rounding bound once
+the measured difference of the two FP64 Newell tensors is taken out, and that
+difference entry by entry to a bound pinned on the CPU); FP32 plans to a few FP32 ulps scaled
 by the transform depth (5e-6 relative on linear operators), and to 1e-5 max-abs
 in m after 1000 steps of the 128x64 film (the stated target).
 """
@@ -11,9 +12,12 @@ import functools
 
 import numpy as np
 import pytest
+from scipy import fft as sfft
+
+import newell_bounds as nb
 
 import workloads
-from oracle import demag, manufactured as mf, operators, scheme
+from oracle import demag, manufactured as mf, operators, scheme, spectral
 
 from helpers import (gpu_plan_reduced, gpu_plan_si, oracle_field_si, oracle_problem_si, rounded_like,
                      to_dev)
@@ -77,6 +81,32 @@ def _spectra(shape):
     return demag.kernel_spectra(shape, CELL)
 
 
+@functools.lru_cache(maxsize=1)
+def _padded(shape, h):
+    return nb.padded_tensor(shape, h)
+
+
+@pytest.mark.parametrize("n,h", [((8, 4, 2), CELL), ((16, 8, 4), (4e-9, 4e-9, 2e-9)), ((64, 32, 8), CELL),
+                                 ((32, 1, 1), CELL), ((256, 256, 32), CELL)],
+                         ids=lambda v: "x".join(map(str, v)) if isinstance(v[0], int) else "x".join(f"{x:g}" for x in v))
+def test_demag_tensor(env, n, h):
+    """The FP64 demagnetising tensor the plan builds, entry by entry against the oracle's,
+    within the per-entry rounding bound of two FP64 evaluations (2 KAPPA u S(d) for the
+    Newell sums, which cancel, KAPPA pinned on the CPU; 8 u |N| for the dipole form)."""
+    torch, sg = env
+    shape = (n[2], n[1], n[0])
+    plan = gpu_plan_si(sg, n, h, DT, ALL, 1)
+    No, offs = nb.padded_tensor(shape, h)
+    bound = nb.entry_bound(shape, h, No, offs)
+    worst = 0.0
+    for k, c in enumerate(demag.COMPONENTS):
+        Ng = plan.demag_tensor(k).cpu().numpy()
+        d = np.abs(Ng - No[c])
+        assert np.all(d <= bound[c]), (c, float(d.max()))
+        worst = max(worst, float((d / np.where(bound[c] > 0, bound[c], 1.0)).max()))
+    print(f"demag tensor {n} cell {h}: max |N_gpu - N_oracle| / bound = {worst:.3f}")
+
+
 @pytest.mark.parametrize("n", STRAY_SHAPES, ids=lambda n: "x".join(map(str, n)))
 @pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
 def test_stray_field(env, n, prec):
@@ -86,13 +116,27 @@ def test_stray_field(env, n, prec):
     plan = gpu_plan_si(sg, n, CELL, DT, ALL, prec)
     hs = plan.stray(to_dev(torch, m, prec)).cpu().numpy()
     ref = demag.stray_field(rounded_like(m, prec), _spectra(shape))
-    # FP64: the two Newell tensors agree to ~1e-12 per entry (cancellation in the
-    # 27-point sum up to the dipole cut-off); summed over N source cells with random
-    # signs that grows like sqrt(N), so the bar widens past 32768 cells
-    tol = 1e-10 * max(1.0, np.sqrt(m[0].size / 32768)) if prec == 1 else 2e-6
     err = np.abs(hs - ref).max()
-    print(f"stray {'fp64' if prec else 'fp32'} {n}: max abs err {err:.3e} (bar {tol:.1e})")
-    assert err <= tol
+    if prec == 0:
+        print(f"stray fp32 {n}: max abs err {err:.3e} (bar 2e-6)")
+        assert err <= 2e-6
+        return
+    # FP64: the library's tensor and the oracle's differ by the rounding of their
+    # Newell sums (test_demag_tensor bounds it entry by entry).  That difference is
+    # measured here and its field, -(N_gpu - N_oracle) (*) m, taken out exactly; what
+    # remains is the two FFT convolutions' rounding, held to its classical bound.
+    No, _ = _padded(shape, CELL)
+    Pp = demag.padded_shape(shape)
+    dN = {c: plan.demag_tensor(k).cpu().numpy() - No[c] for k, c in enumerate(demag.COMPONENTS)}
+    dh = demag.stray_field(m, (Pp, {c: sfft.rfftn(dN[c]) for c in dN}))
+    resid = np.abs(hs - ref - dh).max()
+    fb = nb.fft_conv_bound(shape, _spectra(shape), m)
+    # worst case over every field with |m_b| <= 1 of the tensor difference's field
+    tens = max(sum(float(np.abs(dN[demag._PAIR[(a, b)]]).sum()) for b in range(3)) for a in range(3))
+    print(f"stray fp64 {n}: max abs err {err:.3e} (bound sum|dN| + fft {tens + fb:.2e}); "
+          f"after removing the tensor difference {resid:.3e} (fft bound {fb:.1e}, ratio {resid / fb:.2f})")
+    assert resid <= fb
+    assert err <= tens + fb
 
 
 @pytest.mark.parametrize("n", [(16, 8, 4), (32, 32, 1), (64, 1, 1), (8, 8, 8), (16, 256, 32)],
@@ -133,8 +177,11 @@ def _run_gpu(plan, torch, m0, alphas, fields, prec, src=None):
     return m.cpu().numpy()
 
 
+SCHEME = {"sgspm": 0, "gspm": 1, "sgspm_ff": 2}
+
+
 def _run_oracle(P, m0, alpha, fields, method="sgspm", src=None):
-    step = scheme.sgspm_step if method == "sgspm" else scheme.gspm_step
+    step = {"sgspm": scheme.sgspm_step, "gspm": scheme.gspm_step, "sgspm_ff": scheme.sgspm_ff_step}[method]
     m = np.asarray(m0, np.float64)
     for n in range(len(fields)):
         m = step(P, m, alpha, fields[n], src=None if src is None else src[n])
@@ -163,13 +210,13 @@ def test_manufactured_film_32x32(env, prec):
 
 @pytest.mark.parametrize("n", [(16, 8, 4), (32, 16, 1), (8, 1, 8), (16, 1, 1), (256, 4, 2), (256, 1, 1)],
                          ids=lambda n: "x".join(map(str, n)))
-@pytest.mark.parametrize("method", ["sgspm", "gspm"])
+@pytest.mark.parametrize("method", ["sgspm", "gspm", "sgspm_ff"])
 def test_full_step_fp64(env, n, method):
     torch, sg = env
     shape = (n[2], n[1], n[0])
     m0 = workloads.random_unit(shape, 103)
     B = [(5e-3, 1e-3, -2e-3)] * 10
-    plan = gpu_plan_si(sg, n, CELL, DT, ALL, 1, scheme_=0 if method == "sgspm" else 1)
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, 1, scheme_=SCHEME[method])
     got = _run_gpu(plan, torch, m0, 0.02, B, 1)
     P = oracle_problem_si(n, CELL, DT, ALL)
     ref = _run_oracle(P, m0, 0.02, [oracle_field_si(b, ALL) for b in B], method)
@@ -338,6 +385,90 @@ def test_gspm_fp32(env, n):
     err = np.abs(got - ref).max()
     print(f"gspm fp32 {n}: max|m - m_oracle| after 10 steps = {err:.3e}")
     assert err <= 1e-5
+
+
+# the frozen-field reading (two stray-field evaluations per step) on the generic
+# kernels, the 512-point / register paths, and at the benchmark's full size
+@pytest.mark.parametrize("n", [(16, 8, 4), (128, 64, 1), (16, 256, 32), (256, 256, 32)],
+                         ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_sgspm_ff_steps(env, n, prec):
+    torch, sg = env
+    shape = (n[2], n[1], n[0])
+    m0 = workloads.random_unit(shape, 107) if n[0] * n[1] * n[2] < 1 << 20 else workloads.box_smoothed_unit(shape, 5)
+    steps = 5 if n[0] * n[1] * n[2] < 1 << 20 else 1
+    B = [(5e-3, 1e-3, -2e-3)] * steps
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, prec, scheme_=2)
+    got = _run_gpu(plan, torch, m0, 0.02, B, prec)
+    P = oracle_problem_si(n, CELL, DT, ALL)
+    ref = _run_oracle(P, rounded_like(m0, prec), 0.02, [oracle_field_si(b, ALL) for b in B], "sgspm_ff")
+    err = np.abs(got - ref).max()
+    print(f"sgspm-ff {'fp64' if prec else 'fp32'} {n}: max|m - m_oracle| after {steps} steps = {err:.3e}")
+    assert err <= (1e-10 if prec == 1 else 1e-5)
+
+
+# spectral radius of the sweep matrices (§4) per step, against the oracle's per-cell
+# eigenvalues, and the step it rides on
+@pytest.mark.parametrize("n", [(16, 8, 4), (128, 64, 1), (16, 256, 32)], ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_spectral_radius(env, n, prec):
+    torch, sg = env
+    shape = (n[2], n[1], n[0])
+    m0 = workloads.random_unit(shape, 108)
+    B = (5e-3, 1e-3, -2e-3)
+    P = oracle_problem_si(n, CELL, DT, ALL)
+    ref = spectral.spectral_radii(P, rounded_like(m0, prec), 0.02, oracle_field_si(B, ALL))
+    m_ref = scheme.sgspm_step(P, rounded_like(m0, prec), 0.02, oracle_field_si(B, ALL))
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, prec)
+    m = to_dev(torch, m0, prec)
+    r = plan.step_spectral_radius(m, 0.02, B)
+    e = [abs(r[k] - ref[k]) / ref[k] for k in range(2)]
+    print(f"spectral radius {'fp64' if prec else 'fp32'} {n}: GS {r[0]:.6e} (oracle {ref[0]:.6e}), "
+          f"SGS {r[1]:.6e} (oracle {ref[1]:.6e}); rel err {e[0]:.1e}, {e[1]:.1e}")
+    bar = 1e-9 if prec == 1 else 1e-5
+    assert max(e) <= bar
+    assert np.abs(m.cpu().numpy() - m_ref).max() <= (1e-10 if prec == 1 else 2e-6)
+    # a GSPM plan reports the forward sweep's radius only
+    gp = gpu_plan_si(sg, n, CELL, DT, ALL, prec, scheme_=1)
+    rg = gp.step_spectral_radius(to_dev(torch, m0, prec), 0.02, B)
+    assert np.isnan(rg[1]) and abs(rg[0] - ref[0]) / ref[0] <= bar
+
+
+@pytest.mark.parametrize("dim", [1, 3])
+def test_energy_decay_sgspm_vs_gspm(env, dim):
+    """The paper's central comparison (§3.1 and §3.2 energy figures, §5.2) on the GPU:
+    exchange only (eps = 1), from eq. (m0-1), FP64, 60 steps of dt = 0.01.  SGSPM's
+    energy falls at every step for every alpha in {0, 0.005, 0.01, 0.1, 0.5}; GSPM's
+    rises at some step for alpha in {0, 0.005, 0.01} and falls for 0.1 and 0.5.  Every
+    energy also matches the oracle's along its own trajectory."""
+    torch, sg = env
+    n = (64, 1, 1) if dim == 1 else (16, 16, 16)
+    shape = (n[2], n[1], n[0])
+    h = tuple(1.0 / k if k > 1 else 1.0 for k in n)
+    P = scheme.Problem(n=n, h=h, eps=1.0, dt=0.01)
+    steps = 60
+    worst = 0.0
+    for method, alphas in (("sgspm", (0.0, 0.005, 0.01, 0.1, 0.5)), ("gspm", (0.0, 0.005, 0.01, 0.1, 0.5))):
+        plan = gpu_plan_reduced(sg, n, h, 0.01, 1.0, 0.0, ("exchange",), 1, scheme_=SCHEME[method])
+        ostep = scheme.sgspm_step if method == "sgspm" else scheme.gspm_step
+        for alpha in alphas:
+            m = to_dev(torch, workloads.paper_ic(shape), 1)
+            ref = workloads.paper_ic(shape)
+            E = [plan.energy(m, (0, 0, 0))["total"]]
+            for _ in range(steps):
+                plan.step(m, alpha, (0.0, 0.0, 0.0))
+                ref = ostep(P, ref, alpha, (0, 0, 0))
+                E.append(plan.energy(m, (0, 0, 0))["total"])
+                er = scheme.energies(P, ref, (0, 0, 0))["total"]
+                worst = max(worst, abs(E[-1] - er) / abs(er))
+            dE = np.diff(E)
+            print(f"{dim}-D {method} alpha {alpha}: E0 {E[0]:.6e}, E_end {E[-1]:.6e}, max step change {dE.max():+.3e}")
+            if method == "sgspm" or alpha >= 0.1:
+                assert np.all(dE < 0), (method, alpha)
+            else:
+                # GSPM's energy rises for alpha <= 0.01 on this start (the oracle agrees)
+                assert dE.max() > 0, (method, alpha)
+    assert worst <= 1e-10
 
 
 @pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])

@@ -176,3 +176,27 @@ def test_stray_operator_is_symmetric():
     u, v = rng.normal(size=(2, 3) + shape)
     assert np.sum(v * demag.stray_field(u, spec)) == pytest.approx(
         np.sum(u * demag.stray_field(v, spec)), rel=1e-12)
+
+
+@pytest.mark.parametrize("h,r", [((1.0, 1.0, 1.0), 20), ((4.0, 4.0, 2.0), 12)], ids=["cubic", "flat"])
+def test_oracle_newell_rounding_within_kappa(h, r):
+    """The FP64 Newell sums lose digits to cancellation; measured against the same
+    formulas in extended precision, the oracle's error at every offset of the octant
+    up to r cells stays within KAPPA u S(d), S(d) the sum of the magnitudes of the 27
+    terms.  This fixes the per-entry rounding bound the GPU parity bars are built on."""
+    import newell_bounds as nb
+    rr = np.arange(0, r + 1)
+    IZ, IY, IX = np.meshgrid(rr, rr, rr, indexing="ij")
+    n64 = demag.tensor_at(IX, IY, IZ, h, r_far=10 ** 9)
+    nld = nb.long_double_newell(IX, IY, IZ, h)
+    s = max(h)
+    e = [hh / s for hh in h]
+    P = [IX * e[0], IY * e[1], IZ * e[2]]
+    worst = 0.0
+    for c, (fn, o) in nb._SPEC.items():
+        F = demag.newell_f if fn == "f" else demag.newell_g
+        S = nb._stencil_abs(F, P[o[0]], P[o[1]], P[o[2]], e[o[0]], e[o[1]], e[o[2]])
+        err = np.abs(n64[c] - nld[c].astype(np.float64))
+        worst = max(worst, float((err / (nb.U * S + 1e-300)).max()))
+        assert np.all(err <= nb.KAPPA * nb.U * S + 4 * nb.U * np.abs(n64[c])), c
+    print(f"max FP64 Newell error / (u S): {worst:.2f}")

@@ -116,7 +116,8 @@ def _ll_rhs(P, m, alpha, he):
     return -mxh - alpha * np.cross(m, mxh, axis=0)
 
 
-def test_first_order_with_all_fields_against_rk4():
+@pytest.mark.parametrize("method", ["sgspm", "sgspm_ff"])
+def test_first_order_with_all_fields_against_rk4(method):
     """SGSPM with exchange, anisotropy, stray field and applied field on a small block
     converges at first order in dt to the semi-discrete equation, integrated here by
     classical RK4 with a small step (an integrator that shares nothing with the
@@ -141,11 +142,49 @@ def test_first_order_with_all_fields_against_rk4():
     for dt in (0.02, 0.01, 0.005):
         P = scheme.Problem(n=n, h=(1.0, 1.0, 1.0), eps=0.5, dt=dt, Q=0.3, stray=True)
         mm = m0.copy()
+        step = scheme.sgspm_step if method == "sgspm" else scheme.sgspm_ff_step
         for _ in range(int(round(T / dt))):
-            mm = scheme.sgspm_step(P, mm, alpha, he)
+            mm = step(P, mm, alpha, he)
         errs.append(float(np.abs(mm - ref).max()))
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all((orders > 0.85) & (orders < 1.2)), (errs, orders)
+
+
+def test_frozen_field_reading_equals_latest_state_for_constant_fields():
+    """With exchange and a constant applied field only, f does not depend on the state,
+    so freezing it changes nothing: the two readings coincide to rounding."""
+    n = (8, 4, 2)
+    m0 = _random_unit(n[::-1], 11)
+    P = scheme.Problem(n=n, h=(0.5, 0.5, 0.5), eps=0.3, dt=0.01, Q=0.0, stray=False)
+    he = (0.2, -0.1, 0.05)
+    a = scheme.sgspm_step(P, m0, 0.05, he)
+    b = scheme.sgspm_ff_step(P, m0, 0.05, he)
+    assert np.abs(a - b).max() <= 1e-15
+    # with anisotropy the readings differ at first order in dt
+    Pq = scheme.Problem(n=n, h=(0.5, 0.5, 0.5), eps=0.3, dt=0.01, Q=0.4, stray=False)
+    d = np.abs(scheme.sgspm_step(Pq, m0, 0.05, he) - scheme.sgspm_ff_step(Pq, m0, 0.05, he)).max()
+    assert 1e-7 < d < 1e-3
+
+
+@pytest.mark.parametrize("method,calls", [("sgspm", 6), ("sgspm_ff", 2), ("gspm", 4)])
+def test_stray_field_evaluations_per_step(method, calls):
+    """The cost that separates the readings: the latest-state SGSPM evaluates the stray
+    field six times per step (stages A to E and Step 2), GSPM four times, the frozen-field
+    reading twice (once at m^n, once at m**)."""
+    n = (4, 4, 2)
+    P = scheme.Problem(n=n, h=(1.0, 1.0, 1.0), eps=0.5, dt=0.01, Q=0.3, stray=True)
+    count = [0]
+    orig = P.stray_field
+
+    def counted(u):
+        count[0] += 1
+        return orig(u)
+
+    P.stray_field = counted
+    step = {"sgspm": scheme.sgspm_step, "sgspm_ff": scheme.sgspm_ff_step, "gspm": scheme.gspm_step}[method]
+    m1 = step(P, _random_unit(n[::-1], 12), 0.1, (0.0, 0.0, 0.1))
+    assert count[0] == calls
+    assert np.abs(np.sqrt(np.sum(m1 * m1, axis=0)) - 1.0).max() <= 4e-16
 
 
 def test_fixed_points():
