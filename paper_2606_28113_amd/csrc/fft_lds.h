@@ -1,11 +1,13 @@
 // In-LDS complex FFT engine for gfx950 (wave64, 256-thread workgroups).
 //
 // A workgroup holds a tile of pencils in LDS and transforms all of them along
-// their length L = 2^lgL with self-sorting Stockham stages (radix 8, plus one
-// radix-4 or radix-2 stage when lgL is not a multiple of 3).  Every stage is
-// done in place: each thread loads its butterflies into registers, the group
-// synchronises, then every thread stores its results.  Each thread owns at
-// most VPT complex values per stage, so a tile holds at most VPT * NT values.
+// their length L = 2^a 3^b 5^c with self-sorting Stockham stages (radix 8, one
+// radix-4 or radix-2 stage when a is not a multiple of 3, then radix 5 and
+// radix 3).  Every stage is done in place: each thread loads its butterflies
+// into registers, the group synchronises, then every thread stores its
+// results.  Each thread owns ceil(VPT / R) butterflies of a radix-R stage
+// (VPT complex values for the power-of-two radices, a few more for 3 and 5),
+// so a tile holds at most VPT * NT values.
 //
 // Layout of element j of pencil p in the LDS buffer: buf[p * ps + j * es].
 // Pencils are numbered p = c * P + q with q < P = 2^lgP and c < ncomp, which
@@ -14,7 +16,7 @@
 // consecutive threads take consecutive pencils (for element-major layouts,
 // ps = 1), otherwise consecutive elements of one pencil (pencil-major, es = 1).
 //
-// Twiddles: tw[i] = exp(-2 pi i i / Ltw) in LDS with Ltw = L << twshift; an
+// Twiddles: tw[i] = exp(-2 pi i i / Ltw) in LDS with Ltw = L * tws; an
 // inverse transform conjugates them (unnormalised in both directions).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -256,35 +258,82 @@ template <typename T> __device__ __forceinline__ void dft8_first4(cx<T>* v, bool
   v[3] = e3 + w3;
 }
 
+// 3- and 5-point DFTs (forward sign e^{-2 pi i / R}; the inverse conjugates)
+template <typename T> __device__ __forceinline__ void dft3(cx<T>* v, bool inv) {
+  const T h = (T)0.86602540378443864676372317075294;  // sin(2 pi / 3)
+  const cx<T> a = v[0], t1 = v[1] + v[2];
+  const cx<T> t2 = mk<T>(a.x - (T)0.5 * t1.x, a.y - (T)0.5 * t1.y);
+  const cx<T> d = rot(v[1] - v[2], inv);
+  const cx<T> t3 = mk<T>(h * d.x, h * d.y);
+  v[0] = a + t1;
+  v[1] = t2 + t3;
+  v[2] = t2 - t3;
+}
+
+template <typename T> __device__ __forceinline__ void dft5(cx<T>* v, bool inv) {
+  // cos and sin of 2 pi / 5 and 4 pi / 5
+  const T c1 = (T)0.30901699437494742410229341718282, c2 = (T)-0.80901699437494742410229341718282;
+  const T s1 = (T)0.95105651629515357211643933337938, s2 = (T)0.58778525229247312916870595463907;
+  const cx<T> x0 = v[0];
+  const cx<T> t1 = v[1] + v[4], t2 = v[2] + v[3], t3 = v[1] - v[4], t4 = v[2] - v[3];
+  const cx<T> a1 = mk<T>(x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y);
+  const cx<T> a2 = mk<T>(x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y);
+  const cx<T> b1 = rot(mk<T>(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y), inv);
+  const cx<T> b2 = rot(mk<T>(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y), inv);
+  v[0] = x0 + t1 + t2;
+  v[1] = a1 + b1;
+  v[4] = a1 - b1;
+  v[2] = a2 + b2;
+  v[3] = a2 - b2;
+}
+
 template <typename T, int R> __device__ __forceinline__ void dftR(cx<T>* v, bool inv) {
   if constexpr (R == 2) dft2(v, inv);
+  else if constexpr (R == 3) dft3(v, inv);
   else if constexpr (R == 4) dft4(v, inv);
+  else if constexpr (R == 5) dft5(v, inv);
   else dft8(v, inv);
 }
 
-template <int R> struct Lg;
-template <> struct Lg<2> { static constexpr int v = 1; };
-template <> struct Lg<4> { static constexpr int v = 2; };
-template <> struct Lg<8> { static constexpr int v = 3; };
+// Quotient and remainder by a runtime divisor d = 2^lgd (MX false: every length
+// of the launch is a power of two) or any d, by shifts when lgd >= 0 (MX true).
+template <bool MX> __host__ __device__ __forceinline__ int qdiv(int a, int d, int lgd) {
+  if constexpr (!MX) return a >> lgd;
+  else return lgd >= 0 ? a >> lgd : a / d;
+}
+template <bool MX> __host__ __device__ __forceinline__ int qmod(int a, int d, int lgd) {
+  if constexpr (!MX) return a & (d - 1);
+  else return lgd >= 0 ? (a & (d - 1)) : a % d;
+}
+
+// log2 of n if n is a power of two, else -1
+__host__ __device__ __forceinline__ int lg_or_neg(int n) {
+  if (n <= 0 || (n & (n - 1))) return -1;
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
 
 // Geometry of one FFT call.
 struct FftGeom {
-  int lgL;    // transform length 2^lgL
+  int L;      // transform length, a product of 2, 3 and 5
+  int lgL;    // log2 L when L is a power of two, else -1
   int lgP;    // pencils per group 2^lgP
   int ncomp;  // number of groups
   bool pf;    // pencil-fastest thread mapping
   int ps, es; // LDS strides of pencil and element
-  int twshift;
+  int tws;    // twiddle stride: the LDS table holds W_{L tws}^i
 };
 
-template <typename T, int R, int VPT, int NTH>
+// Each thread takes ceil(VPT / R) butterflies of a radix-R stage, so a tile of
+// VPT * NTH complex values fits every stage whatever the radices.
+template <typename T, int R, int VPT, int NTH, bool MX>
 __device__ __forceinline__ void fft_stage(cx<T>* __restrict__ buf, const cx<T>* __restrict__ tw, const FftGeom& g,
-                                          int Ns, bool inv) {
-  constexpr int NB = VPT / R;
-  constexpr int lgR = Lg<R>::v;
-  const int lgLR = g.lgL - lgR;
-  const int LR = 1 << lgLR;
-  const int total = (g.ncomp << g.lgP) << lgLR;
+                                          int Ns, int lgNs, bool inv) {
+  constexpr int NB = (VPT + R - 1) / R;
+  const int LR = g.L / R;
+  const int lgLR = g.lgL >= 0 ? g.lgL - (R == 2 ? 1 : R == 4 ? 2 : 3) : -1;
+  const int total = (g.ncomp << g.lgP) * LR;
   cx<T> v[NB][R];
   int dst[NB];
 #pragma unroll
@@ -296,19 +345,19 @@ __device__ __forceinline__ void fft_stage(cx<T>* __restrict__ buf, const cx<T>* 
       if (g.pf) {
         const int q = b & ((1 << g.lgP) - 1);
         const int rest = b >> g.lgP;
-        j = rest & (LR - 1);
-        p = ((rest >> lgLR) << g.lgP) + q;
+        j = qmod<MX>(rest, LR, lgLR);
+        p = (qdiv<MX>(rest, LR, lgLR) << g.lgP) + q;
       } else {
-        j = b & (LR - 1);
-        p = b >> lgLR;
+        j = qmod<MX>(b, LR, lgLR);
+        p = qdiv<MX>(b, LR, lgLR);
       }
-      const int k = j & (Ns - 1);
+      const int k = qmod<MX>(j, Ns, lgNs);
       const int base = p * g.ps;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = buf[base + (j + r * LR) * g.es];
       if (Ns > 1) {
         // W_{Ns R}^{r k} = W_L^{r k L / (Ns R)}
-        const int stp = (LR / Ns) << g.twshift;
+        const int stp = qdiv<MX>(LR, Ns, lgNs) * g.tws;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           cx<T> w = tw[r * k * stp];
@@ -332,34 +381,59 @@ __device__ __forceinline__ void fft_stage(cx<T>* __restrict__ buf, const cx<T>* 
 }
 
 // Full transform; the caller has synchronised after filling buf.  A workgroup
-// of NTH threads holds at most VPT * NTH values per stage.
-template <typename T, int VPT = Tile<T>::VPT, int NTH = NT>
+// of NTH threads holds at most VPT * NTH values.  Stages: the
+// power-of-two part (one radix-2 or radix-4 stage, then radix 8), then radix 5,
+// then radix 3 (self-sorting Stockham, any order of radices).  MX false compiles
+// the power-of-two stages only (L must then be a power of two).
+template <typename T, int VPT = Tile<T>::VPT, int NTH = NT, bool MX = false>
 __device__ __forceinline__ void fft_lds(cx<T>* __restrict__ buf, const cx<T>* __restrict__ tw, const FftGeom& g,
                                         bool inv) {
-  int Ns = 1;
-  int rem = g.lgL;
-  if (rem % 3 == 1) {
-    fft_stage<T, 2, VPT, NTH>(buf, tw, g, Ns, inv);
-    Ns <<= 1;
-    rem -= 1;
-  } else if (rem % 3 == 2) {
-    fft_stage<T, 4, VPT, NTH>(buf, tw, g, Ns, inv);
-    Ns <<= 2;
-    rem -= 2;
+  int Ns = 1, lgNs = 0;
+  int m = g.L, e2 = 0;
+  if constexpr (MX) {
+    while (!(m & 1)) {
+      m >>= 1;
+      ++e2;
+    }
+  } else {
+    e2 = g.lgL;
   }
-  while (rem > 0) {
-    fft_stage<T, 8, VPT, NTH>(buf, tw, g, Ns, inv);
+  if (e2 % 3 == 1) {
+    fft_stage<T, 2, VPT, NTH, MX>(buf, tw, g, Ns, lgNs, inv);
+    Ns <<= 1;
+    ++lgNs;
+    e2 -= 1;
+  } else if (e2 % 3 == 2) {
+    fft_stage<T, 4, VPT, NTH, MX>(buf, tw, g, Ns, lgNs, inv);
+    Ns <<= 2;
+    lgNs += 2;
+    e2 -= 2;
+  }
+  while (e2 > 0) {
+    fft_stage<T, 8, VPT, NTH, MX>(buf, tw, g, Ns, lgNs, inv);
     Ns <<= 3;
-    rem -= 3;
+    lgNs += 3;
+    e2 -= 3;
+  }
+  if constexpr (MX) {
+    while (m % 5 == 0) {
+      fft_stage<T, 5, VPT, NTH, MX>(buf, tw, g, Ns, -1, inv);
+      Ns *= 5;
+      m /= 5;
+    }
+    while (m % 3 == 0) {
+      fft_stage<T, 3, VPT, NTH, MX>(buf, tw, g, Ns, -1, inv);
+      Ns *= 3;
+      m /= 3;
+    }
   }
 }
 
-// Copy the length-2^lgL twiddle table (from a global table of length 2^lgTw) into LDS.
+// Copy the twiddles W_L^i, i < L, into LDS from a global table whose entry
+// i * stride is W_L^i.
 template <typename T, int NTH = NT>
-__device__ __forceinline__ void load_twiddles(cx<T>* __restrict__ lds, const cx<T>* __restrict__ gtw, int lgL, int lgTw) {
-  const int L = 1 << lgL;
-  const int sh = lgTw - lgL;
-  for (int i = threadIdx.x; i < L; i += NTH) lds[i] = gtw[i << sh];
+__device__ __forceinline__ void load_twiddles(cx<T>* __restrict__ lds, const cx<T>* __restrict__ gtw, int L, int stride) {
+  for (int i = threadIdx.x; i < L; i += NTH) lds[i] = gtw[i * stride];
 }
 
 // Makhoul's reordering for the DCT-II through a length-n FFT:

@@ -34,12 +34,18 @@ __host__ __device__ inline long nyq_off(long row, long pitch, int nyq, bool bloc
 }
 
 // Row kernels (pencils along x; two real rows share one complex FFT).
+// Lengths: every transform length is 2^a 3^b 5^c; each length field n comes
+// with lgN = log2 n when n is a power of two, else -1 (the kernels then divide
+// instead of shifting).  The generic kernels take their twiddles W_Lmax^i from
+// tw[i * twg]; the register kernels (power-of-two lengths only) from
+// tw[i << (lgTw - log2 L)], tw then being the power-of-two table.
 template <typename T> struct RowFwd {
   int nrows;       // real rows per channel
-  int lgN;         // log2 of values per real row
-  int lgLmax;      // log2 of the longest FFT in the launch (sets the tile)
+  int n, lgN;      // values per real row
+  int Lmax, lgLmax;  // the longest FFT in the launch (sets the tile); the others divide it
   int lgP;         // log2 of complex pencils per tile (2P rows)
-  int lgTw;        // log2 length of the global twiddle table
+  int lgTw;        // log2 length of the power-of-two twiddle table
+  int twg;         // stride of W_Lmax in tw (generic kernel)
   const cx<T>* tw;
   // row value v = a[ch] * u + b * (hs + he[ch]) + wc[ch] * w; u and w may be null (0)
   const T* u[3];
@@ -51,14 +57,14 @@ template <typename T> struct RowFwd {
   T* val_out[3];    // optional store of v (may alias u)
   // optional hs by complex-to-real transform (crop) of an x-level spectrum
   const cx<T>* xin[3];
-  int lgLc;
+  int Lc, lgLc;
   int xin_pitch;
   T* hs_out[3];     // optional store of hs
   T* dct_out[3];    // optional type-II DCT of v along x
   int dct_xmajor;   // store it x-major: [nx][nrows] instead of [nrows][nx]
   const cx<T>* dtw; // exp(-i pi k / (2n)), k < n
   cx<T>* xout[3];   // optional zero-padded real-to-complex transform of v
-  int lgLr;
+  int Lr, lgLr;
   int xout_pitch;
   int xpk;          // xin and xout hold the Nyquist bin in the imaginary part of bin 0
 };
@@ -66,7 +72,7 @@ template <typename T> struct RowFwd {
 enum { ROW_OP_NONE = 0, ROW_OP_GS = 1, ROW_OP_PROJECT = 2 };
 
 template <typename T> struct RowInv {
-  int nrows, lgN, lgLmax, lgP, lgTw;
+  int nrows, n, lgN, Lmax, lgLmax, lgP, lgTw, twg;
   const cx<T>* tw;
   const cx<T>* dtw;
   int nch;             // heat arrays to invert along x (1..3)
@@ -91,7 +97,7 @@ template <typename T> struct RowInv {
   int* flag;
   // optional zero-padded real-to-complex transform of `out`
   cx<T>* xout;
-  int lgLr;
+  int Lr, lgLr;
   int xout_pitch;
   int xpk;             // xout holds the Nyquist bin in the imaginary part of bin 0
 };
@@ -101,14 +107,14 @@ enum { COL_DCT_FWD = 0, COL_DCT_INV = 1, COL_DCT_SOLVE = 2 };
 
 template <typename T> struct ColDct {
   int mode;
-  int lgN;           // pencil length
+  int n, lgN;        // pencil length
   int lgP;           // complex pencils per tile (2P real pencils)
   int ni;            // inner extent
   long sa, sb;       // element strides along the axis and along the batch (grid.y)
   T* data[3];        // in place
   const cx<T>* dtw;
   const cx<T>* tw;
-  int lgTw;
+  int twg;           // W_n^i = tw[i * twg]
   // COL_DCT_SOLVE diagonal 1 / (1 + s (lamX[i] + lamB[batch] + lamA[k]))
   const T* lamX;
   const T* lamB;
@@ -117,13 +123,14 @@ template <typename T> struct ColDct {
 };
 
 template <typename T> struct ColFft {
-  int lgL, n_in, n_out, lgP, ni;
+  int L, lgL, n_in, n_out, lgP, ni;
   long sa_in, sb_in, sa_out, sb_out;
   const cx<T>* in[3];
   cx<T>* out[3];
   int inv;
   const cx<T>* tw;
-  int lgTw;
+  int lgTw;          // the 512-point kernel: power-of-two table
+  int twg;           // the generic kernel: W_L^i = tw[i * twg]
   // the x-level side packs the DC and Nyquist columns in column 0 (ni - 1
   // columns are transformed); the y-level side holds them apart, the Nyquist
   // column ni - 1 in the blocked layout (nyq_off)
@@ -135,11 +142,15 @@ template <typename T> struct ColFft {
 // inverse, in place, 2^lgPP planes per workgroup.
 template <typename T> struct YZSolve {
   T* data[3];
-  int nx, lgNy, lgNz, lgPP;
+  int nx, ny, lgNy, nz, lgNz, lgPP;
   const cx<T>* dtwy;
   const cx<T>* dtwz;
-  const cx<T>* tw;
+  const cx<T>* tw;   // the register kernel: power-of-two table of 2^lgTw entries
   int lgTw;
+  const cx<T>* twy;  // the generic kernel: W_ny^i = twy[i * twy_s], W_nz^i = twz[i * twz_s]
+  int twy_s;
+  const cx<T>* twz;
+  int twz_s;
   const T* lamX;
   const T* lamY;
   const T* lamZ;
@@ -148,13 +159,17 @@ template <typename T> struct YZSolve {
 template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStream_t s);
 // largest plane (ny * nz reals) the fused yz solve holds in one workgroup
 template <typename T> constexpr int yz_max_plane() { return sizeof(T) == 4 ? 8192 : 4096; }
+// ny * nz * planes <= this many reals per workgroup (16 per thread of 512)
+constexpr int YZ_MAX_VALUES = 8192;
+// the generic y-z solve holds 2^lgPP planes of ny x nz in one workgroup
+template <typename T> bool yz_fits(int ny, int nz, int lgPP);
 // planes that the register y-z kernel handles in either precision
 inline bool yz_reg_plane(int ny, int nz) { return ny == 256 && nz == 32; }
 
 // Last-axis convolution: FFT of the three component spectra, multiply by the
 // six-component symmetric tensor spectrum, inverse FFT of the requested outputs.
 template <typename T> struct Conv {
-  int lgL, n, lgP, ni;
+  int L, lgL, n, lgP, ni;
   long sa, sb;
   const cx<T>* S[3]; // null = component identically zero
   cx<T>* O[3];       // null = output not requested
@@ -167,7 +182,8 @@ template <typename T> struct Conv {
   int Hb, Pb;        // folded / full length of the batch axis
   int oddc, oddb;    // bitmask of components odd along the pencil / batch axis
   const cx<T>* tw;
-  int lgTw;
+  int lgTw;          // the 64-point kernel: power-of-two table
+  int twg;           // the generic kernel: W_L^i = tw[i * twg]
   int nyqb;          // S and O hold the Nyquist column ni - 1 in the blocked layout over the batch rows
 };
 
@@ -185,8 +201,9 @@ template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s);
 template <typename T> int launch_col_dct(const ColDct<T>& a, int nbatch, int nch, hipStream_t s);
 template <typename T> int launch_col_fft(const ColFft<T>& a, int nbatch, int nch, hipStream_t s);
 template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t s);
-// kx tile (log2) of the convolution for a padded pencil of 2^lgL and nt tensor components
-template <typename T> int conv_lgP(int lgL, int ni, int nt);
+// kx tile (log2) of the convolution for a padded pencil of L and nt tensor components
+// (-1: no tile fits)
+template <typename T> int conv_lgP(int L, int ni, int nt);
 
 // Demagnetising tensor (FP64): fill the padded real array of one component.
 void launch_newell_fill(double* out, int comp, int nx, int ny, int nz, int Px, int Py, int Pz, double hx, double hy,
@@ -226,7 +243,7 @@ void launch_adj_damp(const T* lw, const T* u, const T* nrm, const T* const uF[3]
 // Spectral radii of the sweep matrices of the last step from its precession
 // solves g = {g2^n, g3^n, g1*, g2*, g3**, g2**} (coefficients eps dt Lap_h g,
 // k_a = eps dt / h_a^2, 0 for an axis of one cell): out[0] = rho(G_GS),
-// out[1] = rho(G_SGS) (only if sgs; else 0).  Power-of-two extents.
+// out[1] = rho(G_SGS) (only if sgs; else 0).
 template <typename T>
 void launch_rho(const T* const g[6], int nx, int ny, int nz, double kx, double ky, double kz, int sgs,
                 double* partials, int nblocks, double* out, hipStream_t s);

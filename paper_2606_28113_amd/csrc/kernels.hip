@@ -46,41 +46,40 @@ __device__ __forceinline__ Blk xcd_block() {
 }
 
 // ---------------------------------------------------------------------------
-// Shared row-kernel helpers (tile: P complex pencils = 2P real rows).
+// Shared row-kernel helpers (tile: P complex pencils = 2P real rows).  Lengths
+// are any 2^a 3^b 5^c; qdiv / qmod shift when a length is a power of two.
 
 // Zero-padded real-to-complex transform of the per-thread row values `val`
 // (element e = tid + i NT of the tile) and store of bins 0..Lr/2.
-template <typename T, int NV>
-__device__ __forceinline__ void row_r2c_store(cx<T>* buf, const cx<T>* tw, const T (&val)[NV], int tot, int lgN, int lgLr,
-                                              int lgLmax, int lgP, int row0, int nrows, cx<T>* xout, int pitch,
-                                              bool xpk) {
-  const int n = 1 << lgN;
-  const int Lr = 1 << lgLr;
+template <typename T, int NV, bool MX>
+__device__ __forceinline__ void row_r2c_store(cx<T>* buf, const cx<T>* tw, const T (&val)[NV], int tot, int n, int lgN,
+                                              int Lr, int lgLr, int Lmax, int lgP, int row0, int nrows, cx<T>* xout,
+                                              int pitch, bool xpk) {
   const int P = 1 << lgP;
   T* bufr = reinterpret_cast<T*>(buf);
   const int ps = Lr + 1;
-  for (int t = threadIdx.x; t < (P << lgLr); t += NT) {
-    const int x = t & (Lr - 1);
-    if (x >= n) buf[(t >> lgLr) * ps + x] = zero<T>();
+  for (int t = threadIdx.x; t < P * Lr; t += NT) {
+    const int x = qmod<MX>(t, Lr, lgLr);
+    if (x >= n) buf[qdiv<MX>(t, Lr, lgLr) * ps + x] = zero<T>();
   }
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const int e = threadIdx.x + i * NT;
     if (e < tot) {
-      const int row = e >> lgN, x = e & (n - 1);
+      const int row = qdiv<MX>(e, n, lgN), x = qmod<MX>(e, n, lgN);
       bufr[2 * ((row >> 1) * ps + x) + (row & 1)] = val[i];
     }
   }
   __syncthreads();
-  FftGeom g{lgLr, lgP, 1, false, ps, 1, lgLmax - lgLr};
-  fft_lds(buf, tw, g, false);
+  FftGeom g{Lr, lgLr, lgP, 1, false, ps, 1, Lmax / Lr};
+  fft_lds<T, Tile<T>::VPT, NT, MX>(buf, tw, g, false);
   const int half = Lr >> 1;
-  for (int t = threadIdx.x; t < (P << lgLr); t += NT) {
-    const int k = t & (Lr - 1);
+  for (int t = threadIdx.x; t < P * Lr; t += NT) {
+    const int k = qmod<MX>(t, Lr, lgLr);
     if (k > half || (xpk && k == half)) continue;
-    const int q = t >> lgLr;
+    const int q = qdiv<MX>(t, Lr, lgLr);
     const cx<T> Zk = buf[q * ps + k];
-    const cx<T> Zm = buf[q * ps + ((Lr - k) & (Lr - 1))];
+    const cx<T> Zm = buf[q * ps + (k ? Lr - k : 0)];
     // X_a = (Z_k + conj Z_{-k}) / 2 ; X_b = (Z_k - conj Z_{-k}) / (2i)
     cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
     cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
@@ -102,13 +101,10 @@ __device__ __forceinline__ void row_r2c_store(cx<T>* buf, const cx<T>* tw, const
 // loads of an index issued before either store; the DCT table is optional (a plain
 // r2c launch, such as the tensor build's, passes none)
 template <typename T>
-__device__ __forceinline__ void load_row_tables(cx<T>* tw, cx<T>* dtl, const RowFwd<T>* fa, const RowInv<T>* ia,
-                                                int lgLmax, int n) {
-  const cx<T>* gtw = fa ? fa->tw : ia->tw;
-  const cx<T>* gdt = fa ? fa->dtw : ia->dtw;
-  const int sh = (fa ? fa->lgTw : ia->lgTw) - lgLmax;
-  for (int i = threadIdx.x; i < (1 << lgLmax); i += NT) {
-    const cx<T> a = gtw[i << sh];
+__device__ __forceinline__ void load_row_tables(cx<T>* tw, cx<T>* dtl, const cx<T>* gtw, int twg, const cx<T>* gdt,
+                                                int Lmax, int n) {
+  for (int i = threadIdx.x; i < Lmax; i += NT) {
+    const cx<T> a = gtw[i * twg];
     const cx<T> d = gdt ? gdt[min(i, n - 1)] : zero<T>();
     tw[i] = a;
     if (i < n) dtl[i] = d;
@@ -118,18 +114,18 @@ __device__ __forceinline__ void load_row_tables(cx<T>* tw, cx<T>* dtl, const Row
 // ---------------------------------------------------------------------------
 // Row forward kernel: [c2r of x-level hs] -> v = a u + b (hs + he) ->
 // [DCT-II along x] and/or [zero-padded r2c along x].
-template <typename T>
+template <typename T, bool MX>
 __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NV = 2 * Tile<T>::VPT, VPT = Tile<T>::VPT;
   const int ch = blockIdx.z;
-  const int Lmax = 1 << A.lgLmax;
+  const int Lmax = A.Lmax;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + Lmax;
   const int P = 1 << A.lgP;
   const int row0 = blockIdx.x * 2 * P;
-  const int n = 1 << A.lgN;
-  const int tot = (2 * P) << A.lgN;
+  const int n = A.n, lgN = A.lgN;
+  const int tot = 2 * P * n;
   // the DCT twiddles in LDS after the tile (no global load among the stores)
   cx<T>* dtl = buf + P * (Lmax + 1);
   T hs[NV];
@@ -137,7 +133,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
   for (int i = 0; i < NV; ++i) hs[i] = (T)0;
 
   const cx<T>* xin = A.xin[ch];
-  const int Lc = 1 << A.lgLc;
+  const int Lc = A.Lc, lgLc = A.lgLc;
   const int half = Lc >> 1;
   // the spectra first (at most VPT per thread: P Lc fits the tile), then the tables,
   // then the LDS stores: one round trip to memory
@@ -147,8 +143,8 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
     for (int j = 0; j < VPT; ++j) {
       const int t = threadIdx.x + j * NT;
       Ra[j] = Rb[j] = zero<T>();
-      if (t < (P << A.lgLc)) {
-        const int q = t >> A.lgLc, k = t & (Lc - 1);
+      if (t < P * Lc) {
+        const int q = qdiv<MX>(t, Lc, lgLc), k = qmod<MX>(t, Lc, lgLc);
         const int ra = row0 + 2 * q;
         const int kk = k > half ? Lc - k : k;
         const int kl = A.xpk && kk == half ? 0 : kk;  // packed: the Nyquist bin is in bin 0
@@ -157,14 +153,14 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
       }
     }
   }
-  load_row_tables<T>(tw, dtl, &A, nullptr, A.lgLmax, n);
+  load_row_tables<T>(tw, dtl, A.tw, A.twg, A.dtw, Lmax, n);
   __syncthreads();
   if (xin) {
 #pragma unroll
     for (int j = 0; j < VPT; ++j) {
       const int t = threadIdx.x + j * NT;
-      if (t < (P << A.lgLc)) {
-        const int q = t >> A.lgLc, k = t & (Lc - 1);
+      if (t < P * Lc) {
+        const int q = qdiv<MX>(t, Lc, lgLc), k = qmod<MX>(t, Lc, lgLc);
         const bool cj = k > half;
         const int kk = cj ? Lc - k : k;
         cx<T> Xa = Ra[j], Xb = Rb[j];
@@ -184,13 +180,13 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
       }
     }
     __syncthreads();
-    FftGeom g{A.lgLc, A.lgP, 1, false, Lc + 1, 1, A.lgLmax - A.lgLc};
-    fft_lds(buf, tw, g, true);
+    FftGeom g{Lc, lgLc, A.lgP, 1, false, Lc + 1, 1, Lmax / Lc};
+    fft_lds<T, Tile<T>::VPT, NT, MX>(buf, tw, g, true);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const int e = threadIdx.x + i * NT;
       if (e < tot) {
-        const int row = e >> A.lgN, x = e & (n - 1);
+        const int row = qdiv<MX>(e, n, lgN), x = qmod<MX>(e, n, lgN);
         const cx<T> z = buf[(row >> 1) * (Lc + 1) + x];
         hs[i] = (row & 1) ? z.y : z.x;
       }
@@ -208,7 +204,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
   // after (loads and stores share one in-order counter)
   auto cidx = [&](int i) {
     const int e = min((int)threadIdx.x + i * NT, tot - 1);
-    return ((long)min(row0 + (e >> A.lgN), A.nrows - 1) << A.lgN) + (e & (n - 1));
+    return (long)min(row0 + qdiv<MX>(e, n, lgN), A.nrows - 1) * n + qmod<MX>(e, n, lgN);
   };
 #pragma unroll
   for (int i = 0; i < NV; ++i) val[i] = bc * (hs[i] + hec);
@@ -230,10 +226,10 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
   for (int i = 0; i < NV; ++i) {
     const int e = threadIdx.x + i * NT;
     if (e < tot) {
-      const int row = e >> A.lgN, x = e & (n - 1);
+      const int row = qdiv<MX>(e, n, lgN), x = qmod<MX>(e, n, lgN);
       const int grow = row0 + row;
       if (grow < A.nrows) {
-        const long idx = ((long)grow << A.lgN) + x;
+        const long idx = (long)grow * n + x;
         if (hso) hso[idx] = hs[i];
         if (vo) vo[idx] = val[i];
       }
@@ -248,19 +244,19 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
     for (int i = 0; i < NV; ++i) {
       const int e = threadIdx.x + i * NT;
       if (e < tot) {
-        const int row = e >> A.lgN, x = e & (n - 1);
+        const int row = qdiv<MX>(e, n, lgN), x = qmod<MX>(e, n, lgN);
         bufr[2 * ((row >> 1) * ps + makhoul_pos(x, n)) + (row & 1)] = val[i];
       }
     }
     __syncthreads();
-    FftGeom g{A.lgN, A.lgP, 1, false, ps, 1, A.lgLmax - A.lgN};
-    fft_lds(buf, tw, g, false);
-    for (int t = threadIdx.x; t < (P << A.lgN); t += NT) {
+    FftGeom g{n, lgN, A.lgP, 1, false, ps, 1, Lmax / n};
+    fft_lds<T, Tile<T>::VPT, NT, MX>(buf, tw, g, false);
+    for (int t = threadIdx.x; t < P * n; t += NT) {
       // x-major stores take consecutive rows per thread group, row-major consecutive k
-      const int q = A.dct_xmajor ? (t & (P - 1)) : (t >> A.lgN);
-      const int k = A.dct_xmajor ? (t >> A.lgP) : (t & (n - 1));
+      const int q = A.dct_xmajor ? (t & (P - 1)) : qdiv<MX>(t, n, lgN);
+      const int k = A.dct_xmajor ? (t >> A.lgP) : qmod<MX>(t, n, lgN);
       const cx<T> Zk = buf[q * ps + k];
-      const cx<T> Zm = buf[q * ps + ((n - k) & (n - 1))];
+      const cx<T> Zm = buf[q * ps + (k ? n - k : 0)];
       const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
       const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
       const cx<T> w = dtl[k];
@@ -270,8 +266,8 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
         if (ra < A.nrows) dout[(long)k * A.nrows + ra] = xa;
         if (ra + 1 < A.nrows) dout[(long)k * A.nrows + ra + 1] = xb;
       } else {
-        if (ra < A.nrows) dout[((long)ra << A.lgN) + k] = xa;
-        if (ra + 1 < A.nrows) dout[((long)(ra + 1) << A.lgN) + k] = xb;
+        if (ra < A.nrows) dout[(long)ra * n + k] = xa;
+        if (ra + 1 < A.nrows) dout[(long)(ra + 1) * n + k] = xb;
       }
     }
     __syncthreads();
@@ -279,7 +275,7 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
 
   cx<T>* xo = A.xout[ch];
   if (xo)
-    row_r2c_store<T, NV>(buf, tw, val, tot, A.lgN, A.lgLr, A.lgLmax, A.lgP, row0, A.nrows, xo, A.xout_pitch,
+    row_r2c_store<T, NV, MX>(buf, tw, val, tot, n, lgN, A.Lr, A.lgLr, Lmax, A.lgP, row0, A.nrows, xo, A.xout_pitch,
                          A.xpk != 0);
 }
 
@@ -287,19 +283,19 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
 // Row inverse kernel: inverse DCT-II along x of 1..3 heat arrays, then a
 // Gauss-Seidel update or the projection, then optionally the zero-padded r2c
 // transform of the updated component.
-template <typename T>
+template <typename T, bool MX>
 __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NV = 2 * Tile<T>::VPT, VPT = Tile<T>::VPT;
-  const int Lmax = 1 << A.lgLmax;
+  const int Lmax = A.Lmax;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + Lmax;
   const int P = 1 << A.lgP;
   const int row0 = blockIdx.x * 2 * P;
-  const int n = 1 << A.lgN;
-  const int tot = (2 * P) << A.lgN;
+  const int n = A.n, lgN = A.lgN;
+  const int tot = 2 * P * n;
   cx<T>* dtl = buf + P * (Lmax + 1);  // DCT twiddles
-  load_row_tables<T>(tw, dtl, nullptr, &A, A.lgLmax, n);
+  load_row_tables<T>(tw, dtl, A.tw, A.twg, A.dtw, Lmax, n);
   const T invn = (T)1 / (T)n;
   T g[3][NV];
 #pragma unroll
@@ -307,77 +303,79 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) g[c][i] = (T)0;
   }
+  // one channel: inverse x DCT of heat array c into gc (one call per channel, so
+  // that every register array is indexed by constants)
+  auto channel = [&](int c, T(&gc)[NV]) {
+    __syncthreads();
+    const T* H = A.heat[c];
+    const int ps = n + 1;
+    // loads in groups of four rows of the loop (at most VPT per thread), each
+    // group issued before its LDS stores
+    constexpr int CH = 4;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    if (c < A.nch) {
-      __syncthreads();
-      const T* H = A.heat[c];
-      const int ps = n + 1;
-      // loads in groups of four rows of the loop (at most VPT per thread), each
-      // group issued before its LDS stores
-      constexpr int CH = 4;
+    for (int j0 = 0; j0 < VPT; j0 += CH) {
+      T rak[CH], ram[CH], rbk[CH], rbm[CH];
 #pragma unroll
-      for (int j0 = 0; j0 < VPT; j0 += CH) {
-        T rak[CH], ram[CH], rbk[CH], rbm[CH];
-#pragma unroll
-        for (int jj = 0; jj < CH; ++jj) {
-          const int t = threadIdx.x + (j0 + jj) * NT;
-          rak[jj] = ram[jj] = rbk[jj] = rbm[jj] = (T)0;
-          if (t < (P << A.lgN)) {
-            const int q = A.heat_xmajor ? (t & (P - 1)) : (t >> A.lgN);
-            const int k = A.heat_xmajor ? (t >> A.lgP) : (t & (n - 1));
-            const int ra = row0 + 2 * q;
-            if (A.heat_xmajor) {
-              const long nr = A.nrows;
-              if (ra < A.nrows) {
-                rak[jj] = H[(long)k * nr + ra];
-                if (k) ram[jj] = H[(long)(n - k) * nr + ra];
-              }
-              if (ra + 1 < A.nrows) {
-                rbk[jj] = H[(long)k * nr + ra + 1];
-                if (k) rbm[jj] = H[(long)(n - k) * nr + ra + 1];
-              }
-            } else {
-              if (ra < A.nrows) {
-                rak[jj] = H[((long)ra << A.lgN) + k];
-                if (k) ram[jj] = H[((long)ra << A.lgN) + n - k];
-              }
-              if (ra + 1 < A.nrows) {
-                rbk[jj] = H[((long)(ra + 1) << A.lgN) + k];
-                if (k) rbm[jj] = H[((long)(ra + 1) << A.lgN) + n - k];
-              }
+      for (int jj = 0; jj < CH; ++jj) {
+        const int t = threadIdx.x + (j0 + jj) * NT;
+        rak[jj] = ram[jj] = rbk[jj] = rbm[jj] = (T)0;
+        if (t < P * n) {
+          const int q = A.heat_xmajor ? (t & (P - 1)) : qdiv<MX>(t, n, lgN);
+          const int k = A.heat_xmajor ? (t >> A.lgP) : qmod<MX>(t, n, lgN);
+          const int ra = row0 + 2 * q;
+          if (A.heat_xmajor) {
+            const long nr = A.nrows;
+            if (ra < A.nrows) {
+              rak[jj] = H[(long)k * nr + ra];
+              if (k) ram[jj] = H[(long)(n - k) * nr + ra];
+            }
+            if (ra + 1 < A.nrows) {
+              rbk[jj] = H[(long)k * nr + ra + 1];
+              if (k) rbm[jj] = H[(long)(n - k) * nr + ra + 1];
+            }
+          } else {
+            if (ra < A.nrows) {
+              rak[jj] = H[(long)ra * n + k];
+              if (k) ram[jj] = H[(long)ra * n + n - k];
+            }
+            if (ra + 1 < A.nrows) {
+              rbk[jj] = H[(long)(ra + 1) * n + k];
+              if (k) rbm[jj] = H[(long)(ra + 1) * n + n - k];
             }
           }
         }
-#pragma unroll
-        for (int jj = 0; jj < CH; ++jj) {
-          const int t = threadIdx.x + (j0 + jj) * NT;
-          if (t < (P << A.lgN)) {
-            const int q = A.heat_xmajor ? (t & (P - 1)) : (t >> A.lgN);
-            const int k = A.heat_xmajor ? (t >> A.lgP) : (t & (n - 1));
-            const cx<T> w = conjg(dtl[k]);
-            const cx<T> Va = cmul(w, mk<T>(rak[jj], -ram[jj]));
-            const cx<T> Vb = cmul(w, mk<T>(rbk[jj], -rbm[jj]));
-            buf[q * ps + k] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
-          }
-        }
       }
-      __syncthreads();
-      FftGeom gm{A.lgN, A.lgP, 1, false, ps, 1, A.lgLmax - A.lgN};
-      fft_lds(buf, tw, gm, true);
-      T* go = A.gout[c];
 #pragma unroll
-      for (int i = 0; i < NV; ++i) {
-        const int e = threadIdx.x + i * NT;
-        if (e < tot) {
-          const int row = e >> A.lgN, x = e & (n - 1);
-          const cx<T> z = buf[(row >> 1) * ps + makhoul_pos(x, n)];
-          g[c][i] = ((row & 1) ? z.y : z.x) * invn;
-          if (go && row0 + row < A.nrows) go[((long)(row0 + row) << A.lgN) + x] = g[c][i];
+      for (int jj = 0; jj < CH; ++jj) {
+        const int t = threadIdx.x + (j0 + jj) * NT;
+        if (t < P * n) {
+          const int q = A.heat_xmajor ? (t & (P - 1)) : qdiv<MX>(t, n, lgN);
+          const int k = A.heat_xmajor ? (t >> A.lgP) : qmod<MX>(t, n, lgN);
+          const cx<T> w = conjg(dtl[k]);
+          const cx<T> Va = cmul(w, mk<T>(rak[jj], -ram[jj]));
+          const cx<T> Vb = cmul(w, mk<T>(rbk[jj], -rbm[jj]));
+          buf[q * ps + k] = mk<T>(Va.x - Vb.y, Va.y + Vb.x);
         }
       }
     }
-  }
+    __syncthreads();
+    FftGeom gm{n, lgN, A.lgP, 1, false, ps, 1, Lmax / n};
+    fft_lds<T, Tile<T>::VPT, NT, MX>(buf, tw, gm, true);
+    T* go = A.gout[c];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e = threadIdx.x + i * NT;
+      if (e < tot) {
+        const int row = qdiv<MX>(e, n, lgN), x = qmod<MX>(e, n, lgN);
+        const cx<T> z = buf[(row >> 1) * ps + makhoul_pos(x, n)];
+        gc[i] = ((row & 1) ? z.y : z.x) * invn;
+        if (go && row0 + row < A.nrows) go[(long)(row0 + row) * n + x] = gc[i];
+      }
+    }
+  };
+  channel(0, g[0]);
+  if (A.nch > 1) channel(1, g[1]);
+  if (A.nch > 2) channel(2, g[2]);
   __syncthreads();
 
   if (A.op == ROW_OP_GS) {
@@ -388,9 +386,9 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
       const int e = threadIdx.x + i * NT;
       val[i] = (T)0;
       if (e < tot) {
-        const int row = e >> A.lgN, x = e & (n - 1);
+        const int row = qdiv<MX>(e, n, lgN), x = qmod<MX>(e, n, lgN);
         if (row0 + row < A.nrows) {
-          const long idx = ((long)(row0 + row) << A.lgN) + x;
+          const long idx = (long)(row0 + row) * n + x;
           const T pv = A.Pch == 0 ? g[0][i] : (A.Pch == 1 ? g[1][i] : A.Pf[idx]);
           const T rv = A.Rch == 0 ? g[0][i] : (A.Rch == 1 ? g[1][i] : A.Rf[idx]);
           T o = A.base[idx] + pv * A.Qf[idx] - rv * A.Sf[idx];
@@ -403,21 +401,21 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
     for (int i = 0; i < NV; ++i) {
       const int e = threadIdx.x + i * NT;
       if (e < tot) {
-        const int row = e >> A.lgN, x = e & (n - 1);
-        if (row0 + row < A.nrows) A.out[((long)(row0 + row) << A.lgN) + x] = val[i];
+        const int row = qdiv<MX>(e, n, lgN), x = qmod<MX>(e, n, lgN);
+        if (row0 + row < A.nrows) A.out[(long)(row0 + row) * n + x] = val[i];
       }
     }
     if (A.xout)
-      row_r2c_store<T, NV>(buf, tw, val, tot, A.lgN, A.lgLr, A.lgLmax, A.lgP, row0, A.nrows, A.xout, A.xout_pitch,
+      row_r2c_store<T, NV, MX>(buf, tw, val, tot, n, lgN, A.Lr, A.lgLr, Lmax, A.lgP, row0, A.nrows, A.xout, A.xout_pitch,
                            A.xpk != 0);
   } else if (A.op == ROW_OP_PROJECT) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const int e = threadIdx.x + i * NT;
       if (e < tot) {
-        const int row = e >> A.lgN, x = e & (n - 1);
+        const int row = qdiv<MX>(e, n, lgN), x = qmod<MX>(e, n, lgN);
         if (row0 + row < A.nrows) {
-          const long idx = ((long)(row0 + row) << A.lgN) + x;
+          const long idx = (long)(row0 + row) * n + x;
           const T c0 = g[0][i], c1 = g[1][i], c2 = g[2][i];
           const T nr = sqrt(c0 * c0 + c1 * c1 + c2 * c2);
           if (!(nr > (T)0) || !isfinite(nr)) A.flag[0] = 1;
@@ -436,14 +434,14 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
 // Column DCT kernel (in place): forward DCT-II, inverse, or the full heat solve
 // along the pencil axis (forward, diagonal, inverse).  Real pencils
 // i0 + q and i0 + q + P share complex pencil q; LDS layout buf[j * P + q].
-template <typename T>
+template <typename T, bool MX>
 __global__ __launch_bounds__(NT) void k_col_dct(const ColDct<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int VPT = Tile<T>::VPT;
-  const int n = 1 << A.lgN;
+  const int n = A.n, lgN = A.lgN;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + n;
-  load_twiddles(tw, A.tw, A.lgN, A.lgTw);
+  load_twiddles(tw, A.tw, n, A.twg);
   const int P = 1 << A.lgP;
   const int i0 = blockIdx.x * 2 * P;
   const int b = blockIdx.y;
@@ -453,24 +451,24 @@ __global__ __launch_bounds__(NT) void k_col_dct(const ColDct<T> A) {
   __syncthreads();
 
   if (A.mode == COL_DCT_FWD || A.mode == COL_DCT_SOLVE) {
-    for (int t = threadIdx.x; t < ((2 * P) << A.lgN); t += NT) {
+    for (int t = threadIdx.x; t < 2 * P * n; t += NT) {
       const int j = t >> (A.lgP + 1), ii = t & (2 * P - 1);
       const int i = i0 + ii;
       const T v = (i < A.ni) ? D[(long)j * A.sa + i] : (T)0;
       bufr[2 * (makhoul_pos(j, n) * P + (ii & (P - 1))) + (ii >> A.lgP)] = v;
     }
     __syncthreads();
-    FftGeom g{A.lgN, A.lgP, 1, true, 1, P, 0};
-    fft_lds(buf, tw, g, false);
+    FftGeom g{n, lgN, A.lgP, 1, true, 1, P, 1};
+    fft_lds<T, Tile<T>::VPT, NT, MX>(buf, tw, g, false);
     T xa[VPT], xb[VPT];
 #pragma unroll
     for (int s = 0; s < VPT; ++s) {
       const int t = threadIdx.x + s * NT;
       xa[s] = xb[s] = (T)0;
-      if (t < (P << A.lgN)) {
+      if (t < P * n) {
         const int k = t >> A.lgP, q = t & (P - 1);
         const cx<T> Zk = buf[k * P + q];
-        const cx<T> Zm = buf[((n - k) & (n - 1)) * P + q];
+        const cx<T> Zm = buf[(k ? n - k : 0) * P + q];
         const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
         const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
         const cx<T> w = A.dtw[k];
@@ -492,7 +490,7 @@ __global__ __launch_bounds__(NT) void k_col_dct(const ColDct<T> A) {
 #pragma unroll
     for (int s = 0; s < VPT; ++s) {
       const int t = threadIdx.x + s * NT;
-      if (t < (P << A.lgN)) buf[t] = mk<T>(xa[s], xb[s]);
+      if (t < P * n) buf[t] = mk<T>(xa[s], xb[s]);
     }
     __syncthreads();
   }
@@ -504,7 +502,7 @@ __global__ __launch_bounds__(NT) void k_col_dct(const ColDct<T> A) {
     for (int s = 0; s < VPT; ++s) {
       const int t = threadIdx.x + s * NT;
       z[s] = zero<T>();
-      if (t < (P << A.lgN)) {
+      if (t < P * n) {
         const int k = t >> A.lgP, q = t & (P - 1);
         T xak, xam = 0, xbk, xbm = 0;
         if (A.mode == COL_DCT_INV) {
@@ -535,12 +533,12 @@ __global__ __launch_bounds__(NT) void k_col_dct(const ColDct<T> A) {
 #pragma unroll
     for (int s = 0; s < VPT; ++s) {
       const int t = threadIdx.x + s * NT;
-      if (t < (P << A.lgN)) buf[t] = z[s];
+      if (t < P * n) buf[t] = z[s];
     }
     __syncthreads();
-    FftGeom g{A.lgN, A.lgP, 1, true, 1, P, 0};
-    fft_lds(buf, tw, g, true);
-    for (int t = threadIdx.x; t < ((2 * P) << A.lgN); t += NT) {
+    FftGeom g{n, lgN, A.lgP, 1, true, 1, P, 1};
+    fft_lds<T, Tile<T>::VPT, NT, MX>(buf, tw, g, true);
+    for (int t = threadIdx.x; t < 2 * P * n; t += NT) {
       const int j = t >> (A.lgP + 1), ii = t & (2 * P - 1);
       const int i = i0 + ii;
       if (i < A.ni) D[(long)j * A.sa + i] = bufr[2 * (makhoul_pos(j, n) * P + (ii & (P - 1))) + (ii >> A.lgP)] * invn;
@@ -552,30 +550,31 @@ __global__ __launch_bounds__(NT) void k_col_dct(const ColDct<T> A) {
 // ---------------------------------------------------------------------------
 // Fused yz heat solve on x-major planes.  Values travel between the passes in
 // registers; each pass scatters them into an element-major LDS layout with a
-// padded pencil stride (es = pencils + 1) and two real pencils per complex one.
+// padded pencil stride (es = pencils + 1) and two real pencils per complex one
+// (pencil rho in slot rho mod H, real or imaginary part by rho / H, with H the
+// number of complex pencils, ceil(real pencils / 2)).
 constexpr int YZ_NT = 512;
 constexpr int YZ_VPT = 8;
 
-template <typename T>
+template <typename T, bool MX>
 __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NTH = YZ_NT;
   constexpr int NV = 2 * YZ_VPT;  // reals per thread
-  const int ny = 1 << A.lgNy, nz = 1 << A.lgNz;
-  const int lgM = A.lgNy + A.lgNz;
-  const int lgR = lgM + A.lgPP;
-  const int R = 1 << lgR;
-  const int lgL = max(A.lgNy, A.lgNz);
-  // y pass: real pencils rho = (p, z), 2^lgPy of them, paired rho <-> rho + Hy
-  const int lgPy = A.lgPP + A.lgNz;
-  const int lgHy = max(0, lgPy - 1), Hy = 1 << lgHy, esy = Hy + 1;
-  // z pass: real pencils rho' = (p, ky)
-  const int lgPz = A.lgPP + A.lgNy;
-  const int lgHz = max(0, lgPz - 1), Hz = 1 << lgHz, esz = Hz + 1;
+  const int ny = A.ny, nz = A.nz, lgNy = A.lgNy, lgNz = A.lgNz;
+  const int M = ny * nz;
   const int PP = 1 << A.lgPP;
-  // LDS: twiddles, the transpose buffer, then the DCT twiddles and eigenvalues
-  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* buf = tw + (1 << lgL);
+  const int R = M * PP;
+  // y pass: real pencils rho = (p, z), NPy of them, paired rho <-> rho + Hy
+  const int NPy = PP * nz, Hy = (NPy + 1) >> 1, esy = Hy + 1;
+  const int lgHy = lg_or_neg(Hy);
+  // z pass: real pencils rho' = (p, ky)
+  const int NPz = PP * ny, Hz = (NPz + 1) >> 1, esz = Hz + 1;
+  const int lgHz = lg_or_neg(Hz);
+  // LDS: the y and z twiddles, the transpose buffer, then the DCT twiddles and eigenvalues
+  cx<T>* Wy = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* Wz = Wy + ny;
+  cx<T>* buf = Wz + nz;
   T* bufr = reinterpret_cast<T*>(buf);
   cx<T>* Dy = buf + max(ny * esy, nz * esz);
   cx<T>* Dz = Dy + ny;
@@ -584,87 +583,95 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
   T* Lx = Lz + nz;
   const int p0 = blockIdx.x << A.lgPP;
   const int nplanes = min(PP, A.nx - p0);
-  T* D = A.data[blockIdx.z] + ((long)p0 << lgM);
+  T* D = A.data[blockIdx.z] + (long)p0 * M;
   // one round trip to memory: the planes, then the tables (each table loop loads
   // before it stores)
   T v[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const int e = threadIdx.x + i * NTH;
-    v[i] = (e < R && (e >> lgM) < nplanes) ? D[e] : (T)0;
+    v[i] = (e < R && e < nplanes * M) ? D[e] : (T)0;
   }
   {
-    const int L = 1 << lgL, sh = A.lgTw - lgL, nt = max(L, PP);
+    const int nt = max(max(ny, nz), PP);
     for (int i = threadIdx.x; i < nt; i += NTH) {
-      const cx<T> a = A.tw[min(i, L - 1) << sh];
-      const cx<T> dy = A.dtwy[min(i, ny - 1)], dz = A.dtwz[min(i, nz - 1)];
-      const T ly = A.lamY[min(i, ny - 1)], lz = A.lamZ[min(i, nz - 1)];
+      const int iy = min(i, ny - 1), iz = min(i, nz - 1);
+      const cx<T> wy = A.twy[iy * A.twy_s], wz = A.twz[iz * A.twz_s];
+      const cx<T> dy = A.dtwy[iy], dz = A.dtwz[iz];
+      const T ly = A.lamY[iy], lz = A.lamZ[iz];
       const T lx = A.lamX[min(p0 + min(i, PP - 1), A.nx - 1)];
-      if (i < L) tw[i] = a;
       if (i < ny) {
+        Wy[i] = wy;
         Dy[i] = dy;
         Ly[i] = ly;
       }
       if (i < nz) {
+        Wz[i] = wz;
         Dz[i] = dz;
         Lz[i] = lz;
       }
       if (i < PP) Lx[i] = p0 + i < A.nx ? lx : (T)0;
     }
   }
+  // pencils of a pass as (lgP, ncomp) of the FFT engine: a power-of-two count
+  // pencil-fastest, any other as ncomp groups of one
+  const int gyP = lgHy >= 0 ? lgHy : 0, gyC = lgHy >= 0 ? 1 : Hy;
+  const int gzP = lgHz >= 0 ? lgHz : 0, gzC = lgHz >= 0 ? 1 : Hz;
   // current order of v[]: 0 plane order (e = tid + i NTH), 1 after the y pass, 2 after the z pass
   int order = 0;
   auto decode = [&](int i, int& p, int& z, int& y) -> bool {
     if (order == 1) {
       const int t = threadIdx.x + (i >> 1) * NTH, part = i & 1;
-      if (t >= (Hy << A.lgNy) || (part && lgPy == 0)) return false;
-      const int rho = (t & (Hy - 1)) + part * Hy;
-      p = rho >> A.lgNz;
-      z = rho & (nz - 1);
-      y = t >> lgHy;
+      if (t >= Hy * ny) return false;
+      const int rho = qmod<MX>(t, Hy, lgHy) + part * Hy;
+      if (rho >= NPy) return false;
+      p = qdiv<MX>(rho, nz, lgNz);
+      z = qmod<MX>(rho, nz, lgNz);
+      y = qdiv<MX>(t, Hy, lgHy);
       return true;
     }
     if (order == 2) {
       const int t = threadIdx.x + i * NTH;
       if (t >= R) return false;
-      const int rho = t >> A.lgNz;
-      p = rho >> A.lgNy;
-      y = rho & (ny - 1);
-      z = t & (nz - 1);
+      const int rho = qdiv<MX>(t, nz, lgNz);
+      p = qdiv<MX>(rho, ny, lgNy);
+      y = qmod<MX>(rho, ny, lgNy);
+      z = qmod<MX>(t, nz, lgNz);
       return true;
     }
     const int e = threadIdx.x + i * NTH;
     if (e >= R) return false;
-    p = e >> lgM;
-    z = (e >> A.lgNy) & (nz - 1);
-    y = e & (ny - 1);
+    p = e / M;
+    const int r = e - p * M;
+    z = qdiv<MX>(r, ny, lgNy);
+    y = qmod<MX>(r, ny, lgNy);
     return true;
   };
   __syncthreads();
 
   if (ny > 1) {
-    if (lgPy == 0)
+    if (NPy & 1)
       for (int t = threadIdx.x; t < ny * esy; t += NTH) buf[t] = zero<T>();
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       int p, z, y;
       if (decode(i, p, z, y)) {
-        const int rho = (p << A.lgNz) + z;
-        bufr[2 * (makhoul_pos(y, ny) * esy + (rho & (Hy - 1))) + (rho >> lgHy)] = v[i];
+        const int rho = p * nz + z;
+        bufr[2 * (makhoul_pos(y, ny) * esy + qmod<MX>(rho, Hy, lgHy)) + qdiv<MX>(rho, Hy, lgHy)] = v[i];
       }
     }
     __syncthreads();
-    FftGeom g{A.lgNy, lgHy, 1, true, 1, esy, lgL - A.lgNy};
-    fft_lds<T, YZ_VPT, NTH>(buf, tw, g, false);
+    FftGeom g{ny, lgNy, gyP, gyC, true, 1, esy, 1};
+    fft_lds<T, YZ_VPT, NTH, MX>(buf, Wy, g, false);
 #pragma unroll
     for (int s2 = 0; s2 < YZ_VPT; ++s2) {
       const int t = threadIdx.x + s2 * NTH;
       v[2 * s2] = v[2 * s2 + 1] = (T)0;
-      if (t < (Hy << A.lgNy)) {
-        const int k = t >> lgHy, q = t & (Hy - 1);
+      if (t < Hy * ny) {
+        const int k = qdiv<MX>(t, Hy, lgHy), q = qmod<MX>(t, Hy, lgHy);
         const cx<T> Zk = buf[k * esy + q];
-        const cx<T> Zm = buf[((ny - k) & (ny - 1)) * esy + q];
+        const cx<T> Zm = buf[(k ? ny - k : 0) * esy + q];
         const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
         const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
         const cx<T> w = Dy[k];
@@ -677,44 +684,44 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
   }
 
   if (nz > 1) {
-    if (lgPz == 0)
+    if (NPz & 1)
       for (int t = threadIdx.x; t < nz * esz; t += NTH) buf[t] = zero<T>();
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       int p, z, y;
       if (decode(i, p, z, y)) {
-        const int rho = (p << A.lgNy) + y;
-        bufr[2 * (makhoul_pos(z, nz) * esz + (rho & (Hz - 1))) + (rho >> lgHz)] = v[i];
+        const int rho = p * ny + y;
+        bufr[2 * (makhoul_pos(z, nz) * esz + qmod<MX>(rho, Hz, lgHz)) + qdiv<MX>(rho, Hz, lgHz)] = v[i];
       }
     }
     __syncthreads();
-    FftGeom g{A.lgNz, lgHz, 1, true, 1, esz, lgL - A.lgNz};
-    fft_lds<T, YZ_VPT, NTH>(buf, tw, g, false);
+    FftGeom g{nz, lgNz, gzP, gzC, true, 1, esz, 1};
+    fft_lds<T, YZ_VPT, NTH, MX>(buf, Wz, g, false);
     T xa[YZ_VPT], xb[YZ_VPT];
 #pragma unroll
     for (int s2 = 0; s2 < YZ_VPT; ++s2) {
       const int t = threadIdx.x + s2 * NTH;
       xa[s2] = xb[s2] = (T)0;
-      if (t < (Hz << A.lgNz)) {
-        const int k = t >> lgHz, q = t & (Hz - 1);
+      if (t < Hz * nz) {
+        const int k = qdiv<MX>(t, Hz, lgHz), q = qmod<MX>(t, Hz, lgHz);
         const cx<T> Zk = buf[k * esz + q];
-        const cx<T> Zm = buf[((nz - k) & (nz - 1)) * esz + q];
+        const cx<T> Zm = buf[(k ? nz - k : 0) * esz + q];
         const cx<T> Va = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
         const cx<T> Vb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
         const cx<T> w = Dz[k];
         const int ra = q, rb = q + Hz;
-        const int pa = ra >> A.lgNy, pb = rb >> A.lgNy;
+        const int pa = qdiv<MX>(ra, ny, lgNy), pb = min(qdiv<MX>(rb, ny, lgNy), PP - 1);
         const T lx_a = Lx[pa], lx_b = Lx[pb];
-        xa[s2] = (w.x * Va.x - w.y * Va.y) / ((T)1 + A.s * (lx_a + Ly[ra & (ny - 1)] + Lz[k]));
-        xb[s2] = (w.x * Vb.x - w.y * Vb.y) / ((T)1 + A.s * (lx_b + Ly[rb & (ny - 1)] + Lz[k]));
+        xa[s2] = (w.x * Va.x - w.y * Va.y) / ((T)1 + A.s * (lx_a + Ly[qmod<MX>(ra, ny, lgNy)] + Lz[k]));
+        xb[s2] = (w.x * Vb.x - w.y * Vb.y) / ((T)1 + A.s * (lx_b + Ly[qmod<MX>(rb, ny, lgNy)] + Lz[k]));
       }
     }
     __syncthreads();
 #pragma unroll
     for (int s2 = 0; s2 < YZ_VPT; ++s2) {
       const int t = threadIdx.x + s2 * NTH;
-      if (t < (Hz << A.lgNz)) buf[(t >> lgHz) * esz + (t & (Hz - 1))] = mk<T>(xa[s2], xb[s2]);
+      if (t < Hz * nz) buf[qdiv<MX>(t, Hz, lgHz) * esz + qmod<MX>(t, Hz, lgHz)] = mk<T>(xa[s2], xb[s2]);
     }
     __syncthreads();
     cx<T> zz[YZ_VPT];
@@ -722,8 +729,8 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
     for (int s2 = 0; s2 < YZ_VPT; ++s2) {
       const int t = threadIdx.x + s2 * NTH;
       zz[s2] = zero<T>();
-      if (t < (Hz << A.lgNz)) {
-        const int k = t >> lgHz, q = t & (Hz - 1);
+      if (t < Hz * nz) {
+        const int k = qdiv<MX>(t, Hz, lgHz), q = qmod<MX>(t, Hz, lgHz);
         const cx<T> Xk = buf[k * esz + q];
         const cx<T> Xm = k ? buf[(nz - k) * esz + q] : zero<T>();
         const cx<T> w = conjg(Dz[k]);
@@ -736,19 +743,19 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
 #pragma unroll
     for (int s2 = 0; s2 < YZ_VPT; ++s2) {
       const int t = threadIdx.x + s2 * NTH;
-      if (t < (Hz << A.lgNz)) buf[(t >> lgHz) * esz + (t & (Hz - 1))] = zz[s2];
+      if (t < Hz * nz) buf[qdiv<MX>(t, Hz, lgHz) * esz + qmod<MX>(t, Hz, lgHz)] = zz[s2];
     }
     __syncthreads();
-    fft_lds<T, YZ_VPT, NTH>(buf, tw, g, true);
+    fft_lds<T, YZ_VPT, NTH, MX>(buf, Wz, g, true);
     const T invn = (T)1 / (T)nz;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const int t = threadIdx.x + i * NTH;
       v[i] = (T)0;
       if (t < R) {
-        const int rho = t >> A.lgNz, z = t & (nz - 1);
-        const cx<T> c = buf[makhoul_pos(z, nz) * esz + (rho & (Hz - 1))];
-        v[i] = ((rho >> lgHz) ? c.y : c.x) * invn;
+        const int rho = qdiv<MX>(t, nz, lgNz), z = qmod<MX>(t, nz, lgNz);
+        const cx<T> c = buf[makhoul_pos(z, nz) * esz + qmod<MX>(rho, Hz, lgHz)];
+        v[i] = (qdiv<MX>(rho, Hz, lgHz) ? c.y : c.x) * invn;
       }
     }
     order = 2;
@@ -765,15 +772,15 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
   }
 
   if (ny > 1) {
-    if (lgPy == 0)
+    if (NPy & 1)
       for (int t = threadIdx.x; t < ny * esy; t += NTH) buf[t] = zero<T>();
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       int p, z, y;
       if (decode(i, p, z, y)) {
-        const int rho = (p << A.lgNz) + z;
-        bufr[2 * (y * esy + (rho & (Hy - 1))) + (rho >> lgHy)] = v[i];
+        const int rho = p * nz + z;
+        bufr[2 * (y * esy + qmod<MX>(rho, Hy, lgHy)) + qdiv<MX>(rho, Hy, lgHy)] = v[i];
       }
     }
     __syncthreads();
@@ -782,8 +789,8 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
     for (int s2 = 0; s2 < YZ_VPT; ++s2) {
       const int t = threadIdx.x + s2 * NTH;
       zz[s2] = zero<T>();
-      if (t < (Hy << A.lgNy)) {
-        const int k = t >> lgHy, q = t & (Hy - 1);
+      if (t < Hy * ny) {
+        const int k = qdiv<MX>(t, Hy, lgHy), q = qmod<MX>(t, Hy, lgHy);
         const cx<T> Xk = buf[k * esy + q];
         const cx<T> Xm = k ? buf[(ny - k) * esy + q] : zero<T>();
         const cx<T> w = conjg(Dy[k]);
@@ -796,20 +803,20 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
 #pragma unroll
     for (int s2 = 0; s2 < YZ_VPT; ++s2) {
       const int t = threadIdx.x + s2 * NTH;
-      if (t < (Hy << A.lgNy)) buf[(t >> lgHy) * esy + (t & (Hy - 1))] = zz[s2];
+      if (t < Hy * ny) buf[qdiv<MX>(t, Hy, lgHy) * esy + qmod<MX>(t, Hy, lgHy)] = zz[s2];
     }
     __syncthreads();
-    FftGeom g{A.lgNy, lgHy, 1, true, 1, esy, lgL - A.lgNy};
-    fft_lds<T, YZ_VPT, NTH>(buf, tw, g, true);
+    FftGeom g{ny, lgNy, gyP, gyC, true, 1, esy, 1};
+    fft_lds<T, YZ_VPT, NTH, MX>(buf, Wy, g, true);
     const T invn = (T)1 / (T)ny;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const int e = threadIdx.x + i * NTH;
       v[i] = (T)0;
       if (e < R) {
-        const int rho = e >> A.lgNy, y = e & (ny - 1);
-        const cx<T> c = buf[makhoul_pos(y, ny) * esy + (rho & (Hy - 1))];
-        v[i] = ((rho >> lgHy) ? c.y : c.x) * invn;
+        const int rho = qdiv<MX>(e, ny, lgNy), y = qmod<MX>(e, ny, lgNy);
+        const cx<T> c = buf[makhoul_pos(y, ny) * esy + qmod<MX>(rho, Hy, lgHy)];
+        v[i] = (qdiv<MX>(rho, Hy, lgHy) ? c.y : c.x) * invn;
       }
     }
     order = 0;
@@ -818,17 +825,17 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const int e = threadIdx.x + i * NTH;
-    if (e < R && (e >> lgM) < nplanes) D[e] = v[i];
+    if (e < R && e < nplanes * M) D[e] = v[i];
   }
 }
 
 // ---------------------------------------------------------------------------
 // Column complex FFT (forward with zero padding n_in -> L, or inverse with
 // crop L -> n_out).  In place allowed (in == out, same strides).
-template <typename T>
+template <typename T, bool MX>
 __global__ __launch_bounds__(NT) void k_col_fft(const ColFft<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int L = 1 << A.lgL;
+  const int L = A.L;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + L;
   const int P = 1 << A.lgP;
@@ -845,17 +852,17 @@ __global__ __launch_bounds__(NT) void k_col_fft(const ColFft<T> A) {
     const int t = threadIdx.x + u * NT;
     const int j = t >> A.lgP, q = t & (P - 1);
     const int i = i0 + q;
-    r[u] = (t < (P << A.lgL) && j < A.n_in && i < A.ni) ? in[(long)j * A.sa_in + i] : zero<T>();
+    r[u] = (t < P * L && j < A.n_in && i < A.ni) ? in[(long)j * A.sa_in + i] : zero<T>();
   }
-  load_twiddles(tw, A.tw, A.lgL, A.lgTw);
+  load_twiddles(tw, A.tw, L, A.twg);
 #pragma unroll
   for (int u = 0; u < VPT; ++u) {
     const int t = threadIdx.x + u * NT;
-    if (t < (P << A.lgL)) buf[t] = r[u];
+    if (t < P * L) buf[t] = r[u];
   }
   __syncthreads();
-  FftGeom g{A.lgL, A.lgP, 1, true, 1, P, 0};
-  fft_lds(buf, tw, g, A.inv != 0);
+  FftGeom g{L, A.lgL, A.lgP, 1, true, 1, P, 1};
+  fft_lds<T, Tile<T>::VPT, NT, MX>(buf, tw, g, A.inv != 0);
   for (int t = threadIdx.x; t < P * A.n_out; t += NT) {
     const int j = t >> A.lgP, q = t & (P - 1);
     const int i = i0 + q;
@@ -1132,17 +1139,17 @@ __device__ __forceinline__ int comp_index(int a, int b) {
 constexpr int CONV_NT = 512;
 constexpr int CONV_VPT = 8;
 
-template <typename T>
+template <typename T, bool MX>
 __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int L = 1 << A.lgL;
+  const int L = A.L;
   const int LH = (L >> 1) + 1;
   const int P = 1 << A.lgP;
   const int es = 3 * P;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* buf = tw + L;
   T* tt = reinterpret_cast<T*>(buf + 3 * P * L);  // [ncomp][LH][P]
-  load_twiddles<T, CONV_NT>(tw, A.tw, A.lgL, A.lgTw);
+  load_twiddles<T, CONV_NT>(tw, A.tw, L, A.twg);
   const int i0 = blockIdx.x * P;
   const int bf = blockIdx.y;
   // folded tensor tile: per chunk of the [LH][P] tile, every used component's entry
@@ -1171,9 +1178,7 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
     const long boff = (long)b * A.sb;
     __syncthreads();
     // the three components' loads first, then the LDS stores.  The kx tile keeps
-    // 3 (P << lgL) <= CONV_VPT CONV_NT with P << lgL a power of two, so P << lgL is at
-    // most 2 CONV_NT: two loads per component and thread
-    static_assert(3 * 4 * CONV_NT > CONV_VPT * CONV_NT, "at most two loads per component and thread");
+    // 3 P L <= CONV_VPT CONV_NT and P L <= 2 CONV_NT: two loads per component and thread
     cx<T> r[3][2];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1183,7 +1188,7 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
         const int t = threadIdx.x + u * CONV_NT;
         const int j = t >> A.lgP, q = t & (P - 1);
         const int i = i0 + q;
-        r[c][u] = (S && t < (P << A.lgL) && j < A.n && i < A.ni) ? S[boff + (long)j * A.sa + i] : zero<T>();
+        r[c][u] = (S && t < P * L && j < A.n && i < A.ni) ? S[boff + (long)j * A.sa + i] : zero<T>();
       }
     }
 #pragma unroll
@@ -1191,14 +1196,14 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int t = threadIdx.x + u * CONV_NT;
-        if (t < (P << A.lgL)) buf[(t >> A.lgP) * es + c * P + (t & (P - 1))] = r[c][u];
+        if (t < P * L) buf[(t >> A.lgP) * es + c * P + (t & (P - 1))] = r[c][u];
       }
     __syncthreads();
     {
-      FftGeom g{A.lgL, A.lgP, 3, true, 1, es, 0};
-      fft_lds<T, CONV_VPT, CONV_NT>(buf, tw, g, false);
+      FftGeom g{L, A.lgL, A.lgP, 3, true, 1, es, 1};
+      fft_lds<T, CONV_VPT, CONV_NT, MX>(buf, tw, g, false);
     }
-    for (int t = threadIdx.x; t < (P << A.lgL); t += CONV_NT) {
+    for (int t = threadIdx.x; t < P * L; t += CONV_NT) {
       const int j = t >> A.lgP, q = t & (P - 1);
       if (i0 + q >= A.ni) continue;
       const bool cneg = j > ch;
@@ -1222,14 +1227,14 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
     }
     __syncthreads();
     if (A.O[0] && A.O[1] && A.O[2]) {
-      FftGeom g{A.lgL, A.lgP, 3, true, 1, es, 0};
-      fft_lds<T, CONV_VPT, CONV_NT>(buf, tw, g, true);
+      FftGeom g{L, A.lgL, A.lgP, 3, true, 1, es, 1};
+      fft_lds<T, CONV_VPT, CONV_NT, MX>(buf, tw, g, true);
     } else {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         if (A.O[a]) {
-          FftGeom g{A.lgL, A.lgP, 1, true, 1, es, 0};
-          fft_lds<T, CONV_VPT, CONV_NT>(buf + a * P, tw, g, true);
+          FftGeom g{L, A.lgL, A.lgP, 1, true, 1, es, 1};
+          fft_lds<T, CONV_VPT, CONV_NT, MX>(buf + a * P, tw, g, true);
         }
       }
     }
@@ -1622,10 +1627,10 @@ template <typename T>
 __global__ __launch_bounds__(NT) void k_rho(const T* g2n, const T* g3n, const T* g1s, const T* g2s, const T* g3ss,
                                             const T* g2ss, int nx, int ny, int nz, double kx, double ky, double kz,
                                             int sgs, double* partials) {
-  const int N = nx * ny * nz, lx = __builtin_ctz(nx), lxy = lx + __builtin_ctz(ny), nxy = nx * ny;
+  const int N = nx * ny * nz, nxy = nx * ny;
   double rg = 0.0, rs = 0.0;
   for (int idx = blockIdx.x * NT + threadIdx.x; idx < N; idx += gridDim.x * NT) {
-    const int x = idx & (nx - 1), y = (idx >> lx) & (ny - 1), z = idx >> lxy;
+    const int x = idx % nx, y = (idx / nx) % ny, z = idx / nxy;
     const int xm = x > 0 ? idx - 1 : idx, xp = x < nx - 1 ? idx + 1 : idx;
     const int ym = y > 0 ? idx - nx : idx, yp = y < ny - 1 ? idx + nx : idx;
     const int zm = z > 0 ? idx - nxy : idx, zp = z < nz - 1 ? idx + nxy : idx;
@@ -1806,13 +1811,13 @@ __global__ __launch_bounds__(NT) void k_adj_damp(const T* lw, const T* u, const 
                                                   const T* uF2, const T* hsF, int nx, int ny, int nz, double ecx,
                                                   double ecy, double ecz, double Q, double he0, double he1, double he2,
                                                   double* partials) {
-  // power-of-two extents, N <= 2^28: 32-bit indices, coordinates by shifts
-  const int N = nx * ny * nz, lx = __builtin_ctz(nx), lxy = lx + __builtin_ctz(ny), nxy = nx * ny;
+  // N <= 2^28: 32-bit indices
+  const int N = nx * ny * nz, nxy = nx * ny;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const T* uF[3] = {uF0, uF1, uF2};
   const double he[3] = {he0, he1, he2};
   for (int idx = blockIdx.x * NT + threadIdx.x; idx < N; idx += gridDim.x * NT) {
-    const int x = idx & (nx - 1), y = (idx >> lx) & (ny - 1), z = idx >> lxy;
+    const int x = idx % nx, y = (idx / nx) % ny, z = idx / nxy;
     const int xm = x > 0 ? idx - 1 : idx, xp = x < nx - 1 ? idx + 1 : idx;
     const int ym = y > 0 ? idx - nx : idx, yp = y < ny - 1 ? idx + nx : idx;
     const int zm = z > 0 ? idx - nxy : idx, zp = z < nz - 1 ? idx + nxy : idx;
@@ -1845,8 +1850,6 @@ int geom_fail(const char* what) {
   g_geom = what;
   return LAUNCH_EGEOM;
 }
-constexpr int lg2c(int n) { return n <= 1 ? 0 : 1 + lg2c(n >> 1); }
-template <typename T> constexpr int lg_tile_elems() { return lg2c(tile_elems<T>()); }
 }  // namespace
 
 const char* launch_geom_error() { return g_geom; }
@@ -2484,17 +2487,20 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
   const int rows = 2 << a.lgP;
   dim3 grid(ceil_div(a.nrows, rows), 1, nch);
   // twiddles, the tile, the DCT twiddles
-  const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1) + ((size_t)1 << a.lgN)) * sizeof(cx<T>);
-  // every transform length and the row length within Lmax (the LDS pitch), and
-  // P Lmax complex values within the tile: each thread then holds its 2 VPT row
-  // values and VPT spectrum values, and every FFT stage its butterflies
+  const size_t lds = ((size_t)a.Lmax + ((size_t)1 << a.lgP) * (a.Lmax + 1) + (size_t)a.n) * sizeof(cx<T>);
+  // every transform length and the row length divide Lmax (the LDS pitch and the
+  // twiddle table), and P Lmax complex values fit the tile: each thread then holds
+  // its 2 VPT row values and VPT spectrum values, and every FFT stage its butterflies
   if (nch < 1 || nch > 3) return geom_fail("k_row_fwd: 1 to 3 channels");
-  if (a.lgLmax < a.lgN || (c2r && a.lgLmax < a.lgLc) || (r2c && a.lgLmax < a.lgLr))
-    return geom_fail("k_row_fwd: a row or transform longer than Lmax");
-  if (a.lgP < 0 || a.lgP + a.lgLmax > lg_tile_elems<T>()) return geom_fail("k_row_fwd: P Lmax beyond the tile");
-  if (a.lgTw < a.lgLmax) return geom_fail("k_row_fwd: twiddle table shorter than Lmax");
+  if (a.n < 1 || a.Lmax % a.n || (c2r && a.Lmax % a.Lc) || (r2c && a.Lmax % a.Lr))
+    return geom_fail("k_row_fwd: a row or transform length does not divide Lmax");
+  if (a.lgP < 0 || ((long)a.Lmax << a.lgP) > tile_elems<T>()) return geom_fail("k_row_fwd: P Lmax beyond the tile");
+  if (a.twg < 1) return geom_fail("k_row_fwd: no twiddle stride");
   if (lds > LDS_LIMIT) return geom_fail("k_row_fwd: LDS beyond the limit");
-  hipLaunchKernelGGL(k_row_fwd<T>, grid, dim3(NT), lds, s, a);
+  if (a.lgN < 0 || a.lgLmax < 0 || (c2r && a.lgLc < 0) || (r2c && a.lgLr < 0))
+    hipLaunchKernelGGL((k_row_fwd<T, true>), grid, dim3(NT), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_row_fwd<T, false>), grid, dim3(NT), lds, s, a);
   return SGSPM_KC_ROW_FWD;
 }
 
@@ -2537,33 +2543,40 @@ template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
   const int rows = 2 << a.lgP;
   dim3 grid(ceil_div(a.nrows, rows), 1, 1);
   // twiddles, the tile, the DCT twiddles
-  const size_t lds = ((size_t)(1 << a.lgLmax) + ((size_t)1 << a.lgP) * ((1 << a.lgLmax) + 1) + ((size_t)1 << a.lgN)) * sizeof(cx<T>);
+  const size_t lds = ((size_t)a.Lmax + ((size_t)1 << a.lgP) * (a.Lmax + 1) + (size_t)a.n) * sizeof(cx<T>);
   if (a.nch < 1 || a.nch > 3) return geom_fail("k_row_inv: 1 to 3 channels");
-  if (a.lgLmax < a.lgN || (a.xout && a.lgLmax < a.lgLr)) return geom_fail("k_row_inv: a row or transform longer than Lmax");
-  if (a.lgP < 0 || a.lgP + a.lgLmax > lg_tile_elems<T>()) return geom_fail("k_row_inv: P Lmax beyond the tile");
-  if (a.lgTw < a.lgLmax) return geom_fail("k_row_inv: twiddle table shorter than Lmax");
+  if (a.n < 1 || a.Lmax % a.n || (a.xout && a.Lmax % a.Lr))
+    return geom_fail("k_row_inv: a row or transform length does not divide Lmax");
+  if (a.lgP < 0 || ((long)a.Lmax << a.lgP) > tile_elems<T>()) return geom_fail("k_row_inv: P Lmax beyond the tile");
+  if (a.twg < 1) return geom_fail("k_row_inv: no twiddle stride");
   if (lds > LDS_LIMIT) return geom_fail("k_row_inv: LDS beyond the limit");
-  hipLaunchKernelGGL(k_row_inv<T>, grid, dim3(NT), lds, s, a);
+  if (a.lgN < 0 || a.lgLmax < 0 || (a.xout && a.lgLr < 0))
+    hipLaunchKernelGGL((k_row_inv<T, true>), grid, dim3(NT), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_row_inv<T, false>), grid, dim3(NT), lds, s, a);
   return SGSPM_KC_ROW_INV;
 }
 
 template <typename T> int launch_col_dct(const ColDct<T>& a, int nbatch, int nch, hipStream_t s) {
   dim3 grid(ceil_div(a.ni, 2 << a.lgP), nbatch, nch);
-  const size_t lds = ((size_t)(1 << a.lgN) + ((size_t)1 << (a.lgP + a.lgN))) * sizeof(cx<T>);
+  const size_t lds = ((size_t)a.n + ((size_t)a.n << a.lgP)) * sizeof(cx<T>);
   if (nch < 1 || nch > 3) return geom_fail("k_col_dct: 1 to 3 channels");
-  if (a.lgP < 0 || a.lgP + a.lgN > lg_tile_elems<T>()) return geom_fail("k_col_dct: P n beyond the tile");
-  if (a.lgTw < a.lgN) return geom_fail("k_col_dct: twiddle table shorter than n");
+  if (a.n < 1 || a.lgP < 0 || ((long)a.n << a.lgP) > tile_elems<T>()) return geom_fail("k_col_dct: P n beyond the tile");
+  if (a.twg < 1) return geom_fail("k_col_dct: no twiddle stride");
   if (lds > LDS_LIMIT) return geom_fail("k_col_dct: LDS beyond the limit");
-  hipLaunchKernelGGL(k_col_dct<T>, grid, dim3(NT), lds, s, a);
+  if (a.lgN < 0)
+    hipLaunchKernelGGL((k_col_dct<T, true>), grid, dim3(NT), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_col_dct<T, false>), grid, dim3(NT), lds, s, a);
   return SGSPM_KC_COL_DCT;
 }
 
 template <typename T> int launch_col_fft(const ColFft<T>& a, int nbatch, int nch, hipStream_t s) {
   if (nch < 1 || nch > 3) return geom_fail("k_col_fft: 1 to 3 channels");
-  if (a.n_in < 1 || a.n_out < 1 || a.n_in > (1 << a.lgL) || a.n_out > (1 << a.lgL))
+  if (a.n_in < 1 || a.n_out < 1 || a.n_in > a.L || a.n_out > a.L)
     return geom_fail("k_col_fft: input or output longer than the transform");
-  if (a.lgTw < a.lgL) return geom_fail("k_col_fft: twiddle table shorter than the transform");
   if (a.lgL == 9) {
+    if (a.lgTw < 9) return geom_fail("k_fft512: twiddle table shorter than the transform");
     constexpr int P = sizeof(T) == 4 ? 8 : 4;
     // packed DC and Nyquist columns: the kernel's ni counts the columns before
     // the Nyquist column, which is column ni
@@ -2578,63 +2591,81 @@ template <typename T> int launch_col_fft(const ColFft<T>& a, int nbatch, int nch
     return SGSPM_KC_FFT512;
   }
   dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, nch);
-  const size_t lds = ((size_t)(1 << a.lgL) + ((size_t)1 << (a.lgP + a.lgL))) * sizeof(cx<T>);
-  if (a.lgP < 0 || a.lgP + a.lgL > lg_tile_elems<T>()) return geom_fail("k_col_fft: P L beyond the tile");
+  const size_t lds = ((size_t)a.L + ((size_t)a.L << a.lgP)) * sizeof(cx<T>);
+  if (a.lgP < 0 || ((long)a.L << a.lgP) > tile_elems<T>()) return geom_fail("k_col_fft: P L beyond the tile");
+  if (a.twg < 1) return geom_fail("k_col_fft: no twiddle stride");
   if (lds > LDS_LIMIT) return geom_fail("k_col_fft: LDS beyond the limit");
-  hipLaunchKernelGGL(k_col_fft<T>, grid, dim3(NT), lds, s, a);
+  if (a.lgL < 0)
+    hipLaunchKernelGGL((k_col_fft<T, true>), grid, dim3(NT), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_col_fft<T, false>), grid, dim3(NT), lds, s, a);
   return SGSPM_KC_COL_FFT;
 }
 
+// LDS of the generic y-z solve and its complex pencils per pass
+template <typename T> size_t yz_lds(int ny, int nz, int lgPP) {
+  const size_t PP = (size_t)1 << lgPP;
+  const size_t Hy = (PP * nz + 1) / 2, Hz = (PP * ny + 1) / 2;
+  const size_t nbuf = std::max((size_t)ny * (Hy + 1), (size_t)nz * (Hz + 1));
+  // y and z twiddles, buffer, y and z DCT twiddles; eigenvalues of y, z and the planes
+  return (2 * ((size_t)ny + nz) + nbuf) * sizeof(cx<T>) + ((size_t)ny + nz + PP) * sizeof(T);
+}
+// the generic y-z solve holds 2^lgPP planes of ny x nz in one workgroup
+template <typename T> bool yz_fits(int ny, int nz, int lgPP) {
+  const long PP = 1L << lgPP;
+  const long R = PP * ny * nz;
+  const long Hy = (PP * nz + 1) / 2, Hz = (PP * ny + 1) / 2;
+  return R <= YZ_MAX_VALUES && R <= yz_max_plane<T>() * 1L && Hy * ny <= (long)YZ_VPT * YZ_NT &&
+         Hz * nz <= (long)YZ_VPT * YZ_NT && yz_lds<T>(ny, nz, lgPP) <= LDS_LIMIT;
+}
+
 template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStream_t s) {
-  const int lgL = std::max(a.lgNy, a.lgNz);
-  const int lgR = a.lgNy + a.lgNz + a.lgPP;
-  const int Hy = 1 << std::max(0, a.lgPP + a.lgNz - 1), Hz = 1 << std::max(0, a.lgPP + a.lgNy - 1);
-  const size_t nbuf = std::max((size_t)(1 << a.lgNy) * (Hy + 1), (size_t)(1 << a.lgNz) * (Hz + 1));
-  // twiddles, buffer, DCT twiddles of y and z, eigenvalues of y, z and the planes
-  const size_t ny = (size_t)1 << a.lgNy, nz = (size_t)1 << a.lgNz;
-  const size_t lds = ((size_t)(1 << lgL) + nbuf + ny + nz) * sizeof(cx<T>) + (ny + nz + ((size_t)1 << a.lgPP)) * sizeof(T);
   if (nch < 1 || nch > 3) return geom_fail("k_yz_solve: 1 to 3 channels");
-  if (a.lgTw < lgL) return geom_fail("k_yz_solve: twiddle table shorter than the longest axis");
-  if (yz_reg_plane(1 << a.lgNy, 1 << a.lgNz)) {
+  if (yz_reg_plane(a.ny, a.nz)) {
+    if (a.lgTw < 8) return geom_fail("k_yz_reg: twiddle table shorter than the y axis");
     constexpr int NY = 256, NZ = 32;
     // W, y and z DCT twiddles, the [NZ/2][NY + 16] buffer, y and z eigenvalues
     const size_t lr = (2 * NY + NZ + (size_t)(NZ / 2) * (NY + 16)) * sizeof(cx<T>) + (NY + NZ) * sizeof(T);
     hipLaunchKernelGGL((k_yz_reg<T, 8, 5>), dim3(a.nx, 1, nch), dim3((NZ / 2) * (NY / 16)), lr, s, a);
     return SGSPM_KC_YZ_REG;
   }
-  // the planes of a workgroup within the 2 YZ_VPT reals each thread holds (the
-  // half-plane FFT tiles then hold YZ_VPT complex values per thread)
-  if (a.lgPP < 0 || lgR > lg2c(2 * YZ_VPT * YZ_NT)) return geom_fail("k_yz_solve: planes beyond the tile");
-  if (lds > LDS_LIMIT) return geom_fail("k_yz_solve: LDS beyond the limit");
+  // the planes of a workgroup within the 2 YZ_VPT reals each thread holds, and each
+  // pass's complex pencils within the YZ_VPT values per thread of the FFT stages
+  if (a.lgPP < 0 || !yz_fits<T>(a.ny, a.nz, a.lgPP)) return geom_fail("k_yz_solve: planes beyond the tile");
+  if (a.twy_s < 1 || a.twz_s < 1) return geom_fail("k_yz_solve: no twiddle stride");
   dim3 grid(ceil_div(a.nx, 1 << a.lgPP), 1, nch);
-  hipLaunchKernelGGL(k_yz_solve<T>, grid, dim3(YZ_NT), lds, s, a);
+  if (a.lgNy < 0 || a.lgNz < 0)
+    hipLaunchKernelGGL((k_yz_solve<T, true>), grid, dim3(YZ_NT), yz_lds<T>(a.ny, a.nz, a.lgPP), s, a);
+  else
+    hipLaunchKernelGGL((k_yz_solve<T, false>), grid, dim3(YZ_NT), yz_lds<T>(a.ny, a.nz, a.lgPP), s, a);
   return SGSPM_KC_YZ_SOLVE;
 }
 
-template <typename T> size_t conv_lds(int lgL, int lgP, int nt) {
-  const size_t L = (size_t)1 << lgL, P = (size_t)1 << lgP;
-  return (L + 3 * P * L) * sizeof(cx<T>) + (size_t)nt * (L / 2 + 1) * P * sizeof(T);
+template <typename T> size_t conv_lds(int L, int lgP, int nt) {
+  const size_t P = (size_t)1 << lgP;
+  return ((size_t)L + 3 * P * L) * sizeof(cx<T>) + (size_t)nt * (L / 2 + 1) * P * sizeof(T);
 }
 
-template <typename T> int conv_lgP(int lgL, int ni, int nt) {
-  // widest power-of-two kx tile whose three padded pencils fit the FFT capacity
-  // and whose LDS (spectra + folded tensor tile) stays within 48 KiB
-  int lgP = 0;
-  while (true) {
-    const int nl = lgP + 1;
-    if ((3L << (nl + lgL)) > (long)CONV_VPT * CONV_NT) break;
-    if (conv_lds<T>(lgL, nl, nt) > 48 * 1024) break;
-    if ((1 << nl) > 2 * ni) break;
+template <typename T> int conv_lgP(int L, int ni, int nt) {
+  // widest power-of-two kx tile whose three padded pencils fit the FFT capacity,
+  // with at most two loads per component and thread, and whose LDS (spectra +
+  // folded tensor tile) stays within 48 KiB; -1 when a single kx does not fit
+  int lgP = -1;
+  for (int nl = 0;; ++nl) {
+    const long pl = (long)L << nl;
+    if (3 * pl > (long)CONV_VPT * CONV_NT || pl > 2L * CONV_NT) break;
+    if (conv_lds<T>(L, nl, nt) > 48 * 1024) break;
+    if (nl > 0 && (1 << nl) > 2 * ni) break;
     lgP = nl;
   }
   return lgP;
 }
 
 template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t s) {
-  if (a.n < 1 || a.n > (1 << a.lgL)) return geom_fail("k_conv: pencil longer than the padded transform");
+  if (a.n < 1 || a.n > a.L) return geom_fail("k_conv: pencil longer than the padded transform");
   if (a.nt < 0 || a.nt > 6) return geom_fail("k_conv: at most six tensor components");
-  if (a.lgTw < a.lgL) return geom_fail("k_conv: twiddle table shorter than the transform");
   if (a.lgL == 6 && a.n == 32) {
+    if (a.lgTw < 6) return geom_fail("k_conv64: twiddle table shorter than the transform");
     // register four-step kernel: P kx x 2 batch rows x 8 threads per pencil
     // 16 kx per workgroup in single precision, 8 in double (LDS 16 / 16 KiB)
     Conv<T> b = a;
@@ -2648,11 +2679,15 @@ template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t 
   }
   // three components' P L values within the FFT capacity, and at most two loads
   // per component and thread
-  const long pl = 1L << (a.lgP + a.lgL);
+  const long pl = (long)a.L << a.lgP;
   if (a.lgP < 0 || 3 * pl > (long)CONV_VPT * CONV_NT || pl > 2L * CONV_NT) return geom_fail("k_conv: P L beyond the tile");
-  if (conv_lds<T>(a.lgL, a.lgP, a.nt) > LDS_LIMIT) return geom_fail("k_conv: LDS beyond the limit");
+  if (a.twg < 1) return geom_fail("k_conv: no twiddle stride");
+  if (conv_lds<T>(a.L, a.lgP, a.nt) > LDS_LIMIT) return geom_fail("k_conv: LDS beyond the limit");
   dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, 1);
-  hipLaunchKernelGGL(k_conv<T>, grid, dim3(CONV_NT), conv_lds<T>(a.lgL, a.lgP, a.nt), s, a);
+  if (a.lgL < 0)
+    hipLaunchKernelGGL((k_conv<T, true>), grid, dim3(CONV_NT), conv_lds<T>(a.L, a.lgP, a.nt), s, a);
+  else
+    hipLaunchKernelGGL((k_conv<T, false>), grid, dim3(CONV_NT), conv_lds<T>(a.L, a.lgP, a.nt), s, a);
   return SGSPM_KC_CONV;
 }
 
@@ -2754,6 +2789,7 @@ template <typename T> void launch_unit_error(const T* m, long N, double* partial
   template int launch_col_fft<T>(const ColFft<T>&, int, int, hipStream_t);                                         \
   template int launch_conv<T>(const Conv<T>&, int, hipStream_t);                                                   \
   template int conv_lgP<T>(int, int, int);                                                                          \
+  template bool yz_fits<T>(int, int, int);                                                                          \
   template int launch_yz_solve<T>(const YZSolve<T>&, int, hipStream_t);                                            \
   template void launch_tensor_pack<T>(const cx<double>*, T*, int, int, int, int, int, int, double, hipStream_t);    \
   template void launch_field_assemble<T>(const T*, const T*, T*, int, int, int, double, double, double, double,    \

@@ -42,6 +42,33 @@ const double GAMMA = 1.7609e11;  // rad / (s T)
 const int R_FAR = 20;            // cells: Newell sum within, point dipole beyond
 
 bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+// n = 2^a 3^b 5^c: the lengths the FFT passes support
+bool smooth235(int n) {
+  if (n <= 0) return false;
+  for (int f : {2, 3, 5})
+    while (n % f == 0) n /= f;
+  return n == 1;
+}
+long gcdl(long a, long b) {
+  while (b) {
+    const long t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+// length of the table of W_L for every non-power-of-two transform length L of a plan
+// (the DCT lengths n_a, and the padded lengths 2 n_a with the stray field), 1 if none
+long mixed_table_len(const int n[3], bool stray) {
+  long L = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] <= 1 || pow2(n[a])) continue;
+    const long l = stray ? 2L * n[a] : n[a];
+    L = L / gcdl(L, l) * l;
+  }
+  return L;
+}
+constexpr long MIXED_TABLE_MAX = 1L << 20;
 int ilog2(long n) {
   int l = 0;
   while ((1L << l) < n) ++l;
@@ -54,8 +81,9 @@ int validate(const sgspm_params* p) {
   const char* nm[3] = {"nx", "ny", "nz"};
   for (int a = 0; a < 3; ++a) {
     if (n[a] <= 0) return fail(SGSPM_EINVAL, std::string(nm[a]) + " must be positive");
-    if (n[a] > 1024) return fail(SGSPM_EUNSUPPORTED, std::string(nm[a]) + " above 1024 is not supported");
-    if (!pow2(n[a])) return fail(SGSPM_EUNSUPPORTED, std::string(nm[a]) + " must be a power of two");
+    if (n[a] > (a == 0 ? 2048 : 1024))
+      return fail(SGSPM_EUNSUPPORTED, std::string(nm[a]) + (a == 0 ? " above 2048" : " above 1024") + " is not supported");
+    if (!smooth235(n[a])) return fail(SGSPM_EUNSUPPORTED, std::string(nm[a]) + " must be a product of 2, 3 and 5");
   }
   const double h[3] = {p->dx, p->dy, p->dz};
   for (int a = 0; a < 3; ++a)
@@ -76,12 +104,22 @@ int validate(const sgspm_params* p) {
     return fail(SGSPM_EINVAL, "unknown scheme");
   const long N = (long)p->nx * p->ny * p->nz;
   if (N > (1L << 28)) return fail(SGSPM_EUNSUPPORTED, "grid too large");
-  if (p->terms & SGSPM_TERM_STRAY) {
+  const bool fp64 = p->precision == SGSPM_FP64;
+  const bool stray = p->terms & SGSPM_TERM_STRAY;
+  // the row kernels hold two rows and their (padded) transforms in one tile
+  const long rowlen = (stray && p->nx > 1) ? 2L * p->nx : p->nx;
+  if (rowlen > (fp64 ? tile_elems<double>() : tile_elems<float>()))
+    return fail(SGSPM_EUNSUPPORTED, std::string("nx = ") + std::to_string(p->nx) +
+                                        " rows do not fit a row tile at this precision" + (stray ? " with the stray field" : ""));
+  if (mixed_table_len(n, stray) > MIXED_TABLE_MAX)
+    return fail(SGSPM_EUNSUPPORTED, "the non-power-of-two lengths need too long a twiddle table");
+  if (stray) {
     // the last-axis convolution holds three padded pencils of its axis in one tile
     const int nc = p->nz > 1 ? p->nz : p->ny;
-    const int lim = p->precision == SGSPM_FP64 ? 256 : 512;
-    if (nc > lim)
-      return fail(SGSPM_EUNSUPPORTED, std::string(p->nz > 1 ? "nz" : "ny") + " above " + std::to_string(lim) +
+    const int L = nc > 1 ? 2 * nc : 1;
+    const int lgP = fp64 ? conv_lgP<double>(L, 1, 6) : conv_lgP<float>(L, 1, 6);
+    if (lgP < 0 && !(L == 64))
+      return fail(SGSPM_EUNSUPPORTED, std::string(p->nz > 1 ? "nz" : "ny") + " = " + std::to_string(nc) +
                                           " is not supported with the stray field at this precision");
   }
   return SGSPM_OK;
@@ -132,6 +170,10 @@ struct sgspm_plan_s {
   int lgTw = 0;
   // typed (T) device tables
   void* tw = nullptr;
+  // W_Lm^i for the non-power-of-two lengths (Lm = 1: none), typed and FP64
+  void* twm = nullptr;
+  void* twm64 = nullptr;
+  long Lm = 1;
   void* dtw[3] = {nullptr, nullptr, nullptr};
   void* lam[3] = {nullptr, nullptr, nullptr};
   // FP64 twiddles for the tensor precompute
@@ -192,8 +234,25 @@ template <typename T> int upload(sgspm_plan_s* P, void** out, const std::vector<
   return hip_check(hipMemcpyAsync(*out, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, P->s), "upload");
 }
 
-// Tiles: complex elements per tile for each precision.
-template <typename T> int lg_tile() { return ilog2(tile_elems<T>()); }
+// Tiles: log2 of the most pencils of length L one tile of the precision holds.
+template <typename T> int lg_tile_for(int L) {
+  int l = 0;
+  while (((long)L << (l + 1)) <= tile_elems<T>()) ++l;
+  return l;
+}
+
+// twiddle table and stride giving W_L^i = t[i * stride] for a transform length L of
+// the plan: the power-of-two table (2^lgTw entries) or the mixed one (Lm entries)
+template <typename V> void table_for(const sgspm_plan_s& P, const void* pow2tab, const void* mixtab, int L,
+                                     const cx<V>*& t, int& stride) {
+  if (lg_or_neg(L) >= 0) {
+    t = (const cx<V>*)pow2tab;
+    stride = (1 << P.lgTw) / L;
+  } else {
+    t = (const cx<V>*)mixtab;
+    stride = (int)(P.Lm / L);
+  }
+}
 
 // largest lgP with (2 << lgP) rows not beyond what the rows need
 int cap_lgP(int lgP, long count_pencils) {
@@ -218,6 +277,7 @@ template <typename T> struct Eng {
   const T* lam[3];
   T* f[NF];
   T* heat[3];
+  void tab(int L, const cx<T>*& t, int& stride) const { table_for<T>(P, P.tw, P.twm, L, t, stride); }
   cx<T>* xlev[3];
   cx<T>* ylev[3];
   cx<T>* yout[3];
@@ -297,24 +357,22 @@ template <typename T> struct Eng {
   void row_fwd(int nch, const RowIO& io) {
     RowFwd<T> A{};
     A.nrows = P.ny * P.nz;
-    A.lgN = ilog2(P.nx);
-    A.lgLc = ilog2(P.Px);
-    A.lgLr = ilog2(P.Px);
-    int lgL = 0;
+    A.n = P.nx;
+    A.lgN = lg_or_neg(P.nx);
+    A.Lc = A.Lr = P.Px;
+    A.lgLc = A.lgLr = lg_or_neg(P.Px);
     bool any_x = io.with_hs;
-    for (int c = 0; c < nch; ++c) {
+    for (int c = 0; c < nch; ++c)
       if (io.xout[c]) any_x = true;
-      if (io.dct_out[c]) lgL = std::max(lgL, A.lgN);
-    }
-    if (any_x) lgL = std::max(lgL, A.lgLr);
     // the tile holds 2P rows of nx values whether or not a transform runs (a pass
     // with no transform, such as the accumulation of a plan without the stray
-    // field, still carries its rows), so the row length bounds it too
-    lgL = std::max(lgL, A.lgN);
-    A.lgLmax = lgL;
-    A.lgP = row_lgP(lg_tile<T>() - lgL, (A.nrows + 1) / 2);
+    // field, still carries its rows); the padded transforms (Px = 2 nx) set it
+    // when they run, and the DCT length nx divides them
+    A.Lmax = any_x ? P.Px : P.nx;
+    A.lgLmax = lg_or_neg(A.Lmax);
+    A.lgP = row_lgP(lg_tile_for<T>(A.Lmax), (A.nrows + 1) / 2);
     A.lgTw = P.lgTw;
-    A.tw = tw;
+    tab(A.Lmax, A.tw, A.twg);
     A.dtw = dtw[0];
     A.b = io.b;
     A.xin_pitch = P.Kxp;
@@ -346,12 +404,15 @@ template <typename T> struct Eng {
 
   void row_inv(RowInv<T>& A, bool r2c) {
     A.nrows = P.ny * P.nz;
-    A.lgN = ilog2(P.nx);
-    A.lgLr = ilog2(P.Px);
-    A.lgLmax = r2c ? std::max(A.lgN, A.lgLr) : A.lgN;
-    A.lgP = row_lgP(lg_tile<T>() - A.lgLmax, (A.nrows + 1) / 2);
+    A.n = P.nx;
+    A.lgN = lg_or_neg(P.nx);
+    A.Lr = P.Px;
+    A.lgLr = lg_or_neg(P.Px);
+    A.Lmax = r2c ? std::max(P.nx, P.Px) : P.nx;
+    A.lgLmax = lg_or_neg(A.Lmax);
+    A.lgP = row_lgP(lg_tile_for<T>(A.Lmax), (A.nrows + 1) / 2);
     A.lgTw = P.lgTw;
-    A.tw = tw;
+    tab(A.Lmax, A.tw, A.twg);
     A.dtw = dtw[0];
     A.xout_pitch = P.Kxp;
     A.xpk = P.dcnq ? 1 : 0;
@@ -373,17 +434,21 @@ template <typename T> struct Eng {
       YZSolve<T> A{};
       for (int c = 0; c < 3; ++c) A.data[c] = d[c];
       A.nx = P.nx;
-      A.lgNy = ilog2(P.ny);
-      A.lgNz = ilog2(P.nz);
-      const int lgM = A.lgNy + A.lgNz;
+      A.ny = P.ny;
+      A.nz = P.nz;
+      A.lgNy = lg_or_neg(P.ny);
+      A.lgNz = lg_or_neg(P.nz);
       // planes per workgroup: fill the tile, but keep at least ~256 workgroups
-      int lgPP = ilog2(yz_max_plane<T>()) - lgM;
+      int lgPP = 0;
+      while (yz_fits<T>(P.ny, P.nz, lgPP + 1)) ++lgPP;
       while (lgPP > 0 && (P.nx >> lgPP) < 256) --lgPP;
-      A.lgPP = std::max(0, lgPP);
+      A.lgPP = lgPP;
       A.dtwy = dtw[1];
       A.dtwz = dtw[2];
       A.tw = tw;
       A.lgTw = P.lgTw;
+      tab(P.ny, A.twy, A.twy_s);
+      tab(P.nz, A.twz, A.twz_s);
       A.lamX = lam[0];
       A.lamY = lam[1];
       A.lamZ = lam[2];
@@ -394,30 +459,30 @@ template <typename T> struct Eng {
     if (P.has_mid) {
       ColDct<T> A{};
       A.mode = COL_DCT_FWD;
-      A.lgN = ilog2(P.ny);
-      A.lgP = cap_lgP(lg_tile<T>() - A.lgN, (P.nx + 1) / 2);
+      A.n = P.ny;
+      A.lgN = lg_or_neg(P.ny);
+      A.lgP = cap_lgP(lg_tile_for<T>(A.n), (P.nx + 1) / 2);
       A.ni = P.nx;
       A.sa = P.nx;
       A.sb = (long)P.ny * P.nx;
       for (int c = 0; c < 3; ++c) A.data[c] = d[c];
       A.dtw = dtw[1];
-      A.tw = tw;
-      A.lgTw = P.lgTw;
+      tab(A.n, A.tw, A.twg);
       timed(2.0 * nch * P.N * TS, [&] { return launch_col_dct<T>(A, P.nz, nch, s); });
     }
     {
       ColDct<T> A{};
       A.mode = COL_DCT_SOLVE;
       const bool z = P.nz > 1;
-      A.lgN = ilog2(z ? P.nz : P.ny);
-      A.lgP = cap_lgP(lg_tile<T>() - A.lgN, (P.nx + 1) / 2);
+      A.n = z ? P.nz : P.ny;
+      A.lgN = lg_or_neg(A.n);
+      A.lgP = cap_lgP(lg_tile_for<T>(A.n), (P.nx + 1) / 2);
       A.ni = P.nx;
       A.sa = z ? (long)P.ny * P.nx : P.nx;
       A.sb = z ? P.nx : 0;
       for (int c = 0; c < 3; ++c) A.data[c] = d[c];
       A.dtw = dtw[z ? 2 : 1];
-      A.tw = tw;
-      A.lgTw = P.lgTw;
+      tab(A.n, A.tw, A.twg);
       A.lamX = lam[0];
       A.lamB = z ? lam[1] : lam[2];
       A.lamA = z ? lam[2] : lam[1];
@@ -427,15 +492,15 @@ template <typename T> struct Eng {
     if (P.has_mid) {
       ColDct<T> A{};
       A.mode = COL_DCT_INV;
-      A.lgN = ilog2(P.ny);
-      A.lgP = cap_lgP(lg_tile<T>() - A.lgN, (P.nx + 1) / 2);
+      A.n = P.ny;
+      A.lgN = lg_or_neg(P.ny);
+      A.lgP = cap_lgP(lg_tile_for<T>(A.n), (P.nx + 1) / 2);
       A.ni = P.nx;
       A.sa = P.nx;
       A.sb = (long)P.ny * P.nx;
       for (int c = 0; c < 3; ++c) A.data[c] = d[c];
       A.dtw = dtw[1];
-      A.tw = tw;
-      A.lgTw = P.lgTw;
+      tab(A.n, A.tw, A.twg);
       timed(2.0 * nch * P.N * TS, [&] { return launch_col_dct<T>(A, P.nz, nch, s); });
     }
   }
@@ -445,10 +510,11 @@ template <typename T> struct Eng {
   void mid_fwd(int mask) {
     if (!P.has_mid) return;
     ColFft<T> A{};
-    A.lgL = ilog2(P.Py);
+    A.L = P.Py;
+    A.lgL = lg_or_neg(P.Py);
     A.n_in = P.ny;
     A.n_out = P.Py;
-    A.lgP = cap_lgP(lg_tile<T>() - A.lgL, P.Kx);
+    A.lgP = cap_lgP(lg_tile_for<T>(A.L), P.Kx);
     A.ni = P.Kx;
     A.sa_in = P.Kxp;
     A.sb_in = (long)P.ny * P.Kxp;
@@ -462,8 +528,8 @@ template <typename T> struct Eng {
         ++k;
       }
     A.inv = 0;
-    A.tw = tw;
     A.lgTw = P.lgTw;
+    tab(A.L, A.tw, A.twg);
     A.pack = P.dcnq ? 1 : 0;
     const double cb = (double)P.Kx * P.nz * 2 * TS;
     timed(k * cb * (P.ny + P.Py), [&] { return launch_col_fft<T>(A, P.nz, k, s); });
@@ -471,10 +537,11 @@ template <typename T> struct Eng {
   void mid_inv(int mask) {
     if (!P.has_mid) return;
     ColFft<T> A{};
-    A.lgL = ilog2(P.Py);
+    A.L = P.Py;
+    A.lgL = lg_or_neg(P.Py);
     A.n_in = P.Py;
     A.n_out = P.ny;
-    A.lgP = cap_lgP(lg_tile<T>() - A.lgL, P.Kx);
+    A.lgP = cap_lgP(lg_tile_for<T>(A.L), P.Kx);
     A.ni = P.Kx;
     A.sa_in = P.Kxp;
     A.sb_in = (long)P.Py * P.Kxp;
@@ -488,8 +555,8 @@ template <typename T> struct Eng {
         ++k;
       }
     A.inv = 1;
-    A.tw = tw;
     A.lgTw = P.lgTw;
+    tab(A.L, A.tw, A.twg);
     A.pack = P.dcnq ? 1 : 0;
     const double cb = (double)P.Kx * P.nz * 2 * TS;
     timed(k * cb * (P.ny + P.Py), [&] { return launch_col_fft<T>(A, P.nz, k, s); });
@@ -498,7 +565,8 @@ template <typename T> struct Eng {
     Conv<T> A{};
     const bool z = P.nz > 1;
     const int L = z ? P.Pz : P.Py;
-    A.lgL = ilog2(L);
+    A.L = L;
+    A.lgL = lg_or_neg(L);
     A.n = z ? P.nz : P.ny;
     A.ni = P.Kx;
     if (z) {
@@ -534,7 +602,7 @@ template <typename T> struct Eng {
         A.clist[A.nt++] = c;
       }
     }
-    A.lgP = conv_lgP<T>(A.lgL, P.Kx, A.nt);
+    A.lgP = conv_lgP<T>(A.L, P.Kx, A.nt);
     {
       // small grids: fewer kx per workgroup until the launch has ~256 workgroups
       const long nbw = (z && P.has_mid) ? P.Hy : 1;
@@ -544,8 +612,8 @@ template <typename T> struct Eng {
     A.nyqb = P.dcnq ? 1 : 0;
     A.tcs = (long)P.Hz * P.Hy * P.Kt;
     A.tkx = P.Kt;
-    A.tw = tw;
     A.lgTw = P.lgTw;
+    tab(A.L, A.tw, A.twg);
     const int nb = (z && P.has_mid) ? P.Hy : 1;
     const int nrows = (z && P.has_mid) ? P.Py : 1;
     const double slab = (double)A.n * A.ni * nrows * 2 * TS;
@@ -1124,20 +1192,17 @@ int build_tensor(sgspm_plan_s* P) {
   cell_ratios(P, hx, hy, hz);
   const long tcs = (long)P->Hz * P->Hy * P->Kt;
   const double scale = -1.0 / (double)padded;
-  const cx<double>* tw64 = (const cx<double>*)P->tw64;
   for (int comp = 0; comp < 6; ++comp) {
     launch_newell_fill((double*)real, comp, P->nx, P->ny, P->nz, P->Px, P->Py, P->Pz, hx, hy, hz, R_FAR, P->s);
     // x: real-to-complex, full length
     {
       RowFwd<double> A{};
       A.nrows = P->Py * P->Pz;
-      A.lgN = ilog2(P->Px);
-      A.lgLr = A.lgN;
-      A.lgLc = A.lgN;
-      A.lgLmax = A.lgN;
-      A.lgP = cap_lgP(lg_tile<double>() - A.lgN, (A.nrows + 1) / 2);
+      A.n = A.Lr = A.Lc = A.Lmax = P->Px;
+      A.lgN = A.lgLr = A.lgLc = A.lgLmax = lg_or_neg(P->Px);
+      A.lgP = cap_lgP(lg_tile_for<double>(A.Lmax), (A.nrows + 1) / 2);
       A.lgTw = P->lgTw;
-      A.tw = tw64;
+      table_for<double>(*P, P->tw64, P->twm64, A.Lmax, A.tw, A.twg);
       A.u[0] = (const double*)real;
       A.a[0] = 1.0;
       A.b = 0.0;
@@ -1150,10 +1215,11 @@ int build_tensor(sgspm_plan_s* P) {
       const int L = ax == 1 ? P->Py : P->Pz;
       if (L == 1) continue;
       ColFft<double> A{};
-      A.lgL = ilog2(L);
+      A.L = L;
+      A.lgL = lg_or_neg(L);
       A.n_in = L;
       A.n_out = L;
-      A.lgP = cap_lgP(lg_tile<double>() - A.lgL, P->Kx);
+      A.lgP = cap_lgP(lg_tile_for<double>(L), P->Kx);
       A.ni = P->Kx;
       if (ax == 1) {
         A.sa_in = A.sa_out = P->Kxp;
@@ -1165,8 +1231,8 @@ int build_tensor(sgspm_plan_s* P) {
       A.in[0] = (const cx<double>*)spec;
       A.out[0] = (cx<double>*)spec;
       A.inv = 0;
-      A.tw = tw64;
       A.lgTw = P->lgTw;
+      table_for<double>(*P, P->tw64, P->twm64, L, A.tw, A.twg);
       if (launch_col_fft<double>(A, ax == 1 ? P->Pz : P->Py, 1, P->s) < 0)
         return fail(SGSPM_EUNSUPPORTED, launch_geom_error());
     }
@@ -1203,6 +1269,21 @@ template <typename T> int make_tables(sgspm_plan_s* P) {
   if ((rc = upload(P, &P->tw, tw))) return rc;
   if ((rc = upload(P, &P->tw64, tw64))) return rc;
   const int n[3] = {P->nx, P->ny, P->nz};
+  // W_Lm for the non-power-of-two transform lengths
+  P->Lm = mixed_table_len(n, P->stray);
+  if (P->Lm > 1) {
+    std::vector<cx<T>> m(P->Lm);
+    std::vector<cx<double>> m64(P->Lm);
+    for (long i = 0; i < P->Lm; ++i) {
+      const double a = -2.0 * M_PI * (double)i / (double)P->Lm;
+      m64[i].x = std::cos(a);
+      m64[i].y = std::sin(a);
+      m[i].x = (T)m64[i].x;
+      m[i].y = (T)m64[i].y;
+    }
+    if ((rc = upload(P, &P->twm, m))) return rc;
+    if ((rc = upload(P, &P->twm64, m64))) return rc;
+  }
   const double c[3] = {P->cxx, P->cyy, P->czz};
   for (int a = 0; a < 3; ++a) {
     std::vector<cx<T>> d(n[a]);
@@ -1329,8 +1410,7 @@ int sgspm_plan(const sgspm_params* p, void* hip_stream, sgspm_plan_t* out) {
   // slots of padding (nx a multiple of 16)
   P->dcnq = P->has_mid && p->ny == 256 && p->nz == 32 && p->nx >= 16 && p->nx % 16 == 0 &&
             P->Kxp == P->Kx - 1 + 16;
-  P->yz = yz_reg_plane(p->ny, p->nz) ||
-          (long)p->ny * p->nz <= (P->fp64 ? yz_max_plane<double>() : yz_max_plane<float>());
+  P->yz = yz_reg_plane(p->ny, p->nz) || (P->fp64 ? yz_fits<double>(p->ny, p->nz, 0) : yz_fits<float>(p->ny, p->nz, 0));
   double red[5];
   reduce(p, red);
   P->eps = red[0];
