@@ -43,7 +43,7 @@ extern "C" {
 enum {
   SGSPM_OK = 0,
   SGSPM_EINVAL = -1,       /* bad argument (null pointer, non-positive size, ...) */
-  SGSPM_EUNSUPPORTED = -2, /* valid but not implemented (e.g. non power-of-two axis) */
+  SGSPM_EUNSUPPORTED = -2, /* valid but not implemented (e.g. an extent with a prime factor above 5) */
   SGSPM_ENOMEM = -3,       /* device allocation failed */
   SGSPM_EHIP = -4,         /* a HIP runtime call failed */
   SGSPM_ENUMERIC = -5      /* a projection met |m***| = 0 or a non-finite value */
@@ -61,8 +61,11 @@ enum { SGSPM_SCHEME_SGS = 0, SGSPM_SCHEME_GS = 1, SGSPM_SCHEME_SGS_FF = 2 };
 
 /* Problem statement (paper §2 and §3): grid, cell size, constants, time step. */
 typedef struct {
-  int32_t nx, ny, nz;   /* cells; each a power of two in [1, 1024]; with the stray field the
-                           last axis of extent > 1 among (ny, nz) is at most 512 (FP32) / 256 (FP64) */
+  int32_t nx, ny, nz;   /* cells; each a product of 2, 3 and 5 (1 included), nx <= 2048,
+                           ny, nz <= 1024.  Rows must fit one tile: nx <= 2048 (FP32) / 1024 (FP64)
+                           without the stray field, nx <= 1024 with it (its tensor is transformed
+                           in FP64 at either precision).  With the stray field the last axis of
+                           extent > 1 among (ny, nz) is at most 512 (FP32) / 256 (FP64) */
   double dx, dy, dz;    /* cell edges: metres (SI) or reduced lengths */
   int32_t units;        /* SGSPM_UNITS_SI or SGSPM_UNITS_REDUCED */
   double A, Ms, Ku;     /* SI only: exchange J/m, saturation A/m, uniaxial J/m^3 (easy axis x) */

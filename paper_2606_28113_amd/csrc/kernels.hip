@@ -1575,7 +1575,7 @@ __global__ __launch_bounds__(NT) void k_energy(const T* m, const T* hs, int nx, 
     if (hs) acc[2] += m0 * (double)hs[idx] + m1 * (double)hs[N + idx] + m2 * (double)hs[2 * N + idx];
     acc[3] += m0 * he0 + m1 * he1 + m2 * he2;
   }
-  __shared__ double red[4][NT / 64];
+  static __shared__ double red[4][NT / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -1591,7 +1591,7 @@ __global__ __launch_bounds__(NT) void k_energy(const T* m, const T* hs, int nx, 
 }
 
 __global__ __launch_bounds__(NT) void k_energy_final(const double* partials, int nblocks, double* out) {
-  __shared__ double red[4][NT];
+  static __shared__ double red[4][NT];
   for (int k = 0; k < 4; ++k) {
     double s = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += NT) s += partials[(long)b * 4 + k];
@@ -1657,7 +1657,7 @@ __global__ __launch_bounds__(NT) void k_rho(const T* g2n, const T* g3n, const T*
       rs = fmax(rs, rho2(x11, x12, x21, x22));
     }
   }
-  __shared__ double red[2][NT / 64];
+  static __shared__ double red[2][NT / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double mg = wave_max(rg), ms = wave_max(rs);
   if (lane == 0) {
@@ -1680,7 +1680,7 @@ __global__ __launch_bounds__(NT) void k_unit_error(const T* m, long N, double* p
     const double a = m[idx], b = m[N + idx], c = m[2 * N + idx];
     v = fmax(v, fabs(sqrt(a * a + b * b + c * c) - 1.0));
   }
-  __shared__ double red[NT / 64];
+  static __shared__ double red[NT / 64];
   const double w = wave_max(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
   __syncthreads();
@@ -1693,7 +1693,7 @@ __global__ __launch_bounds__(NT) void k_unit_error(const T* m, long N, double* p
 }
 
 __global__ __launch_bounds__(NT) void k_rho_final(const double* partials, int nblocks, double* out) {
-  __shared__ double red[2][NT];
+  static __shared__ double red[2][NT];
   for (int k = 0; k < 2; ++k) {
     double v = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += NT) v = fmax(v, partials[(long)b * 4 + k]);
@@ -1756,7 +1756,7 @@ __global__ void k_adj_project(const T* lam, const T* u, const T* nrm, T* lc, lon
 }
 
 __device__ __forceinline__ void block_partials4(double acc[4], double* partials) {
-  __shared__ double red[4][NT / 64];
+  static __shared__ double red[4][NT / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -1787,7 +1787,7 @@ __global__ __launch_bounds__(NT) void k_wsum(const T* x0, const T* x1, const T* 
 // Adds the weighted totals of the block partials into grad (one thread: fixed order).
 __global__ void k_partials_to_grad(const double* partials, int nblocks, int nterms, double w0, double w1, double w2,
                                    double w3, int s0, int s1, int s2, int s3, double* grad) {
-  __shared__ double red[4][NT];
+  static __shared__ double red[4][NT];
   for (int k = 0; k < 4; ++k) {
     double s = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += NT) s += partials[(long)b * 4 + k];

@@ -111,6 +111,10 @@ int validate(const sgspm_params* p) {
   if (rowlen > (fp64 ? tile_elems<double>() : tile_elems<float>()))
     return fail(SGSPM_EUNSUPPORTED, std::string("nx = ") + std::to_string(p->nx) +
                                         " rows do not fit a row tile at this precision" + (stray ? " with the stray field" : ""));
+  // the demagnetising tensor is transformed in FP64 whatever the plan's precision
+  if (stray && rowlen > tile_elems<double>())
+    return fail(SGSPM_EUNSUPPORTED, std::string("nx = ") + std::to_string(p->nx) +
+                                        " rows of the FP64 demagnetising tensor do not fit a row tile");
   if (mixed_table_len(n, stray) > MIXED_TABLE_MAX)
     return fail(SGSPM_EUNSUPPORTED, "the non-power-of-two lengths need too long a twiddle table");
   if (stray) {

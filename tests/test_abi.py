@@ -56,6 +56,8 @@ def test_validate_accepts_configs():
 @pytest.mark.parametrize("bad,code", [
     (dict(nx=0), -1), (dict(ny=-4), -1), (dict(nx=7), -2), (dict(ny=42), -2), (dict(nz=2048), -2),
     (dict(nx=4096), -2), (dict(nx=1536, precision=1), -2), (dict(nx=2000, ny=1, nz=1, precision=1), -2),
+    # FP32 rows of 2000 fit, but the demagnetising tensor is transformed in FP64
+    (dict(nx=2000, ny=1, nz=1), -2), (dict(nx=1280, ny=2, nz=2), -2),
     (dict(dx=0.0), -1), (dict(dt=-1.0), -1), (dict(dt=float("nan")), -1), (dict(Ms=0.0), -1),
     (dict(A=-1.0), -1), (dict(units=7), -1), (dict(terms=16), -1), (dict(precision=3), -1),
     (dict(scheme=3), -1),
@@ -71,7 +73,8 @@ def test_validate_rejects(bad, code):
 
 @pytest.mark.parametrize("ok", [
     dict(nx=100, ny=100, nz=4), dict(nx=480, ny=30, nz=5), dict(nx=2000, ny=1, nz=1, terms=1, precision=1),
-    dict(nx=2000, ny=1, nz=1), dict(nx=3, ny=5, nz=15), dict(nx=1024, ny=256, nz=32),
+    dict(nx=2000, ny=1, nz=1, terms=1), dict(nx=3, ny=5, nz=15), dict(nx=1024, ny=256, nz=32),
+    dict(nx=1024, ny=1, nz=1, precision=1),
 ], ids=lambda d: "x".join(str(d[k]) for k in ("nx", "ny", "nz")) + ("-fp64" if d.get("precision") else ""))
 def test_validate_accepts_products_of_2_3_5(ok):
     """Grid extents that are products of 2, 3 and 5 (the paper's 100 x 100 x 4 film and its
