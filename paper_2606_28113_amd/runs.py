@@ -51,3 +51,57 @@ def run_logged(plan, m, steps, alpha, h_e, log_every=10, sink=None, run_id=0, ex
     mono = all(b <= a for a, b in zip(E, E[1:]))
     return {"records": records, "monotone": mono, "step_seconds": step_s,
             "seconds": time.perf_counter() - t_all}
+
+
+def run_sweep(plans, ms, alphas, fields, steps, log_every=10, sink=None, extras=None):
+    """Advance independent runs together, each on its own plan and HIP stream.
+
+    plans[i] must have been created under a stream of its own (torch.cuda.stream),
+    with ms[i] allocated under the same stream; every run steps with constant
+    alphas[i] and fields[i] by graph replay on its plan's stream, so the small
+    launches of different runs execute concurrently.  After every `log_every`
+    steps of all runs the device is synchronised and each run's energies and
+    unit-length error are recorded as in run_logged (run id i, plus extras[i]).
+
+    Returns {"records": per-run lists, "monotone": per-run bools, "step_seconds"
+    (synchronised wall of the stepping alone), "seconds"}.
+    """
+    import torch
+    n = len(plans)
+    records = [[] for _ in range(n)]
+    t_all = time.perf_counter()
+    step_s = 0.0
+
+    def record(i, k):
+        p, m = plans[i], ms[i]
+        with torch.cuda.stream(p.stream):
+            r = {"run": i, "step": k, "alpha": alphas[i], "h_e": [float(x) for x in fields[i]],
+                 "energy": p.energy(m, fields[i]), "unit_error": p.unit_error(m)}
+        if extras:
+            r.update(extras[i])
+        records[i].append(r)
+        if sink is not None:
+            if isinstance(sink, list):
+                sink.append(r)
+            else:
+                sink.write(json.dumps(r) + "\n")
+
+    for i in range(n):
+        record(i, 0)
+    done = 0
+    while done < steps:
+        k = min(log_every, steps - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n):
+            with torch.cuda.stream(plans[i].stream):
+                plans[i].steps(ms[i], k, alphas[i], fields[i])
+        torch.cuda.synchronize()
+        step_s += time.perf_counter() - t0
+        done += k
+        for i in range(n):
+            record(i, done)
+    for p in plans:
+        p.check()
+    mono = [all(b["energy"]["total"] <= a["energy"]["total"] for a, b in zip(rs, rs[1:])) for rs in records]
+    return {"records": records, "monotone": mono, "step_seconds": step_s, "seconds": time.perf_counter() - t_all}

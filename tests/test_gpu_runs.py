@@ -97,3 +97,33 @@ def test_run_logged_strip(env):
     assert max(r["unit_error"] for r in sink) <= 1e-6
     E = [r["energy"]["total"] for r in sink]
     assert out["monotone"] == all(b <= a for a, b in zip(E, E[1:]))
+
+
+def test_concurrent_sweep_matches_sequential_runs(env):
+    """Runs stepped together on their own streams (run_sweep) give bit for bit the
+    states and records of the same runs stepped one after another (run_logged)."""
+    torch, sg = env
+    from paper_2606_28113_amd import runs
+    n = (128, 16, 2)
+    shape = (n[2], n[1], n[0])
+    m0 = workloads.random_unit(shape, 410)
+    cases = [(0.01, (1e-3, 0.0, 0.0)), (0.001, (5e-3, 0.0, 0.0)), (0.0001, (2e-2, 0.0, 0.0)), (0.01, (0.0, 1e-2, 0.0))]
+    plans, ms = [], []
+    for _ in cases:
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            plans.append(gpu_plan_si(sg, n, CELL, DT, ALL, 0))
+            ms.append(to_dev(torch, m0, 0))
+    torch.cuda.synchronize()
+    r = runs.run_sweep(plans, ms, [a for a, _ in cases], [b for _, b in cases], 25, log_every=10)
+    ref_plan = gpu_plan_si(sg, n, CELL, DT, ALL, 0)
+    for i, (a, b) in enumerate(cases):
+        m = to_dev(torch, m0, 0)
+        q = runs.run_logged(ref_plan, m, 25, a, b, log_every=10)
+        torch.cuda.synchronize()
+        assert torch.equal(m, ms[i]), i
+        assert [x["step"] for x in r["records"][i]] == [0, 10, 20, 25]
+        assert [x["energy"] for x in r["records"][i]] == [x["energy"] for x in q["records"]], i
+        assert r["monotone"][i] == q["monotone"]
+    for p in plans + [ref_plan]:
+        p.close()
