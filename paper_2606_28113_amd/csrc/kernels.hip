@@ -877,8 +877,11 @@ __global__ __launch_bounds__(NT) void k_col_fft(const ColFft<T> A) {
 // W_512^{t k2}; transpose; thread (k2, t0) takes t = t0 + 8 t1, DFT-8 over t1
 // and W_64^{t0 ka}; transpose; thread (k2, ka) finishes with a DFT-8 over t0
 // and owns k = k2 + 8 ka + 64 kb.  The inverse runs the same digits backwards.
-// LDS rows are padded (fft512_stride) against bank conflicts.
-template <typename T, int P> constexpr int fft512_stride() { return 8 * P + (sizeof(T) == 4 ? 8 : 4); }
+// LDS rows are padded (fft512_stride) against bank conflicts: with 64 four-byte
+// banks, the 8 rows x P pencils that half a wave touches in a transpose fall in
+// distinct banks when the row stride is P mod 32 complex (float) or P mod 16
+// (double).
+template <typename T, int P> constexpr int fft512_stride() { return 9 * P; }
 
 template <typename T, int P, bool INV>
 __global__ __launch_bounds__(64 * P) void k_fft512(const ColFft<T> A) {
@@ -2052,6 +2055,12 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
 // Two real rows share one complex pencil (a in .x, b in .y); P pencils per
 // workgroup, thread (q = tid % P, t = tid / P).
 
+// The 512-point row kernels keep W_512^e in LDS at slot e + e / 8: the twiddles
+// that a wave reads at once are spaced by multiples of 8 entries, which one pad
+// entry per 8 spreads over the banks.
+constexpr int W512_SLOTS = 512 + 64;
+__host__ __device__ __forceinline__ int w512_slot(int e) { return e + (e >> 3); }
+
 // natural order in: v[m] = x[t + 64 m]; digit order out: v[kb] = X[(t >> 3) + 8 (t & 7) + 64 kb],
 // the forward DFT, or with INV the unnormalised inverse (conjugate twiddles);
 // xb the LDS transpose buffer [64][S], W the table W_512^i in LDS;
@@ -2060,7 +2069,7 @@ template <typename T, int P, int S, bool INV>
 __device__ __forceinline__ void f512_dif(cx<T> (&v)[8], int t, int q, cx<T>* xb, const cx<T>* W, bool lo4,
                                          bool first4) {
   auto tw = [&](int e) {
-    cx<T> w = W[e & 511];
+    cx<T> w = W[w512_slot(e & 511)];
     if (INV) w.y = -w.y;
     return w;
   };
@@ -2108,7 +2117,7 @@ __device__ __forceinline__ void f512_inv(cx<T> (&v)[8], int t, int q, cx<T>* xb,
     const int k2 = t >> 3, ka = t & 7;
     dft8(v, true);
 #pragma unroll
-    for (int t0 = 1; t0 < 8; ++t0) v[t0] = cmul(v[t0], conjg(W[(8 * t0 * ka) & 511]));
+    for (int t0 = 1; t0 < 8; ++t0) v[t0] = cmul(v[t0], conjg(W[w512_slot((8 * t0 * ka) & 511)]));
 #pragma unroll
     for (int t0 = 0; t0 < 8; ++t0) xb[(k2 * 8 + t0) * S + ka * P + q] = v[t0];
   }
@@ -2119,7 +2128,7 @@ __device__ __forceinline__ void f512_inv(cx<T> (&v)[8], int t, int q, cx<T>* xb,
     for (int a = 0; a < 8; ++a) v[a] = xb[(kk2 * 8 + t0) * S + a * P + q];
     dft8(v, true);
 #pragma unroll
-    for (int t1 = 0; t1 < 8; ++t1) v[t1] = cmul(v[t1], conjg(W[((t0 + 8 * t1) * kk2) & 511]));
+    for (int t1 = 0; t1 < 8; ++t1) v[t1] = cmul(v[t1], conjg(W[w512_slot(((t0 + 8 * t1) * kk2) & 511)]));
     __syncthreads();
 #pragma unroll
     for (int t1 = 0; t1 < 8; ++t1) xb[(t0 + 8 * t1) * S + kk2 * P + q] = v[t1];
@@ -2132,15 +2141,23 @@ __device__ __forceinline__ void f512_inv(cx<T> (&v)[8], int t, int q, cx<T>* xb,
   else dft8(v, true);
 }
 
-// the spectrum X[k] of this thread's pencil, after f512_fwd, to its natural slot in xb
-template <typename T, int P, int S>
+// X[k] of pencil q in natural order: row k & 63, column (k >> 6) P + q of xb, the
+// column XORed with P ((k >> 3) & 7).  The spill writes rows 8 apart at once; the
+// swizzle puts them in distinct banks (the columns of a row stay within 8 P).
+template <typename T, int P, int S> __device__ __forceinline__ int f512_slot(int k, int q) {
+  const int r = k & 63;
+  return r * S + ((((k >> 6) * P) ^ (P * ((r >> 3) & 7))) + q);
+}
+// the spectrum of this thread's pencil, after f512_fwd (digit order), to its natural
+// slots; NKB: the first NKB digits only
+template <typename T, int P, int S, int NKB = 8>
 __device__ __forceinline__ void f512_spill(const cx<T> (&v)[8], int t, int q, cx<T>* xb) {
   const int kl = (t >> 3) + 8 * (t & 7);
 #pragma unroll
-  for (int kb = 0; kb < 8; ++kb) xb[kl * S + kb * P + q] = v[kb];
+  for (int kb = 0; kb < NKB; ++kb) xb[f512_slot<T, P, S>(kl + 64 * kb, q)] = v[kb];
 }
 template <typename T, int P, int S> __device__ __forceinline__ cx<T> f512_at(const cx<T>* xb, int k, int q) {
-  return xb[(k & 63) * S + (k >> 6) * P + q];
+  return xb[f512_slot<T, P, S>(k, q)];
 }
 
 // Memory order in both kernels: every global load (operands, spectra, DCT
@@ -2151,8 +2168,8 @@ template <typename T, int P>
 __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
   constexpr int N = 256, S = fft512_stride<T, P>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);  // W_512^i
-  cx<T>* xb = W + 512;
+  cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);  // W_512^i at w512_slot(i)
+  cx<T>* xb = W + W512_SLOTS;
   const Blk bk = xcd_block();
   const int tid = threadIdx.x, q = tid % P, t = tid / P, ch = bk.z;
   const int ra = bk.x * 2 * P + 2 * q;
@@ -2189,7 +2206,7 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
     pw[m] = w ? mk<T>(ld_off(w, la + xo4), ld_off(w, lb + xo4)) : zero<T>();
     wk[m] = dout ? A.dtw[t + 64 * m] : zero<T>();
   }
-  for (int i = tid; i < 512; i += 64 * P) W[i] = A.tw[i << (A.lgTw - 9)];
+  for (int i = tid; i < 512; i += 64 * P) W[w512_slot(i)] = A.tw[i << (A.lgTw - 9)];
   __syncthreads();
   cx<T> v[8];
   if (xin) {
@@ -2215,11 +2232,7 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
     }
     // x in digit order, only x < 256 (kb < 4); back to x = t + 64 m through LDS
     f512_dif<T, P, S, true>(v, t, q, xb, W, false, true);
-    {
-      const int kl = (t >> 3) + 8 * (t & 7);
-#pragma unroll
-      for (int kb = 0; kb < 4; ++kb) xb[kl * S + kb * P + q] = v[kb];
-    }
+    f512_spill<T, P, S, 4>(v, t, q, xb);
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < 4; ++m) v[m] = f512_at<T, P, S>(xb, t + 64 * m, q);
@@ -2308,8 +2321,8 @@ template <typename T, int P, int NCH, bool XM, int OP>
 __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
   constexpr int N = 256, S = fft512_stride<T, P>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* xb = W + 512;
+  cx<T>* W = reinterpret_cast<cx<T>*>(smem_raw);  // W_512^i at w512_slot(i)
+  cx<T>* xb = W + W512_SLOTS;
   const Blk bk = xcd_block();
   const int tid = threadIdx.x, q = tid % P, t = tid / P;
   const int ra = bk.x * 2 * P + 2 * q;
@@ -2359,7 +2372,7 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
       pre_src[m] = A.src ? mk<T>(ld_off(A.src, la + xo), ld_off(A.src, lb + xo)) : zero<T>();
     }
   }
-  for (int i = tid; i < 512; i += 64 * P) W[i] = A.tw[i << (A.lgTw - 9)];
+  for (int i = tid; i < 512; i += 64 * P) W[w512_slot(i)] = A.tw[i << (A.lgTw - 9)];
   __syncthreads();
   const T invn = (T)1 / (T)N;
   cx<T> g[NCH][4];
@@ -2477,7 +2490,7 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
   }
   if (row256<T>(a.lgN, a.lgLc, a.lgLr, c2r, r2c)) {
     constexpr int P = row_fwd512_pencils<T>();
-    const size_t lds = (512 + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
+    const size_t lds = (W512_SLOTS + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
     const dim3 grid(ceil_div(a.nrows, 2 * P), 1, nch);
     RowFwd<T> b = a;
     b.dct_xmajor = a.dct_xmajor && a.nrows > 1;  // one row: both layouts coincide
@@ -2535,7 +2548,7 @@ template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
                        (a.op == ROW_OP_PROJECT && a.nch == 3) || a.op == ROW_OP_NONE;
   if (mode_ok && row256<T>(a.lgN, a.lgLr, a.lgLr, false, a.xout != nullptr)) {
     constexpr int P = row_inv512_pencils<T>();
-    const size_t lds = (512 + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
+    const size_t lds = (W512_SLOTS + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
     const dim3 grid(ceil_div(a.nrows, 2 * P));
     launch_row_inv512_mode<T>(a, grid, lds, s);
     return SGSPM_KC_ROW_INV512;

@@ -104,8 +104,9 @@ def _run(exe, tmp_path, n, prec, scheme_=0, terms=ALL, steps=2, sample=0, seed=3
 
 
 # the grid shapes of the generic kernels (power-of-two and mixed-radix extents,
-# films, lines and single cells), every workgroup, FP64, against the oracle
-FULL = [(16, 8, 4), (12, 10, 3), (4, 1, 8), (30, 1, 1), (1, 1, 1)]
+# films, lines and single cells) and rows of 256 (the 512-point register row
+# kernels), every workgroup, FP64, against the oracle
+FULL = [(16, 8, 4), (12, 10, 3), (4, 1, 8), (30, 1, 1), (1, 1, 1), (256, 2, 1)]
 FULL_MORE = [(8, 4, 2), (1, 16, 1), (6, 5, 1)]
 # SGSPM_EMU_ALL=1 adds the longer lists below to the default ones
 EMU_ALL = os.environ.get("SGSPM_EMU_ALL") == "1"
@@ -137,7 +138,7 @@ def test_every_access_in_bounds_fp64(emu_exe, tmp_path, n):
 
 
 @pytest.mark.skipif(not EMU_ALL, reason="longer emulation list (SGSPM_EMU_ALL=1)")
-@pytest.mark.parametrize("n", [(16, 8, 4), (12, 10, 3)], ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("n", [(16, 8, 4), (12, 10, 3), (256, 2, 1)], ids=lambda n: "x".join(map(str, n)))
 def test_every_access_in_bounds_fp32(emu_exe, tmp_path, n):
     m0, _, got = _run(emu_exe, tmp_path, n, 0)
     P = oracle_problem_si(n, (CELL,) * 3, DT, ("exchange", "aniso", "stray", "zeeman"))
