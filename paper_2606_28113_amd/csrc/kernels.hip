@@ -2470,12 +2470,14 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
   }
 }
 
-// pencils (pairs of rows) per workgroup of the 512-point row kernels.  Single
-// precision: 8 for the forward kernel (16 measured slower: larger barriers, one
-// workgroup per CU), 4 for the inverse kernel, whose Gauss-Seidel variants hold
-// 110-142 VGPRs: smaller workgroups pack the CU more finely (8 measured 8% slower
-// for one channel, 25% for two)
-template <typename T> constexpr int row_fwd512_pencils() { return sizeof(T) == 4 ? 8 : 4; }
+// pencils (pairs of rows) per workgroup of the 512-point row kernels.  The lanes
+// of a wave cover P pencils x 64/P positions, so a row-major access touches 2P
+// rows per instruction and an x-major one 2P consecutive values.  Single
+// precision: 2 for the forward kernel, whose loads are row-major (10% faster than
+// 4 or 8; 16 was slower still), 4 for the inverse kernel, which reads its heat
+// arrays x-major (2 measured 7% slower, 8 measured 8% slower for one channel and
+// 25% for two)
+template <typename T> constexpr int row_fwd512_pencils() { return sizeof(T) == 4 ? 2 : 4; }
 template <typename T> constexpr int row_inv512_pencils() { return 4; }
 
 template <typename T> bool row256(int lgN, int lgLc, int lgLr, bool c2r, bool r2c) {

@@ -145,6 +145,35 @@ def test_adjoint_step_block_256x256x32(env, prec):
     assert e_l <= bar and e_h <= bar and e_a <= bar
 
 
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_adjoint_step_large_without_stray(env, prec):
+    """A grid above 2^20 cells with rows of 512 (the generic LDS row kernels) and no
+    stray field: the accumulation passes of the adjoint then run row launches with no
+    transform, whose tiles must still hold every row.  Element by element against the
+    oracle adjoint."""
+    torch, sg = env
+    n = (512, 64, 64)
+    terms = ("exchange", "aniso", "zeeman")
+    shape = (n[2], n[1], n[0])
+    m0 = workloads.random_unit(shape, 120)
+    lam = np.random.default_rng(121).normal(size=(3,) + shape)
+    B = (4e-3, -2e-3, 1e-3)
+    plan = gpu_plan_si(sg, n, CELL, DT, terms, prec)
+    lam_d = to_dev(torch, lam, prec)
+    grad = torch.zeros(4, dtype=torch.float64, device="cuda")
+    plan.adjoint_step(to_dev(torch, m0, prec), 0.05, B, lam_d, grad)
+    torch.cuda.synchronize()
+    P = oracle_problem_si(n, CELL, DT, terms)
+    lref, dh, da = oadj.adjoint_step(P, rounded_like(m0, prec), 0.05, oracle_field_si(B, terms),
+                                     rounded_like(lam, prec))
+    g = grad.cpu().numpy()
+    e_l, e_h, e_a = _rel_inf(lam_d.cpu().numpy(), lref), _rel_inf(g[:3], dh * FSCALE), abs(g[3] - da) / abs(da)
+    print(f"512x64x64 {'fp64' if prec else 'fp32'} adjoint step without the stray field: lam {e_l:.2e}, "
+          f"dh_e {e_h:.2e}, dalpha {e_a:.2e}")
+    bar = 1e-10 if prec == 1 else 1e-5
+    assert e_l <= bar and e_h <= bar and e_a <= bar
+
+
 def test_block_checkpointed_adjoint_k20(env):
     """The block's checkpointed backward pass (checkpoints every 20 steps, each segment
     recomputed from its checkpoint) gives bit for bit the gradients of a pass that keeps
