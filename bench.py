@@ -97,9 +97,9 @@ def algorithmic_step_bytes(c, dbytes):
     return field, tensor
 
 
-def make_plan(sg, c, precision, scheme=0):
+def make_plan(sg, c, precision, scheme=0, batch=0):
     kw = dict(nx=c.n[0], ny=c.n[1], nz=c.n[2], dx=c.h[0], dy=c.h[1], dz=c.h[2], dt=c.dt, precision=precision,
-              scheme=scheme)
+              scheme=scheme, batch=batch)
     if c.units == "si":
         kw.update(units=sg.UNITS_SI, A=c.A, Ms=c.Ms, Ku=c.Ku, terms=sg.TERM_ALL)
     else:
@@ -384,15 +384,11 @@ def main():
         log = open(args.metrics_log, "w") if args.metrics_log else None
         cases = [(float(b_mT), a) for b_mT in cs.extra["fields_mT"] for a in cs.extra["alphas"]]
         t0 = time.perf_counter()
-        # one plan and one HIP stream per run: the runs' small launches overlap
-        plans, mss = [], []
-        for _ in cases:
-            st = torch.cuda.Stream()
-            with torch.cuda.stream(st):
-                plans.append(make_plan(sg, cs, sg.FP32))
-                mss.append(torch.tensor(m0s, dtype=torch.float32, device="cuda"))
+        # one batched plan: every launch of a step covers the 15 runs
+        pb = make_plan(sg, cs, sg.FP32, batch=len(cases))
+        mss = torch.tensor(np.repeat(m0s[:, None], len(cases), axis=1), dtype=torch.float32, device="cuda")
         torch.cuda.synchronize()
-        r = runs_mod.run_sweep(plans, mss, [a for _, a in cases], [(b * 1e-3, 0.0, 0.0) for b, _ in cases],
+        r = runs_mod.run_batch(pb, mss, [a for _, a in cases], [(b * 1e-3, 0.0, 0.0) for b, _ in cases],
                                args.sweep_steps, log_every=10, sink=log, extras=[{"B_mT": b} for b, _ in cases])
         step_s = r["step_seconds"]
         detail = []
@@ -403,9 +399,8 @@ def main():
         wall = time.perf_counter() - t0
         if log:
             log.close()
-        for p_ in plans:
-            p_.close()
-        del plans, mss
+        pb.close()
+        del mss
         cu = cs.cells * args.sweep_steps * len(detail)
         sweep = {"workload": f"{cs.name}: {WORKLOAD_TEXT[cs.name].split(', 5 mT')[0]}, fields "
                              f"{', '.join(f'{b:g}' for b in cs.extra['fields_mT'])} mT x alpha "
@@ -413,10 +408,10 @@ def main():
                  "runs": len(detail), "steps_per_run": args.sweep_steps, "dtype": "f32",
                  "value": cu / step_s, "unit": "cell-updates/s", "step_seconds": step_s,
                  "value_incl_logging": cu / wall, "wall_s": wall,
-                 "note": "15 runs, one plan and HIP stream each, stepped together (every run's steps replayed "
-                         "from its own captured HIP graph, so the runs' launches overlap on the GPU); FP64 "
-                         "energies per term and max ||m| - 1| of every run every 10 steps (synchronising); "
-                         "value counts the stepping alone",
+                 "note": "15 runs in one batched plan (every launch of a step covers all runs; steps replayed "
+                         "from a captured HIP graph of the batched step); FP64 energies per term of every run "
+                         "and max ||m| - 1| over the runs every 10 steps (synchronising); value counts the "
+                         "stepping alone",
                  "runs_with_monotone_energy": sum(1 for d in detail if d["monotone_energy"]),
                  "detail": detail}
         print(f"[bench] strip sweep: {len(detail)} runs x {args.sweep_steps} steps, stepping {step_s:.2f} s "

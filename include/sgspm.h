@@ -74,6 +74,11 @@ typedef struct {
   uint32_t terms;       /* bitmask of SGSPM_TERM_* */
   int32_t precision;    /* SGSPM_FP32 or SGSPM_FP64 */
   int32_t scheme;       /* SGSPM_SCHEME_SGS (default), SGSPM_SCHEME_GS or SGSPM_SCHEME_SGS_FF */
+  int32_t batch;        /* independent runs of the same grid and constants stepped together
+                           (0 or 1: one run).  A batched plan (2 <= batch <= 256) takes fields
+                           of shape [3][batch][nz][ny][nx], each run with its own alpha and
+                           applied field (sgspm_step_batch); SGS or GS scheme, no source term,
+                           ny * nz even, and grids whose heat solve is the fused y-z kernel */
 } sgspm_params;
 
 typedef struct sgspm_plan_s* sgspm_plan_t;
@@ -180,6 +185,26 @@ int sgspm_adjoint_step(sgspm_plan_t plan, const void* m_n, double alpha, const d
  * field is written before it is read. */
 int sgspm_adjoint_step_noalloc(sgspm_plan_t plan, const void* m_n, double alpha, const double h_e[3],
                                void* lam, double* grad_dev);
+
+/* Batched plans (params.batch = B >= 2): B independent runs of the same grid
+ * and constants share every launch of a step, so small grids fill the GPU.  m is
+ * device [3][B][nz][ny][nx] of the plan's precision (component-major: component c
+ * of run b at m + (c B + b) nz ny nx); run b steps with alpha[b] and the applied
+ * field h_e[3 b .. 3 b + 2] (host arrays).  The result of each run is bit for bit
+ * the one a single-run plan computes from the same input.  Per-run values are
+ * staged in a plan-owned device buffer before the launches, so calls on one plan
+ * must not overlap.  The single-run entry points (sgspm_step, sgspm_steps,
+ * sgspm_energy, sgspm_field, sgspm_stray, sgspm_heat_solve, the adjoint and the
+ * spectral-radius step) return SGSPM_EINVAL on a batched plan; sgspm_unit_error
+ * returns the maximum over every run. */
+int sgspm_step_batch(sgspm_plan_t plan, void* m, const double* alpha, const double* h_e);
+/* nsteps batched steps with constant per-run alpha and h_e, replayed from one
+ * captured HIP graph of the batched step (captured again when m changes).  The
+ * per-run values are read from the plan's device buffer at every replay. */
+int sgspm_steps_batch(sgspm_plan_t plan, void* m, int nsteps, const double* alpha, const double* h_e);
+/* Energies of every run (as sgspm_energy): e_out = host double[5 B], run b at
+ * e_out[5 b]; h_e = host double[3 B].  Synchronises the stream. */
+int sgspm_energy_batch(sgspm_plan_t plan, const void* m, const double* h_e, double* e_out);
 
 /* Measurement support.  Kernel classes of the step's launches; each class is
  * one kernel (its float or double instance): */

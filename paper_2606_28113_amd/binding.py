@@ -13,6 +13,7 @@ FP32, FP64 = 0, 1
 SCHEME_SGS, SCHEME_GS, SCHEME_SGS_FF = 0, 1, 2
 
 EXPORTS = ("sgspm_validate", "sgspm_reduced_constants", "sgspm_plan", "sgspm_step", "sgspm_steps",
+           "sgspm_step_batch", "sgspm_steps_batch", "sgspm_energy_batch",
            "sgspm_step_spectral_radius",
            "sgspm_energy", "sgspm_unit_error",
            "sgspm_field", "sgspm_stray", "sgspm_heat_solve", "sgspm_adjoint_step",
@@ -37,7 +38,8 @@ class Params(ctypes.Structure):
                 ("dt", ctypes.c_double),
                 ("terms", ctypes.c_uint32),
                 ("precision", ctypes.c_int32),
-                ("scheme", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32),
+                ("batch", ctypes.c_int32)]
 
 
 def _load():
@@ -52,6 +54,9 @@ def _load():
     L.sgspm_step.argtypes = [vp, vp, ctypes.c_double, dp, vp]
     L.sgspm_step_spectral_radius.argtypes = [vp, vp, ctypes.c_double, dp, vp, dp]
     L.sgspm_steps.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, dp]
+    L.sgspm_step_batch.argtypes = [vp, vp, dp, dp]
+    L.sgspm_steps_batch.argtypes = [vp, vp, ctypes.c_int, dp, dp]
+    L.sgspm_energy_batch.argtypes = [vp, vp, dp, dp]
     L.sgspm_energy.argtypes = [vp, vp, dp, dp]
     L.sgspm_unit_error.argtypes = [vp, vp, dp]
     L.sgspm_field.argtypes = [vp, vp, dp, vp]
@@ -80,8 +85,8 @@ def _check(rc):
 
 
 def make_params(nx, ny, nz, dx, dy, dz, dt, units=UNITS_SI, A=0.0, Ms=1.0, Ku=0.0, eps=0.0, Q=0.0,
-                terms=TERM_ALL, precision=FP32, scheme=SCHEME_SGS):
-    return Params(nx, ny, nz, dx, dy, dz, units, A, Ms, Ku, eps, Q, dt, terms, precision, scheme)
+                terms=TERM_ALL, precision=FP32, scheme=SCHEME_SGS, batch=0):
+    return Params(nx, ny, nz, dx, dy, dz, units, A, Ms, Ku, eps, Q, dt, terms, precision, scheme, batch)
 
 
 def validate(**kw):
@@ -106,7 +111,8 @@ class Plan:
 
     Keyword arguments are the fields of sgspm_params (see make_params).
     Field tensors: CUDA, contiguous, shape (3, nz, ny, nx), dtype float32 for
-    FP32 plans and float64 for FP64 plans.
+    FP32 plans and float64 for FP64 plans; a batched plan (batch = B >= 2) takes
+    (3, B, nz, ny, nx) and the *_batch methods.
     """
 
     def __init__(self, **kw):
@@ -121,9 +127,40 @@ class Plan:
                               ctypes.byref(self._h)))
 
     @property
+    def batch(self):
+        return max(1, self.params.batch)
+
+    @property
     def shape(self):
         nx, ny, nz = self.n
-        return (3, nz, ny, nx)
+        return (3, self.batch, nz, ny, nx) if self.batch > 1 else (3, nz, ny, nx)
+
+    def _runs(self, alpha, h_e):
+        B = self.batch
+        a = [float(x) for x in alpha]
+        h = [float(x) for row in h_e for x in row]
+        if len(a) != B or len(h) != 3 * B:
+            raise ValueError(f"alpha needs {B} values and h_e {B} rows of 3")
+        return (ctypes.c_double * B)(*a), (ctypes.c_double * (3 * B))(*h)
+
+    def step_batch(self, m, alpha, h_e):
+        """One step of every run of a batched plan: run b with alpha[b] and h_e[b]."""
+        a, h = self._runs(alpha, h_e)
+        _check(lib.sgspm_step_batch(self._h, self._ptr(m, self.shape, "m"), a, h))
+
+    def steps_batch(self, m, nsteps, alpha, h_e):
+        """nsteps batched steps with constant per-run alpha and h_e (captured HIP graph)."""
+        a, h = self._runs(alpha, h_e)
+        _check(lib.sgspm_steps_batch(self._h, self._ptr(m, self.shape, "m"), int(nsteps), a, h))
+
+    def energy_batch(self, m, h_e):
+        """Energies of every run: a list of dicts as energy() returns."""
+        B = self.batch
+        _, h = self._runs([0.0] * B, h_e)
+        out = (ctypes.c_double * (5 * B))()
+        _check(lib.sgspm_energy_batch(self._h, self._ptr(m, self.shape, "m"), h, out))
+        keys = ("total", "exchange", "anisotropy", "stray", "zeeman")
+        return [dict(zip(keys, list(out[5 * b:5 * b + 5]))) for b in range(B)]
 
     def _ptr(self, t, shape=None, name="tensor"):
         if not t.is_cuda or not t.is_contiguous() or t.dtype != self.dtype:
@@ -206,7 +243,7 @@ class Plan:
         _check(lib.sgspm_timing(self._h, 1 if enable else 0))
 
     def timing_read(self):
-        """{class: (ms, algorithmic bytes, launches)} since the last enable / read."""
+        """{class: (ms, launch-level bytes, launches)} since the last enable / read."""
         n = len(KERNEL_CLASSES)
         ms, by, cnt = (ctypes.c_double * n)(), (ctypes.c_double * n)(), (ctypes.c_int64 * n)()
         _check(lib.sgspm_timing_read(self._h, ms, by, cnt))

@@ -67,7 +67,20 @@ template <typename T> struct RowFwd {
   int Lr, lgLr;
   int xout_pitch;
   int xpk;          // xin and xout hold the Nyquist bin in the imaginary part of bin 0
+  // independent runs of a batched plan (runp null: one run): rows b rpr ...
+  // (b + 1) rpr - 1 belong to run b, and a tile never holds rows of two runs.
+  // Run b's applied field (he[ch] <- runp[b RUNP + rcomp[ch]]) replaces he; in
+  // the damping step (rstageF) its a[ch] and b as well (runp[b RUNP + 3 + rcomp],
+  // runp[b RUNP + 6])
+  const T* runp;
+  int rpr;
+  int rstageF;
+  int rcomp[3];
 };
+// per-run values of a batched plan, in the plan's precision: the applied field
+// (3, by component), the damping step's a (3, by component) and b, and its heat
+// scale s = alpha dt
+constexpr int RUNP = 8;
 
 enum { ROW_OP_NONE = 0, ROW_OP_GS = 1, ROW_OP_PROJECT = 2 };
 
@@ -155,6 +168,12 @@ template <typename T> struct YZSolve {
   const T* lamY;
   const T* lamZ;
   T s;
+  // a batched plan: nx planes per run, stored [nx][runs] (plane x of run b at
+  // x runs + b); in the damping step (rstageF) the planes of run b take
+  // s = runp[b RUNP + 7] (runs 0: one run)
+  int runs;
+  const T* runp;
+  int rstageF;
 };
 template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStream_t s);
 // largest plane (ny * nz reals) the fused yz solve holds in one workgroup
@@ -185,6 +204,10 @@ template <typename T> struct Conv {
   int lgTw;          // the 64-point kernel: power-of-two table
   int twg;           // the generic kernel: W_L^i = tw[i * twg]
   int nyqb;          // S and O hold the Nyquist column ni - 1 in the blocked layout over the batch rows
+  // a batched plan: runs of the plan (grid z; 0 or 1: one run), run b's S and O
+  // at S[c] + b rs_in and O[a] + b rs_out
+  int runs;
+  long rs_in, rs_out;
 };
 
 // Launch-geometry errors.  Every launcher checks, before it launches, the
@@ -212,6 +235,11 @@ void launch_newell_fill(double* out, int comp, int nx, int ny, int nz, int Px, i
 template <typename T>
 void launch_tensor_pack(const cx<double>* spec, T* out, int Hz, int Hy, int Kx, int Kxp, int Kt, int Py, double scale,
                         hipStream_t s);
+
+// dst[i] = values[i], i < n (host values passed in the launch arguments, 256
+// per launch): the per-run values of a batched plan, stream-ordered and
+// capturable without a host buffer that must outlive the call
+template <typename T> void launch_fill(T* dst, const T* values, long n, hipStream_t s);
 
 // Pointwise product terms: for each term t in order,
 //   out_t = (acc_t ? out_t : 0) + c0_t * x0_t * y0_t + c1_t * x1_t * y1_t

@@ -199,7 +199,17 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
   const T* w = A.w[ch];
   T* hso = A.hs_out[ch];
   T* vo = A.val_out[ch];
-  const T ac = A.a[ch], hec = A.he[ch], bc = A.b, wcc = A.wc[ch];
+  T ac = A.a[ch], hec = A.he[ch], bc = A.b;
+  const T wcc = A.wc[ch];
+  if (A.runp) {
+    // every row of the tile belongs to one run
+    const T* r = A.runp + (long)(min(row0, A.nrows - 1) / A.rpr) * RUNP;
+    hec = r[A.rcomp[ch]];
+    if (A.rstageF) {
+      ac = r[3 + A.rcomp[ch]];
+      bc = r[6];
+    }
+  }
   // loads of every element first (clamped indices, no branch between them), stores
   // after (loads and stores share one in-order counter)
   auto cidx = [&](int i) {
@@ -562,7 +572,7 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
   constexpr int NTH = YZ_NT;
   constexpr int NV = 2 * YZ_VPT;  // reals per thread
   const int ny = A.ny, nz = A.nz, lgNy = A.lgNy, lgNz = A.lgNz;
-  const int M = ny * nz;
+  const int M = ny * nz, lgM = lg_or_neg(M);
   const int PP = 1 << A.lgPP;
   const int R = M * PP;
   // y pass: real pencils rho = (p, z), NPy of them, paired rho <-> rho + Hy
@@ -581,16 +591,24 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
   T* Ly = reinterpret_cast<T*>(Dz + nz);
   T* Lz = Ly + ny;
   T* Lx = Lz + nz;
-  const int p0 = blockIdx.x << A.lgPP;
+  T* Sx = Lx + PP;  // the scale s of each plane
+  // a batched plan: workgroup (xg, run b) holds planes x0 ... x0 + PP - 1 of run b,
+  // which sit runs planes apart ([nx][runs][nz][ny]); its pairing of rows into
+  // complex pencils is the single-run plan's
+  const int runs = A.runs > 0 ? A.runs : 1;
+  const int rb = blockIdx.x % runs;
+  const int p0 = (blockIdx.x / runs) << A.lgPP;
   const int nplanes = min(PP, A.nx - p0);
-  T* D = A.data[blockIdx.z] + (long)p0 * M;
+  const long pstride = (long)runs * M;
+  T* D = A.data[blockIdx.z] + ((long)p0 * runs + rb) * M;
+  auto doff = [&](int e) { return (long)qdiv<MX>(e, M, lgM) * pstride + qmod<MX>(e, M, lgM); };
   // one round trip to memory: the planes, then the tables (each table loop loads
   // before it stores)
   T v[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const int e = threadIdx.x + i * NTH;
-    v[i] = (e < R && e < nplanes * M) ? D[e] : (T)0;
+    v[i] = (e < R && e < nplanes * M) ? D[doff(e)] : (T)0;
   }
   {
     const int nt = max(max(ny, nz), PP);
@@ -600,6 +618,7 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
       const cx<T> dy = A.dtwy[iy], dz = A.dtwz[iz];
       const T ly = A.lamY[iy], lz = A.lamZ[iz];
       const T lx = A.lamX[min(p0 + min(i, PP - 1), A.nx - 1)];
+      const T sp = (A.runp && A.rstageF) ? A.runp[(long)rb * RUNP + 7] : A.s;
       if (i < ny) {
         Wy[i] = wy;
         Dy[i] = dy;
@@ -610,7 +629,10 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
         Dz[i] = dz;
         Lz[i] = lz;
       }
-      if (i < PP) Lx[i] = p0 + i < A.nx ? lx : (T)0;
+      if (i < PP) {
+        Lx[i] = p0 + i < A.nx ? lx : (T)0;
+        Sx[i] = sp;
+      }
     }
   }
   // pencils of a pass as (lgP, ncomp) of the FFT engine: a power-of-two count
@@ -713,8 +735,8 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
         const int ra = q, rb = q + Hz;
         const int pa = qdiv<MX>(ra, ny, lgNy), pb = min(qdiv<MX>(rb, ny, lgNy), PP - 1);
         const T lx_a = Lx[pa], lx_b = Lx[pb];
-        xa[s2] = (w.x * Va.x - w.y * Va.y) / ((T)1 + A.s * (lx_a + Ly[qmod<MX>(ra, ny, lgNy)] + Lz[k]));
-        xb[s2] = (w.x * Vb.x - w.y * Vb.y) / ((T)1 + A.s * (lx_b + Ly[qmod<MX>(rb, ny, lgNy)] + Lz[k]));
+        xa[s2] = (w.x * Va.x - w.y * Va.y) / ((T)1 + Sx[pa] * (lx_a + Ly[qmod<MX>(ra, ny, lgNy)] + Lz[k]));
+        xb[s2] = (w.x * Vb.x - w.y * Vb.y) / ((T)1 + Sx[pb] * (lx_b + Ly[qmod<MX>(rb, ny, lgNy)] + Lz[k]));
       }
     }
     __syncthreads();
@@ -766,7 +788,7 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
     for (int i = 0; i < NV; ++i) {
       int p, z, y;
       if (decode(i, p, z, y)) {
-        v[i] /= (T)1 + A.s * (Lx[p] + Ly[y] + Lz[0]);
+        v[i] /= (T)1 + Sx[p] * (Lx[p] + Ly[y] + Lz[0]);
       }
     }
   }
@@ -825,7 +847,7 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const int e = threadIdx.x + i * NTH;
-    if (e < R && e < nplanes * M) D[e] = v[i];
+    if (e < R && e < nplanes * M) D[doff(e)] = v[i];
   }
 }
 
@@ -1185,7 +1207,7 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
     cx<T> r[3][2];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const cx<T>* S = A.S[c];
+      const cx<T>* S = A.S[c] ? A.S[c] + (long)blockIdx.z * A.rs_in : nullptr;
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int t = threadIdx.x + u * CONV_NT;
@@ -1245,7 +1267,7 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
     for (int a = 0; a < 3; ++a) {
       cx<T>* O = A.O[a];
       if (!O) continue;
-      O += boff;
+      O += boff + (long)blockIdx.z * A.rs_out;
       for (int t = threadIdx.x; t < P * A.n; t += CONV_NT) {
         const int j = t >> A.lgP, q = t & (P - 1);
         const int i = i0 + q;
@@ -1324,7 +1346,7 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 5 : 1) void k_conv64(const
   cx<T> v[3][8];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const cx<T>* S = A.S[c];
+    const cx<T>* S = A.S[c] ? A.S[c] + (long)bk.z * A.rs_in : nullptr;
 #pragma unroll
     for (int m = 0; m < 4; ++m) v[c][m] = S ? ld_off(S, soff + (unsigned)(t + 8 * m) * sa) : zero<T>();
   }
@@ -1405,7 +1427,7 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 5 : 1) void k_conv64(const
 #pragma unroll
     for (int bb = 0; bb < 8; ++bb) xb[c64_idx(0, bb, t, NP, pen)] = o[bb];
     __syncthreads();
-    cx<T>* O = A.O[a];
+    cx<T>* O = A.O[a] + (long)bk.z * A.rs_out;
     cx<T> u[8];
 #pragma unroll
     for (int tt2 = 0; tt2 < 8; ++tt2) u[tt2] = xb[c64_idx(0, t, tt2, NP, pen)];
@@ -1896,7 +1918,7 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
   T* D = A.data[blockIdx.z] + (long)blockIdx.x * (NY * NZ);
   cx<T>* zs = Zs + r * RS;
   auto minv = [](int p) { return p < NY / 2 ? 2 * p : 2 * (NY - 1 - p) + 1; };
-  T lx;
+  T lx, sp;
 
   // ---- y forward
   {
@@ -1913,7 +1935,10 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
     const int iz = min(tid, NZ - 1);
     const cx<T> dz_i = A.dtwz[iz];
     const T lz_i = A.lamZ[iz];
-    lx = A.lamX[blockIdx.x];
+    // a batched plan: plane blockIdx.x = x runs + b
+    const int runs = A.runs > 0 ? A.runs : 1;
+    lx = A.lamX[blockIdx.x / runs];
+    sp = (A.runp && A.rstageF) ? A.runp[(long)(blockIdx.x % runs) * RUNP + 7] : A.s;
     Wy[tid] = w_i;
     Dy[tid] = dy_i;
     Ly[tid] = ly_i;
@@ -1967,7 +1992,7 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
       else u[pb >> 1].x = yb;
     }
     dft16(u, false);
-    const T dc = (T)1 + A.s * (lx + Ly[c]);
+    const T dc = (T)1 + sp * (lx + Ly[c]);
     T X[NZ];
     // V_k = E_k + W_32^k O_k from U_k and conj U_(16-k); V_(32-k) = conj V_k
 #pragma unroll
@@ -1978,10 +2003,10 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
       const cx<T> O = mk<T>((Uk.y - Um.y) * (T)0.5, (Um.x - Uk.x) * (T)0.5);
       const cx<T> V = E + tw32v(O, k, false);
       const cx<T> wk = Dz[k];
-      X[k] = (wk.x * V.x - wk.y * V.y) * recip(dc + A.s * Lz[k]);
+      X[k] = (wk.x * V.x - wk.y * V.y) * recip(dc + sp * Lz[k]);
       if (k > 0 && k < HZ) {
         const cx<T> wm = Dz[NZ - k];
-        X[NZ - k] = (wm.x * V.x + wm.y * V.y) * recip(dc + A.s * Lz[NZ - k]);
+        X[NZ - k] = (wm.x * V.x + wm.y * V.y) * recip(dc + sp * Lz[NZ - k]);
       }
     }
     // DCT-III input V_j = conj(dtwz_j) (X_j - i X_(32-j)), folded to 16 points:
@@ -2245,7 +2270,17 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
   {
     T* hso = A.hs_out[ch];
     T* vo = A.val_out[ch];
-    const T ac = A.a[ch], hec = A.he[ch], bc = A.b, wcc = A.wc[ch];
+    T ac = A.a[ch], hec = A.he[ch], bc = A.b;
+    const T wcc = A.wc[ch];
+    if (A.runp) {
+      // every row of the tile belongs to one run
+      const T* rp = A.runp + (long)(min(bk.x * 2 * P, A.nrows - 1) / A.rpr) * RUNP;
+      hec = rp[A.rcomp[ch]];
+      if (A.rstageF) {
+        ac = rp[3 + A.rcomp[ch]];
+        bc = rp[6];
+      }
+    }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const unsigned xo4 = (unsigned)(t + 64 * m) * TB;
@@ -2490,7 +2525,7 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
     c2r = c2r || a.xin[c];
     r2c = r2c || a.xout[c];
   }
-  if (row256<T>(a.lgN, a.lgLc, a.lgLr, c2r, r2c)) {
+  if (row256<T>(a.lgN, a.lgLc, a.lgLr, c2r, r2c) && (!a.runp || a.rpr % (2 * row_fwd512_pencils<T>()) == 0)) {
     constexpr int P = row_fwd512_pencils<T>();
     const size_t lds = (W512_SLOTS + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
     const dim3 grid(ceil_div(a.nrows, 2 * P), 1, nch);
@@ -2512,6 +2547,7 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
   if (a.lgP < 0 || ((long)a.Lmax << a.lgP) > tile_elems<T>()) return geom_fail("k_row_fwd: P Lmax beyond the tile");
   if (a.twg < 1) return geom_fail("k_row_fwd: no twiddle stride");
   if (lds > LDS_LIMIT) return geom_fail("k_row_fwd: LDS beyond the limit");
+  if (a.runp && (a.rpr < 1 || a.rpr % rows)) return geom_fail("k_row_fwd: a tile holds rows of two runs");
   if (a.lgN < 0 || a.lgLmax < 0 || (c2r && a.lgLc < 0) || (r2c && a.lgLr < 0))
     hipLaunchKernelGGL((k_row_fwd<T, true>), grid, dim3(NT), lds, s, a);
   else
@@ -2622,8 +2658,9 @@ template <typename T> size_t yz_lds(int ny, int nz, int lgPP) {
   const size_t PP = (size_t)1 << lgPP;
   const size_t Hy = (PP * nz + 1) / 2, Hz = (PP * ny + 1) / 2;
   const size_t nbuf = std::max((size_t)ny * (Hy + 1), (size_t)nz * (Hz + 1));
-  // y and z twiddles, buffer, y and z DCT twiddles; eigenvalues of y, z and the planes
-  return (2 * ((size_t)ny + nz) + nbuf) * sizeof(cx<T>) + ((size_t)ny + nz + PP) * sizeof(T);
+  // y and z twiddles, buffer, y and z DCT twiddles; eigenvalues of y, z and the
+  // planes, and the planes' scales
+  return (2 * ((size_t)ny + nz) + nbuf) * sizeof(cx<T>) + ((size_t)ny + nz + 2 * PP) * sizeof(T);
 }
 // the generic y-z solve holds 2^lgPP planes of ny x nz in one workgroup
 template <typename T> bool yz_fits(int ny, int nz, int lgPP) {
@@ -2641,14 +2678,15 @@ template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStrea
     constexpr int NY = 256, NZ = 32;
     // W, y and z DCT twiddles, the [NZ/2][NY + 16] buffer, y and z eigenvalues
     const size_t lr = (2 * NY + NZ + (size_t)(NZ / 2) * (NY + 16)) * sizeof(cx<T>) + (NY + NZ) * sizeof(T);
-    hipLaunchKernelGGL((k_yz_reg<T, 8, 5>), dim3(a.nx, 1, nch), dim3((NZ / 2) * (NY / 16)), lr, s, a);
+    hipLaunchKernelGGL((k_yz_reg<T, 8, 5>), dim3(a.nx * std::max(1, a.runs), 1, nch), dim3((NZ / 2) * (NY / 16)), lr, s,
+                       a);
     return SGSPM_KC_YZ_REG;
   }
   // the planes of a workgroup within the 2 YZ_VPT reals each thread holds, and each
   // pass's complex pencils within the YZ_VPT values per thread of the FFT stages
   if (a.lgPP < 0 || !yz_fits<T>(a.ny, a.nz, a.lgPP)) return geom_fail("k_yz_solve: planes beyond the tile");
   if (a.twy_s < 1 || a.twz_s < 1) return geom_fail("k_yz_solve: no twiddle stride");
-  dim3 grid(ceil_div(a.nx, 1 << a.lgPP), 1, nch);
+  dim3 grid(ceil_div(a.nx, 1 << a.lgPP) * std::max(1, a.runs), 1, nch);
   if (a.lgNy < 0 || a.lgNz < 0)
     hipLaunchKernelGGL((k_yz_solve<T, true>), grid, dim3(YZ_NT), yz_lds<T>(a.ny, a.nz, a.lgPP), s, a);
   else
@@ -2686,7 +2724,7 @@ template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t 
     Conv<T> b = a;
     b.lgP = c64_lgP<T>();
     const int P = 1 << b.lgP;
-    dim3 grid(ceil_div(a.ni, P), nbatch, 1);
+    dim3 grid(ceil_div(a.ni, P), nbatch, std::max(1, a.runs));
     // W_64, the transpose buffer, the tensor tile
     const size_t lds = (64 + (size_t)64 * 2 * P) * sizeof(cx<T>) + (size_t)a.nt * 33 * P * sizeof(T);
     hipLaunchKernelGGL(k_conv64<T>, grid, dim3(16 * P), lds, s, b);
@@ -2698,7 +2736,7 @@ template <typename T> int launch_conv(const Conv<T>& a, int nbatch, hipStream_t 
   if (a.lgP < 0 || 3 * pl > (long)CONV_VPT * CONV_NT || pl > 2L * CONV_NT) return geom_fail("k_conv: P L beyond the tile");
   if (a.twg < 1) return geom_fail("k_conv: no twiddle stride");
   if (conv_lds<T>(a.L, a.lgP, a.nt) > LDS_LIMIT) return geom_fail("k_conv: LDS beyond the limit");
-  dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, 1);
+  dim3 grid(ceil_div(a.ni, 1 << a.lgP), nbatch, std::max(1, a.runs));
   if (a.lgL < 0)
     hipLaunchKernelGGL((k_conv<T, true>), grid, dim3(CONV_NT), conv_lds<T>(a.L, a.lgP, a.nt), s, a);
   else
@@ -2792,6 +2830,24 @@ void launch_rho(const T* const g[6], int nx, int ny, int nz, double kx, double k
   hipLaunchKernelGGL(k_rho_final, dim3(1), dim3(NT), 0, s, partials, nblocks, out);
 }
 
+template <typename T> struct FillArgs {
+  T* dst;
+  int n;
+  T v[256];
+};
+template <typename T> __global__ __launch_bounds__(256) void k_fill(const FillArgs<T> a) {
+  if ((int)threadIdx.x < a.n) a.dst[threadIdx.x] = a.v[threadIdx.x];
+}
+template <typename T> void launch_fill(T* dst, const T* values, long n, hipStream_t s) {
+  for (long i0 = 0; i0 < n; i0 += 256) {
+    FillArgs<T> a;
+    a.dst = dst + i0;
+    a.n = (int)std::min<long>(256, n - i0);
+    for (int i = 0; i < a.n; ++i) a.v[i] = values[i0 + i];
+    hipLaunchKernelGGL(k_fill<T>, dim3(1), dim3(256), 0, s, a);
+  }
+}
+
 template <typename T> void launch_unit_error(const T* m, long N, double* partials, int nblocks, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_unit_error<T>, dim3(nblocks), dim3(NT), 0, s, m, N, partials);
   hipLaunchKernelGGL(k_rho_final, dim3(1), dim3(NT), 0, s, partials, nblocks, out);
@@ -2820,7 +2876,8 @@ template <typename T> void launch_unit_error(const T* m, long N, double* partial
                                    hipStream_t);                                                                    \
   template void launch_rho<T>(const T* const*, int, int, int, double, double, double, int, double*, int, double*,   \
                               hipStream_t);                                                                         \
-  template void launch_unit_error<T>(const T*, long, double*, int, double*, hipStream_t);
+  template void launch_unit_error<T>(const T*, long, double*, int, double*, hipStream_t);                          \
+  template void launch_fill<T>(T*, const T*, long, hipStream_t);
 
 SGSPM_INSTANTIATE(float)
 SGSPM_INSTANTIATE(double)

@@ -102,8 +102,19 @@ int validate(const sgspm_params* p) {
   if (p->precision != SGSPM_FP32 && p->precision != SGSPM_FP64) return fail(SGSPM_EINVAL, "unknown precision");
   if (p->scheme != SGSPM_SCHEME_SGS && p->scheme != SGSPM_SCHEME_GS && p->scheme != SGSPM_SCHEME_SGS_FF)
     return fail(SGSPM_EINVAL, "unknown scheme");
+  if (p->batch < 0 || p->batch > 256) return fail(SGSPM_EINVAL, "batch must be in [0, 256]");
+  const long B = std::max(1, (int)p->batch);
   const long N = (long)p->nx * p->ny * p->nz;
-  if (N > (1L << 28)) return fail(SGSPM_EUNSUPPORTED, "grid too large");
+  if (N * B > (1L << 28)) return fail(SGSPM_EUNSUPPORTED, "grid too large");
+  if (B > 1) {
+    if (p->scheme == SGSPM_SCHEME_SGS_FF)
+      return fail(SGSPM_EUNSUPPORTED, "batched plans take the SGS or GS scheme");
+    if (((long)p->ny * p->nz) % 2)
+      return fail(SGSPM_EUNSUPPORTED, "batched plans need ny * nz even (row pairs of one run)");
+    const bool fused = yz_reg_plane(p->ny, p->nz) ||
+                       (p->precision == SGSPM_FP64 ? yz_fits<double>(p->ny, p->nz, 0) : yz_fits<float>(p->ny, p->nz, 0));
+    if (!fused) return fail(SGSPM_EUNSUPPORTED, "batched plans need y-z planes that one workgroup solves");
+  }
   const bool fp64 = p->precision == SGSPM_FP64;
   const bool stray = p->terms & SGSPM_TERM_STRAY;
   // the row kernels hold two rows and their (padded) transforms in one tile
@@ -162,7 +173,11 @@ struct sgspm_plan_s {
   int dev = 0;  // device current at plan creation (owner of the plan's memory)
   bool fp64 = false;
   int nx = 1, ny = 1, nz = 1;
+  // cells of one component array: nx ny nz per run, times B runs in a batched plan
   long N = 0;
+  int B = 1;            // runs (batched plan: fields [3][B][nz][ny][nx])
+  long Nrun = 0;        // nx ny nz
+  void* runp = nullptr; // batched plan: per-run values [B][RUNP] of the precision
   int Px = 1, Py = 1, Pz = 1, Kx = 1, Kxp = 1, Hy = 1, Hz = 1;
   bool stray = false, zeeman = false, has_mid = false;
   // the x-level spectra carry their (real) Nyquist bin in bin 0, and the y
@@ -295,8 +310,8 @@ template <typename T> struct Eng {
     }
     for (int i = 0; i < NF; ++i) f[i] = (T*)P.fld + (long)i * P.N;
     for (int c = 0; c < 3; ++c) heat[c] = (T*)P.heat + (long)c * P.N;
-    const long xl = (long)P.nz * P.ny * P.Kxp;
-    const long yl = (long)P.nz * P.Py * P.Kxp;
+    const long xl = (long)P.B * P.nz * P.ny * P.Kxp;
+    const long yl = (long)P.B * P.nz * P.Py * P.Kxp;
     for (int c = 0; c < 3; ++c) {
       xlev[c] = P.xlev ? (cx<T>*)P.xlev + c * xl : nullptr;
       ylev[c] = P.ylev ? (cx<T>*)P.ylev + c * yl : nullptr;
@@ -357,10 +372,14 @@ template <typename T> struct Eng {
     T* hs_out[3] = {nullptr, nullptr, nullptr};
     T* dct_out[3] = {nullptr, nullptr, nullptr};
     cx<T>* xout[3] = {nullptr, nullptr, nullptr};
+    // batched plan: the component of each channel (run values by component) and
+    // whether this is the damping step's right-hand side
+    int rcomp[3] = {0, 1, 2};
+    bool stageF = false;
   };
   void row_fwd(int nch, const RowIO& io) {
     RowFwd<T> A{};
-    A.nrows = P.ny * P.nz;
+    A.nrows = P.ny * P.nz * P.B;
     A.n = P.nx;
     A.lgN = lg_or_neg(P.nx);
     A.Lc = A.Lr = P.Px;
@@ -375,6 +394,14 @@ template <typename T> struct Eng {
     A.Lmax = any_x ? P.Px : P.nx;
     A.lgLmax = lg_or_neg(A.Lmax);
     A.lgP = row_lgP(lg_tile_for<T>(A.Lmax), (A.nrows + 1) / 2);
+    if (P.B > 1) {
+      // a tile holds rows of one run
+      A.runp = (const T*)P.runp;
+      A.rpr = P.ny * P.nz;
+      A.rstageF = io.stageF ? 1 : 0;
+      for (int c = 0; c < 3; ++c) A.rcomp[c] = io.rcomp[c];
+      while (A.lgP > 0 && A.rpr % (2 << A.lgP)) --A.lgP;
+    }
     A.lgTw = P.lgTw;
     tab(A.Lmax, A.tw, A.twg);
     A.dtw = dtw[0];
@@ -407,7 +434,7 @@ template <typename T> struct Eng {
   bool tape = false;
 
   void row_inv(RowInv<T>& A, bool r2c) {
-    A.nrows = P.ny * P.nz;
+    A.nrows = P.ny * P.nz * P.B;
     A.n = P.nx;
     A.lgN = lg_or_neg(P.nx);
     A.Lr = P.Px;
@@ -431,13 +458,18 @@ template <typename T> struct Eng {
   }
 
   // ---- heat solves: after row_fwd wrote DCT_x(rhs) into heat[0..nch)
-  void heat_rest(int nch, T scale) {
+  void heat_rest(int nch, T scale, bool stageF = false) {
     T* d[3] = {heat[0], heat[1], heat[2]};
     const T sdt = (T)(scale * P.dt);
     if (P.yz) {
       YZSolve<T> A{};
       for (int c = 0; c < 3; ++c) A.data[c] = d[c];
+      // a batched plan: the planes are (x, run) pairs, [nx][B] (the kernels group
+      // planes per workgroup by run, as a single-run plan does)
       A.nx = P.nx;
+      A.runs = P.B;
+      A.runp = (const T*)P.runp;
+      A.rstageF = (stageF && P.B > 1) ? 1 : 0;
       A.ny = P.ny;
       A.nz = P.nz;
       A.lgNy = lg_or_neg(P.ny);
@@ -536,7 +568,7 @@ template <typename T> struct Eng {
     tab(A.L, A.tw, A.twg);
     A.pack = P.dcnq ? 1 : 0;
     const double cb = (double)P.Kx * P.nz * 2 * TS;
-    timed(k * cb * (P.ny + P.Py), [&] { return launch_col_fft<T>(A, P.nz, k, s); });
+    timed(P.B * k * cb * (P.ny + P.Py), [&] { return launch_col_fft<T>(A, P.nz * P.B, k, s); });
   }
   void mid_inv(int mask) {
     if (!P.has_mid) return;
@@ -563,7 +595,7 @@ template <typename T> struct Eng {
     tab(A.L, A.tw, A.twg);
     A.pack = P.dcnq ? 1 : 0;
     const double cb = (double)P.Kx * P.nz * 2 * TS;
-    timed(k * cb * (P.ny + P.Py), [&] { return launch_col_fft<T>(A, P.nz, k, s); });
+    timed(P.B * k * cb * (P.ny + P.Py), [&] { return launch_col_fft<T>(A, P.nz * P.B, k, s); });
   }
   void conv(int mask, int smask = 7) {
     Conv<T> A{};
@@ -609,9 +641,13 @@ template <typename T> struct Eng {
     A.lgP = conv_lgP<T>(A.L, P.Kx, A.nt);
     {
       // small grids: fewer kx per workgroup until the launch has ~256 workgroups
-      const long nbw = (z && P.has_mid) ? P.Hy : 1;
+      const long nbw = ((z && P.has_mid) ? P.Hy : 1) * (long)P.B;
       while (A.lgP > 0 && ((P.Kx + (1L << A.lgP) - 1) >> A.lgP) * nbw < 256) --A.lgP;
     }
+    // a batched plan: one grid layer per run
+    A.runs = P.B;
+    A.rs_in = (long)P.nz * (P.has_mid ? P.Py : P.ny) * P.Kxp;
+    A.rs_out = A.rs_in;
     A.tens = tens;
     A.nyqb = P.dcnq ? 1 : 0;
     A.tcs = (long)P.Hz * P.Hy * P.Kt;
@@ -620,7 +656,7 @@ template <typename T> struct Eng {
     tab(A.L, A.tw, A.twg);
     const int nb = (z && P.has_mid) ? P.Hy : 1;
     const int nrows = (z && P.has_mid) ? P.Py : 1;
-    const double slab = (double)A.n * A.ni * nrows * 2 * TS;
+    const double slab = (double)A.n * A.ni * nrows * 2 * TS * P.B;
     const double tb = A.nt * (double)(z ? P.Hz : P.Hy) * A.Hb * A.ni * TS;
     timed(3 * slab + nout * slab + tb, [&] { return launch_conv<T>(A, nb, s); });
   }
@@ -651,9 +687,12 @@ template <typename T> struct Eng {
   }
 
   // RHS + forward x DCT for heat solves of components comps[0..nch)
-  void heat_rhs(int nch, const int comps[3], const T* const u[3], T beta, const T he[3], T* const hs_store[3] = nullptr) {
+  void heat_rhs(int nch, const int comps[3], const T* const u[3], T beta, const T he[3], T* const hs_store[3] = nullptr,
+                bool stageF = false) {
     RowIO io;
+    io.stageF = stageF;
     for (int c = 0; c < nch; ++c) {
+      io.rcomp[c] = comps[c];
       io.u[c] = u[c];
       io.a[c] = (T)(1.0 - (double)beta * (comps[c] > 0 ? P.Q : 0.0));
       io.he[c] = he[comps[c]];
@@ -752,8 +791,8 @@ template <typename T> struct Eng {
     {
       const int comps[3] = {0, 1, 2};
       T* hsF[3] = {f[F_HS0], f[F_HS1], f[F_HS2]};
-      heat_rhs(3, comps, uF, (T)(alpha * P.dt), he, (tape && P.stray) ? hsF : nullptr);
-      heat_rest(3, (T)alpha);
+      heat_rhs(3, comps, uF, (T)(alpha * P.dt), he, (tape && P.stray) ? hsF : nullptr, true);
+      heat_rest(3, (T)alpha, true);
     }
     // Step 3: projection
     {
@@ -1324,9 +1363,10 @@ template <typename T> int alloc_workspace(sgspm_plan_s* P) {
   int rc;
   if ((rc = dalloc(P, &P->fld, (size_t)NF * P->N * sizeof(T)))) return rc;
   if ((rc = dalloc(P, &P->heat, (size_t)3 * P->N * sizeof(T)))) return rc;
+  if (P->B > 1 && (rc = dalloc(P, &P->runp, (size_t)P->B * RUNP * sizeof(T)))) return rc;
   if (P->stray) {
-    const long xl = (long)P->nz * P->ny * P->Kxp;
-    const long yl = (long)P->nz * P->Py * P->Kxp;
+    const long xl = (long)P->B * P->nz * P->ny * P->Kxp;
+    const long yl = (long)P->B * P->nz * P->Py * P->Kxp;
     if ((rc = dalloc(P, &P->xlev, 3 * xl * sizeof(cx<T>)))) return rc;
     if (P->has_mid) {
       if ((rc = dalloc(P, &P->ylev, 3 * yl * sizeof(cx<T>)))) return rc;
@@ -1338,7 +1378,7 @@ template <typename T> int alloc_workspace(sgspm_plan_s* P) {
   }
   P->nred = (int)std::min<long>(1024, (P->N + NT - 1) / NT);
   if ((rc = dalloc(P, (void**)&P->partials, (size_t)P->nred * 4 * sizeof(double)))) return rc;
-  if ((rc = dalloc(P, (void**)&P->eout, 8 * sizeof(double)))) return rc;
+  if ((rc = dalloc(P, (void**)&P->eout, (size_t)std::max(8, 4 * P->B) * sizeof(double)))) return rc;
   if ((rc = dalloc(P, (void**)&P->flag, sizeof(int)))) return rc;
   rc = hip_check(hipMemsetAsync(P->flag, 0, sizeof(int), P->s), "flag clear");
   if (rc) return rc;
@@ -1362,6 +1402,66 @@ template <typename T> int dispatch_step(sgspm_plan_s* P, void* m, double alpha, 
   return launch_status(P, "sgspm_step launch");
 }
 
+// per-run values of a batched plan into its device buffer (stream-ordered)
+template <typename T> int upload_runs(sgspm_plan_s* P, const double* alpha, const double* h_e) {
+  std::vector<T> v((size_t)P->B * RUNP, (T)0);
+  for (int b = 0; b < P->B; ++b) {
+    T* r = v.data() + (size_t)b * RUNP;
+    // the values the single-run step forms from (alpha, h_e), by the same expressions
+    for (int c = 0; c < 3; ++c) r[c] = P->zeeman ? (T)(h_e[3 * b + c] * P->fscale) : (T)0;
+    const T beta = (T)(alpha[b] * P->dt);
+    for (int c = 0; c < 3; ++c) r[3 + c] = (T)(1.0 - (double)beta * (c > 0 ? P->Q : 0.0));
+    r[6] = beta;
+    const T scale = (T)alpha[b];
+    r[7] = (T)(scale * P->dt);
+  }
+  launch_fill<T>((T*)P->runp, v.data(), (long)v.size(), P->s);
+  return hip_check(hipGetLastError(), "per-run values");
+}
+
+int check_batch_args(sgspm_plan_s* P, const void* m, const double* alpha, const double* h_e, const char* what) {
+  if (!P || !m || !alpha || !h_e) return fail(SGSPM_EINVAL, std::string(what) + ": NULL argument");
+  if (P->B < 2) return fail(SGSPM_EINVAL, std::string(what) + ": the plan is not batched");
+  for (int b = 0; b < P->B; ++b) {
+    if (!(alpha[b] >= 0.0) || !std::isfinite(alpha[b])) return fail(SGSPM_EINVAL, "alpha must be >= 0 and finite");
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(h_e[3 * b + c])) return fail(SGSPM_EINVAL, "h_e must be finite");
+  }
+  return SGSPM_OK;
+}
+
+// energies of every run of a batched plan: the stray field of all runs at once,
+// then run by run its components and their stray field gathered contiguous in
+// the workspace and reduced as for one run
+template <typename T> int energy_runs(sgspm_plan_s* P, const void* m, const double* h_e) {
+  const double cx_ = P->nx > 1 ? 1.0 / (P->prm.dx * P->prm.dx) : 0.0;
+  const double cy_ = P->ny > 1 ? 1.0 / (P->prm.dy * P->prm.dy) : 0.0;
+  const double cz_ = P->nz > 1 ? 1.0 / (P->prm.dz * P->prm.dz) : 0.0;
+  const long n = P->Nrun, NB = P->N;
+  Eng<T> e(*P);
+  T* hs = P->stray ? e.f[F_HS0] : nullptr;
+  if (hs) e.stray_to((const T*)m, hs);
+  // 6 n values from the start of the workspace (below the stray field, which
+  // starts at F_HS0 NB >= 12 n)
+  T* tm = e.f[0];
+  T* th = tm + 3 * n;
+  int rc = SGSPM_OK;
+  for (int b = 0; b < P->B && !rc; ++b) {
+    double he[3];
+    for (int c = 0; c < 3; ++c) he[c] = P->zeeman ? h_e[3 * b + c] * P->fscale : 0.0;
+    for (int c = 0; c < 3 && !rc; ++c) {
+      rc = hip_check(hipMemcpyAsync(tm + c * n, (const T*)m + c * NB + b * n, n * sizeof(T), hipMemcpyDeviceToDevice,
+                                    P->s), "energy gather");
+      if (!rc && hs)
+        rc = hip_check(hipMemcpyAsync(th + c * n, hs + c * NB + b * n, n * sizeof(T), hipMemcpyDeviceToDevice, P->s),
+                       "energy gather");
+    }
+    if (!rc)
+      launch_energy<T>(tm, hs ? th : nullptr, P->nx, P->ny, P->nz, cx_, cy_, cz_, he, P->partials, P->nred,
+                       P->eout + 4 * b, P->s);
+  }
+  return rc;
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1397,7 +1497,9 @@ int sgspm_plan(const sgspm_params* p, void* hip_stream, sgspm_plan_t* out) {
   P->nx = p->nx;
   P->ny = p->ny;
   P->nz = p->nz;
-  P->N = (long)p->nx * p->ny * p->nz;
+  P->B = std::max(1, (int)p->batch);
+  P->Nrun = (long)p->nx * p->ny * p->nz;
+  P->N = P->Nrun * P->B;
   P->Px = p->nx > 1 ? 2 * p->nx : 1;
   P->Py = p->ny > 1 ? 2 * p->ny : 1;
   P->Pz = p->nz > 1 ? 2 * p->nz : 1;
@@ -1441,6 +1543,7 @@ int sgspm_plan(const sgspm_params* p, void* hip_stream, sgspm_plan_t* out) {
 
 int sgspm_step(sgspm_plan_t P, void* m, double alpha, const double h_e[3], const void* src) {
   if (!P || !m || !h_e) return fail(SGSPM_EINVAL, "NULL argument");
+  if (P->B > 1) return fail(SGSPM_EINVAL, "sgspm_step: a batched plan takes the batched entry points");
   if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SGSPM_EINVAL, "alpha must be >= 0 and finite");
   for (int c = 0; c < 3; ++c)
     if (!std::isfinite(h_e[c])) return fail(SGSPM_EINVAL, "h_e must be finite");
@@ -1518,6 +1621,7 @@ int sgspm_step_spectral_radius(sgspm_plan_t P, void* m, double alpha, const doub
 
 int sgspm_steps(sgspm_plan_t P, void* m, int nsteps, double alpha, const double h_e[3]) {
   if (!P || !m || !h_e) return fail(SGSPM_EINVAL, "NULL argument");
+  if (P->B > 1) return fail(SGSPM_EINVAL, "sgspm_steps: a batched plan takes the batched entry points");
   if (nsteps < 0) return fail(SGSPM_EINVAL, "nsteps must be >= 0");
   if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SGSPM_EINVAL, "alpha must be >= 0 and finite");
   for (int c = 0; c < 3; ++c)
@@ -1536,8 +1640,72 @@ int sgspm_steps(sgspm_plan_t P, void* m, int nsteps, double alpha, const double 
   return SGSPM_OK;
 }
 
+int sgspm_step_batch(sgspm_plan_t P, void* m, const double* alpha, const double* h_e) {
+  int rc = check_batch_args(P, m, alpha, h_e, "sgspm_step_batch");
+  if (rc) return rc;
+  rc = P->fp64 ? upload_runs<double>(P, alpha, h_e) : upload_runs<float>(P, alpha, h_e);
+  if (rc) return rc;
+  const double zero[3] = {0.0, 0.0, 0.0};
+  return P->fp64 ? dispatch_step<double>(P, m, 0.0, zero, nullptr) : dispatch_step<float>(P, m, 0.0, zero, nullptr);
+}
+
+int sgspm_steps_batch(sgspm_plan_t P, void* m, int nsteps, const double* alpha, const double* h_e) {
+  int rc = check_batch_args(P, m, alpha, h_e, "sgspm_steps_batch");
+  if (rc) return rc;
+  if (nsteps < 0) return fail(SGSPM_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return SGSPM_OK;
+  rc = P->fp64 ? upload_runs<double>(P, alpha, h_e) : upload_runs<float>(P, alpha, h_e);
+  if (rc) return rc;
+  // the graph reads the per-run values from the plan's buffer at every replay: it
+  // is captured again only for another array
+  const double zero[3] = {0.0, 0.0, 0.0};
+  if (!P->gexec || P->g_m != m) {
+    rc = capture_step(P, m, 0.0, zero);
+    if (rc) return rc;
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    rc = hip_check(hipGraphLaunch(P->gexec, P->s), "graph launch");
+    if (rc) return rc;
+  }
+  return SGSPM_OK;
+}
+
+int sgspm_energy_batch(sgspm_plan_t P, const void* m, const double* h_e, double* e_out) {
+  if (!P || !e_out) return fail(SGSPM_EINVAL, "NULL argument");
+  const std::vector<double> zero_alpha((size_t)std::max(1, P->B), 0.0);
+  int rc = check_batch_args(P, m, zero_alpha.data(), h_e, "sgspm_energy_batch");
+  if (rc) return rc;
+  rc = P->fp64 ? energy_runs<double>(P, m, h_e) : energy_runs<float>(P, m, h_e);
+  if (rc) return rc;
+  rc = launch_status(P, "sgspm_energy_batch launch");
+  if (rc) return rc;
+  std::vector<double> acc((size_t)4 * P->B);
+  rc = hip_check(hipMemcpyAsync(acc.data(), P->eout, acc.size() * sizeof(double), hipMemcpyDeviceToHost, P->s),
+                 "energy copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(P->s), "energy sync");
+  if (rc) return rc;
+  const double V = P->prm.dx * P->prm.dy * P->prm.dz;
+  const double es = P->escale;
+  for (int b = 0; b < P->B; ++b) {
+    const double* a = acc.data() + 4 * b;
+    const double ex = 0.5 * P->eps * V * a[0];
+    const double an = 0.5 * P->Q * V * a[1];
+    const double st = -0.5 * V * a[2];
+    const double ze = -V * a[3];
+    double* o = e_out + 5 * b;
+    o[1] = ex * es;
+    o[2] = an * es;
+    o[3] = st * es;
+    o[4] = ze * es;
+    o[0] = (ex + an + st + ze) * es;
+  }
+  return SGSPM_OK;
+}
+
 int sgspm_stray(sgspm_plan_t P, const void* m, void* hs_out) {
   if (!P || !m || !hs_out) return fail(SGSPM_EINVAL, "NULL argument");
+  if (P->B > 1) return fail(SGSPM_EINVAL, "sgspm_stray: a batched plan takes the batched entry points");
   if (!P->stray) {
     const size_t bytes = 3 * P->N * (P->fp64 ? 8 : 4);
     return hip_check(hipMemsetAsync(hs_out, 0, bytes, P->s), "stray zero");
@@ -1549,6 +1717,7 @@ int sgspm_stray(sgspm_plan_t P, const void* m, void* hs_out) {
 
 int sgspm_field(sgspm_plan_t P, const void* m, const double h_e[3], void* h_out) {
   if (!P || !m || !h_e || !h_out) return fail(SGSPM_EINVAL, "NULL argument");
+  if (P->B > 1) return fail(SGSPM_EINVAL, "sgspm_field: a batched plan takes the batched entry points");
   double he[3];
   for (int c = 0; c < 3; ++c) he[c] = P->zeeman ? h_e[c] * P->fscale : 0.0;
   const bool ex = P->eps != 0.0;
@@ -1572,6 +1741,7 @@ int sgspm_field(sgspm_plan_t P, const void* m, const double h_e[3], void* h_out)
 
 int sgspm_heat_solve(sgspm_plan_t P, const void* r, double s, void* g) {
   if (!P || !r || !g) return fail(SGSPM_EINVAL, "NULL argument");
+  if (P->B > 1) return fail(SGSPM_EINVAL, "sgspm_heat_solve: a batched plan takes the batched entry points");
   if (!(s >= 0.0) || !std::isfinite(s)) return fail(SGSPM_EINVAL, "s must be >= 0 and finite");
   if (P->fp64) Eng<double>(*P).heat_solve((const double*)r, s, (double*)g);
   else Eng<float>(*P).heat_solve((const float*)r, (float)s, (float*)g);
@@ -1580,6 +1750,7 @@ int sgspm_heat_solve(sgspm_plan_t P, const void* r, double s, void* g) {
 
 int sgspm_energy(sgspm_plan_t P, const void* m, const double h_e[3], double e_out[5]) {
   if (!P || !m || !h_e || !e_out) return fail(SGSPM_EINVAL, "NULL argument");
+  if (P->B > 1) return fail(SGSPM_EINVAL, "sgspm_energy: a batched plan takes the batched entry points");
   double he[3];
   for (int c = 0; c < 3; ++c) he[c] = P->zeeman ? h_e[c] * P->fscale : 0.0;
   const double cx_ = P->nx > 1 ? 1.0 / (P->prm.dx * P->prm.dx) : 0.0;
@@ -1633,6 +1804,7 @@ int sgspm_unit_error(sgspm_plan_t P, const void* m, double* out) {
 int sgspm_adjoint_step(sgspm_plan_t P, const void* m_n, double alpha, const double h_e[3], void* lam,
                        double* grad_dev) {
   if (!P || !m_n || !h_e || !lam || !grad_dev) return fail(SGSPM_EINVAL, "NULL argument");
+  if (P->B > 1) return fail(SGSPM_EINVAL, "sgspm_adjoint_step: a batched plan takes the batched entry points");
   if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SGSPM_EINVAL, "alpha must be >= 0 and finite");
   if (P->prm.scheme != SGSPM_SCHEME_SGS) return fail(SGSPM_EUNSUPPORTED, "the adjoint covers the SGS scheme only");
   if (!P->adj) {
@@ -1647,6 +1819,7 @@ int sgspm_adjoint_step(sgspm_plan_t P, const void* m_n, double alpha, const doub
 int sgspm_adjoint_step_noalloc(sgspm_plan_t P, const void* m_n, double alpha, const double h_e[3], void* lam,
                                double* grad_dev) {
   if (!P || !m_n || !h_e || !lam || !grad_dev) return fail(SGSPM_EINVAL, "NULL argument");
+  if (P->B > 1) return fail(SGSPM_EINVAL, "sgspm_adjoint_step_noalloc: a batched plan takes the batched entry points");
   if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SGSPM_EINVAL, "alpha must be >= 0 and finite");
   if (P->prm.scheme != SGSPM_SCHEME_SGS) return fail(SGSPM_EUNSUPPORTED, "the adjoint covers the SGS scheme only");
   const size_t need = (size_t)ADJ_FIELDS * P->N * (P->fp64 ? 8 : 4);

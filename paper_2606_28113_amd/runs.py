@@ -105,3 +105,49 @@ def run_sweep(plans, ms, alphas, fields, steps, log_every=10, sink=None, extras=
         p.check()
     mono = [all(b["energy"]["total"] <= a["energy"]["total"] for a, b in zip(rs, rs[1:])) for rs in records]
     return {"records": records, "monotone": mono, "step_seconds": step_s, "seconds": time.perf_counter() - t_all}
+
+
+def run_batch(plan, m, alphas, fields, steps, log_every=10, sink=None, extras=None):
+    """Advance the runs of a batched plan together (sgspm_steps_batch: every launch of
+    a step covers all runs), recording every run's energies every `log_every` steps
+    as run_logged does; "unit_error" is the maximum over all runs of the batch.
+
+    m: (3, B, nz, ny, nx); alphas: B values; fields: B applied fields (3 each).
+    Returns {"records": per-run lists, "monotone": per-run bools, "step_seconds",
+    "seconds"}.
+    """
+    import torch
+    B = plan.batch
+    records = [[] for _ in range(B)]
+    t_all = time.perf_counter()
+    step_s = 0.0
+
+    def record(k):
+        es = plan.energy_batch(m, fields)
+        ue = plan.unit_error(m)
+        for i in range(B):
+            r = {"run": i, "step": k, "alpha": alphas[i], "h_e": [float(x) for x in fields[i]], "energy": es[i],
+                 "unit_error": ue}
+            if extras:
+                r.update(extras[i])
+            records[i].append(r)
+            if sink is not None:
+                if isinstance(sink, list):
+                    sink.append(r)
+                else:
+                    sink.write(json.dumps(r) + "\n")
+
+    record(0)
+    done = 0
+    while done < steps:
+        k = min(log_every, steps - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.steps_batch(m, k, alphas, fields)
+        torch.cuda.synchronize()
+        step_s += time.perf_counter() - t0
+        done += k
+        record(done)
+    plan.check()
+    mono = [all(b["energy"]["total"] <= a["energy"]["total"] for a, b in zip(rs, rs[1:])) for rs in records]
+    return {"records": records, "monotone": mono, "step_seconds": step_s, "seconds": time.perf_counter() - t_all}

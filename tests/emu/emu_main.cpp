@@ -29,6 +29,66 @@ static void die(const char* what, int rc) {
 
 static sgspm_plan_t plan_for_check = nullptr;
 
+// EMU_BATCH=B: a batched plan of B runs (run b with alpha (1 + b / 2) and h_e (1 + b)
+// times the given ones, all from m0) against B single-run plans.  out.bin: the
+// batched m (3 B N) and energies (5 B), then each single run's m (3 N) and
+// energies (5).
+static int batch_main(sgspm_params p, int B, int steps, double alpha0, const double he0[3], const std::vector<double>& m0,
+                      const char* fout) {
+  const long N = (long)p.nx * p.ny * p.nz;
+  const bool f64 = p.precision == SGSPM_FP64;
+  const size_t es = f64 ? 8 : 4;
+  std::vector<double> alpha(B), he(3 * B), out;
+  for (int b = 0; b < B; ++b) {
+    alpha[b] = alpha0 * (1.0 + 0.5 * b);
+    for (int c = 0; c < 3; ++c) he[3 * b + c] = he0[c] * (1.0 + b);
+  }
+  auto put = [&](void* d, long i, double v) {
+    if (f64) static_cast<double*>(d)[i] = v;
+    else static_cast<float*>(d)[i] = (float)v;
+  };
+  auto get = [&](const void* d, long i) { return f64 ? static_cast<const double*>(d)[i] : static_cast<const float*>(d)[i]; };
+  sgspm_params pb = p;
+  pb.batch = B;
+  sgspm_plan_t plan;
+  int rc = sgspm_plan(&pb, nullptr, &plan);
+  if (rc) die("sgspm_plan (batched)", rc);
+  void* m;
+  hipMalloc(&m, 3 * B * N * es);
+  for (int c = 0; c < 3; ++c)
+    for (int b = 0; b < B; ++b)
+      for (long i = 0; i < N; ++i) put(m, (c * B + b) * N + i, m0[c * N + i]);
+  for (int s = 0; s < steps; ++s)
+    if ((rc = sgspm_step_batch(plan, m, alpha.data(), he.data()))) die("sgspm_step_batch", rc);
+  if ((rc = sgspm_check(plan))) die("sgspm_check (batched)", rc);
+  for (long i = 0; i < 3 * B * N; ++i) out.push_back(get(m, i));
+  std::vector<double> e(5 * B);
+  if ((rc = sgspm_energy_batch(plan, m, he.data(), e.data()))) die("sgspm_energy_batch", rc);
+  out.insert(out.end(), e.begin(), e.end());
+  sgspm_destroy(plan);
+  hipFree(m);
+  for (int b = 0; b < B; ++b) {
+    sgspm_plan_t q;
+    if ((rc = sgspm_plan(&p, nullptr, &q))) die("sgspm_plan", rc);
+    void* mb;
+    hipMalloc(&mb, 3 * N * es);
+    for (long i = 0; i < 3 * N; ++i) put(mb, i, m0[i]);
+    for (int s = 0; s < steps; ++s)
+      if ((rc = sgspm_step(q, mb, alpha[b], he.data() + 3 * b, nullptr))) die("sgspm_step", rc);
+    for (long i = 0; i < 3 * N; ++i) out.push_back(get(mb, i));
+    double eb[5];
+    if ((rc = sgspm_energy(q, mb, he.data() + 3 * b, eb))) die("sgspm_energy", rc);
+    out.insert(out.end(), eb, eb + 5);
+    sgspm_destroy(q);
+    hipFree(mb);
+  }
+  FILE* fo = fopen(fout, "wb");
+  fwrite(out.data(), 8, out.size(), fo);
+  fclose(fo);
+  printf("launches %ld workgroups %ld\n", emu_launch_count(), emu_group_count());
+  return 0;
+}
+
 int main(int argc, char** argv) {
   if (argc != 19) {
     fprintf(stderr, "usage: emu_sgspm nx ny nz precision scheme terms steps A Ms Ku h dt alpha he0 he1 he2 in.bin out.bin\n");
@@ -69,6 +129,10 @@ int main(int argc, char** argv) {
     return 2;
   }
   fclose(fi);
+  if (getenv("EMU_BATCH")) {
+    std::vector<double> m0(in.begin(), in.begin() + 3 * N);
+    return batch_main(p, atoi(getenv("EMU_BATCH")), steps, alpha, he, m0, argv[18]);
+  }
   auto upload = [&](const double* src, long n) {
     void* d;
     hipMalloc(&d, n * es);

@@ -60,7 +60,9 @@ def test_validate_accepts_configs():
     (dict(nx=2000, ny=1, nz=1), -2), (dict(nx=1280, ny=2, nz=2), -2),
     (dict(dx=0.0), -1), (dict(dt=-1.0), -1), (dict(dt=float("nan")), -1), (dict(Ms=0.0), -1),
     (dict(A=-1.0), -1), (dict(units=7), -1), (dict(terms=16), -1), (dict(precision=3), -1),
-    (dict(scheme=3), -1),
+    (dict(scheme=3), -1), (dict(batch=-1), -1), (dict(batch=257), -1),
+    # batched plans: SGS or GS, row pairs of one run, fused y-z planes
+    (dict(batch=2, scheme=2), -2), (dict(batch=2, ny=3, nz=1), -2), (dict(batch=2, ny=1024, nz=64), -2),
 ])
 def test_validate_rejects(bad, code):
     import paper_2606_28113_amd as sg

@@ -198,3 +198,42 @@ def test_validated_extremes_run(emu_exe, tmp_path, n, prec, terms):
         assert e.code == -2, str(e)
         return
     _run(emu_exe, tmp_path, n, prec, terms=terms, steps=1, sample=2)
+
+
+def _run_batch(exe, tmp_path, n, prec, B, scheme_=0, steps=2, seed=310):
+    shape = (n[2], n[1], n[0])
+    m0, lam = _inputs(shape, seed)
+    fin, fout = tmp_path / "in.bin", tmp_path / "out.bin"
+    np.concatenate([m0.ravel(), lam.ravel()]).tofile(fin)
+    env = dict(os.environ, EMU_MAX_GROUPS="0", EMU_BATCH=str(B),
+               ASAN_OPTIONS="detect_leaks=0:abort_on_error=1:detect_stack_use_after_return=0")
+    args = [exe] + [str(v) for v in (n[0], n[1], n[2], prec, scheme_, ALL, steps, workloads.A_PY,
+                                     workloads.MS_PY, workloads.K_PY, CELL, DT, ALPHA, *HE)] + [str(fin), str(fout)]
+    print("emulating batch", B, " ".join(args[1:-2]), flush=True)
+    r = subprocess.run(args, env=env, capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-6000:])
+    out = np.fromfile(fout)
+    N = int(np.prod(shape))
+    mb = out[:3 * B * N].reshape((3, B) + shape)
+    eb = out[3 * B * N:3 * B * N + 5 * B].reshape(B, 5)
+    rest = out[3 * B * N + 5 * B:].reshape(B, 3 * N + 5)
+    return mb, eb, rest[:, :3 * N].reshape((B, 3) + shape), rest[:, 3 * N:]
+
+
+# batched plans (runs sharing every launch): every run equals its single-run plan
+# bit for bit, states and energies; 3-D with the y pass, a film, mixed radix, rows
+# of 256 (register row kernels in single precision), several y-z planes per
+# workgroup (1024 x 2 x 2), both schemes
+BATCH_CASES = [((16, 8, 4), 1, 3, 0, "16x8x4-fp64-B3"), ((1024, 2, 2), 0, 2, 0, "1024x2x2-fp32-B2")]
+if EMU_ALL:
+    BATCH_CASES += [((12, 10, 2), 0, 2, 0, "12x10x2-fp32-B2"), ((16, 8, 1), 1, 2, 1, "16x8x1-fp64-B2-gspm"),
+                    ((256, 2, 2), 0, 2, 0, "256x2x2-fp32-B2")]
+
+
+@pytest.mark.parametrize("n,prec,B,sch", [c[:4] for c in BATCH_CASES], ids=[c[4] for c in BATCH_CASES])
+def test_batched_runs_match_single_runs(emu_exe, tmp_path, n, prec, B, sch):
+    mb, eb, ms, es = _run_batch(emu_exe, tmp_path, n, prec, B, scheme_=sch)
+    for b in range(B):
+        assert np.array_equal(mb[:, b], ms[b]), b
+        assert np.array_equal(eb[b], es[b]), b
+    assert not np.array_equal(ms[0], ms[1])
