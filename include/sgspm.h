@@ -230,7 +230,7 @@ enum {
 int sgspm_timing(sgspm_plan_t plan, int enable);
 
 /* Synchronise and return, per kernel class since the last enable/read: total
- * kernel milliseconds, total algorithmic bytes (each input array read once and
+ * kernel milliseconds, total launch-level bytes (each input array read once and
  * each output written once per launch) and the number of launches (host
  * arrays of SGSPM_KC_COUNT entries).  Clears the records. */
 int sgspm_timing_read(sgspm_plan_t plan, double ms[SGSPM_KC_COUNT], double bytes[SGSPM_KC_COUNT],

@@ -180,6 +180,8 @@ template <typename T> int launch_yz_solve(const YZSolve<T>& a, int nch, hipStrea
 template <typename T> constexpr int yz_max_plane() { return sizeof(T) == 4 ? 8192 : 4096; }
 // ny * nz * planes <= this many reals per workgroup (16 per thread of 512)
 constexpr int YZ_MAX_VALUES = 8192;
+// threads of the generic y-z solve's workgroup
+constexpr int YZ_NT = 512;
 // the generic y-z solve holds 2^lgPP planes of ny x nz in one workgroup
 template <typename T> bool yz_fits(int ny, int nz, int lgPP);
 // planes that the register y-z kernel handles in either precision

@@ -563,7 +563,6 @@ __global__ __launch_bounds__(NT) void k_col_dct(const ColDct<T> A) {
 // padded pencil stride (es = pencils + 1) and two real pencils per complex one
 // (pencil rho in slot rho mod H, real or imaginary part by rho / H, with H the
 // number of complex pencils, ceil(real pencils / 2)).
-constexpr int YZ_NT = 512;
 constexpr int YZ_VPT = 8;
 
 template <typename T, bool MX>

@@ -320,7 +320,7 @@ template <typename T> struct Eng {
     tens = (const T*)P.tens;
   }
 
-  // ---- timing: events around a launch, with the launch's algorithmic bytes
+  // ---- timing: events around a launch, with the launch's launch-level bytes
   hipEvent_t ev() {
     if (P.evnext == P.evpool.size()) {
       hipEvent_t e;
@@ -375,6 +375,7 @@ template <typename T> struct Eng {
     // batched plan: the component of each channel (run values by component) and
     // whether this is the damping step's right-hand side
     int rcomp[3] = {0, 1, 2};
+    bool per_run = false;  // the heat right-hand sides of a batched plan
     bool stageF = false;
   };
   void row_fwd(int nch, const RowIO& io) {
@@ -394,7 +395,7 @@ template <typename T> struct Eng {
     A.Lmax = any_x ? P.Px : P.nx;
     A.lgLmax = lg_or_neg(A.Lmax);
     A.lgP = row_lgP(lg_tile_for<T>(A.Lmax), (A.nrows + 1) / 2);
-    if (P.B > 1) {
+    if (P.B > 1 && io.per_run) {
       // a tile holds rows of one run
       A.runp = (const T*)P.runp;
       A.rpr = P.ny * P.nz;
@@ -474,10 +475,14 @@ template <typename T> struct Eng {
       A.nz = P.nz;
       A.lgNy = lg_or_neg(P.ny);
       A.lgNz = lg_or_neg(P.nz);
-      // planes per workgroup: fill the tile, but keep at least ~256 workgroups
+      // planes per workgroup: fill the tile, but keep at least ~256 workgroups,
+      // and at least four values per thread (small planes leave most of a
+      // workgroup idle otherwise; a batched plan then has B times the workgroups)
       int lgPP = 0;
       while (yz_fits<T>(P.ny, P.nz, lgPP + 1)) ++lgPP;
+      const int lgmax = lgPP;
       while (lgPP > 0 && (P.nx >> lgPP) < 256) --lgPP;
+      while (lgPP < lgmax && ((long)P.ny * P.nz << lgPP) < 4L * YZ_NT) ++lgPP;
       A.lgPP = lgPP;
       A.dtwy = dtw[1];
       A.dtwz = dtw[2];
@@ -690,6 +695,7 @@ template <typename T> struct Eng {
   void heat_rhs(int nch, const int comps[3], const T* const u[3], T beta, const T he[3], T* const hs_store[3] = nullptr,
                 bool stageF = false) {
     RowIO io;
+    io.per_run = true;
     io.stageF = stageF;
     for (int c = 0; c < nch; ++c) {
       io.rcomp[c] = comps[c];
@@ -1363,7 +1369,11 @@ template <typename T> int alloc_workspace(sgspm_plan_s* P) {
   int rc;
   if ((rc = dalloc(P, &P->fld, (size_t)NF * P->N * sizeof(T)))) return rc;
   if ((rc = dalloc(P, &P->heat, (size_t)3 * P->N * sizeof(T)))) return rc;
-  if (P->B > 1 && (rc = dalloc(P, &P->runp, (size_t)P->B * RUNP * sizeof(T)))) return rc;
+  if (P->B > 1) {
+    // per-run values start at zero (each batched step fills them first)
+    if ((rc = dalloc(P, &P->runp, (size_t)P->B * RUNP * sizeof(T)))) return rc;
+    if ((rc = hip_check(hipMemsetAsync(P->runp, 0, (size_t)P->B * RUNP * sizeof(T), P->s), "per-run clear"))) return rc;
+  }
   if (P->stray) {
     const long xl = (long)P->B * P->nz * P->ny * P->Kxp;
     const long yl = (long)P->B * P->nz * P->Py * P->Kxp;

@@ -31,8 +31,9 @@ static sgspm_plan_t plan_for_check = nullptr;
 
 // EMU_BATCH=B: a batched plan of B runs (run b with alpha (1 + b / 2) and h_e (1 + b)
 // times the given ones, all from m0) against B single-run plans.  out.bin: the
-// batched m (3 B N) and energies (5 B), then each single run's m (3 N) and
-// energies (5).
+// batched m (3 B N), energies after the steps (5 B) and before them (5 B), then
+// for each single run its energies before the steps (5), m (3 N) and energies
+// after them (5).
 static int batch_main(sgspm_params p, int B, int steps, double alpha0, const double he0[3], const std::vector<double>& m0,
                       const char* fout) {
   const long N = (long)p.nx * p.ny * p.nz;
@@ -58,6 +59,9 @@ static int batch_main(sgspm_params p, int B, int steps, double alpha0, const dou
   for (int c = 0; c < 3; ++c)
     for (int b = 0; b < B; ++b)
       for (long i = 0; i < N; ++i) put(m, (c * B + b) * N + i, m0[c * N + i]);
+  // energies before any batched step too (the per-run values are not set yet)
+  std::vector<double> e0(5 * B);
+  if ((rc = sgspm_energy_batch(plan, m, he.data(), e0.data()))) die("sgspm_energy_batch", rc);
   for (int s = 0; s < steps; ++s)
     if ((rc = sgspm_step_batch(plan, m, alpha.data(), he.data()))) die("sgspm_step_batch", rc);
   if ((rc = sgspm_check(plan))) die("sgspm_check (batched)", rc);
@@ -65,6 +69,7 @@ static int batch_main(sgspm_params p, int B, int steps, double alpha0, const dou
   std::vector<double> e(5 * B);
   if ((rc = sgspm_energy_batch(plan, m, he.data(), e.data()))) die("sgspm_energy_batch", rc);
   out.insert(out.end(), e.begin(), e.end());
+  out.insert(out.end(), e0.begin(), e0.end());
   sgspm_destroy(plan);
   hipFree(m);
   for (int b = 0; b < B; ++b) {
@@ -73,6 +78,9 @@ static int batch_main(sgspm_params p, int B, int steps, double alpha0, const dou
     void* mb;
     hipMalloc(&mb, 3 * N * es);
     for (long i = 0; i < 3 * N; ++i) put(mb, i, m0[i]);
+    double eb0[5];
+    if ((rc = sgspm_energy(q, mb, he.data() + 3 * b, eb0))) die("sgspm_energy", rc);
+    out.insert(out.end(), eb0, eb0 + 5);
     for (int s = 0; s < steps; ++s)
       if ((rc = sgspm_step(q, mb, alpha[b], he.data() + 3 * b, nullptr))) die("sgspm_step", rc);
     for (long i = 0; i < 3 * N; ++i) out.push_back(get(mb, i));

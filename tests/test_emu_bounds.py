@@ -216,8 +216,9 @@ def _run_batch(exe, tmp_path, n, prec, B, scheme_=0, steps=2, seed=310):
     N = int(np.prod(shape))
     mb = out[:3 * B * N].reshape((3, B) + shape)
     eb = out[3 * B * N:3 * B * N + 5 * B].reshape(B, 5)
-    rest = out[3 * B * N + 5 * B:].reshape(B, 3 * N + 5)
-    return mb, eb, rest[:, :3 * N].reshape((B, 3) + shape), rest[:, 3 * N:]
+    eb0 = out[3 * B * N + 5 * B:3 * B * N + 10 * B].reshape(B, 5)
+    rest = out[3 * B * N + 10 * B:].reshape(B, 5 + 3 * N + 5)
+    return mb, eb, eb0, rest[:, 5:5 + 3 * N].reshape((B, 3) + shape), rest[:, 5 + 3 * N:], rest[:, :5]
 
 
 # batched plans (runs sharing every launch): every run equals its single-run plan
@@ -232,8 +233,9 @@ if EMU_ALL:
 
 @pytest.mark.parametrize("n,prec,B,sch", [c[:4] for c in BATCH_CASES], ids=[c[4] for c in BATCH_CASES])
 def test_batched_runs_match_single_runs(emu_exe, tmp_path, n, prec, B, sch):
-    mb, eb, ms, es = _run_batch(emu_exe, tmp_path, n, prec, B, scheme_=sch)
+    mb, eb, eb0, ms, es, es0 = _run_batch(emu_exe, tmp_path, n, prec, B, scheme_=sch)
     for b in range(B):
         assert np.array_equal(mb[:, b], ms[b]), b
         assert np.array_equal(eb[b], es[b]), b
+        assert np.array_equal(eb0[b], es0[b]), b
     assert not np.array_equal(ms[0], ms[1])

@@ -62,6 +62,8 @@ def test_batched_runs_equal_single_runs(env, n, prec, B, scheme_):
     alphas, fields = _runs(B)
     plan = _batched_plan(sg, n, prec, B, scheme_)
     m = to_dev(torch, m0, prec)
+    # energies before any batched step (the per-run values are not set yet)
+    e0 = plan.energy_batch(m, fields)
     for _ in range(4):
         plan.step_batch(m, alphas, fields)
     torch.cuda.synchronize()
@@ -70,6 +72,7 @@ def test_batched_runs_equal_single_runs(env, n, prec, B, scheme_):
     for b in range(B):
         p1 = gpu_plan_si(sg, n, CELL, DT, ALL, prec, scheme_=scheme_)
         mb = to_dev(torch, np.ascontiguousarray(m0[:, b]), prec)
+        assert e0[b] == p1.energy(mb, fields[b]), b
         for _ in range(4):
             p1.step(mb, alphas[b], fields[b])
         torch.cuda.synchronize()
