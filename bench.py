@@ -200,6 +200,8 @@ def main():
                          "to this JSONL file")
     ap.add_argument("--backward-steps", type=int, default=-1,
                     help="steps of the timed checkpointed backward pass (-1: the workload's adjoint length, 0: skip)")
+    ap.add_argument("--film-steps", type=int, default=200,
+                    help="steps of the film-128x64 timing (0 skips the film workloads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (hardware-counter calibration)")
@@ -374,6 +376,43 @@ def main():
             print(f"[bench] {name} backward pass, {SB} steps, checkpoints every {KB}: "
                   f"{backward[name]['backward_ms']:.1f} ms", file=sys.stderr, flush=True)
 
+    # ---- the film workloads: one film-128x64 run (eager and graph-replayed steps) and
+    # the adjoint film's checkpointed backward pass at its own length (500 steps,
+    # checkpoints every 50)
+    films = None
+    if args.film_steps > 0:
+        films = {}
+        cf = workloads.config("film-128x64")
+        pf = make_plan(sg, cf, sg.FP32)
+        mf = torch.tensor(workloads.initial_state(cf), dtype=torch.float32, device="cuda")
+        Bf = workloads.field_schedule(cf, 1)[0]
+        pf.steps(mf, 10, cf.alpha, Bf)
+        for _ in range(10):
+            pf.step(mf, cf.alpha, Bf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.film_steps):
+            pf.step(mf, cf.alpha, Bf)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pf.steps(mf, args.film_steps, cf.alpha, Bf)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        pf.check()
+        pf.close()
+        ms_e, ms_g = (t1 - t0) * 1e3 / args.film_steps, (t2 - t1) * 1e3 / args.film_steps
+        films["film-128x64"] = {"dtype": "f32", "steps": args.film_steps, "eager_ms_per_step": ms_e,
+                                "graph_ms_per_step": ms_g, "value": cf.cells / (ms_g * 1e-3),
+                                "unit": "cell-updates/s", "note": "value: graph-replayed steps (sgspm_steps)"}
+        print(f"[bench] film-128x64 fp32 step: eager {ms_e:.4f} ms, graph-replayed {ms_g:.4f} ms",
+              file=sys.stderr, flush=True)
+        ca = workloads.config("adjoint-film-128x128")
+        films["adjoint-film-128x128_backward"] = time_backward(
+            torch, sg, ca, sg.FP32, workloads.initial_state(ca), ca.alpha, ca.adjoint_steps, ca.ckpt_every)
+        print(f"[bench] adjoint-film-128x128 fp32 backward pass, {ca.adjoint_steps} steps, checkpoints every "
+              f"{ca.ckpt_every}: {films['adjoint-film-128x128_backward']['backward_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+
     # ---- the strip workload as specified: 5 fields x 3 dampings, 15 independent runs,
     # FP64 energies every 10 steps (graph-replayed steps between the records)
     sweep = None
@@ -462,6 +501,7 @@ def main():
         "wall_sweep": sweep,
         "adjoint": adj,
         "backward_pass": backward,
+        "films": films,
         "error_vs_oracle": err,
         "passes_ms_per_step": passes,
         "kernels": breakdown,
