@@ -47,13 +47,18 @@ template <typename T> struct RowFwd {
   int lgTw;        // log2 length of the power-of-two twiddle table
   int twg;         // stride of W_Lmax in tw (generic kernel)
   const cx<T>* tw;
-  // row value v = a[ch] * u + b * (hs + he[ch]) + wc[ch] * w; u and w may be null (0)
+  // row value v = (b (hs + he[ch]) + alo[ch] u + wclo[ch] w) + a[ch] u + wc[ch] w;
+  // u and w may be null (0). A coefficient near one (1 - beta Q) comes as a = 1 and
+  // alo = -beta Q: rounded to the working precision as one number it would keep
+  // few of beta Q's digits, and lose the same ones at every step.
   const T* u[3];
   T a[3];
+  T alo[3];
   T b;
   T he[3];
   const T* w[3];
   T wc[3];
+  T wclo[3];
   T* val_out[3];    // optional store of v (may alias u)
   // optional hs by complex-to-real transform (crop) of an x-level spectrum
   const cx<T>* xin[3];
@@ -70,17 +75,17 @@ template <typename T> struct RowFwd {
   // independent runs of a batched plan (runp null: one run): rows b rpr ...
   // (b + 1) rpr - 1 belong to run b, and a tile never holds rows of two runs.
   // Run b's applied field (he[ch] <- runp[b RUNP + rcomp[ch]]) replaces he; in
-  // the damping step (rstageF) its a[ch] and b as well (runp[b RUNP + 3 + rcomp],
-  // runp[b RUNP + 6])
+  // the damping step (rstageF) its a[ch], alo[ch] and b as well (runp[b RUNP + 3 +
+  // rcomp], runp[b RUNP + 8 + rcomp], runp[b RUNP + 6])
   const T* runp;
   int rpr;
   int rstageF;
   int rcomp[3];
 };
 // per-run values of a batched plan, in the plan's precision: the applied field
-// (3, by component), the damping step's a (3, by component) and b, and its heat
-// scale s = alpha dt
-constexpr int RUNP = 8;
+// (3, by component), the damping step's a (3, by component) and b, its heat
+// scale s = alpha dt, and the damping step's alo (3, by component)
+constexpr int RUNP = 12;
 
 enum { ROW_OP_NONE = 0, ROW_OP_GS = 1, ROW_OP_PROJECT = 2 };
 

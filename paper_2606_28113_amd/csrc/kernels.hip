@@ -18,6 +18,14 @@ namespace sgspm {
 
 template <typename T> __device__ __forceinline__ cx<T> zero() { return mk<T>((T)0, (T)0); }
 
+// A heat-solve coefficient v / (1 + x), x = s (lx + ly + lz) >= 0, taken as v - v q
+// with q = x / (1 + x). The low modes of the damping solve have x of order 1e-7:
+// 1 + x rounded to single precision keeps one or two of x's digits, the same ones
+// for that mode at every step, which acts as a changed damping constant. q keeps
+// x's relative precision.
+template <typename T> __device__ __forceinline__ T heat_q(T x) { return x / ((T)1 + x); }
+template <typename T> __device__ __forceinline__ T heat_apply(T v, T q) { return v - v * q; }
+
 // element at a byte offset from a base pointer
 template <typename V> __device__ __forceinline__ V ld_off(const V* base, unsigned byte_off) {
   return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + byte_off);
@@ -199,14 +207,15 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
   const T* w = A.w[ch];
   T* hso = A.hs_out[ch];
   T* vo = A.val_out[ch];
-  T ac = A.a[ch], hec = A.he[ch], bc = A.b;
-  const T wcc = A.wc[ch];
+  T ac = A.a[ch], aloc = A.alo[ch], hec = A.he[ch], bc = A.b;
+  const T wcc = A.wc[ch], wcloc = A.wclo[ch];
   if (A.runp) {
     // every row of the tile belongs to one run
     const T* r = A.runp + (long)(min(row0, A.nrows - 1) / A.rpr) * RUNP;
     hec = r[A.rcomp[ch]];
     if (A.rstageF) {
       ac = r[3 + A.rcomp[ch]];
+      aloc = r[8 + A.rcomp[ch]];
       bc = r[6];
     }
   }
@@ -218,17 +227,25 @@ __global__ __launch_bounds__(NT) void k_row_fwd(const RowFwd<T> A) {
   };
 #pragma unroll
   for (int i = 0; i < NV; ++i) val[i] = bc * (hs[i] + hec);
+  // the small parts first, the leading coefficients last
+  T pu[NV], pw[NV];
   if (u) {
-    T pu[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) pu[i] = u[cidx(i)];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) val[i] += aloc * pu[i];
+  }
+  if (w) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) pw[i] = w[cidx(i)];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) val[i] += wcloc * pw[i];
+  }
+  if (u) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) val[i] += ac * pu[i];
   }
   if (w) {
-    T pw[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) pw[i] = w[cidx(i)];
 #pragma unroll
     for (int i = 0; i < NV; ++i) val[i] += wcc * pw[i];
   }
@@ -490,8 +507,8 @@ __global__ __launch_bounds__(NT) void k_col_dct(const ColDct<T> A) {
           if (ib < A.ni) D[(long)k * A.sa + ib] = xb[s];
         } else {
           const T lb = (A.lamB ? A.lamB[b] : (T)0) + A.lamA[k];
-          if (ia < A.ni) xa[s] *= (T)1 / ((T)1 + A.s * (A.lamX[ia] + lb));
-          if (ib < A.ni) xb[s] *= (T)1 / ((T)1 + A.s * (A.lamX[ib] + lb));
+          if (ia < A.ni) xa[s] = heat_apply(xa[s], heat_q(A.s * (A.lamX[ia] + lb)));
+          if (ib < A.ni) xb[s] = heat_apply(xb[s], heat_q(A.s * (A.lamX[ib] + lb)));
         }
       }
     }
@@ -734,8 +751,8 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
         const int ra = q, rb = q + Hz;
         const int pa = qdiv<MX>(ra, ny, lgNy), pb = min(qdiv<MX>(rb, ny, lgNy), PP - 1);
         const T lx_a = Lx[pa], lx_b = Lx[pb];
-        xa[s2] = (w.x * Va.x - w.y * Va.y) / ((T)1 + Sx[pa] * (lx_a + Ly[qmod<MX>(ra, ny, lgNy)] + Lz[k]));
-        xb[s2] = (w.x * Vb.x - w.y * Vb.y) / ((T)1 + Sx[pb] * (lx_b + Ly[qmod<MX>(rb, ny, lgNy)] + Lz[k]));
+        xa[s2] = heat_apply(w.x * Va.x - w.y * Va.y, heat_q(Sx[pa] * (lx_a + Ly[qmod<MX>(ra, ny, lgNy)] + Lz[k])));
+        xb[s2] = heat_apply(w.x * Vb.x - w.y * Vb.y, heat_q(Sx[pb] * (lx_b + Ly[qmod<MX>(rb, ny, lgNy)] + Lz[k])));
       }
     }
     __syncthreads();
@@ -787,7 +804,7 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
     for (int i = 0; i < NV; ++i) {
       int p, z, y;
       if (decode(i, p, z, y)) {
-        v[i] /= (T)1 + Sx[p] * (Lx[p] + Ly[y] + Lz[0]);
+        v[i] = heat_apply(v[i], heat_q(Sx[p] * (Lx[p] + Ly[y] + Lz[0])));
       }
     }
   }
@@ -1991,7 +2008,7 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
       else u[pb >> 1].x = yb;
     }
     dft16(u, false);
-    const T dc = (T)1 + sp * (lx + Ly[c]);
+    const T xc = sp * (lx + Ly[c]);
     T X[NZ];
     // V_k = E_k + W_32^k O_k from U_k and conj U_(16-k); V_(32-k) = conj V_k
 #pragma unroll
@@ -2002,10 +2019,12 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
       const cx<T> O = mk<T>((Uk.y - Um.y) * (T)0.5, (Um.x - Uk.x) * (T)0.5);
       const cx<T> V = E + tw32v(O, k, false);
       const cx<T> wk = Dz[k];
-      X[k] = (wk.x * V.x - wk.y * V.y) * recip(dc + sp * Lz[k]);
+      const T xk = xc + sp * Lz[k];
+      X[k] = heat_apply(wk.x * V.x - wk.y * V.y, xk * recip((T)1 + xk));
       if (k > 0 && k < HZ) {
         const cx<T> wm = Dz[NZ - k];
-        X[NZ - k] = (wm.x * V.x + wm.y * V.y) * recip(dc + sp * Lz[NZ - k]);
+        const T xm = xc + sp * Lz[NZ - k];
+        X[NZ - k] = heat_apply(wm.x * V.x + wm.y * V.y, xm * recip((T)1 + xm));
       }
     }
     // DCT-III input V_j = conj(dtwz_j) (X_j - i X_(32-j)), folded to 16 points:
@@ -2265,18 +2284,19 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) v[m] = zero<T>();
   }
-  // v = a u + b (hs + he) + wc w at x = t + 64 m
+  // v = b (hs + he) + (alo + a) u + (wclo + wc) w at x = t + 64 m
   {
     T* hso = A.hs_out[ch];
     T* vo = A.val_out[ch];
-    T ac = A.a[ch], hec = A.he[ch], bc = A.b;
-    const T wcc = A.wc[ch];
+    T ac = A.a[ch], aloc = A.alo[ch], hec = A.he[ch], bc = A.b;
+    const T wcc = A.wc[ch], wcloc = A.wclo[ch];
     if (A.runp) {
       // every row of the tile belongs to one run
       const T* rp = A.runp + (long)(min(bk.x * 2 * P, A.nrows - 1) / A.rpr) * RUNP;
       hec = rp[A.rcomp[ch]];
       if (A.rstageF) {
         ac = rp[3 + A.rcomp[ch]];
+        aloc = rp[8 + A.rcomp[ch]];
         bc = rp[6];
       }
     }
@@ -2285,6 +2305,15 @@ __global__ __launch_bounds__(64 * P) void k_row_fwd512(const RowFwd<T> A) {
       const unsigned xo4 = (unsigned)(t + 64 * m) * TB;
       const T hsa = v[m].x, hsb = v[m].y;
       T va = bc * (hsa + hec), vb = bc * (hsb + hec);
+      // the small parts first, the leading coefficients last
+      if (u) {
+        va += aloc * pu[m].x;
+        vb += aloc * pu[m].y;
+      }
+      if (w) {
+        va += wcloc * pw[m].x;
+        vb += wcloc * pw[m].y;
+      }
       if (u) {
         va += ac * pu[m].x;
         vb += ac * pu[m].y;

@@ -363,11 +363,13 @@ template <typename T> struct Eng {
   struct RowIO {
     const T* u[3] = {nullptr, nullptr, nullptr};
     T a[3] = {1, 1, 1};
+    T alo[3] = {0, 0, 0};  // coefficients of u and w near one: a + alo, wc + wclo
     T b = 0;
     T he[3] = {0, 0, 0};
     bool with_hs = false;
     const T* w[3] = {nullptr, nullptr, nullptr};
     T wc[3] = {0, 0, 0};
+    T wclo[3] = {0, 0, 0};
     T* val_out[3] = {nullptr, nullptr, nullptr};
     T* hs_out[3] = {nullptr, nullptr, nullptr};
     T* dct_out[3] = {nullptr, nullptr, nullptr};
@@ -414,9 +416,11 @@ template <typename T> struct Eng {
     for (int c = 0; c < nch; ++c) {
       A.u[c] = io.u[c];
       A.a[c] = io.a[c];
+      A.alo[c] = io.alo[c];
       A.he[c] = io.he[c];
       A.w[c] = io.w[c];
       A.wc[c] = io.wc[c];
+      A.wclo[c] = io.wclo[c];
       A.val_out[c] = io.val_out[c];
       A.xin[c] = io.with_hs ? c2r_src_for_[c] : nullptr;
       A.hs_out[c] = io.hs_out[c];
@@ -700,7 +704,9 @@ template <typename T> struct Eng {
     for (int c = 0; c < nch; ++c) {
       io.rcomp[c] = comps[c];
       io.u[c] = u[c];
-      io.a[c] = (T)(1.0 - (double)beta * (comps[c] > 0 ? P.Q : 0.0));
+      // 1 - beta Q as 1 + (-beta Q)
+      io.a[c] = (T)1;
+      io.alo[c] = (T)(-(double)beta * (comps[c] > 0 ? P.Q : 0.0));
       io.he[c] = he[comps[c]];
       io.dct_out[c] = heat[c];
       if (hs_store) io.hs_out[c] = hs_store[c];
@@ -1033,7 +1039,7 @@ template <typename T> struct Eng {
   // acc_a = acc_in_a + kscale K(v)_a + wc_a w_a for a = 0, 1, 2 (null v_c: zero component,
   // null acc_in / w: zero); the stray operator is skipped when the plan has no stray field
   void stray_accumulate(const T* const v[3], T kscale, T* const acc[3], const T* const acc_in[3],
-                        const T* const w[3], const T wc[3]) {
+                        const T* const w[3], const T wc[3], const T* wclo = nullptr) {
     int mask = 0;
     for (int c = 0; c < 3; ++c)
       if (v[c]) mask |= 1 << c;
@@ -1050,6 +1056,7 @@ template <typename T> struct Eng {
       io.a[c] = 1;
       io.w[c] = w[c];
       io.wc[c] = wc[c];
+      io.wclo[c] = wclo ? wclo[c] : (T)0;
       io.val_out[c] = acc[c];
     }
     io.b = kscale;
@@ -1133,7 +1140,8 @@ template <typename T> struct Eng {
       const T wc[3] = {0, (T)(-alpha * dt * Q), (T)(-alpha * dt * Q)};
       stray_accumulate(v, (T)(alpha * dt), acc, v, v, wc);
     }
-    const T cq = (T)(1.0 - dt * Q);
+    // the coefficient 1 - dt Q of the precession right-hand sides, as 1 + (-dt Q)
+    const T cql = (T)(-dt * Q);
     const T dtt = (T)dt;
     // m1** = m1 + g2** m3** - g3** m2**
     pw({set1(lam0, 1, Jf(LB1)), set1(Jf(TMP), 1, Jf(LB1), f[F_A3]), add1(Jf(LA3), 1, Jf(LB1), f[F_G2SS]),
@@ -1148,8 +1156,8 @@ template <typename T> struct Eng {
       T* acc[3] = {Jf(LA1), Jf(LB2), Jf(LA3)};
       const T* ai[3] = {nullptr, Jf(LB2), Jf(LA3)};
       const T* w[3] = {nullptr, Jf(MU), nullptr};
-      const T wc[3] = {0, cq, 0};
-      stray_accumulate(v, dtt, acc, ai, w, wc);
+      const T wc[3] = {0, 1, 0}, wl[3] = {0, cql, 0};
+      stray_accumulate(v, dtt, acc, ai, w, wc, wl);
     }
     // m2** = m2 + g3** m1* - g1* m3**
     pw({set1(lam1, 1, Jf(LB2)), add1(Jf(LG3), 1, Jf(LB2), f[F_A1]), add1(Jf(LA1), 1, Jf(LB2), f[F_G3SS]),
@@ -1164,8 +1172,8 @@ template <typename T> struct Eng {
       T* acc[3] = {Jf(LA1), Jf(LA2), Jf(LA3)};
       const T* ai[3] = {Jf(LA1), nullptr, Jf(LA3)};
       const T* w[3] = {nullptr, nullptr, Jf(MU)};
-      const T wc[3] = {0, 0, cq};
-      stray_accumulate(v, dtt, acc, ai, w, wc);
+      const T wc[3] = {0, 0, 1}, wl[3] = {0, 0, cql};
+      stray_accumulate(v, dtt, acc, ai, w, wc, wl);
     }
     // m3* = m3 + g1* m2* - g2* m1*
     pw({set1(lam2, 1, Jf(LA3)), add1(Jf(LG1), 1, Jf(LA3), f[F_A2]), add1(Jf(LA2), 1, Jf(LA3), f[F_G1S]),
@@ -1180,8 +1188,8 @@ template <typename T> struct Eng {
       T* acc[3] = {Jf(LA1), Jf(LA2), lam2};
       const T* ai[3] = {Jf(LA1), Jf(LA2), lam2};
       const T* w[3] = {nullptr, Jf(MU), nullptr};
-      const T wc[3] = {0, cq, 0};
-      stray_accumulate(v, dtt, acc, ai, w, wc);
+      const T wc[3] = {0, 1, 0}, wl[3] = {0, cql, 0};
+      stray_accumulate(v, dtt, acc, ai, w, wc, wl);
     }
     // m2* = m2 + g3^n m1* - g1* m3
     pw({add1(lam1, 1, Jf(LA2)), set1(Jf(LG3N), 1, Jf(LA2), f[F_A1]), add1(Jf(LA1), 1, Jf(LA2), f[F_G3N]),
@@ -1212,8 +1220,8 @@ template <typename T> struct Eng {
       T* acc[3] = {lam0, lam1, lam2};
       const T* ai[3] = {lam0, lam1, lam2};
       const T* w[3] = {nullptr, Jf(MU), Jf(LG3)};
-      const T wc[3] = {0, cq, cq};
-      stray_accumulate(v, dtt, acc, ai, w, wc);
+      const T wc[3] = {0, 1, 1}, wl[3] = {0, cql, cql};
+      stray_accumulate(v, dtt, acc, ai, w, wc, wl);
     }
     static_assert(NJ == ADJ_FIELDS, "adjoint workspace fields");
   }
@@ -1420,7 +1428,10 @@ template <typename T> int upload_runs(sgspm_plan_s* P, const double* alpha, cons
     // the values the single-run step forms from (alpha, h_e), by the same expressions
     for (int c = 0; c < 3; ++c) r[c] = P->zeeman ? (T)(h_e[3 * b + c] * P->fscale) : (T)0;
     const T beta = (T)(alpha[b] * P->dt);
-    for (int c = 0; c < 3; ++c) r[3 + c] = (T)(1.0 - (double)beta * (c > 0 ? P->Q : 0.0));
+    for (int c = 0; c < 3; ++c) {
+      r[3 + c] = (T)1;
+      r[8 + c] = (T)(-(double)beta * (c > 0 ? P->Q : 0.0));
+    }
     r[6] = beta;
     const T scale = (T)alpha[b];
     r[7] = (T)(scale * P->dt);
