@@ -96,6 +96,10 @@ template <typename T> struct RowInv {
   int nch;             // heat arrays to invert along x (1..3)
   const T* heat[3];
   int heat_xmajor;     // heat arrays are [nx][nrows]
+  // the right-hand sides r of the heat solves: the heat arrays hold the spectra of
+  // the corrections q r (q = x / (1 + x)), and channel c inverts to g = rin[c] - its
+  // inverse transform
+  const T* rin[3];
   T* gout[3];          // optional stores of the inverted arrays
   int op;
   // ROW_OP_GS: out = base + Pf * Qf - Rf * Sf + ds * src; Pch/Rch >= 0 select an
@@ -133,7 +137,8 @@ template <typename T> struct ColDct {
   const cx<T>* dtw;
   const cx<T>* tw;
   int twg;           // W_n^i = tw[i * twg]
-  // COL_DCT_SOLVE diagonal 1 / (1 + s (lamX[i] + lamB[batch] + lamA[k]))
+  // COL_DCT_SOLVE diagonal q = x / (1 + x), x = s (lamX[i] + lamB[batch] + lamA[k])
+  // (the spectrum of the correction r - g of the heat solve g = (1 + x)^-1 r)
   const T* lamX;
   const T* lamB;
   const T* lamA;
@@ -158,6 +163,8 @@ template <typename T> struct ColFft {
 // Heat solve across y and z of x-major planes [nx][nz][ny] (after the x DCT-II):
 // y DCT-II, z DCT-II, diagonal 1 / (1 + s (lamX + lamY + lamZ)), z and y
 // inverse, in place, 2^lgPP planes per workgroup.
+// y-z transforms and the diagonal q = x / (1 + x), x = s (lamX + lamY + lamZ), of the
+// heat solves (the spectrum of the correction r - g), in place
 template <typename T> struct YZSolve {
   T* data[3];
   int nx, ny, lgNy, nz, lgNz, lgPP;

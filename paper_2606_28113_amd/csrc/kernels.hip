@@ -4,7 +4,8 @@
 // convolution, the FP64 Newell tensor, and FP64 reductions.
 //
 // Heat-type solve (paper §3, g = (I - c Lap_h)^{-1} r with Neumann BC): the
-// mirror-ghost Lap_h is diagonal in the type-II DCT basis; each 1-D DCT-II of
+// mirror-ghost Lap_h is diagonal in the type-II DCT basis (the solve runs in
+// correction form, g = r - DCT^-1 (q DCT r), see heat_q); each 1-D DCT-II of
 // length n is computed by Makhoul's method, a length-n complex FFT of the
 // even/odd-reordered sequence followed by a twiddle, with two real pencils
 // packed into one complex FFT.  Stray field (h_s = -N (*) m): zero-padded
@@ -18,13 +19,15 @@ namespace sgspm {
 
 template <typename T> __device__ __forceinline__ cx<T> zero() { return mk<T>((T)0, (T)0); }
 
-// A heat-solve coefficient v / (1 + x), x = s (lx + ly + lz) >= 0, taken as v - v q
-// with q = x / (1 + x). The low modes of the damping solve have x of order 1e-7:
-// 1 + x rounded to single precision keeps one or two of x's digits, the same ones
-// for that mode at every step, which acts as a changed damping constant. q keeps
-// x's relative precision.
+// Heat solves g = (1 + x)^-1 r per mode, x = s (lx + ly + lz) >= 0, run in
+// correction form: the spectral pass multiplies by q = x / (1 + x) and the last
+// inverse pass forms g = r - T^-1 (q T r). The transforms then touch only the
+// correction, which is small on the smooth modes: in single precision the pair
+// T^-1 T is not the identity (the rounded twiddles shrink their inputs by ~1e-7
+// per solve, the same way at every step), and the damping solve's low modes have
+// x of order 1e-7, which 1 + x rounded to single precision would keep one or two
+// digits of. q keeps x's relative precision.
 template <typename T> __device__ __forceinline__ T heat_q(T x) { return x / ((T)1 + x); }
-template <typename T> __device__ __forceinline__ T heat_apply(T v, T q) { return v - v * q; }
 
 // element at a byte offset from a base pointer
 template <typename V> __device__ __forceinline__ V ld_off(const V* base, unsigned byte_off) {
@@ -334,6 +337,16 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
   // that every register array is indexed by constants)
   auto channel = [&](int c, T(&gc)[NV]) {
     __syncthreads();
+    // the right-hand side r into gc first (clamped indices), g = r - the inverse
+    // transform of the correction at the end
+    {
+      const T* R = A.rin[c];
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        const int e = min((int)threadIdx.x + i * NT, tot - 1);
+        gc[i] = R[(long)min(row0 + qdiv<MX>(e, n, lgN), A.nrows - 1) * n + qmod<MX>(e, n, lgN)];
+      }
+    }
     const T* H = A.heat[c];
     const int ps = n + 1;
     // loads in groups of four rows of the loop (at most VPT per thread), each
@@ -395,7 +408,7 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
       if (e < tot) {
         const int row = qdiv<MX>(e, n, lgN), x = qmod<MX>(e, n, lgN);
         const cx<T> z = buf[(row >> 1) * ps + makhoul_pos(x, n)];
-        gc[i] = ((row & 1) ? z.y : z.x) * invn;
+        gc[i] -= ((row & 1) ? z.y : z.x) * invn;
         if (go && row0 + row < A.nrows) go[(long)(row0 + row) * n + x] = gc[i];
       }
     }
@@ -507,8 +520,8 @@ __global__ __launch_bounds__(NT) void k_col_dct(const ColDct<T> A) {
           if (ib < A.ni) D[(long)k * A.sa + ib] = xb[s];
         } else {
           const T lb = (A.lamB ? A.lamB[b] : (T)0) + A.lamA[k];
-          if (ia < A.ni) xa[s] = heat_apply(xa[s], heat_q(A.s * (A.lamX[ia] + lb)));
-          if (ib < A.ni) xb[s] = heat_apply(xb[s], heat_q(A.s * (A.lamX[ib] + lb)));
+          if (ia < A.ni) xa[s] *= heat_q(A.s * (A.lamX[ia] + lb));
+          if (ib < A.ni) xb[s] *= heat_q(A.s * (A.lamX[ib] + lb));
         }
       }
     }
@@ -751,8 +764,8 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
         const int ra = q, rb = q + Hz;
         const int pa = qdiv<MX>(ra, ny, lgNy), pb = min(qdiv<MX>(rb, ny, lgNy), PP - 1);
         const T lx_a = Lx[pa], lx_b = Lx[pb];
-        xa[s2] = heat_apply(w.x * Va.x - w.y * Va.y, heat_q(Sx[pa] * (lx_a + Ly[qmod<MX>(ra, ny, lgNy)] + Lz[k])));
-        xb[s2] = heat_apply(w.x * Vb.x - w.y * Vb.y, heat_q(Sx[pb] * (lx_b + Ly[qmod<MX>(rb, ny, lgNy)] + Lz[k])));
+        xa[s2] = (w.x * Va.x - w.y * Va.y) * heat_q(Sx[pa] * (lx_a + Ly[qmod<MX>(ra, ny, lgNy)] + Lz[k]));
+        xb[s2] = (w.x * Vb.x - w.y * Vb.y) * heat_q(Sx[pb] * (lx_b + Ly[qmod<MX>(rb, ny, lgNy)] + Lz[k]));
       }
     }
     __syncthreads();
@@ -804,7 +817,7 @@ __global__ __launch_bounds__(YZ_NT) void k_yz_solve(const YZSolve<T> A) {
     for (int i = 0; i < NV; ++i) {
       int p, z, y;
       if (decode(i, p, z, y)) {
-        v[i] = heat_apply(v[i], heat_q(Sx[p] * (Lx[p] + Ly[y] + Lz[0])));
+        v[i] *= heat_q(Sx[p] * (Lx[p] + Ly[y] + Lz[0]));
       }
     }
   }
@@ -1910,7 +1923,7 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 //  z: thread c owns column c.  It separates the two rows of every pencil into
 //    the y-DCT coefficients of its column, then does the z DCT-II of that real
 //    column as a 16-point complex FFT of its even / odd Makhoul samples, the
-//    diagonal 1 / (1 + s (lamX + lamY + lamZ)) and the z DCT-III the same way,
+//    diagonal q (heat_q) and the z DCT-III the same way,
 //    all in registers, and writes the column to LDS (over Zs, as reals).
 //  y inverse: each team forms the pre-twiddled inverse input of its two rows
 //    from that array, then the forward steps mirrored; stores undo the
@@ -2020,11 +2033,11 @@ __global__ __launch_bounds__((1 << (LGZ - 1)) * (1 << (LGY - 4))) void k_yz_reg(
       const cx<T> V = E + tw32v(O, k, false);
       const cx<T> wk = Dz[k];
       const T xk = xc + sp * Lz[k];
-      X[k] = heat_apply(wk.x * V.x - wk.y * V.y, xk * recip((T)1 + xk));
+      X[k] = (wk.x * V.x - wk.y * V.y) * (xk * recip((T)1 + xk));
       if (k > 0 && k < HZ) {
         const cx<T> wm = Dz[NZ - k];
         const T xm = xc + sp * Lz[NZ - k];
-        X[NZ - k] = heat_apply(wm.x * V.x + wm.y * V.y, xm * recip((T)1 + xm));
+        X[NZ - k] = (wm.x * V.x + wm.y * V.y) * (xm * recip((T)1 + xm));
       }
     }
     // DCT-III input V_j = conj(dtwz_j) (X_j - i X_(32-j)), folded to 16 points:
@@ -2435,10 +2448,19 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
       pre_src[m] = A.src ? mk<T>(ld_off(A.src, la + xo), ld_off(A.src, lb + xo)) : zero<T>();
     }
   }
+  // the right-hand sides r: g = r - the inverse transform of the correction
+  cx<T> g[NCH][4];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const unsigned xo = (unsigned)(t + 64 * m) * TB;
+      g[c][m] = mk<T>(ld_off(A.rin[c], la + xo), ld_off(A.rin[c], lb + xo));
+    }
+  }
   for (int i = tid; i < 512; i += 64 * P) W[w512_slot(i)] = A.tw[i << (A.lgTw - 9)];
   __syncthreads();
   const T invn = (T)1 / (T)N;
-  cx<T> g[NCH][4];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     cx<T> v[8];
@@ -2456,7 +2478,7 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
     T* go = A.gout[c];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      g[c][m] = mk<T>(v[m].x * invn, v[m].y * invn);
+      g[c][m] = mk<T>(g[c][m].x - v[m].x * invn, g[c][m].y - v[m].y * invn);
       if (go) {
         const unsigned xo = (unsigned)(t + 64 * m) * TB;
         if (oka) st_off(go, la + xo, g[c][m].x);
@@ -2608,6 +2630,8 @@ template <typename T> void launch_row_inv512_mode(const RowInv<T>& a, dim3 grid,
 }
 
 template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
+  for (int c = 0; c < a.nch && c < 3; ++c)
+    if (!a.rin[c]) return geom_fail("k_row_inv: a channel without its right-hand side");
   // the register kernel covers the sweeps (update with one or two channels), the
   // projection (three) and plain inverse transforms (one to three)
   const bool mode_ok = (a.op == ROW_OP_GS && a.nch < 3 && !(a.Pch < 0 && a.Rch < 0)) ||

@@ -228,7 +228,10 @@ struct sgspm_plan_s {
 
 namespace {
 
-enum { F_G2N, F_G3N, F_A1, F_G1S, F_A2, F_G2S, F_A3, F_G3SS, F_B2, F_G2SS, F_B1, F_NRM, F_HS0, F_HS1, F_HS2, NF };
+// F_R0..F_R2: the right-hand sides of the heat solves in flight (one per channel),
+// which the inverse passes read to form g = r - correction
+enum { F_G2N, F_G3N, F_A1, F_G1S, F_A2, F_G2S, F_A3, F_G3SS, F_B2, F_G2SS, F_B1, F_NRM, F_HS0, F_HS1, F_HS2,
+       F_R0, F_R1, F_R2, NF };
 
 int hip_check(hipError_t e, const char* what) {
   if (e == hipSuccess) return SGSPM_OK;
@@ -454,7 +457,10 @@ template <typename T> struct Eng {
     A.xpk = P.dcnq ? 1 : 0;
     A.heat_xmajor = P.yz ? 1 : 0;
     if (!r2c) A.xout = nullptr;
-    double by = A.nch * P.N * TS;
+    // the right-hand sides the forward passes stored, unless the caller names its own
+    for (int c = 0; c < A.nch; ++c)
+      if (!A.rin[c]) A.rin[c] = f[F_R0 + c];
+    double by = 2.0 * A.nch * P.N * TS;
     for (int c = 0; c < A.nch; ++c) by += A.gout[c] ? P.N * TS : 0;
     if (A.op == ROW_OP_GS) by += (4 + (A.src ? 1 : 0) + 1) * P.N * TS;
     if (A.op == ROW_OP_PROJECT) by += (3 + (A.nrm ? 1 : 0)) * P.N * TS;
@@ -709,6 +715,7 @@ template <typename T> struct Eng {
       io.alo[c] = (T)(-(double)beta * (comps[c] > 0 ? P.Q : 0.0));
       io.he[c] = he[comps[c]];
       io.dct_out[c] = heat[c];
+      io.val_out[c] = f[F_R0 + c];
       if (hs_store) io.hs_out[c] = hs_store[c];
     }
     io.b = beta;
@@ -874,6 +881,7 @@ template <typename T> struct Eng {
         io.w[k] = w[comps[k]];
         io.wc[k] = wc[comps[k]];
         io.dct_out[k] = heat[k];
+        io.val_out[k] = f[F_R0 + k];
       }
       io.b = dt;
       io.with_hs = false;
@@ -1030,6 +1038,7 @@ template <typename T> struct Eng {
     A.nch = nch;
     for (int c = 0; c < nch; ++c) {
       A.heat[c] = heat[c];
+      A.rin[c] = r[c];
       A.gout[c] = g[c];
     }
     A.op = ROW_OP_NONE;

@@ -269,12 +269,10 @@ def test_adjoint_film_full_length(env, prec):
     the 20-step one. FP32 cannot follow a chaotic trajectory for 500 steps; it runs from the
     paper's exchange-test state eq. (m0-1) on the same film, which is well conditioned.
 
-    FP32 bars: the stated 1e-4 relative gradient error for m0 and for the field schedule.
-    The alpha gradient is held to 1e-3 and misses 1e-4 (measured 2.6e-4): each step's
-    contribution agrees with the oracle's to ~1e-6 along the oracle's own trajectory
-    (the first reverse step, against a rough terminal cotangent, to 1e-4), so the loss
-    comes from the FP32 forward trajectory, to which this gradient is the most sensitive
-    (an FP32 model of the oracle with single-precision transforms reaches 2.2e-5)."""
+    FP32 bars: the stated 1e-4 relative gradient error for m0, the field schedule and
+    alpha. The alpha gradient is the most sensitive of the three: the loss is nearly
+    stationary in alpha, and a state or cotangent that drifts by 1e-7 per step moves it
+    by 1e-4. Measured: 8.4e-6 (alpha), 5.8e-6 (m0)."""
     torch, sg = env
     c = workloads.config("adjoint-film-128x128")
     S, K = c.steps, 50
@@ -293,6 +291,5 @@ def test_adjoint_film_full_length(env, prec):
     if prec == 1:
         assert max(errs) <= 1e-6
     else:
-        assert errs[0] <= 1e-4 and errs[1] <= 1e-4
-        assert errs[2] <= 1e-3
+        assert max(errs) <= 1e-4
     assert L == pytest.approx(Lr, rel=1e-9 if prec == 1 else 1e-5)
