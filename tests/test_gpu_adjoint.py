@@ -221,10 +221,13 @@ def test_checkpointed_gradients_vs_oracle(env, prec):
     Lr, gmr, ghr, gar = oadj.run_with_grad(P, rounded_like(m0, prec), c.alpha,
                                            [oracle_field_si(b, ALL) for b in B], rounded_like(target, prec))
     errs = (_rel(gm, gmr), _rel(gh, ghr * FSCALE), abs(ga - gar) / abs(gar))
+    # element by element: max |g - g_oracle| over max |g_oracle|
+    einf = (_rel_inf(gm, gmr), _rel_inf(gh, ghr * FSCALE))
     print(f"adjoint-film {'fp64' if prec else 'fp32'} 20-step gradients: rel err m0 {errs[0]:.2e}, "
-          f"h_e {errs[1]:.2e}, alpha {errs[2]:.2e}; loss {L:.6e} vs {Lr:.6e}")
+          f"h_e {errs[1]:.2e}, alpha {errs[2]:.2e}; element-wise m0 {einf[0]:.2e}, h_e {einf[1]:.2e}; "
+          f"loss {L:.6e} vs {Lr:.6e}")
     tol = 1e-10 if prec == 1 else 1e-4
-    assert max(errs) <= tol
+    assert max(errs) <= tol and max(einf) <= tol
     assert L == pytest.approx(Lr, rel=1e-12 if prec == 1 else 1e-5)
 
 
@@ -286,10 +289,13 @@ def test_adjoint_film_full_length(env, prec):
     Lr, gmr, ghr, gar = oadj.run_with_grad(P, rounded_like(m0, prec), c.alpha,
                                            [oracle_field_si(b, ALL) for b in B], rounded_like(target, prec))
     errs = (_rel(gm, gmr), _rel(gh, ghr * FSCALE), abs(ga - gar) / abs(gar))
+    einf = (_rel_inf(gm, gmr), _rel_inf(gh, ghr * FSCALE))
     print(f"adjoint-film {'fp64' if prec else 'fp32'} 500-step gradients (checkpoints every {K}): rel err m0 "
-          f"{errs[0]:.2e}, h_e {errs[1]:.2e}, alpha {errs[2]:.2e}; loss {L:.9e} vs {Lr:.9e}")
+          f"{errs[0]:.2e}, h_e {errs[1]:.2e}, alpha {errs[2]:.2e}; element-wise m0 {einf[0]:.2e}, "
+          f"h_e {einf[1]:.2e}; loss {L:.9e} vs {Lr:.9e}")
+    # the same bars element by element (measured: FP64 8.2e-8, 5.2e-8; FP32 6.9e-6, 1.8e-6)
     if prec == 1:
-        assert max(errs) <= 1e-6
+        assert max(errs) <= 1e-6 and max(einf) <= 1e-6
     else:
-        assert max(errs) <= 1e-4
+        assert max(errs) <= 1e-4 and max(einf) <= 1e-4
     assert L == pytest.approx(Lr, rel=1e-9 if prec == 1 else 1e-5)
