@@ -161,10 +161,9 @@ template <typename T> struct ColFft {
 };
 
 // Heat solve across y and z of x-major planes [nx][nz][ny] (after the x DCT-II):
-// y DCT-II, z DCT-II, diagonal 1 / (1 + s (lamX + lamY + lamZ)), z and y
-// inverse, in place, 2^lgPP planes per workgroup.
-// y-z transforms and the diagonal q = x / (1 + x), x = s (lamX + lamY + lamZ), of the
-// heat solves (the spectrum of the correction r - g), in place
+// y DCT-II, z DCT-II, the diagonal q = x / (1 + x), x = s (lamX + lamY + lamZ)
+// (the spectrum of the correction r - g), z and y inverse, in place, 2^lgPP planes
+// per workgroup.
 template <typename T> struct YZSolve {
   T* data[3];
   int nx, ny, lgNy, nz, lgNz, lgPP;
