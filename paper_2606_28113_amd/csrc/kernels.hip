@@ -2575,7 +2575,10 @@ template <typename T> int launch_row_fwd(const RowFwd<T>& a, int nch, hipStream_
     c2r = c2r || a.xin[c];
     r2c = r2c || a.xout[c];
   }
-  if (row256<T>(a.lgN, a.lgLc, a.lgLr, c2r, r2c) && (!a.runp || a.rpr % (2 * row_fwd512_pencils<T>()) == 0)) {
+  // x-major DCT output is stored as row pairs (2r, 2r + 1) of 8 bytes: an even row
+  // count (or one row, where the layouts coincide); the generic kernel takes the rest
+  const bool xm_ok = !a.dct_xmajor || a.nrows == 1 || a.nrows % 2 == 0;
+  if (xm_ok && row256<T>(a.lgN, a.lgLc, a.lgLr, c2r, r2c) && (!a.runp || a.rpr % (2 * row_fwd512_pencils<T>()) == 0)) {
     constexpr int P = row_fwd512_pencils<T>();
     const size_t lds = (W512_SLOTS + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
     const dim3 grid(ceil_div(a.nrows, 2 * P), 1, nch);
@@ -2636,7 +2639,10 @@ template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
   // projection (three) and plain inverse transforms (one to three)
   const bool mode_ok = (a.op == ROW_OP_GS && a.nch < 3 && !(a.Pch < 0 && a.Rch < 0)) ||
                        (a.op == ROW_OP_PROJECT && a.nch == 3) || a.op == ROW_OP_NONE;
-  if (mode_ok && row256<T>(a.lgN, a.lgLr, a.lgLr, false, a.xout != nullptr)) {
+  // x-major heat arrays are read as row pairs (2r, 2r + 1) of 8 bytes: an even row
+  // count (or one row, where the layouts coincide); the generic kernel takes the rest
+  const bool xm_ok = !a.heat_xmajor || a.nrows == 1 || a.nrows % 2 == 0;
+  if (mode_ok && xm_ok && row256<T>(a.lgN, a.lgLr, a.lgLr, false, a.xout != nullptr)) {
     constexpr int P = row_inv512_pencils<T>();
     const size_t lds = (W512_SLOTS + (size_t)64 * fft512_stride<T, P>()) * sizeof(cx<T>);
     const dim3 grid(ceil_div(a.nrows, 2 * P));

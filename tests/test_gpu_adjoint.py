@@ -42,7 +42,7 @@ def _rel_inf(a, b):
     return float(np.abs(np.ravel(a) - np.ravel(b)).max() / max(np.abs(np.ravel(b)).max(), 1e-300))
 
 
-@pytest.mark.parametrize("n", [(16, 8, 4), (32, 16, 1), (8, 1, 8), (16, 1, 1), (4, 4, 4), (256, 4, 2)],
+@pytest.mark.parametrize("n", [(16, 8, 4), (32, 16, 1), (8, 1, 8), (16, 1, 1), (4, 4, 4), (256, 4, 2), (256, 3, 1)],
                          ids=lambda n: "x".join(map(str, n)))
 @pytest.mark.parametrize("terms", [ALL, ("exchange",), ("exchange", "aniso", "zeeman"), ("stray", "zeeman")],
                          ids=lambda t: "+".join(t))

@@ -267,8 +267,11 @@ def test_full_step_fp64(env, n, method):
 
 # rows of 256 (the 512-point row kernels), the 512-point y pass with and without
 # the DC/Nyquist packing, the 64-point convolution and the 256x32 register y-z
-# solve, through whole steps from a random start
-@pytest.mark.parametrize("n", [(16, 256, 32), (256, 256, 1), (256, 8, 32)], ids=lambda n: "x".join(map(str, n)))
+# solve, through whole steps from a random start; rows of 256 in odd number
+# (3, 15), whose x-major heat arrays the register row kernels cannot pair, run the
+# generic row kernels
+@pytest.mark.parametrize("n", [(16, 256, 32), (256, 256, 1), (256, 8, 32), (256, 3, 1), (256, 5, 3)],
+                         ids=lambda n: "x".join(map(str, n)))
 @pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
 def test_steps_512_paths(env, n, prec):
     torch, sg = env
