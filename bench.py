@@ -146,8 +146,19 @@ def time_adjoint(torch, sg, c, precision, m0, B, alpha, KA):
         pa.adjoint_step(ma, alpha, B[n], lam, grad)
     stats = pa.timing_read()
     pa.timing(False)
+    # the same adjoint step from a tape (the backward pass keeps its replayed steps' tapes)
+    tape = pa.new_tapes(1)[0]
+    mt = ma.clone()
+    pa.step_taped(mt, alpha, B[0], tape)
+    pa.adjoint_step_taped(ma, alpha, B[0], tape, lam, grad)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(KA):
+        pa.adjoint_step_taped(ma, alpha, B[0], tape, lam, grad)
+    torch.cuda.synchronize()
+    mst = (time.perf_counter() - t0) * 1e3 / KA
     pa.close()
-    return msa, kernel_breakdown(stats, KA)
+    return msa, kernel_breakdown(stats, KA), mst
 
 
 def time_backward(torch, sg, c, precision, m0, alpha, S, K):
@@ -179,8 +190,10 @@ def time_backward(torch, sg, c, precision, m0, alpha, S, K):
     ok = bool(torch.isfinite(m.grad).all()) and bool(np.isfinite(float(a.grad)))
     return {"steps": S, "ckpt_every": K, "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
             "backward_value": c.cells * S / (t2 - t1), "unit": "cell-updates/s",
-            "note": "backward = recompute of every segment from its checkpoint plus S adjoint steps "
-                    "(each recomputing its forward step); value = cells x S / backward wall",
+            "note": "backward = replay of every segment from its checkpoint, keeping each step's tape, "
+                    "plus S adjoint steps from those tapes (each step runs forward once; the recompute "
+                    "path when the tapes do not fit); value = cells x S / backward wall",
+            "taped": bool(sg.autograd.TAPED),
             "grads_finite": ok}
 
 
@@ -356,11 +369,14 @@ def main():
         KA = args.adjoint_steps
         adj = {"unit": "cell-updates/s", "steps": KA,
                "note": "one adjoint step recomputes its forward step internally; cotangent = seeded "
-                       "N(0, 1) values, state = the workload's initial state"}
+                       "N(0, 1) values, state = the workload's initial state; from_tape: the same step "
+                       "from the tape of its forward step (sgspm_adjoint_step_taped, no recompute)"}
         for name, prec in (("f32", sg.FP32), ("f64", sg.FP64)):
-            msa, bd = time_adjoint(torch, sg, c, prec, m0, B, alpha, KA)
-            adj[name] = {"value": N / (msa * 1e-3), "ms_per_step": msa, "kernels": bd}
-            print(f"[bench] {name} adjoint {msa:.4f} ms/step", file=sys.stderr, flush=True)
+            msa, bd, mst = time_adjoint(torch, sg, c, prec, m0, B, alpha, KA)
+            adj[name] = {"value": N / (msa * 1e-3), "ms_per_step": msa, "kernels": bd,
+                         "from_tape": {"value": N / (mst * 1e-3), "ms_per_step": mst}}
+            print(f"[bench] {name} adjoint {msa:.4f} ms/step, from its tape {mst:.4f} ms/step",
+                  file=sys.stderr, flush=True)
         adj["value"] = adj["f32"]["value"]
         adj["ms_per_step"] = adj["f32"]["ms_per_step"]
 

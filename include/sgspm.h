@@ -34,6 +34,7 @@
 #ifndef SGSPM_H
 #define SGSPM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -170,6 +171,26 @@ int sgspm_demag_tensor(sgspm_plan_t plan, int comp, void* out);
  * m_n.  Asynchronous.  Source terms carry no gradient and are not accepted. */
 int sgspm_adjoint_step(sgspm_plan_t plan, const void* m_n, double alpha, const double h_e[3],
                        void* lam, double* grad_dev);
+
+/* The adjoint step split at its tape, so that a backward pass that replays a
+ * segment of steps does not run each step a second time (the chain rule of the
+ * step above; the paper has none).
+ *   sgspm_tape_bytes: *bytes = the device bytes of one step's tape (18 fields of
+ *     N values in the plan's precision: the step's intermediate fields and its
+ *     new state).
+ *   sgspm_step_taped: one SGSPM step in place, exactly as sgspm_step (same
+ *     result, bit for bit), that also writes its tape into `tape` (device, owned
+ *     by the caller, sgspm_tape_bytes long).
+ *   sgspm_adjoint_step_taped: sgspm_adjoint_step (same lam and grad_dev
+ *     results, bit for bit) from the tape that sgspm_step_taped wrote for the
+ *     same m_n, alpha and h_e; the tape is only read.  A tape of other inputs
+ *     gives a meaningless result; nothing checks it.
+ * SGS scheme only (SGSPM_EUNSUPPORTED otherwise); single-run plans; no source
+ * terms.  Asynchronous on the plan's stream. */
+int sgspm_tape_bytes(sgspm_plan_t plan, size_t* bytes);
+int sgspm_step_taped(sgspm_plan_t plan, void* m, double alpha, const double h_e[3], void* tape);
+int sgspm_adjoint_step_taped(sgspm_plan_t plan, const void* m_n, double alpha, const double h_e[3],
+                             const void* tape, void* lam, double* grad_dev);
 
 /* For callers that cannot allocate device memory during the call (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the

@@ -1,11 +1,27 @@
 """Final-state gradients of an SGSPM run behind torch.autograd.Function.
 
 Forward runs S library steps and keeps m every K steps; backward replays each
-segment from its checkpoint and pulls the cotangent back one step at a time
-with the library's adjoint step (sgspm_adjoint_step).  Gradients: m0 (ambient
-R^{3N}, no renormalisation), the applied-field schedule h_e (S, 3) and alpha.
+segment from its checkpoint, keeping every step's tape (sgspm_step_taped), and
+pulls the cotangent back one step at a time from those tapes
+(sgspm_adjoint_step_taped), so each step runs forward once in the backward
+pass.  When the K tapes do not fit in device memory (or TAPED is False) each
+adjoint step recomputes its step instead (sgspm_adjoint_step); the gradients
+are the same bit for bit.  Gradients: m0 (ambient R^{3N}, no renormalisation),
+the applied-field schedule h_e (S, 3) and alpha.
 """
 import torch
+
+# keep the tapes of a replayed segment (K tapes of 18 fields each)
+TAPED = True
+
+
+def _tapes(plan, K):
+    if not TAPED:
+        return None
+    try:
+        return plan.new_tapes(K)
+    except (RuntimeError, torch.cuda.OutOfMemoryError):
+        return None
 
 
 def run_steps(plan, m, alpha, h_e_sched, src=None):
@@ -43,16 +59,26 @@ class SGSPMFunction(torch.autograd.Function):
         gstep = torch.zeros(4, dtype=torch.float64, device=lam.device)
         dhe = torch.zeros((S, 3), dtype=torch.float64, device=lam.device)
         dalpha = torch.zeros((), dtype=torch.float64, device=lam.device)
+        tapes = _tapes(plan, K)
         for s0 in sorted(ctx.ckpts.keys(), reverse=True):
             s1 = min(s0 + K, S)
             states = [ctx.ckpts[s0]]
             m = ctx.ckpts[s0].clone()
-            for n in range(s0, s1 - 1):
-                plan.step(m, a, he[n].tolist(), None)
-                states.append(m.clone())
+            if tapes is not None:
+                for n in range(s0, s1):
+                    plan.step_taped(m, a, he[n].tolist(), tapes[n - s0])
+                    if n + 1 < s1:
+                        states.append(m.clone())
+            else:
+                for n in range(s0, s1 - 1):
+                    plan.step(m, a, he[n].tolist(), None)
+                    states.append(m.clone())
             for n in range(s1 - 1, s0 - 1, -1):
                 gstep.zero_()
-                plan.adjoint_step(states[n - s0], a, he[n].tolist(), lam, gstep)
+                if tapes is not None:
+                    plan.adjoint_step_taped(states[n - s0], a, he[n].tolist(), tapes[n - s0], lam, gstep)
+                else:
+                    plan.adjoint_step(states[n - s0], a, he[n].tolist(), lam, gstep)
                 dhe[n] = gstep[:3]
                 dalpha += gstep[3]
         g_m0 = lam

@@ -17,7 +17,8 @@ EXPORTS = ("sgspm_validate", "sgspm_reduced_constants", "sgspm_plan", "sgspm_ste
            "sgspm_step_spectral_radius",
            "sgspm_energy", "sgspm_unit_error",
            "sgspm_field", "sgspm_stray", "sgspm_heat_solve", "sgspm_adjoint_step",
-           "sgspm_adjoint_step_noalloc", "sgspm_demag_tensor", "sgspm_timing",
+           "sgspm_adjoint_step_noalloc", "sgspm_tape_bytes", "sgspm_step_taped", "sgspm_adjoint_step_taped",
+           "sgspm_demag_tensor", "sgspm_timing",
            "sgspm_timing_read", "sgspm_check", "sgspm_destroy", "sgspm_last_error")
 KERNEL_CLASSES = ("row_fwd", "row_fwd512", "row_inv", "row_inv512", "col_dct", "yz_solve", "yz_reg",
                   "col_fft", "fft512", "conv", "conv64", "other")
@@ -64,6 +65,9 @@ def _load():
     L.sgspm_heat_solve.argtypes = [vp, vp, ctypes.c_double, vp]
     L.sgspm_adjoint_step.argtypes = [vp, vp, ctypes.c_double, dp, vp, vp]
     L.sgspm_adjoint_step_noalloc.argtypes = [vp, vp, ctypes.c_double, dp, vp, vp]
+    L.sgspm_tape_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.sgspm_step_taped.argtypes = [vp, vp, ctypes.c_double, dp, vp]
+    L.sgspm_adjoint_step_taped.argtypes = [vp, vp, ctypes.c_double, dp, vp, vp, vp]
     L.sgspm_demag_tensor.argtypes = [vp, ctypes.c_int, vp]
     L.sgspm_timing.argtypes = [vp, ctypes.c_int]
     L.sgspm_timing_read.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_int64)]
@@ -227,6 +231,38 @@ class Plan:
             raise ValueError("grad must be a contiguous CUDA float64 tensor of 4 values")
         _check(lib.sgspm_adjoint_step_noalloc(self._h, self._ptr(m_n, self.shape, "m_n"), float(alpha), _d3(h_e),
                                               self._ptr(lam, self.shape, "lam"), ctypes.c_void_p(grad.data_ptr())))
+
+    def tape_bytes(self):
+        """Device bytes of one step's tape (step_taped / adjoint_step_taped)."""
+        n = ctypes.c_size_t()
+        _check(lib.sgspm_tape_bytes(self._h, ctypes.byref(n)))
+        return n.value
+
+    def new_tapes(self, count):
+        """Device storage for `count` step tapes: a uint8 tensor, one row per tape."""
+        import torch
+        return torch.empty((int(count), self.tape_bytes()), dtype=torch.uint8, device="cuda")
+
+    def _tape_ptr(self, tape):
+        import torch
+        if (not tape.is_cuda or not tape.is_contiguous() or tape.dtype != torch.uint8
+                or tape.numel() < self.tape_bytes()):
+            raise ValueError(f"tape must be a contiguous CUDA uint8 tensor of at least {self.tape_bytes()} bytes")
+        return ctypes.c_void_p(tape.data_ptr())
+
+    def step_taped(self, m, alpha, h_e, tape):
+        """One step in place (as step) that also writes its tape."""
+        _check(lib.sgspm_step_taped(self._h, self._ptr(m, self.shape, "m"), float(alpha), _d3(h_e),
+                                    self._tape_ptr(tape)))
+
+    def adjoint_step_taped(self, m_n, alpha, h_e, tape, lam, grad):
+        """adjoint_step from the tape step_taped wrote for the same m_n, alpha and h_e."""
+        import torch
+        if not grad.is_cuda or grad.dtype != torch.float64 or grad.numel() != 4 or not grad.is_contiguous():
+            raise ValueError("grad must be a contiguous CUDA float64 tensor of 4 values")
+        _check(lib.sgspm_adjoint_step_taped(self._h, self._ptr(m_n, self.shape, "m_n"), float(alpha), _d3(h_e),
+                                            self._tape_ptr(tape), self._ptr(lam, self.shape, "lam"),
+                                            ctypes.c_void_p(grad.data_ptr())))
 
     def demag_tensor(self, comp, out=None):
         """Real-space FP64 tensor component comp (0..5 = xx yy zz xy xz yz) on the padded grid (Pz, Py, Px)."""

@@ -22,6 +22,8 @@ using namespace sgspm;
 // device with that device current (at plan creation), and is kept per device.
 static constexpr size_t SCRATCH_BYTES = size_t(8) << 20;
 static constexpr int ADJ_FIELDS = 16;
+// field of the adjoint workspace that holds the recomputed new state
+static constexpr int ADJ_MT = 13;
 static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
 
 namespace {
@@ -232,6 +234,8 @@ namespace {
 // which the inverse passes read to form g = r - correction
 enum { F_G2N, F_G3N, F_A1, F_G1S, F_A2, F_G2S, F_A3, F_G3SS, F_B2, F_G2SS, F_B1, F_NRM, F_HS0, F_HS1, F_HS2,
        F_R0, F_R1, F_R2, NF };
+// a step's tape: the fields before F_R0 (what the reverse reads) and the new state
+constexpr int TAPE_FIELDS = F_R0 + 3;
 
 int hip_check(hipError_t e, const char* what) {
   if (e == hipSuccess) return SGSPM_OK;
@@ -1101,11 +1105,27 @@ template <typename T> struct Eng {
 
   // Adjoint of one SGSPM step (reverse of step(), latest-state reading).
   void adjoint(const T* m_n, double alpha, const double he_in[3], T* lam, double* grad, void* work) {
+    T* mt = (T*)work + (long)ADJ_MT * P.N;
+    (void)hipMemcpyAsync(mt, m_n, 3 * P.N * sizeof(T), hipMemcpyDeviceToDevice, s);
+    tape = true;
+    step(mt, alpha, he_in, nullptr);
+    tape = false;
+    reverse(m_n, mt, alpha, he_in, lam, grad, work);
+  }
+
+  // the step's intermediate fields (the tape) live in tp: fields 0 .. F_R0 - 1 of f,
+  // then the new state (3 fields); the right-hand-side fields stay in the workspace
+  void use_tape(T* tp) {
+    for (int i = 0; i < F_R0; ++i) f[i] = tp + (long)i * P.N;
+  }
+
+  // The reverse of one step from its tape (f) and its new state u; J = work.
+  void reverse(const T* m_n, const T* u, double alpha, const double he_in[3], T* lam, double* grad, void* work) {
     const long N = P.N;
     T* J = (T*)work;
     enum { LA1, LA2, LA3, LB1, LB2, LG1, LG3, LG3N, TMP, MU, LW, MT = LW + 3, NJ = MT + 3 };
+    static_assert(MT == ADJ_MT, "adjoint workspace layout");
     T* LW_[3] = {J + (long)LW * N, J + (long)(LW + 1) * N, J + (long)(LW + 2) * N};
-    T* mt = J + (long)MT * N;
     auto Jf = [&](int k) { return J + (long)k * N; };
     const T* m2 = m_n + N;
     const T* m3 = m_n + 2 * N;
@@ -1117,11 +1137,6 @@ template <typename T> struct Eng {
     const double dh = P.zeeman ? dt * P.fscale : 0.0;  // d(reduced h_e)/d(argument) * dt
     double he[3];
     for (int c = 0; c < 3; ++c) he[c] = P.zeeman ? he_in[c] * P.fscale : 0.0;
-    (void)hipMemcpyAsync(mt, m_n, 3 * N * sizeof(T), hipMemcpyDeviceToDevice, s);
-    tape = true;
-    step(mt, alpha, he_in, nullptr);
-    tape = false;
-    const T* u = mt;
     const T* nrm = f[F_NRM];
     // projection and heat flow
     // reads lam, u (3 N each) and |c| (N), writes 3 N
@@ -1844,6 +1859,58 @@ int sgspm_adjoint_step(sgspm_plan_t P, const void* m_n, double alpha, const doub
   if (P->fp64) Eng<double>(*P).adjoint((const double*)m_n, alpha, h_e, (double*)lam, grad_dev, P->adj);
   else Eng<float>(*P).adjoint((const float*)m_n, alpha, h_e, (float*)lam, grad_dev, P->adj);
   return launch_status(P, "sgspm_adjoint_step launch");
+}
+
+int sgspm_tape_bytes(sgspm_plan_t P, size_t* bytes) {
+  if (!P || !bytes) return fail(SGSPM_EINVAL, "NULL argument");
+  *bytes = (size_t)TAPE_FIELDS * P->N * (P->fp64 ? 8 : 4);
+  return SGSPM_OK;
+}
+
+int sgspm_step_taped(sgspm_plan_t P, void* m, double alpha, const double h_e[3], void* tape) {
+  if (!P || !m || !h_e || !tape) return fail(SGSPM_EINVAL, "NULL argument");
+  if (P->B > 1) return fail(SGSPM_EINVAL, "sgspm_step_taped: a batched plan takes the batched entry points");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SGSPM_EINVAL, "alpha must be >= 0 and finite");
+  if (P->prm.scheme != SGSPM_SCHEME_SGS) return fail(SGSPM_EUNSUPPORTED, "the adjoint covers the SGS scheme only");
+  if (P->fp64) {
+    Eng<double> e(*P);
+    e.use_tape((double*)tape);
+    e.tape = true;
+    e.step((double*)m, alpha, h_e, nullptr);
+    (void)hipMemcpyAsync((double*)tape + (long)F_R0 * P->N, m, 3 * P->N * sizeof(double), hipMemcpyDeviceToDevice, P->s);
+  } else {
+    Eng<float> e(*P);
+    e.use_tape((float*)tape);
+    e.tape = true;
+    e.step((float*)m, alpha, h_e, nullptr);
+    (void)hipMemcpyAsync((float*)tape + (long)F_R0 * P->N, m, 3 * P->N * sizeof(float), hipMemcpyDeviceToDevice, P->s);
+  }
+  return launch_status(P, "sgspm_step_taped launch");
+}
+
+int sgspm_adjoint_step_taped(sgspm_plan_t P, const void* m_n, double alpha, const double h_e[3], const void* tape,
+                             void* lam, double* grad_dev) {
+  if (!P || !m_n || !h_e || !tape || !lam || !grad_dev) return fail(SGSPM_EINVAL, "NULL argument");
+  if (P->B > 1) return fail(SGSPM_EINVAL, "sgspm_adjoint_step_taped: a batched plan takes the batched entry points");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SGSPM_EINVAL, "alpha must be >= 0 and finite");
+  if (P->prm.scheme != SGSPM_SCHEME_SGS) return fail(SGSPM_EUNSUPPORTED, "the adjoint covers the SGS scheme only");
+  if (!P->adj) {
+    int rc = dalloc(P, &P->adj, (size_t)ADJ_FIELDS * P->N * (P->fp64 ? 8 : 4));
+    if (rc) return rc;
+  }
+  // the reverse only reads the tape
+  if (P->fp64) {
+    Eng<double> e(*P);
+    double* tp = const_cast<double*>(static_cast<const double*>(tape));
+    e.use_tape(tp);
+    e.reverse((const double*)m_n, tp + (long)F_R0 * P->N, alpha, h_e, (double*)lam, grad_dev, P->adj);
+  } else {
+    Eng<float> e(*P);
+    float* tp = const_cast<float*>(static_cast<const float*>(tape));
+    e.use_tape(tp);
+    e.reverse((const float*)m_n, tp + (long)F_R0 * P->N, alpha, h_e, (float*)lam, grad_dev, P->adj);
+  }
+  return launch_status(P, "sgspm_adjoint_step_taped launch");
 }
 
 int sgspm_adjoint_step_noalloc(sgspm_plan_t P, const void* m_n, double alpha, const double h_e[3], void* lam,

@@ -10,7 +10,9 @@
 // spectral radii of a step from m0 (2); at m0: h_eff (3N), h_s (3N), the heat
 // solve of m1 with s = 1 (N); lambda after one adjoint step from m0 (3N) and
 // its gradient (4); the same from the no-allocation adjoint (zeros where an
-// entry point does not apply).
+// entry point does not apply).  The taped step and adjoint are checked against
+// sgspm_step and sgspm_adjoint_step bit for bit here in runs of every workgroup
+// (exit status 5 otherwise).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -211,6 +213,44 @@ int main(int argc, char** argv) {
       }
       hipFree(lam);
       hipFree(g);
+    }
+    // the taped pair: the step equals sgspm_step, the adjoint from its tape equals
+    // sgspm_adjoint_step, bit for bit (abort otherwise)
+    {
+      size_t tb = 0;
+      if ((rc = sgspm_tape_bytes(plan, &tb))) die("sgspm_tape_bytes", rc);
+      void* tape = nullptr;
+      hipMalloc(&tape, tb);
+      void* ms = upload(in.data(), 3 * N);
+      void* mt = upload(in.data(), 3 * N);
+      if ((rc = sgspm_step(plan, ms, alpha, he, nullptr))) die("sgspm_step", rc);
+      if ((rc = sgspm_step_taped(plan, mt, alpha, he, tape))) die("sgspm_step_taped", rc);
+      void* la = upload(in.data() + 3 * N, 3 * N);
+      void* lb = upload(in.data() + 3 * N, 3 * N);
+      double *ga, *gb;
+      hipMalloc(&ga, 32);
+      hipMalloc(&gb, 32);
+      for (int i = 0; i < 4; ++i) ga[i] = gb[i] = 0.0;
+      if ((rc = sgspm_adjoint_step(plan, m0, alpha, he, la, ga))) die("sgspm_adjoint_step", rc);
+      if ((rc = sgspm_adjoint_step_taped(plan, m0, alpha, he, tape, lb, gb))) die("sgspm_adjoint_step_taped", rc);
+      std::vector<double> xa, xb;
+      fetch(ms, 3 * N, xa);
+      fetch(mt, 3 * N, xb);
+      fetch(la, 3 * N, xa);
+      fetch(lb, 3 * N, xb);
+      xa.insert(xa.end(), ga, ga + 4);
+      xb.insert(xb.end(), gb, gb + 4);
+      // a sampled run leaves the workgroups it skips unwritten: compare full runs only
+      const char* sampled = getenv("EMU_MAX_GROUPS");
+      const bool full = !sampled || atol(sampled) == 0;
+      for (size_t i = 0; full && i < xa.size(); ++i)
+        if (xa[i] != xb[i]) {
+          fprintf(stderr, "taped step or adjoint differs at %zu: %.17g vs %.17g\n", i, xa[i], xb[i]);
+          exit(5);
+        }
+      for (void* q : {tape, ms, mt, la, lb}) hipFree(q);
+      hipFree(ga);
+      hipFree(gb);
     }
     hipFree(m0);
   } else {

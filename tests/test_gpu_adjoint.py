@@ -299,3 +299,59 @@ def test_adjoint_film_full_length(env, prec):
     else:
         assert max(errs) <= 1e-4 and max(einf) <= 1e-4
     assert L == pytest.approx(Lr, rel=1e-9 if prec == 1 else 1e-5)
+
+
+@pytest.mark.parametrize("n", [(16, 8, 4), (128, 128, 1), (256, 256, 32)], ids=lambda n: "x".join(map(str, n)))
+@pytest.mark.parametrize("prec", [1, 0], ids=["fp64", "fp32"])
+def test_taped_step_and_adjoint_equal_untaped(env, n, prec):
+    """sgspm_step_taped gives sgspm_step's state and sgspm_adjoint_step_taped, from that
+    tape, sgspm_adjoint_step's cotangent and gradient, bit for bit; the tape is only read
+    (a second adjoint from it gives the same again)."""
+    torch, sg = env
+    shape = (n[2], n[1], n[0])
+    m0 = workloads.random_unit(shape, 211)
+    lam0 = np.random.default_rng(212).normal(size=(3,) + shape)
+    B = (4e-3, -2e-3, 1e-3)
+    plan = gpu_plan_si(sg, n, CELL, DT, ALL, prec)
+    dt_ = torch.float64 if prec == 1 else torch.float32
+    m = torch.tensor(m0, dtype=dt_, device="cuda")
+    ms, mt = m.clone(), m.clone()
+    tape = plan.new_tapes(1)[0]
+    plan.step(ms, 0.02, B)
+    plan.step_taped(mt, 0.02, B, tape)
+    assert torch.equal(ms, mt)
+    outs = []
+    for kind in ("recompute", "tape", "tape"):
+        lam = torch.tensor(lam0, dtype=dt_, device="cuda")
+        g = torch.zeros(4, dtype=torch.float64, device="cuda")
+        if kind == "recompute":
+            plan.adjoint_step(m, 0.02, B, lam, g)
+        else:
+            plan.adjoint_step_taped(m, 0.02, B, tape, lam, g)
+        torch.cuda.synchronize()
+        outs.append((lam.cpu(), g.cpu()))
+    for lam, g in outs[1:]:
+        assert torch.equal(lam, outs[0][0]) and torch.equal(g, outs[0][1])
+
+
+def test_taped_backward_pass_equals_recompute(env):
+    """The checkpointed backward pass with tapes (one forward run per step) and without
+    (every adjoint step recomputes its step) give the same gradients bit for bit."""
+    torch, sg = env
+    from paper_2606_28113_amd import autograd as ag
+    c = workloads.config("adjoint-film-128x128")
+    S, K = 20, 6
+    m0 = workloads.initial_state(c)
+    B = workloads.field_schedule(c, S)
+    target = workloads.target_state(c)
+    plan = gpu_plan_si(sg, c.n, c.h, c.dt, ALL, 0)
+    res = []
+    for taped in (True, False):
+        ag.TAPED = taped
+        try:
+            res.append(_loss_grads_gpu(torch, sg, plan, m0, B, c.alpha, target, K, 0))
+        finally:
+            ag.TAPED = True
+    (L1, gm1, gh1, ga1), (L2, gm2, gh2, ga2) = res
+    assert L1 == L2 and ga1 == ga2
+    assert np.array_equal(gm1, gm2) and np.array_equal(gh1, gh2)
