@@ -163,7 +163,7 @@ def time_adjoint(torch, sg, c, precision, m0, B, alpha, KA):
 
 def time_backward(torch, sg, c, precision, m0, alpha, S, K):
     """Forward with checkpoints every K steps and the full backward pass (segment
-    recompute plus S adjoint steps) of the terminal misfit L = mean (m_S - target)^2."""
+    replays with tapes plus S adjoint steps) of the terminal misfit L = mean (m_S - target)^2."""
     plan = make_plan(sg, c, precision)
     dt_ = torch.float32 if precision == sg.FP32 else torch.float64
     B = workloads.field_schedule(c, S)
@@ -172,8 +172,9 @@ def time_backward(torch, sg, c, precision, m0, alpha, S, K):
     m = torch.tensor(m0, dtype=dt_, device="cuda", requires_grad=True)
     he = torch.tensor(B, dtype=torch.float64, requires_grad=True)
     a = torch.tensor(alpha, dtype=torch.float64, requires_grad=True)
-    # untimed one-step pass: the plan's adjoint workspace and the autograd engine start here
-    sg.SGSPMFunction.apply(m, he[:1], a, plan, 1).sum().backward()
+    # an untimed pass of the same length first: the plan's adjoint workspace, the tapes,
+    # the autograd engine and the allocator's blocks for every checkpoint and state start here
+    sg.SGSPMFunction.apply(m, he, a, plan, K).sum().backward()
     m.grad = None
     he.grad = None
     a.grad = None
@@ -422,6 +423,28 @@ def main():
                                 "unit": "cell-updates/s", "note": "value: graph-replayed steps (sgspm_steps)"}
         print(f"[bench] film-128x64 fp32 step: eager {ms_e:.4f} ms, graph-replayed {ms_g:.4f} ms",
               file=sys.stderr, flush=True)
+        # many independent film runs in one batched plan (every launch covers all runs)
+        BF = 64
+        pb = make_plan(sg, cf, sg.FP32, batch=BF)
+        m1 = torch.tensor(workloads.initial_state(cf), dtype=torch.float32, device="cuda")
+        mb = m1.unsqueeze(1).expand(3, BF, *m1.shape[1:]).contiguous()
+        alphas = [cf.alpha] * BF
+        fields = [tuple(float(x) * (1.0 + 0.01 * b) for x in Bf) for b in range(BF)]
+        pb.steps_batch(mb, 10, alphas, fields)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb.steps_batch(mb, args.film_steps, alphas, fields)
+        torch.cuda.synchronize()
+        ms_b = (time.perf_counter() - t0) * 1e3 / args.film_steps
+        pb.check()
+        pb.close()
+        films["film-128x64_batched"] = {"dtype": "f32", "runs": BF, "steps": args.film_steps,
+                                        "ms_per_step": ms_b, "value": BF * cf.cells / (ms_b * 1e-3),
+                                        "unit": "cell-updates/s",
+                                        "note": f"{BF} runs of the film (applied fields 1.00 to 1.63 times 5 mT) "
+                                                "in one batched plan, graph-replayed batched steps"}
+        print(f"[bench] film-128x64 x {BF} runs, batched: {ms_b:.4f} ms per step of all runs "
+              f"({BF * cf.cells / (ms_b * 1e-3):.3e} cell-updates/s)", file=sys.stderr, flush=True)
         ca = workloads.config("adjoint-film-128x128")
         films["adjoint-film-128x128_backward"] = time_backward(
             torch, sg, ca, sg.FP32, workloads.initial_state(ca), ca.alpha, ca.adjoint_steps, ca.ckpt_every)
