@@ -107,10 +107,11 @@ def _run(exe, tmp_path, n, prec, scheme_=0, terms=ALL, steps=2, sample=0, seed=3
 # films, lines and single cells) and rows of 256 (the 512-point register row
 # kernels; an odd number of rows, whose x-major heat arrays the register kernels
 # cannot pair, goes to the generic ones), every workgroup, FP64, against the oracle
-FULL = [(16, 8, 4), (12, 10, 3), (4, 1, 8), (30, 1, 1), (1, 1, 1), (256, 2, 1), (256, 3, 1), (256, 5, 3)]
+FULL = [(16, 8, 4), (12, 10, 3), (4, 1, 8), (30, 1, 1), (1, 1, 1), (256, 2, 1), (256, 3, 1)]
 # and (SGSPM_EMU_ALL=1) the special extents (rows of 256, the 256-point y pass) mixed
 # with odd ones
-FULL_MORE = [(8, 4, 2), (1, 16, 1), (6, 5, 1), (256, 1, 3), (256, 3, 5), (3, 256, 1), (5, 256, 3), (256, 2, 3)]
+FULL_MORE = [(8, 4, 2), (1, 16, 1), (6, 5, 1), (256, 5, 3), (256, 1, 3), (256, 3, 5), (3, 256, 1), (5, 256, 3),
+             (256, 2, 3)]
 # SGSPM_EMU_ALL=1 adds the longer lists below to the default ones
 EMU_ALL = os.environ.get("SGSPM_EMU_ALL") == "1"
 
