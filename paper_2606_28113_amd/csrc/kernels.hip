@@ -1269,8 +1269,9 @@ __global__ __launch_bounds__(CONV_NT) void k_conv(const Conv<T> A) {
         T tv[3];
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb) {
+          // an absent input component: its tensor components are not loaded
           const int c = comp_index(a, bb);
-          T v = tt[(A.cpos[c] * LH + kf) * P + q];
+          T v = A.S[bb] ? tt[(A.cpos[c] * LH + kf) * P + q] : (T)0;
           if (cneg && ((A.oddc >> c) & 1)) v = -v;
           if (bneg && ((A.oddb >> c) & 1)) v = -v;
           tv[bb] = v;
@@ -1440,6 +1441,8 @@ __global__ __launch_bounds__(C64_NT, sizeof(T) == 4 ? 5 : 1) void k_conv64(const
     for (int k1 = 0; k1 < 8; ++k1) o[k1] = zero<T>();
 #pragma unroll
     for (int bb = 0; bb < 3; ++bb) {
+      // an absent input component: its tensor components are not loaded
+      if (!A.S[bb]) continue;
       const int c = comp_index(a, bb);
       const T* tc = tt + A.cpos[c] * 33 * P + q;
       const bool zodd = (A.oddc >> c) & 1;

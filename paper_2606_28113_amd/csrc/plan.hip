@@ -646,7 +646,9 @@ template <typename T> struct Eng {
       A.O[c] = (mask >> c & 1) ? yout[c] : nullptr;
       if (mask >> c & 1) {
         ++nout;
-        for (int b = 0; b < 3; ++b) used |= 1u << (c == b ? c : 2 + c + b);
+        // the tensor components of the inputs present
+        for (int b = 0; b < 3; ++b)
+          if (smask >> b & 1) used |= 1u << (c == b ? c : 2 + c + b);
       }
     }
     A.nt = 0;
@@ -677,7 +679,8 @@ template <typename T> struct Eng {
     const int nrows = (z && P.has_mid) ? P.Py : 1;
     const double slab = (double)A.n * A.ni * nrows * 2 * TS * P.B;
     const double tb = A.nt * (double)(z ? P.Hz : P.Hy) * A.Hb * A.ni * TS;
-    timed(3 * slab + nout * slab + tb, [&] { return launch_conv<T>(A, nb, s); });
+    const int nin = (smask & 1) + (smask >> 1 & 1) + (smask >> 2 & 1);
+    timed(nin * slab + nout * slab + tb, [&] { return launch_conv<T>(A, nb, s); });
   }
 
   // forward transforms of real fields into the component spectra
