@@ -467,6 +467,10 @@ __global__ __launch_bounds__(NT) void k_row_inv(const RowInv<T> A) {
         }
       }
     }
+  } else if (A.op == ROW_OP_NONE && A.nch == 1 && A.xout) {
+    // a plain inverse of one channel: the r2c of its result
+    row_r2c_store<T, NV, MX>(buf, tw, g[0], tot, n, lgN, A.Lr, A.lgLr, Lmax, A.lgP, row0, A.nrows, A.xout,
+                             A.xout_pitch, A.xpk != 0);
   }
 }
 
@@ -2489,6 +2493,32 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
       }
     }
   }
+  // the zero-padded r2c of this thread's two rows (v[m] at x = t + 64 m, m < 4) into A.xout
+  auto r2c_store = [&](cx<T>(&v)[8]) {
+#pragma unroll
+    for (int m = 4; m < 8; ++m) v[m] = zero<T>();
+    f512_fwd<T, P, S>(v, t, q, xb, W, true);
+    f512_spill<T, P, S>(v, t, q, xb);
+    __syncthreads();
+    constexpr unsigned CB = sizeof(cx<T>);
+    const unsigned pitch = (unsigned)A.xout_pitch;
+#pragma unroll
+    for (int j = 0; j <= 4; ++j) {
+      const int k = t + 64 * j;
+      if (j == 4 && (t || A.xpk)) break;  // packed: the Nyquist bin goes with bin 0
+      const cx<T> Zk = f512_at<T, P, S>(xb, k, q), Zm = f512_at<T, P, S>(xb, (512 - k) & 511, q);
+      cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
+      cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
+      if (j == 0 && A.xpk && t == 0) {
+        // X[256] of both rows (real: Re Z_256, Im Z_256) as bin 0's imaginary part
+        const cx<T> Zn = f512_at<T, P, S>(xb, 256, q);
+        Xa.y = Zn.x;
+        Xb.y = Zn.y;
+      }
+      if (oka) st_off(A.xout, ((unsigned)ra * pitch + (unsigned)k) * CB, Xa);
+      if (okb) st_off(A.xout, ((unsigned)(ra + 1) * pitch + (unsigned)k) * CB, Xb);
+    }
+  };
   if constexpr (gs) {
     constexpr int C1 = NCH > 1 ? 1 : 0;
     const T ds = A.ds;
@@ -2511,30 +2541,14 @@ __global__ __launch_bounds__(64 * P) void k_row_inv512(const RowInv<T> A) {
       if (okb) st_off(A.out, lb + xo, o[1]);
       v[m] = mk<T>(o[0], o[1]);
     }
+    if (A.xout) r2c_store(v);
+  } else if constexpr (NCH == 1 && OP == ROW_OP_NONE) {
+    // a plain inverse of one channel: optionally the r2c of its result
     if (A.xout) {
+      cx<T> v[8];
 #pragma unroll
-      for (int m = 4; m < 8; ++m) v[m] = zero<T>();
-      f512_fwd<T, P, S>(v, t, q, xb, W, true);
-      f512_spill<T, P, S>(v, t, q, xb);
-      __syncthreads();
-      constexpr unsigned CB = sizeof(cx<T>);
-      const unsigned pitch = (unsigned)A.xout_pitch;
-#pragma unroll
-      for (int j = 0; j <= 4; ++j) {
-        const int k = t + 64 * j;
-        if (j == 4 && (t || A.xpk)) break;  // packed: the Nyquist bin goes with bin 0
-        const cx<T> Zk = f512_at<T, P, S>(xb, k, q), Zm = f512_at<T, P, S>(xb, (512 - k) & 511, q);
-        cx<T> Xa = mk<T>((Zk.x + Zm.x) * (T)0.5, (Zk.y - Zm.y) * (T)0.5);
-        cx<T> Xb = mk<T>((Zk.y + Zm.y) * (T)0.5, (Zm.x - Zk.x) * (T)0.5);
-        if (j == 0 && A.xpk && t == 0) {
-          // X[256] of both rows (real: Re Z_256, Im Z_256) as bin 0's imaginary part
-          const cx<T> Zn = f512_at<T, P, S>(xb, 256, q);
-          Xa.y = Zn.x;
-          Xb.y = Zn.y;
-        }
-        if (oka) st_off(A.xout, ((unsigned)ra * pitch + (unsigned)k) * CB, Xa);
-        if (okb) st_off(A.xout, ((unsigned)(ra + 1) * pitch + (unsigned)k) * CB, Xb);
-      }
+      for (int m = 0; m < 4; ++m) v[m] = g[0][m];
+      r2c_store(v);
     }
   } else if constexpr (NCH == 3 && OP == ROW_OP_PROJECT) {
 #pragma unroll
@@ -2638,6 +2652,9 @@ template <typename T> void launch_row_inv512_mode(const RowInv<T>& a, dim3 grid,
 template <typename T> int launch_row_inv(const RowInv<T>& a, hipStream_t s) {
   for (int c = 0; c < a.nch && c < 3; ++c)
     if (!a.rin[c]) return geom_fail("k_row_inv: a channel without its right-hand side");
+  // the r2c output follows a Gauss-Seidel update or a plain inverse of one channel
+  if (a.xout && !(a.op == ROW_OP_GS || (a.op == ROW_OP_NONE && a.nch == 1)))
+    return geom_fail("k_row_inv: an r2c output needs a Gauss-Seidel update or one plain channel");
   // the register kernel covers the sweeps (update with one or two channels), the
   // projection (three) and plain inverse transforms (one to three)
   const bool mode_ok = (a.op == ROW_OP_GS && a.nch < 3 && !(a.Pch < 0 && a.Rch < 0)) ||

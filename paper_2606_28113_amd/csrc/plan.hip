@@ -1032,8 +1032,9 @@ template <typename T> struct Eng {
     heat_solve_n(1, in, scale, out);
   }
 
-  // g_c = (I - scale eps dt Lap_h)^{-1} r_c for nch channels (in place allowed)
-  void heat_solve_n(int nch, const T* const r[3], T scale, T* const g[3]) {
+  // g_c = (I - scale eps dt Lap_h)^{-1} r_c for nch channels (in place allowed); with one
+  // channel, xout0 (optional) receives the zero-padded r2c of g (the x-level spectrum)
+  void heat_solve_n(int nch, const T* const r[3], T scale, T* const g[3], cx<T>* xout0 = nullptr) {
     RowIO io;
     for (int c = 0; c < nch; ++c) {
       io.u[c] = r[c];
@@ -1049,18 +1050,22 @@ template <typename T> struct Eng {
       A.gout[c] = g[c];
     }
     A.op = ROW_OP_NONE;
-    row_inv(A, false);
+    A.xout = nch == 1 ? xout0 : nullptr;
+    row_inv(A, A.xout != nullptr);
   }
 
   // acc_a = acc_in_a + kscale K(v)_a + wc_a w_a for a = 0, 1, 2 (null v_c: zero component,
   // null acc_in / w: zero); the stray operator is skipped when the plan has no stray field
+  // spectra: the x-level spectra of v are already in place (r2c_slot), as the heat
+  // solve that produced v can leave them
   void stray_accumulate(const T* const v[3], T kscale, T* const acc[3], const T* const acc_in[3],
-                        const T* const w[3], const T wc[3], const T* wclo = nullptr) {
+                        const T* const w[3], const T wc[3], const T* wclo = nullptr, bool spectra = false) {
     int mask = 0;
     for (int c = 0; c < 3; ++c)
       if (v[c]) mask |= 1 << c;
     if (P.stray && mask) {
-      stray_from_fields(v, mask);
+      if (spectra) mid_fwd(mask);
+      else stray_from_fields(v, mask);
       conv(7, mask);
       mid_inv(7);
       const int comps[3] = {0, 1, 2};
@@ -1177,14 +1182,14 @@ template <typename T> struct Eng {
     {
       const T* in[3] = {Jf(TMP)};
       T* out[3] = {Jf(MU)};
-      heat_solve_n(1, in, (T)1, out);
+      heat_solve_n(1, in, (T)1, out, P.stray ? r2c_slot(1) : nullptr);
       sums({Jf(MU)}, {dh}, {1}, grad);
       const T* v[3] = {nullptr, Jf(MU), nullptr};
       T* acc[3] = {Jf(LA1), Jf(LB2), Jf(LA3)};
       const T* ai[3] = {nullptr, Jf(LB2), Jf(LA3)};
       const T* w[3] = {nullptr, Jf(MU), nullptr};
       const T wc[3] = {0, 1, 0}, wl[3] = {0, cql, 0};
-      stray_accumulate(v, dtt, acc, ai, w, wc, wl);
+      stray_accumulate(v, dtt, acc, ai, w, wc, wl, P.stray);
     }
     // m2** = m2 + g3** m1* - g1* m3**
     pw({set1(lam1, 1, Jf(LB2)), add1(Jf(LG3), 1, Jf(LB2), f[F_A1]), add1(Jf(LA1), 1, Jf(LB2), f[F_G3SS]),
@@ -1193,14 +1198,14 @@ template <typename T> struct Eng {
     {
       const T* in[3] = {Jf(LG3)};
       T* out[3] = {Jf(MU)};
-      heat_solve_n(1, in, (T)1, out);
+      heat_solve_n(1, in, (T)1, out, P.stray ? r2c_slot(2) : nullptr);
       sums({Jf(MU)}, {dh}, {2}, grad);
       const T* v[3] = {nullptr, nullptr, Jf(MU)};
       T* acc[3] = {Jf(LA1), Jf(LA2), Jf(LA3)};
       const T* ai[3] = {Jf(LA1), nullptr, Jf(LA3)};
       const T* w[3] = {nullptr, nullptr, Jf(MU)};
       const T wc[3] = {0, 0, 1}, wl[3] = {0, 0, cql};
-      stray_accumulate(v, dtt, acc, ai, w, wc, wl);
+      stray_accumulate(v, dtt, acc, ai, w, wc, wl, P.stray);
     }
     // m3* = m3 + g1* m2* - g2* m1*
     pw({set1(lam2, 1, Jf(LA3)), add1(Jf(LG1), 1, Jf(LA3), f[F_A2]), add1(Jf(LA2), 1, Jf(LA3), f[F_G1S]),
@@ -1209,14 +1214,14 @@ template <typename T> struct Eng {
     {
       const T* in[3] = {Jf(TMP)};
       T* out[3] = {Jf(MU)};
-      heat_solve_n(1, in, (T)1, out);
+      heat_solve_n(1, in, (T)1, out, P.stray ? r2c_slot(1) : nullptr);
       sums({Jf(MU)}, {dh}, {1}, grad);
       const T* v[3] = {nullptr, Jf(MU), nullptr};
       T* acc[3] = {Jf(LA1), Jf(LA2), lam2};
       const T* ai[3] = {Jf(LA1), Jf(LA2), lam2};
       const T* w[3] = {nullptr, Jf(MU), nullptr};
       const T wc[3] = {0, 1, 0}, wl[3] = {0, cql, 0};
-      stray_accumulate(v, dtt, acc, ai, w, wc, wl);
+      stray_accumulate(v, dtt, acc, ai, w, wc, wl, P.stray);
     }
     // m2* = m2 + g3^n m1* - g1* m3
     pw({add1(lam1, 1, Jf(LA2)), set1(Jf(LG3N), 1, Jf(LA2), f[F_A1]), add1(Jf(LA1), 1, Jf(LA2), f[F_G3N]),
@@ -1225,14 +1230,14 @@ template <typename T> struct Eng {
     {
       const T* in[3] = {Jf(LG1)};
       T* out[3] = {Jf(MU)};
-      heat_solve_n(1, in, (T)1, out);
+      heat_solve_n(1, in, (T)1, out, P.stray ? r2c_slot(0) : nullptr);
       sums({Jf(MU)}, {dh}, {0}, grad);
       const T* v[3] = {Jf(MU), nullptr, nullptr};
       T* acc[3] = {Jf(LA1), lam1, lam2};
       const T* ai[3] = {Jf(LA1), lam1, lam2};
       const T* w[3] = {Jf(MU), nullptr, nullptr};
       const T wc[3] = {1, 0, 0};
-      stray_accumulate(v, dtt, acc, ai, w, wc);
+      stray_accumulate(v, dtt, acc, ai, w, wc, nullptr, P.stray);
     }
     // m1* = m1 + g2^n m3 - g3^n m2
     pw({add1(lam0, 1, Jf(LA1)), set1(Jf(TMP), 1, Jf(LA1), m3), add1(lam2, 1, Jf(LA1), f[F_G2N]),
