@@ -1111,7 +1111,8 @@ template <typename T> struct Eng {
     timed(n * P.N * TS, [&] { launch_wsum<T>(x, w, sl, n, P.N, P.partials, P.nred, grad, s); return (int)SGSPM_KC_OTHER; });
   }
 
-  // Adjoint of one SGSPM step (reverse of step(), latest-state reading).
+  // Adjoint of one SGSPM step (latest-state reading): the step recomputed from m_n,
+  // its tape left in the workspace fields, then the reverse.
   void adjoint(const T* m_n, double alpha, const double he_in[3], T* lam, double* grad, void* work) {
     T* mt = (T*)work + (long)ADJ_MT * P.N;
     (void)hipMemcpyAsync(mt, m_n, 3 * P.N * sizeof(T), hipMemcpyDeviceToDevice, s);
