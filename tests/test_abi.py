@@ -108,3 +108,26 @@ def test_terms_switch_constants_off():
     kw = dict(GOOD, terms=sg.TERM_STRAY | sg.TERM_ZEEMAN)
     eps, Q, *_ = sg.reduced_constants(**kw)
     assert eps == 0.0 and Q == 0.0
+
+
+def test_entry_points_reject_a_null_plan():
+    """Every entry point that takes a plan returns SGSPM_EINVAL for a NULL plan, before any
+    device work (so this runs without a GPU), and leaves a message."""
+    from paper_2606_28113_amd import binding
+    lib = binding.lib
+    d3 = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    buf = ctypes.c_void_p(1)   # never dereferenced: the plan check comes first
+    nb = ctypes.c_size_t()
+    calls = {
+        "sgspm_step": lambda: lib.sgspm_step(None, buf, 0.01, d3, None),
+        "sgspm_step_taped": lambda: lib.sgspm_step_taped(None, buf, 0.01, d3, buf),
+        "sgspm_adjoint_step": lambda: lib.sgspm_adjoint_step(None, buf, 0.01, d3, buf, buf),
+        "sgspm_adjoint_step_taped": lambda: lib.sgspm_adjoint_step_taped(None, buf, 0.01, d3, buf, buf, buf),
+        "sgspm_adjoint_step_noalloc": lambda: lib.sgspm_adjoint_step_noalloc(None, buf, 0.01, d3, buf, buf),
+        "sgspm_tape_bytes": lambda: lib.sgspm_tape_bytes(None, ctypes.byref(nb)),
+        "sgspm_heat_solve": lambda: lib.sgspm_heat_solve(None, buf, 1.0, buf),
+        "sgspm_stray": lambda: lib.sgspm_stray(None, buf, buf),
+    }
+    for name, call in calls.items():
+        assert call() == binding.EINVAL, name
+        assert lib.sgspm_last_error(), name
